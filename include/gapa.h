@@ -1,0 +1,178 @@
+/*
+ * gapa.h -- C ABI of the MI355X population-fitness engine for GA-based
+ * critical node detection (CND), the perturbed-substructure-optimisation
+ * problem of "Efficient Parallel Genetic Algorithm for Perturbed Substructure
+ * Optimization in Complex Network" (Section III).
+ *
+ * The library evaluates and evolves populations of k-node removal sets S over
+ * one undirected, unweighted graph G = (V, E) (Section III-A).  The fitness of
+ * an individual is the pairwise connectivity of G - S,
+ *
+ *     PC(S) = sum over connected components C of G - S of |C| (|C| - 1) / 2,
+ *
+ * the CND measure PC(G) of Section IV-C / Table III, which the GA minimises
+ * under the budget |S| = k (the cost constraint C(p) of eq. 1).  Removing a
+ * node removes all of its edges (Section III-C, eq. 13).  PC is computed
+ * exactly (the components of G - S), not with the six-hop truncation of
+ * eq. 15; MCN is the size of the largest component.
+ *
+ * Conventions for every entry point
+ *   - Return value: GAPA_OK or a gapa_status code; the message of the last
+ *     failure on the calling thread is gapa_last_error().  No C++ exception
+ *     crosses the ABI.  Outputs are unspecified when a call fails.
+ *   - Ownership: input arrays are borrowed for the duration of the call (and
+ *     copied where kept); outputs are caller-allocated; handles are owned by
+ *     the library until their *_destroy call.  *_destroy(NULL) is GAPA_OK.
+ *   - Devices and streams: a handle lives on the HIP device that was current
+ *     when it was created.  `stream` is a hipStream_t (NULL: the device's null
+ *     stream).  Host-pointer calls return after their results are on the
+ *     host; GAPA_DEVICE_PTRS calls only enqueue work on `stream`.
+ *   - A device error (GAPA_E_DEVICE) is sticky on the handle it happened on:
+ *     destroy the handle.
+ *   - Threading: calls on one handle must not overlap; distinct handles may be
+ *     used from distinct threads.
+ *   - Results never depend on the stream, the launch geometry or how the
+ *     population is split into chunks.
+ */
+#ifndef GAPA_H
+#define GAPA_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define GAPA_API __attribute__((visibility("default")))
+#else
+#define GAPA_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gapa_graph gapa_graph;
+typedef struct gapa_ga gapa_ga;
+
+typedef enum gapa_status {
+    GAPA_OK = 0,
+    GAPA_E_INVALID_ARG = 1, /* a size, pointer or parameter is out of range     */
+    GAPA_E_BAD_GRAPH = 2,   /* the CSR is not a symmetric simple sorted graph   */
+    GAPA_E_BAD_GENE = 3,    /* a gene is not a node id in [0, n)                */
+    GAPA_E_NO_DEVICE = 4,   /* no usable HIP device                             */
+    GAPA_E_DEVICE = 5,      /* a HIP call or kernel failed (sticky)             */
+    GAPA_E_OOM = 6,         /* device or host allocation failed                 */
+    GAPA_E_STATE = 7        /* the handle is unusable (earlier failure, or a
+                               random draw exhausted its 2^24 attempts)          */
+} gapa_status;
+
+enum {
+    GAPA_DEVICE_PTRS = 1u << 0, /* genes/fitness/mcn are device pointers; the call
+                                   is asynchronous on `stream`                  */
+    GAPA_TRUST_INPUT = 1u << 1, /* skip host-side validation                    */
+    GAPA_WANT_MCN = 1u << 2     /* also compute the largest component size      */
+};
+
+/* ---------------------------------------------------------------------------
+ * Graph (Section III-A: undirected, unweighted G = (V, E), |V| = n).
+ *
+ * row_ptr: int32 [n + 1], col_idx: int32 [nnz], host memory, the symmetric
+ * CSR of G: every undirected edge {u, v} appears as v in row u and u in row v;
+ * neighbour lists strictly ascending (no repeated edges), no self-loops,
+ * row_ptr[0] = 0, row_ptr[n] = nnz.  Both arrays are copied to the device.
+ * Validation (skipped with GAPA_TRUST_INPUT) fails with GAPA_E_BAD_GRAPH.
+ * Limits: 1 <= n <= 2^30, 0 <= nnz < 2^31.
+ * ------------------------------------------------------------------------- */
+GAPA_API int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                      uint32_t flags, gapa_graph **out);
+GAPA_API int gapa_graph_destroy(gapa_graph *g);
+
+/* ---------------------------------------------------------------------------
+ * Batched fitness (Section III-C, eq. 13: the perturbation of a whole
+ * population applied to G at once, then evaluated).
+ *
+ * genes:   int32 [P][k] row-major node ids, any order within a row; a repeated
+ *          id in a row is one removal (set semantics).
+ * fitness: int64 [P] out, PC of each row.
+ * mcn:     int32 [P] out or NULL; written only with GAPA_WANT_MCN.
+ * An id outside [0, n) gives GAPA_E_BAD_GENE (with GAPA_DEVICE_PTRS the check
+ * runs on the device and the call waits for it unless GAPA_TRUST_INPUT).
+ * P >= 0 (P = 0 is a no-op), 0 <= k <= n.
+ * ------------------------------------------------------------------------- */
+GAPA_API int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k,
+                         int64_t *fitness, int32_t *mcn, uint32_t flags, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Genetic algorithm (Section III-B, Fig. 1 single-GPU "S" mode).
+ *
+ * k          budget: genes per individual (1 <= k <= n / 2)
+ * pop        P: population kept by elitism (eq. 10-11), >= 1
+ * tournament T: contestants per tournament, 1..64 (replaces the roulette
+ *            wheel of eq. 5; winner = smallest (PC, position))
+ * offspring  lambda: children per generation, 0 means P
+ * seed       Philox4x32-10 key; all randomness is a pure function of
+ *            (seed, generation, individual, slot)
+ * pc, pm     per-gene crossover (eq. 4) and mutation (eq. 8) probabilities,
+ *            in [0, 1]
+ * ------------------------------------------------------------------------- */
+typedef struct gapa_params {
+    int32_t k;
+    int32_t pop;
+    int32_t tournament;
+    int32_t offspring;
+    uint64_t seed;
+    double pc;
+    double pm;
+    uint32_t flags;   /* reserved, 0 */
+    int32_t reserved; /* 0 */
+} gapa_params;
+
+/* Creates the GA on graph g (g must outlive it): draws the initial population
+ * (eq. 2), evaluates it and orders it by (PC, index): generation 0.  The work
+ * is enqueued on `stream`; the call returns once it is enqueued. */
+GAPA_API int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **out);
+
+/* Runs n_generations >= 0 further generations, each: tournament selection,
+ * crossover (eq. 3-6) with duplicate repair, mutation (eq. 7-9), batched
+ * fitness of the offspring, elitism (eq. 10-11) keeping the P best of parents
+ * and offspring.  Enqueues only; no host synchronisation. */
+GAPA_API int gapa_generation_step(gapa_ga *ga, int32_t n_generations, void *stream);
+
+/* Best individual after the last enqueued generation (eq. 1's arg max): its k
+ * genes ascending (genes_out, k int32, may be NULL), PC (may be NULL) and the
+ * generation count (may be NULL).  Host pointers; waits for the GA's work. */
+GAPA_API int gapa_best(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out, int64_t *generation_out);
+
+/* Whole population, ordered by (PC, tag): genes_out int32 [P][k], fitness_out
+ * int64 [P] (either may be NULL).  Host pointers; waits for the GA's work. */
+GAPA_API int gapa_get_population(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out);
+
+GAPA_API int gapa_ga_destroy(gapa_ga *ga);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics
+ * ------------------------------------------------------------------------- */
+
+/* Kernel timing: while enabled on a handle, the library brackets the launches
+ * of each kernel with HIP events on the launch stream.  gapa_kernel_times
+ * fills up to `cap` entries with the kernel name, launch count and summed
+ * milliseconds (it waits for outstanding work) and returns the number of
+ * entries through *count.  Names stay valid until the handle is destroyed. */
+typedef struct gapa_kernel_time {
+    const char *name;
+    int64_t launches;
+    double total_ms;
+} gapa_kernel_time;
+
+GAPA_API int gapa_graph_set_timing(gapa_graph *g, int32_t enable);
+GAPA_API int gapa_graph_kernel_times(gapa_graph *g, gapa_kernel_time *out, int32_t cap, int32_t *count);
+GAPA_API int gapa_ga_set_timing(gapa_ga *ga, int32_t enable);
+GAPA_API int gapa_ga_kernel_times(gapa_ga *ga, gapa_kernel_time *out, int32_t cap, int32_t *count);
+
+/* Message of the last failed call on this thread ("" if none). */
+GAPA_API const char *gapa_last_error(void);
+GAPA_API const char *gapa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAPA_H */

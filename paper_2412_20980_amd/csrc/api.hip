@@ -1,0 +1,593 @@
+// The C ABI of the library (include/gapa.h): argument and graph validation,
+// device buffers, streams, error reporting and kernel timing around the
+// fitness and genetic-operator kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace gapa {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    set_error("HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
+    return e == hipErrorOutOfMemory ? GAPA_E_OOM : GAPA_E_DEVICE;
+}
+
+int DevBuf::reserve(size_t want)
+{
+    if (want <= bytes && ptr) return GAPA_OK;
+    release();
+    if (want == 0) want = 4;
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        bytes = 0;
+        (void)hipGetLastError();
+        set_error("device allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
+        return GAPA_E_OOM;
+    }
+    bytes = want;
+    return GAPA_OK;
+}
+
+void DevBuf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+// ------------------------------------------------------------------ timer ----
+
+hipEvent_t KernelTimer::take()
+{
+    if (!free_.empty()) {
+        hipEvent_t e = free_.back();
+        free_.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void KernelTimer::begin(const char *name, hipStream_t s)
+{
+    Pending p;
+    p.name = name;
+    p.a = take();
+    p.b = take();
+    if (!p.a || !p.b) return;
+    (void)hipEventRecord(p.a, s);
+    pending_.push_back(p);
+    open_ = &pending_.back();
+}
+
+void KernelTimer::end(hipStream_t s)
+{
+    if (!open_) return;
+    (void)hipEventRecord(open_->b, s);
+    open_ = nullptr;
+}
+
+int KernelTimer::collect(gapa_kernel_time *out, int cap, int *count)
+{
+    for (auto &p : pending_) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(p.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        auto &t = totals_[p.name];
+        t.first += 1;
+        t.second += ms;
+        free_.push_back(p.a);
+        free_.push_back(p.b);
+    }
+    pending_.clear();
+    names_.clear();
+    for (auto &kv : totals_) names_.push_back(kv.first);
+    int i = 0;
+    for (auto &kv : totals_) {
+        if (i < cap && out) {
+            out[i].name = names_[i].c_str();
+            out[i].launches = kv.second.first;
+            out[i].total_ms = kv.second.second;
+        }
+        ++i;
+    }
+    if (count) *count = (int)totals_.size();
+    return GAPA_OK;
+}
+
+KernelTimer::~KernelTimer()
+{
+    for (auto &p : pending_) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : free_) (void)hipEventDestroy(e);
+}
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int check_device(int *dev)
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        set_error("no HIP device available");
+        return GAPA_E_NO_DEVICE;
+    }
+    if (hipGetDevice(dev) != hipSuccess) {
+        set_error("hipGetDevice failed");
+        return GAPA_E_NO_DEVICE;
+    }
+    return GAPA_OK;
+}
+
+uint64_t bernoulli_threshold(double p)
+{
+    if (!(p > 0.0)) return 0;
+    if (p >= 1.0) return 1ull << 32;
+    return (uint64_t)std::floor(std::ldexp(p, 32));
+}
+
+int validate_graph(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci)
+{
+    if (rp[0] != 0) {
+        set_error("row_ptr[0] = %d, expected 0", rp[0]);
+        return GAPA_E_BAD_GRAPH;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        if (rp[v + 1] < rp[v]) {
+            set_error("row_ptr decreases at node %d", v);
+            return GAPA_E_BAD_GRAPH;
+        }
+    }
+    if ((int64_t)rp[n] != nnz) {
+        set_error("row_ptr[n] = %d but nnz = %lld", rp[n], (long long)nnz);
+        return GAPA_E_BAD_GRAPH;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            const int32_t u = ci[e];
+            if (u < 0 || u >= n) {
+                set_error("neighbour %d of node %d is out of range", u, v);
+                return GAPA_E_BAD_GRAPH;
+            }
+            if (u == v) {
+                set_error("self-loop at node %d", v);
+                return GAPA_E_BAD_GRAPH;
+            }
+            if (e > rp[v] && ci[e - 1] >= u) {
+                set_error("neighbours of node %d are not strictly ascending", v);
+                return GAPA_E_BAD_GRAPH;
+            }
+            // symmetric: v must appear in u's (ascending) list
+            if (!std::binary_search(ci + rp[u], ci + rp[u + 1], v)) {
+                set_error("edge (%d, %d) has no reverse entry", v, u);
+                return GAPA_E_BAD_GRAPH;
+            }
+        }
+    }
+    return GAPA_OK;
+}
+
+#define API_TRY(expr)                  \
+    do {                               \
+        int _rc = (expr);              \
+        if (_rc != GAPA_OK) return _rc; \
+    } while (0)
+
+int fail_handle(bool *failed, int rc)
+{
+    if (rc == GAPA_E_DEVICE) *failed = true;
+    return rc;
+}
+
+}  // namespace
+}  // namespace gapa
+
+using namespace gapa;
+
+extern "C" {
+
+const char *gapa_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+const char *gapa_version(void)
+{
+    return "gapa-mi355x 0.1 (gfx950)";
+}
+
+int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, uint32_t flags,
+                      gapa_graph **out)
+{
+    g_last_error.clear();
+    if (!out) {
+        set_error("out is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (n < 1 || n > (1 << 30) || nnz < 0 || nnz >= (1ll << 31) || !row_ptr || (nnz > 0 && !col_idx)) {
+        set_error("invalid graph sizes or pointers (n=%d, nnz=%lld)", n, (long long)nnz);
+        return GAPA_E_INVALID_ARG;
+    }
+    if (!(flags & GAPA_TRUST_INPUT)) API_TRY(validate_graph(n, nnz, row_ptr, col_idx));
+    int dev = 0;
+    API_TRY(check_device(&dev));
+    gapa_graph *g = new (std::nothrow) gapa_graph();
+    if (!g) {
+        set_error("host allocation failed");
+        return GAPA_E_OOM;
+    }
+    g->device = dev;
+    g->n = n;
+    g->nnz = nnz;
+    g->words = (n + 31) / 32;
+    std::vector<int32_t> src((size_t)std::max<int64_t>(nnz, 1));
+    for (int32_t v = 0; v < n; ++v)
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) src[e] = v;
+    auto fail = [&](int rc) {
+        gapa_graph_destroy(g);
+        return rc;
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&g->d_row_ptr, (size_t)(n + 1) * 4)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&g->d_col, (size_t)std::max<int64_t>(nnz, 1) * 4)) != hipSuccess)
+        return fail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&g->d_src, (size_t)std::max<int64_t>(nnz, 1) * 4)) != hipSuccess)
+        return fail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMemcpy(g->d_row_ptr, row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_fail(e, "hipMemcpy"));
+    if (nnz > 0) {
+        if ((e = hipMemcpy(g->d_col, col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(hip_fail(e, "hipMemcpy"));
+        if ((e = hipMemcpy(g->d_src, src.data(), (size_t)nnz * 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(hip_fail(e, "hipMemcpy"));
+    }
+    *out = g;
+    return GAPA_OK;
+}
+
+int gapa_graph_destroy(gapa_graph *g)
+{
+    if (!g) return GAPA_OK;
+    {
+        DeviceGuard dg(g->device);
+        (void)hipDeviceSynchronize();
+        if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
+        if (g->d_col) (void)hipFree(g->d_col);
+        if (g->d_src) (void)hipFree(g->d_src);
+        FitnessWorkspace &w = g->ws;
+        for (DevBuf *b : {&w.parent, &w.count, &w.masks, &w.genes, &w.fitness, &w.mcn, &w.flag}) b->release();
+    }
+    delete g;
+    return GAPA_OK;
+}
+
+int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int64_t *fitness,
+                         int32_t *mcn, uint32_t flags, void *stream)
+{
+    g_last_error.clear();
+    if (!g) {
+        set_error("graph is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (g->failed) {
+        set_error("graph handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    if (P < 0 || k < 0 || k > g->n || (P > 0 && ((k > 0 && !genes) || !fitness))) {
+        set_error("invalid population arguments (P=%d, k=%d)", P, k);
+        return GAPA_E_INVALID_ARG;
+    }
+    if (P == 0) return GAPA_OK;
+    const bool dev_ptrs = flags & GAPA_DEVICE_PTRS;
+    const bool trust = flags & GAPA_TRUST_INPUT;
+    const bool want_mcn = (flags & GAPA_WANT_MCN) && mcn;
+    if (!dev_ptrs && !trust) {
+        for (int64_t i = 0; i < (int64_t)P * k; ++i) {
+            if (genes[i] < 0 || genes[i] >= g->n) {
+                set_error("gene %d (row %lld) is not a node id in [0, %d)", genes[i], (long long)(i / std::max(k, 1)),
+                          g->n);
+                return GAPA_E_BAD_GENE;
+            }
+        }
+    }
+    DeviceGuard dg(g->device);
+    if (!dg.ok) {
+        set_error("cannot select device %d", g->device);
+        return GAPA_E_DEVICE;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FitnessWorkspace &w = g->ws;
+    const int32_t W = g->words;
+    int rc;
+    if ((rc = w.masks.reserve((size_t)P * W * 4)) != GAPA_OK) return rc;
+    if ((rc = w.flag.reserve(16)) != GAPA_OK) return rc;
+    const int32_t *d_genes = genes;
+    int64_t *d_fit = fitness;
+    int32_t *d_mcn = want_mcn ? mcn : nullptr;
+    if (!dev_ptrs) {
+        if ((rc = w.genes.reserve((size_t)std::max<int64_t>((int64_t)P * k, 1) * 4)) != GAPA_OK) return rc;
+        if ((rc = w.fitness.reserve((size_t)P * 8)) != GAPA_OK) return rc;
+        if (want_mcn && (rc = w.mcn.reserve((size_t)P * 4)) != GAPA_OK) return rc;
+        if (k > 0)
+            GAPA_HIP(hipMemcpyAsync(w.genes.ptr, genes, (size_t)P * k * 4, hipMemcpyHostToDevice, s));
+        d_genes = w.genes.as<int32_t>();
+        d_fit = w.fitness.as<int64_t>();
+        d_mcn = want_mcn ? w.mcn.as<int32_t>() : nullptr;
+    }
+    if ((rc = launch_fill_u32(w.flag.ptr, 0u, 4, s)) != GAPA_OK) return fail_handle(&g->failed, rc);
+    {
+        TimedScope ts(&g->timer, "mask_build", s);
+        if ((rc = launch_mask_build(d_genes, P, k, g->n, W, w.masks.as<uint32_t>(), w.flag.as<int32_t>(), s)) !=
+            GAPA_OK)
+            return fail_handle(&g->failed, rc);
+    }
+    if ((rc = eval_masks(g, w.masks.as<uint32_t>(), P, d_fit, d_mcn, w, &g->timer, s)) != GAPA_OK)
+        return fail_handle(&g->failed, rc);
+    if (dev_ptrs && trust) return GAPA_OK;
+    int32_t hflag[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(hflag, w.flag.ptr, 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && !dev_ptrs) e = hipMemcpyAsync(fitness, d_fit, (size_t)P * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && !dev_ptrs && want_mcn)
+        e = hipMemcpyAsync(mcn, d_mcn, (size_t)P * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_handle(&g->failed, hip_fail(e, "eval_population copy-back"));
+    if (hflag[0]) {
+        set_error("a gene is not a node id in [0, %d)", g->n);
+        return GAPA_E_BAD_GENE;
+    }
+    return GAPA_OK;
+}
+
+int gapa_graph_set_timing(gapa_graph *g, int32_t enable)
+{
+    if (!g) return GAPA_E_INVALID_ARG;
+    g->timer.enabled = enable != 0;
+    return GAPA_OK;
+}
+
+int gapa_graph_kernel_times(gapa_graph *g, gapa_kernel_time *out, int32_t cap, int32_t *count)
+{
+    if (!g) return GAPA_E_INVALID_ARG;
+    DeviceGuard dg(g->device);
+    int c = 0;
+    int rc = g->timer.collect(out, cap, &c);
+    if (count) *count = c;
+    return rc;
+}
+
+// ---------------------------------------------------------------------- GA ---
+
+int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **out)
+{
+    g_last_error.clear();
+    if (!out || !g || !p) {
+        set_error("NULL argument");
+        return GAPA_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (g->failed) {
+        set_error("graph handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    const int32_t lambda = p->offspring > 0 ? p->offspring : p->pop;
+    if (p->k < 1 || p->k > g->n / 2 || p->pop < 1 || p->tournament < 1 || p->tournament > 64 || p->offspring < 0 ||
+        !(p->pc >= 0.0 && p->pc <= 1.0) || !(p->pm >= 0.0 && p->pm <= 1.0) || p->flags != 0) {
+        set_error("invalid GA parameters (need 1 <= k <= n/2, pop >= 1, 1 <= T <= 64, pc, pm in [0, 1])");
+        return GAPA_E_INVALID_ARG;
+    }
+    if ((int64_t)p->pop * p->k >= (1ll << 31) || (int64_t)lambda * p->k >= (1ll << 31)) {
+        set_error("population too large");
+        return GAPA_E_INVALID_ARG;
+    }
+    const size_t lds = ga_op_lds_bytes(g->n, p->k);
+    if (lds > 160 * 1024) {
+        set_error("n = %d and k = %d need %zu bytes of LDS for the operator kernels (limit 160 KiB)", g->n, p->k, lds);
+        return GAPA_E_INVALID_ARG;
+    }
+    DeviceGuard dg(g->device);
+    gapa_ga *ga = new (std::nothrow) gapa_ga();
+    if (!ga) {
+        set_error("host allocation failed");
+        return GAPA_E_OOM;
+    }
+    ga->graph = g;
+    ga->params = *p;
+    ga->lambda = lambda;
+    ga->t_pc = bernoulli_threshold(p->pc);
+    ga->t_pm = bernoulli_threshold(p->pm);
+    ga->op_lds_bytes = lds;
+    const int32_t P = p->pop, k = p->k, W = g->words;
+    const int32_t rows = std::max(P, lambda);
+    int rc = GAPA_OK;
+    auto fail = [&](int code) {
+        gapa_ga_destroy(ga);
+        return code;
+    };
+    for (int i = 0; i < 2 && rc == GAPA_OK; ++i) {
+        rc = ga->pop[i].reserve((size_t)P * k * 4);
+        if (rc == GAPA_OK) rc = ga->fit[i].reserve((size_t)P * 8);
+    }
+    if (rc == GAPA_OK) rc = ga->children.reserve((size_t)rows * k * 4);
+    if (rc == GAPA_OK) rc = ga->child_fit.reserve((size_t)rows * 8);
+    if (rc == GAPA_OK) rc = ga->masks.reserve((size_t)rows * W * 4);
+    if (rc == GAPA_OK) rc = ga->src.reserve((size_t)P * 4);
+    if (rc == GAPA_OK) rc = ga->flag.reserve(16);
+    if (rc != GAPA_OK) return fail(rc);
+    if ((rc = ga_prepare_kernels(lds)) != GAPA_OK) return fail(rc);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = launch_fill_u32(ga->flag.ptr, 0u, 4, s)) != GAPA_OK) return fail(rc);
+    if ((rc = ga_init_population(ga, s)) != GAPA_OK) return fail(rc);
+    ga->last_stream = s;
+    *out = ga;
+    return GAPA_OK;
+}
+
+int gapa_generation_step(gapa_ga *ga, int32_t n_generations, void *stream)
+{
+    g_last_error.clear();
+    if (!ga || n_generations < 0) {
+        set_error("invalid arguments");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (ga->failed) {
+        set_error("GA handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    if (ga->generation + n_generations >= (1ll << 32) - 1) {
+        set_error("generation counter would exceed 2^32 - 1");
+        return GAPA_E_INVALID_ARG;
+    }
+    DeviceGuard dg(ga->graph->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (s != ga->last_stream) {
+        // order this call after work enqueued earlier on another stream
+        hipError_t e = hipStreamSynchronize(ga->last_stream);
+        if (e != hipSuccess) return fail_handle(&ga->failed, hip_fail(e, "hipStreamSynchronize"));
+        ga->last_stream = s;
+    }
+    for (int32_t i = 0; i < n_generations; ++i) {
+        int rc = ga_generation(ga, s);
+        if (rc != GAPA_OK) return fail_handle(&ga->failed, rc);
+    }
+    return GAPA_OK;
+}
+
+static int ga_sync_check(gapa_ga *ga)
+{
+    int32_t hflag[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(hflag, ga->flag.ptr, 16, hipMemcpyDeviceToHost, ga->last_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ga->last_stream);
+    if (e != hipSuccess) return fail_handle(&ga->failed, hip_fail(e, "GA synchronisation"));
+    if (hflag[0]) {
+        ga->failed = true;
+        set_error("a random draw exhausted its 2^24 attempts");
+        return GAPA_E_STATE;
+    }
+    return GAPA_OK;
+}
+
+int gapa_best(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out, int64_t *generation_out)
+{
+    g_last_error.clear();
+    if (!ga) {
+        set_error("GA is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (ga->failed) {
+        set_error("GA handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    DeviceGuard dg(ga->graph->device);
+    hipStream_t s = ga->last_stream;
+    hipError_t e = hipSuccess;
+    if (genes_out)
+        e = hipMemcpyAsync(genes_out, ga->pop[ga->cur].ptr, (size_t)ga->params.k * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && fitness_out)
+        e = hipMemcpyAsync(fitness_out, ga->fit[ga->cur].ptr, 8, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail_handle(&ga->failed, hip_fail(e, "gapa_best copy"));
+    int rc = ga_sync_check(ga);
+    if (rc != GAPA_OK) return rc;
+    if (generation_out) *generation_out = ga->generation;
+    return GAPA_OK;
+}
+
+int gapa_get_population(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out)
+{
+    g_last_error.clear();
+    if (!ga) {
+        set_error("GA is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (ga->failed) {
+        set_error("GA handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    DeviceGuard dg(ga->graph->device);
+    hipStream_t s = ga->last_stream;
+    const int32_t P = ga->params.pop, k = ga->params.k;
+    hipError_t e = hipSuccess;
+    if (genes_out) e = hipMemcpyAsync(genes_out, ga->pop[ga->cur].ptr, (size_t)P * k * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && fitness_out)
+        e = hipMemcpyAsync(fitness_out, ga->fit[ga->cur].ptr, (size_t)P * 8, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail_handle(&ga->failed, hip_fail(e, "gapa_get_population copy"));
+    return ga_sync_check(ga);
+}
+
+int gapa_ga_destroy(gapa_ga *ga)
+{
+    if (!ga) return GAPA_OK;
+    {
+        DeviceGuard dg(ga->graph->device);
+        (void)hipDeviceSynchronize();
+        for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit,
+                        &ga->masks, &ga->src, &ga->flag})
+            b->release();
+        FitnessWorkspace &w = ga->ws;
+        for (DevBuf *b : {&w.parent, &w.count, &w.masks, &w.genes, &w.fitness, &w.mcn, &w.flag}) b->release();
+    }
+    delete ga;
+    return GAPA_OK;
+}
+
+int gapa_ga_set_timing(gapa_ga *ga, int32_t enable)
+{
+    if (!ga) return GAPA_E_INVALID_ARG;
+    ga->timer.enabled = enable != 0;
+    return GAPA_OK;
+}
+
+int gapa_ga_kernel_times(gapa_ga *ga, gapa_kernel_time *out, int32_t cap, int32_t *count)
+{
+    if (!ga) return GAPA_E_INVALID_ARG;
+    DeviceGuard dg(ga->graph->device);
+    int c = 0;
+    int rc = ga->timer.collect(out, cap, &c);
+    if (count) *count = c;
+    return rc;
+}
+
+}  // extern "C"

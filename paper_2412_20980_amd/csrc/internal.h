@@ -1,0 +1,155 @@
+// Host-side internals of the HIP library: handle layouts, device buffers,
+// kernel-timing bookkeeping and the launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "gapa.h"
+
+namespace gapa {
+
+// ---------------------------------------------------------------- errors ----
+
+void set_error(const char *fmt, ...);
+
+struct Status {
+    int code = GAPA_OK;
+    bool ok() const { return code == GAPA_OK; }
+};
+
+// ------------------------------------------------------- device buffers -----
+
+// Grow-only device allocation (contents not preserved on growth).
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int reserve(size_t want);  // GAPA_OK or GAPA_E_OOM
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// ---------------------------------------------------------------- timing ----
+
+// While enabled, each named kernel launch is bracketed by a pair of HIP
+// events recorded on its stream; totals are folded in on collect().
+class KernelTimer {
+public:
+    bool enabled = false;
+    void begin(const char *name, hipStream_t s);
+    void end(hipStream_t s);
+    int collect(gapa_kernel_time *out, int cap, int *count);
+    ~KernelTimer();
+
+private:
+    struct Pending {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending_;
+    std::vector<hipEvent_t> free_;
+    std::map<std::string, std::pair<int64_t, double>> totals_;
+    std::vector<std::string> names_;  // stable storage for returned names
+    hipEvent_t take();
+    Pending *open_ = nullptr;
+};
+
+struct TimedScope {
+    KernelTimer *t;
+    hipStream_t s;
+    TimedScope(KernelTimer *timer, const char *name, hipStream_t stream) : t(timer), s(stream)
+    {
+        if (t && t->enabled) t->begin(name, s);
+    }
+    ~TimedScope()
+    {
+        if (t && t->enabled) t->end(s);
+    }
+};
+
+// ----------------------------------------------------------------- graph ----
+
+// Scratch for the batched fitness of one chunk of individuals.
+struct FitnessWorkspace {
+    DevBuf parent;   // int32 [B][n]  union-find parents
+    DevBuf count;    // int32 [B][n]  component sizes at roots
+    DevBuf masks;    // uint32 [P][W] removed-node bit sets (eval_population)
+    DevBuf genes;    // int32 [P][k]  staged host genes
+    DevBuf fitness;  // int64 [P]
+    DevBuf mcn;      // int32 [P]
+    DevBuf flag;     // int32 [4]     device error flags
+};
+
+}  // namespace gapa
+
+struct gapa_graph {
+    int device = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t words = 0;          // ceil(n / 32): words of a node bit set
+    int32_t *d_row_ptr = nullptr;
+    int32_t *d_col = nullptr;
+    int32_t *d_src = nullptr;   // source node of every CSR entry (COO rows)
+    gapa::FitnessWorkspace ws;
+    gapa::KernelTimer timer;
+    bool failed = false;
+};
+
+namespace gapa {
+
+// Fitness of P individuals given as removed-node bit sets masks[P][W] (device).
+// Writes fitness[P] (int64) and, if mcn != nullptr, mcn[P] (int32).
+int eval_masks(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,
+               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+
+// Fills count 32-bit words at p with value (a kernel, not a memset node).
+int launch_fill_u32(void *p, uint32_t value, int64_t count, hipStream_t s);
+
+// genes[P][k] (device) -> masks[P][W]; out-of-range genes raise flag[0].
+int launch_mask_build(const int32_t *genes, int32_t P, int32_t k, int32_t n, int32_t W, uint32_t *masks,
+                      int32_t *flag, hipStream_t s);
+
+// ------------------------------------------------------------------- GA -----
+
+// Dynamic LDS of the operator kernels for n nodes and budget k, and the
+// function attributes they need when it exceeds the default 64 KiB.
+size_t ga_op_lds_bytes(int32_t n, int32_t k);
+int ga_prepare_kernels(size_t lds);
+
+int ga_init_population(gapa_ga *ga, hipStream_t s);
+int ga_generation(gapa_ga *ga, hipStream_t s);
+
+// Error reporting for HIP calls.
+int hip_fail(hipError_t e, const char *what);
+#define GAPA_HIP(call)                                                  \
+    do {                                                                \
+        hipError_t _e = (call);                                         \
+        if (_e != hipSuccess) return ::gapa::hip_fail(_e, #call);       \
+    } while (0)
+
+}  // namespace gapa
+
+struct gapa_ga {
+    gapa_graph *graph = nullptr;
+    gapa_params params{};
+    int32_t lambda = 0;
+    uint64_t t_pc = 0, t_pm = 0;  // Bernoulli thresholds floor(p * 2^32)
+    int64_t generation = 0;
+    int cur = 0;                  // which population buffer is current
+    gapa::DevBuf pop[2];          // int32 [P][k]
+    gapa::DevBuf fit[2];          // int64 [P]
+    gapa::DevBuf children;        // int32 [lambda][k]
+    gapa::DevBuf child_fit;       // int64 [lambda]
+    gapa::DevBuf masks;           // uint32 [max(P, lambda)][W]
+    gapa::DevBuf src;             // int32 [P] elitism: source tag of each kept row
+    gapa::DevBuf flag;            // int32 [4] device error flags
+    gapa::FitnessWorkspace ws;
+    gapa::KernelTimer timer;
+    hipStream_t last_stream = nullptr;
+    size_t op_lds_bytes = 0;      // dynamic LDS of the operator kernels
+    bool failed = false;
+};

@@ -1,0 +1,270 @@
+"""Python binding of libgapa.so (include/gapa.h): argument marshalling only.
+
+Every step of fitness evaluation and of the genetic algorithm runs in the HIP
+library; this module converts numpy arrays / torch tensors to pointers and
+status codes to exceptions.  There is no fallback: if the library is not
+built, importing the binding raises.
+
+PyTorch, when installed, is imported before the library is loaded so that the
+process maps a single HIP runtime (torch's); torch tensors on the GPU can then
+be passed directly (GAPA_DEVICE_PTRS) together with torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:  # load torch's HIP runtime first, so libgapa binds to the same one
+    import torch  # noqa: F401
+    _HAVE_TORCH = True
+except Exception:  # pragma: no cover - torch is part of the image
+    torch = None
+    _HAVE_TORCH = False
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgapa.so")
+
+GAPA_OK = 0
+GAPA_E_INVALID_ARG = 1
+GAPA_E_BAD_GRAPH = 2
+GAPA_E_BAD_GENE = 3
+GAPA_E_NO_DEVICE = 4
+GAPA_E_DEVICE = 5
+GAPA_E_OOM = 6
+GAPA_E_STATE = 7
+
+GAPA_DEVICE_PTRS = 1 << 0
+GAPA_TRUST_INPUT = 1 << 1
+GAPA_WANT_MCN = 1 << 2
+
+EXPORTED = (
+    "gapa_graph_create", "gapa_graph_destroy", "gapa_eval_population",
+    "gapa_ga_create", "gapa_generation_step", "gapa_best", "gapa_get_population", "gapa_ga_destroy",
+    "gapa_graph_set_timing", "gapa_graph_kernel_times", "gapa_ga_set_timing", "gapa_ga_kernel_times",
+    "gapa_last_error", "gapa_version",
+)
+
+
+class GapaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gapa error {code}: {msg}")
+        self.code = code
+
+
+class gapa_params(C.Structure):
+    _fields_ = [
+        ("k", C.c_int32), ("pop", C.c_int32), ("tournament", C.c_int32), ("offspring", C.c_int32),
+        ("seed", C.c_uint64), ("pc", C.c_double), ("pm", C.c_double),
+        ("flags", C.c_uint32), ("reserved", C.c_int32),
+    ]
+
+
+class gapa_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2412_20980_amd.build_lib`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32p, i64p = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    L.gapa_graph_create.argtypes = [C.c_int32, C.c_int64, vp, vp, C.c_uint32, C.POINTER(vp)]
+    L.gapa_graph_destroy.argtypes = [vp]
+    L.gapa_eval_population.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, C.c_uint32, vp]
+    L.gapa_ga_create.argtypes = [vp, C.POINTER(gapa_params), vp, C.POINTER(vp)]
+    L.gapa_generation_step.argtypes = [vp, C.c_int32, vp]
+    L.gapa_best.argtypes = [vp, vp, i64p, i64p]
+    L.gapa_get_population.argtypes = [vp, vp, vp]
+    L.gapa_ga_destroy.argtypes = [vp]
+    for f in (L.gapa_graph_set_timing, L.gapa_ga_set_timing):
+        f.argtypes = [vp, C.c_int32]
+    for f in (L.gapa_graph_kernel_times, L.gapa_ga_kernel_times):
+        f.argtypes = [vp, C.POINTER(gapa_kernel_time), C.c_int32, i32p]
+    L.gapa_last_error.restype = C.c_char_p
+    L.gapa_version.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != GAPA_OK:
+        raise GapaError(rc, lib().gapa_last_error().decode())
+
+
+def gapa_version() -> str:
+    return lib().gapa_version().decode()
+
+
+def _is_dev_tensor(x) -> bool:
+    return _HAVE_TORCH and isinstance(x, torch.Tensor) and x.is_cuda
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        if _HAVE_TORCH and torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return C.c_void_p(None)
+    if _HAVE_TORCH and isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+# ----------------------------------------------------------------- graph ----
+
+def gapa_graph_create(n: int, row_ptr, col_idx, flags: int = 0) -> C.c_void_p:
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib().gapa_graph_create(n, ci.shape[0], rp.ctypes.data, ci.ctypes.data if ci.size else None, flags,
+                                   C.byref(h)))
+    return h
+
+
+def gapa_graph_destroy(h):
+    _check(lib().gapa_graph_destroy(h))
+
+
+def gapa_eval_population(h, genes, fitness=None, mcn=None, flags: int = 0, stream=None):
+    """genes: numpy [P, k] int32 (host) or a torch int32 CUDA tensor (device;
+    fitness/mcn must then be torch CUDA tensors too).  Returns fitness (and mcn
+    when requested)."""
+    if _is_dev_tensor(genes):
+        assert genes.dtype == torch.int32 and genes.is_contiguous() and genes.dim() == 2
+        P, k = genes.shape
+        if fitness is None:
+            fitness = torch.empty(P, dtype=torch.int64, device=genes.device)
+        if flags & GAPA_WANT_MCN and mcn is None:
+            mcn = torch.zeros(P, dtype=torch.int32, device=genes.device)
+        _check(lib().gapa_eval_population(h, genes.data_ptr(), P, k, fitness.data_ptr(),
+                                          mcn.data_ptr() if mcn is not None else None,
+                                          flags | GAPA_DEVICE_PTRS, _stream_ptr(stream)))
+    else:
+        G = np.ascontiguousarray(genes, dtype=np.int32)
+        if G.ndim == 1:
+            G = G[None, :]
+        P, k = G.shape
+        if fitness is None:
+            fitness = np.zeros(P, dtype=np.int64)
+        if flags & GAPA_WANT_MCN and mcn is None:
+            mcn = np.zeros(P, dtype=np.int32)
+        _check(lib().gapa_eval_population(h, G.ctypes.data, P, k, fitness.ctypes.data,
+                                          mcn.ctypes.data if mcn is not None else None,
+                                          flags & ~GAPA_DEVICE_PTRS, _stream_ptr(stream)))
+    return (fitness, mcn) if flags & GAPA_WANT_MCN else fitness
+
+
+def _kernel_times(fn, h) -> dict:
+    cap = 64
+    arr = (gapa_kernel_time * cap)()
+    cnt = C.c_int32(0)
+    _check(fn(h, arr, cap, C.byref(cnt)))
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(cnt.value, cap))}
+
+
+class Graph:
+    """A CSR graph resident on the current HIP device."""
+
+    def __init__(self, n: int, row_ptr, col_idx, trust: bool = False):
+        self.n = int(n)
+        self.handle = gapa_graph_create(self.n, row_ptr, col_idx, GAPA_TRUST_INPUT if trust else 0)
+
+    @classmethod
+    def from_csr(cls, g, trust: bool = False) -> "Graph":
+        return cls(g.n, g.row_ptr, g.col_idx, trust)
+
+    def eval(self, genes, want_mcn: bool = False, trust: bool = False, stream=None):
+        flags = (GAPA_WANT_MCN if want_mcn else 0) | (GAPA_TRUST_INPUT if trust else 0)
+        return gapa_eval_population(self.handle, genes, flags=flags, stream=stream)
+
+    def set_timing(self, on: bool = True):
+        _check(lib().gapa_graph_set_timing(self.handle, int(on)))
+
+    def kernel_times(self) -> dict:
+        return _kernel_times(lib().gapa_graph_kernel_times, self.handle)
+
+    def close(self):
+        if self.handle:
+            gapa_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# -------------------------------------------------------------------- GA ----
+
+def gapa_ga_create(graph_handle, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, stream=None):
+    p = gapa_params(k=k, pop=pop, tournament=tournament, offspring=offspring, seed=seed, pc=pc, pm=pm, flags=0,
+                    reserved=0)
+    h = C.c_void_p()
+    _check(lib().gapa_ga_create(graph_handle, C.byref(p), _stream_ptr(stream), C.byref(h)))
+    return h
+
+
+def gapa_generation_step(h, n_generations: int = 1, stream=None):
+    _check(lib().gapa_generation_step(h, n_generations, _stream_ptr(stream)))
+
+
+def gapa_best(h, k: int):
+    genes = np.zeros(k, dtype=np.int32)
+    f = C.c_int64(0)
+    g = C.c_int64(0)
+    _check(lib().gapa_best(h, genes.ctypes.data, C.byref(f), C.byref(g)))
+    return genes, int(f.value), int(g.value)
+
+
+def gapa_get_population(h, P: int, k: int):
+    genes = np.zeros((P, k), dtype=np.int32)
+    F = np.zeros(P, dtype=np.int64)
+    _check(lib().gapa_get_population(h, genes.ctypes.data, F.ctypes.data))
+    return genes, F
+
+
+def gapa_ga_destroy(h):
+    _check(lib().gapa_ga_destroy(h))
+
+
+class GA:
+    """The GA on one graph; generation 0 is drawn and evaluated at creation."""
+
+    def __init__(self, graph: Graph, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, stream=None):
+        self.graph = graph
+        self.k, self.pop = int(k), int(pop)
+        self.handle = gapa_ga_create(graph.handle, k, pop, seed, pc, pm, tournament, offspring, stream)
+
+    def step(self, n: int = 1, stream=None):
+        gapa_generation_step(self.handle, n, stream)
+
+    def best(self):
+        return gapa_best(self.handle, self.k)
+
+    def population(self):
+        return gapa_get_population(self.handle, self.pop, self.k)
+
+    def set_timing(self, on: bool = True):
+        _check(lib().gapa_ga_set_timing(self.handle, int(on)))
+
+    def kernel_times(self) -> dict:
+        return _kernel_times(lib().gapa_ga_kernel_times, self.handle)
+
+    def close(self):
+        if self.handle:
+            gapa_ga_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,156 @@
+"""GPU parity of the whole GA trajectory against the CPU oracle, through the
+C ABI: every generation's population (rows and int64 fitness, in order) must
+be bit-identical."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cnd_oracle as O
+from paper_2412_20980_amd import inputs
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def gp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2412_20980_amd import gapa
+    return gapa
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(os.path.join(HERE, "golden", "trajectories.json")) as f:
+        return json.load(f)
+
+
+def state_hash(pop, F):
+    h = hashlib.sha256()
+    h.update(pop.astype("<i4").tobytes())
+    h.update(F.astype("<i8").tobytes())
+    return h.hexdigest()[:32]
+
+
+def lockstep(gp, g, k, P, seed, pc, pm, T, lam, gens, graph=None):
+    graph = graph or gp.Graph.from_csr(g)
+    print(f"GA n={g.n} k={k} P={P} T={T} lambda={lam} gens={gens}", flush=True)
+    ga = gp.GA(graph, k, P, seed, pc, pm, T, lam)
+    oga = O.OracleGA(g, k, P, seed, pc, pm, T, lam)
+    for gen in range(gens + 1):
+        pop, F = ga.population()
+        assert np.array_equal(F, oga.F), f"fitness differs at generation {gen}"
+        assert np.array_equal(pop, oga.pop), f"population differs at generation {gen}"
+        if gen < gens:
+            ga.step(1)
+            oga.step()
+    genes, f, gcount = ga.best()
+    assert gcount == gens and f == oga.F[0] and np.array_equal(genes, oga.pop[0])
+
+
+def test_ba200_full_trajectory(gp, ba200):
+    W = inputs.workload("ba200_k10_p32")
+    lockstep(gp, ba200, W.k, W.pop, W.seed, W.pc, W.pm, W.tournament, 0, W.generations)
+
+
+@pytest.mark.parametrize("n,k,P,T,pc,pm,lam,seed", [
+    (60, 5, 8, 2, 0.5, 0.3, 0, 3),
+    (40, 20, 5, 3, 0.9, 0.2, 7, 4),
+    (90, 12, 6, 5, 0.7, 0.05, 3, 5),
+    (30, 1, 4, 1, 1.0, 1.0, 0, (1 << 40) + 9),
+    (50, 7, 1, 2, 0.7, 0.5, 0, 6),
+    (500, 50, 80, 2, 0.5, 0.3, 0, 7),     # the paper's CND shape: Table II SixDST rates, 10% budget
+    (3000, 300, 33, 4, 0.6, 0.2, 50, 8),  # k > 256 slots per operator block, ragged P
+])
+def test_small_config_trajectories(gp, n, k, P, T, pc, pm, lam, seed):
+    g = inputs.erdos_renyi(n, 3.0, seed=n)
+    lockstep(gp, g, k, P, seed, pc, pm, T, lam, 6)
+
+
+def test_no_variation_fixed_point(gp, ba200):
+    graph = gp.Graph.from_csr(ba200)
+    ga = gp.GA(graph, 10, 32, 0, pc=0.0, pm=0.0)
+    pop0, F0 = ga.population()
+    ga.step(5)
+    pop5, F5 = ga.population()
+    assert np.array_equal(pop0, pop5) and np.array_equal(F0, F5)
+
+
+def test_ba10k_trajectory_matches_golden(gp, ba10k, golden):
+    W = inputs.workload("ba10k_k100_p256")
+    ref = golden[W.name]
+    assert ref["graph_sha256"] == ba10k.sha256()
+    graph = gp.Graph.from_csr(ba10k)
+    ga = gp.GA(graph, W.k, W.pop, W.seed, W.pc, W.pm, W.tournament)
+    pop, F = ga.population()
+    assert state_hash(pop, F) == ref["hash"][0]
+    for gen in range(1, W.generations + 1):
+        ga.step(1)
+        pop, F = ga.population()
+        assert state_hash(pop, F) == ref["hash"][gen], f"generation {gen}"
+        assert F[0] == ref["best"][gen]
+
+
+def test_cl200k_first_generations_match_golden(gp, cl200k, golden):
+    W = inputs.workload("cl200k_k2000_p1024")
+    ref = golden[W.name]
+    assert ref["graph_sha256"] == cl200k.sha256()
+    graph = gp.Graph.from_csr(cl200k)
+    ga = gp.GA(graph, W.k, W.pop, W.seed, W.pc, W.pm, W.tournament)
+    pop, F = ga.population()
+    assert state_hash(pop, F) == ref["hash"][0]
+    for gen in range(1, ref["generations"] + 1):
+        ga.step(1)
+        pop, F = ga.population()
+        assert state_hash(pop, F) == ref["hash"][gen], f"generation {gen}"
+
+
+def test_cl200k_sampled_offspring_against_oracle(gp, cl200k):
+    """At the full workload size, a sample of one generation's offspring is
+    rebuilt one by one by the oracle's operators from the GPU's parent
+    population, and the elitism result is checked for order and fitness."""
+    W = inputs.workload("cl200k_k2000_p1024")
+    graph = gp.Graph.from_csr(cl200k)
+    ga = gp.GA(graph, W.k, W.pop, W.seed, W.pc, W.pm, W.tournament)
+    ga.step(2)
+    pop2, F2 = ga.population()
+    params = O.make_params(cl200k.n, W.k, W.pop, W.seed, W.pc, W.pm, W.tournament)
+    kids = []
+    for o in range(0, W.pop, 97):
+        child, _, _, _ = O.make_child(params, 3, o, pop2, F2)
+        kids.append(child)
+    kids = np.array(kids)
+    Fk = O.eval_population(cl200k, kids)
+    ga.step(1)
+    pop3, F3 = ga.population()
+    assert np.all(np.diff(F3) >= 0)
+    assert np.all(np.diff(pop3, axis=1) > 0)
+    # each kept row's fitness is its true PC
+    idx = np.arange(0, W.pop, 128)
+    assert np.array_equal(O.eval_population(cl200k, pop3[idx]), F3[idx])
+    # sampled offspring that survived appear in the new population with their fitness
+    rows = {r.tobytes(): f for r, f in zip(pop3, F3)}
+    for child, f in zip(kids, Fk):
+        if f < F3[-1]:
+            assert rows.get(child.astype(np.int32).tobytes()) == f
+
+
+def test_side_stream_and_timing(gp, ba10k):
+    import torch
+    W = inputs.workload("ba10k_k100_p256")
+    graph = gp.Graph.from_csr(ba10k)
+    s = torch.cuda.Stream()
+    ga = gp.GA(graph, W.k, W.pop, W.seed, W.pc, W.pm, W.tournament, stream=s)
+    ga.set_timing(True)
+    ga.step(3, stream=s)
+    oga = O.OracleGA(ba10k, W.k, W.pop, W.seed, W.pc, W.pm, W.tournament)
+    for _ in range(3):
+        oga.step()
+    pop, F = ga.population()
+    assert np.array_equal(pop, oga.pop) and np.array_equal(F, oga.F)
+    t = ga.kernel_times()
+    assert "ga_offspring" in t and t["ga_offspring"][0] == 3
