@@ -42,6 +42,8 @@ def kernel_unit_bytes(name: str, n: int, nnz: int) -> int | None:
         "cc_init": 4 * n,
         "cc_reduce": 4 * n,
     }
+    if name.startswith("k_"):
+        return algorithmic_bytes_per_eval(n, nnz)
     return table.get(name)
 
 
@@ -141,6 +143,7 @@ def main():
                      "algorithmic_bytes_per_individual": unit, "individuals_per_launch": per_launch_inds},
         "effective_eval_GBs": evals_per_s * algorithmic_bytes_per_eval(g.n, g.nnz) / 1e9,
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(times.items())},
+        "fitness_stats": ga.fitness_stats(),
         "best_pc": best_f,
         "generation": gen_count,
     }

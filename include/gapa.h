@@ -68,7 +68,10 @@ enum {
     GAPA_DEVICE_PTRS = 1u << 0, /* genes/fitness/mcn are device pointers; the call
                                    is asynchronous on `stream`                  */
     GAPA_TRUST_INPUT = 1u << 1, /* skip host-side validation                    */
-    GAPA_WANT_MCN = 1u << 2     /* also compute the largest component size      */
+    GAPA_WANT_MCN = 1u << 2,    /* also compute the largest component size      */
+    GAPA_UNIONFIND = 1u << 3    /* gapa_graph_create: evaluate with edge-parallel
+                                   union-find instead of bit-parallel sweeps
+                                   (same results, slower; a cross-check)        */
 };
 
 /* ---------------------------------------------------------------------------
@@ -166,6 +169,14 @@ GAPA_API int gapa_graph_set_timing(gapa_graph *g, int32_t enable);
 GAPA_API int gapa_graph_kernel_times(gapa_graph *g, gapa_kernel_time *out, int32_t cap, int32_t *count);
 GAPA_API int gapa_ga_set_timing(gapa_ga *ga, int32_t enable);
 GAPA_API int gapa_ga_kernel_times(gapa_ga *ga, gapa_kernel_time *out, int32_t cap, int32_t *count);
+
+/* Counters of the last chunk the bit-parallel fitness evaluated on a handle
+ * (waits for outstanding work): out[0] individuals per chunk, out[1] nodes
+ * still pending after the ordered sweep, out[2] (individual, node) pairs left
+ * to the union-find pass, out[3] follow-up sweeps that still changed
+ * something.  All zero before the first evaluation. */
+GAPA_API int gapa_graph_fitness_stats(gapa_graph *g, int64_t out[4]);
+GAPA_API int gapa_ga_fitness_stats(gapa_ga *ga, int64_t out[4]);
 
 /* Message of the last failed call on this thread ("" if none). */
 GAPA_API const char *gapa_last_error(void);

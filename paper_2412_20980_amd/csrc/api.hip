@@ -210,11 +210,95 @@ int validate_graph(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci)
     return GAPA_OK;
 }
 
+// Host-side orderings used by the bit-parallel fitness kernels:
+//   order  - all nodes by (degree desc, id): root candidates;
+//   colD   - each neighbour list by (degree desc, id): hubs are read first;
+//   bands  - non-isolated nodes by breadth-first level from the highest-degree
+//            nodes of G (multi-source), levels merged into at most kMaxBands
+//            bands; nodes no source reaches form the last band.
+constexpr int kSources = 64;
+constexpr int kMaxBands = 24;
+
+void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, std::vector<int32_t> &order,
+                     std::vector<int32_t> &colD, std::vector<int32_t> &band_v, std::vector<int32_t> &band_off)
+{
+    std::vector<int32_t> deg(n);
+    for (int32_t v = 0; v < n; ++v) deg[v] = rp[v + 1] - rp[v];
+    auto by_degree = [&](int32_t a, int32_t b) { return deg[a] != deg[b] ? deg[a] > deg[b] : a < b; };
+    order.resize(n);
+    for (int32_t v = 0; v < n; ++v) order[v] = v;
+    std::sort(order.begin(), order.end(), by_degree);
+    colD.assign(ci, ci + rp[n]);
+    for (int32_t v = 0; v < n; ++v) std::sort(colD.begin() + rp[v], colD.begin() + rp[v + 1], by_degree);
+
+    std::vector<int32_t> level(n, -1);
+    std::vector<int32_t> frontier, next;
+    for (int32_t p = 0; p < n && (int)frontier.size() < kSources; ++p) {
+        const int32_t v = order[p];
+        if (deg[v] == 0) break;
+        level[v] = 0;
+        frontier.push_back(v);
+    }
+    int32_t lv = 0;
+    while (!frontier.empty()) {
+        next.clear();
+        for (int32_t v : frontier)
+            for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+                if (level[ci[e]] < 0) {
+                    level[ci[e]] = lv + 1;
+                    next.push_back(ci[e]);
+                }
+        frontier.swap(next);
+        ++lv;
+    }
+    const int32_t unreached = lv;  // non-isolated nodes no source reaches
+    band_v.clear();
+    for (int32_t v = 0; v < n; ++v)
+        if (deg[v] > 0) {
+            if (level[v] < 0) level[v] = unreached;
+            band_v.push_back(v);
+        }
+    std::sort(band_v.begin(), band_v.end(),
+              [&](int32_t a, int32_t b) { return level[a] != level[b] ? level[a] < level[b] : a < b; });
+    const int32_t nlev = unreached + 1;
+    const int32_t nb = std::min<int32_t>(nlev, kMaxBands);
+    band_off.assign(1, 0);
+    size_t pos = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int32_t lev_end = (int32_t)(((int64_t)(b + 1) * nlev) / nb);  // levels [.., lev_end)
+        while (pos < band_v.size() && level[band_v[pos]] < lev_end) ++pos;
+        band_off.push_back((int32_t)pos);
+    }
+}
+
 #define API_TRY(expr)                  \
     do {                               \
         int _rc = (expr);              \
         if (_rc != GAPA_OK) return _rc; \
     } while (0)
+
+void release_workspace(FitnessWorkspace &w)
+{
+    for (DevBuf *b : {&w.parent, &w.count, &w.dead, &w.reach, &w.ucount, &w.pairs, &w.worklist, &w.small, &w.masks,
+                      &w.genes, &w.fitness, &w.mcn, &w.flag})
+        b->release();
+    w.stats_ctr = nullptr;
+}
+
+int fitness_stats(FitnessWorkspace &w, int64_t out[4])
+{
+    for (int i = 0; i < 4; ++i) out[i] = 0;
+    if (!w.stats_ctr) return GAPA_OK;
+    int32_t h[8] = {0};
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(h, w.stats_ctr, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "fitness stats");
+    out[0] = w.stats_B;
+    out[1] = h[0];
+    out[2] = h[1];
+    for (int i = 3; i < 8; ++i) out[3] += h[i] != 0;  // changed flags of sweeps 1..
+    return GAPA_OK;
+}
 
 int fail_handle(bool *failed, int rc)
 {
@@ -264,9 +348,13 @@ int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int3
     g->n = n;
     g->nnz = nnz;
     g->words = (n + 31) / 32;
+    g->algorithm = (flags & GAPA_UNIONFIND) ? 1 : 0;
     std::vector<int32_t> src((size_t)std::max<int64_t>(nnz, 1));
     for (int32_t v = 0; v < n; ++v)
         for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) src[e] = v;
+    std::vector<int32_t> order, colD, band_v;
+    graph_orderings(n, row_ptr, col_idx, order, colD, band_v, g->band_off);
+    g->n_noniso = (int32_t)band_v.size();
     auto fail = [&](int rc) {
         gapa_graph_destroy(g);
         return rc;
@@ -279,12 +367,24 @@ int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int3
         return fail(hip_fail(e, "hipMalloc"));
     if ((e = hipMemcpy(g->d_row_ptr, row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(hip_fail(e, "hipMemcpy"));
+    if ((e = hipMalloc(&g->d_colD, (size_t)std::max<int64_t>(nnz, 1) * 4)) != hipSuccess)
+        return fail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&g->d_order, (size_t)n * 4)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&g->d_band_v, (size_t)std::max<size_t>(band_v.size(), 1) * 4)) != hipSuccess)
+        return fail(hip_fail(e, "hipMalloc"));
     if (nnz > 0) {
         if ((e = hipMemcpy(g->d_col, col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice)) != hipSuccess)
             return fail(hip_fail(e, "hipMemcpy"));
         if ((e = hipMemcpy(g->d_src, src.data(), (size_t)nnz * 4, hipMemcpyHostToDevice)) != hipSuccess)
             return fail(hip_fail(e, "hipMemcpy"));
+        if ((e = hipMemcpy(g->d_colD, colD.data(), (size_t)nnz * 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(hip_fail(e, "hipMemcpy"));
     }
+    if ((e = hipMemcpy(g->d_order, order.data(), (size_t)n * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_fail(e, "hipMemcpy"));
+    if (!band_v.empty() &&
+        (e = hipMemcpy(g->d_band_v, band_v.data(), band_v.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_fail(e, "hipMemcpy"));
     *out = g;
     return GAPA_OK;
 }
@@ -297,9 +397,9 @@ int gapa_graph_destroy(gapa_graph *g)
         (void)hipDeviceSynchronize();
         if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
         if (g->d_col) (void)hipFree(g->d_col);
-        if (g->d_src) (void)hipFree(g->d_src);
-        FitnessWorkspace &w = g->ws;
-        for (DevBuf *b : {&w.parent, &w.count, &w.masks, &w.genes, &w.fitness, &w.mcn, &w.flag}) b->release();
+        for (int32_t *p : {g->d_src, g->d_colD, g->d_order, g->d_band_v})
+            if (p) (void)hipFree(p);
+        release_workspace(g->ws);
     }
     delete g;
     return GAPA_OK;
@@ -341,9 +441,7 @@ int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     FitnessWorkspace &w = g->ws;
-    const int32_t W = g->words;
     int rc;
-    if ((rc = w.masks.reserve((size_t)P * W * 4)) != GAPA_OK) return rc;
     if ((rc = w.flag.reserve(16)) != GAPA_OK) return rc;
     const int32_t *d_genes = genes;
     int64_t *d_fit = fitness;
@@ -359,13 +457,7 @@ int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t
         d_mcn = want_mcn ? w.mcn.as<int32_t>() : nullptr;
     }
     if ((rc = launch_fill_u32(w.flag.ptr, 0u, 4, s)) != GAPA_OK) return fail_handle(&g->failed, rc);
-    {
-        TimedScope ts(&g->timer, "mask_build", s);
-        if ((rc = launch_mask_build(d_genes, P, k, g->n, W, w.masks.as<uint32_t>(), w.flag.as<int32_t>(), s)) !=
-            GAPA_OK)
-            return fail_handle(&g->failed, rc);
-    }
-    if ((rc = eval_masks(g, w.masks.as<uint32_t>(), P, d_fit, d_mcn, w, &g->timer, s)) != GAPA_OK)
+    if ((rc = eval_genes(g, d_genes, P, k, false, d_fit, d_mcn, w.flag.as<int32_t>(), w, &g->timer, s)) != GAPA_OK)
         return fail_handle(&g->failed, rc);
     if (dev_ptrs && trust) return GAPA_OK;
     int32_t hflag[4] = {0, 0, 0, 0};
@@ -380,6 +472,20 @@ int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t
         return GAPA_E_BAD_GENE;
     }
     return GAPA_OK;
+}
+
+int gapa_graph_fitness_stats(gapa_graph *g, int64_t out[4])
+{
+    if (!g || !out) return GAPA_E_INVALID_ARG;
+    DeviceGuard dg(g->device);
+    return fitness_stats(g->ws, out);
+}
+
+int gapa_ga_fitness_stats(gapa_ga *ga, int64_t out[4])
+{
+    if (!ga || !out) return GAPA_E_INVALID_ARG;
+    DeviceGuard dg(ga->graph->device);
+    return fitness_stats(ga->ws, out);
 }
 
 int gapa_graph_set_timing(gapa_graph *g, int32_t enable)
@@ -440,7 +546,7 @@ int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **
     ga->t_pc = bernoulli_threshold(p->pc);
     ga->t_pm = bernoulli_threshold(p->pm);
     ga->op_lds_bytes = lds;
-    const int32_t P = p->pop, k = p->k, W = g->words;
+    const int32_t P = p->pop, k = p->k;
     const int32_t rows = std::max(P, lambda);
     int rc = GAPA_OK;
     auto fail = [&](int code) {
@@ -453,7 +559,6 @@ int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **
     }
     if (rc == GAPA_OK) rc = ga->children.reserve((size_t)rows * k * 4);
     if (rc == GAPA_OK) rc = ga->child_fit.reserve((size_t)rows * 8);
-    if (rc == GAPA_OK) rc = ga->masks.reserve((size_t)rows * W * 4);
     if (rc == GAPA_OK) rc = ga->src.reserve((size_t)P * 4);
     if (rc == GAPA_OK) rc = ga->flag.reserve(16);
     if (rc != GAPA_OK) return fail(rc);
@@ -563,11 +668,10 @@ int gapa_ga_destroy(gapa_ga *ga)
     {
         DeviceGuard dg(ga->graph->device);
         (void)hipDeviceSynchronize();
-        for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit,
-                        &ga->masks, &ga->src, &ga->flag})
+        for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit, &ga->src,
+                        &ga->flag})
             b->release();
-        FitnessWorkspace &w = ga->ws;
-        for (DevBuf *b : {&w.parent, &w.count, &w.masks, &w.genes, &w.fitness, &w.mcn, &w.flag}) b->release();
+        release_workspace(ga->ws);
     }
     delete ga;
     return GAPA_OK;

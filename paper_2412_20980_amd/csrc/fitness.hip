@@ -181,8 +181,23 @@ int launch_mask_build(const int32_t *genes, int32_t P, int32_t k, int32_t n, int
     return GAPA_OK;
 }
 
-int eval_masks(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,
-               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
+int eval_genes(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, bool distinct, int64_t *fitness,
+               int32_t *mcn, int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
+{
+    if (P <= 0) return GAPA_OK;
+    if (g->algorithm != 1) return eval_genes_bits(g, genes, P, k, distinct, fitness, mcn, flag, ws, timer, s);
+    int rc;
+    if ((rc = ws.masks.reserve((size_t)P * g->words * 4)) != GAPA_OK) return rc;
+    {
+        TimedScope ts(timer, "mask_build", s);
+        if ((rc = launch_mask_build(genes, P, k, g->n, g->words, ws.masks.as<uint32_t>(), flag, s)) != GAPA_OK)
+            return rc;
+    }
+    return eval_masks_unionfind(g, ws.masks.as<uint32_t>(), P, fitness, mcn, ws, timer, s);
+}
+
+int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,
+                         FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
 {
     if (P <= 0) return GAPA_OK;
     const int32_t n = g->n, W = g->words;

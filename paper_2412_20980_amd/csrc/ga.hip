@@ -2,10 +2,9 @@
 // tournament selection, positional crossover (eq. 3-6) with duplicate repair,
 // swap mutation (eq. 7-9) and elitism (eq. 10-11).
 //
-// One workgroup builds one individual.  Its membership bit set over the nodes
-// lives in LDS while the row is built and is written out as the individual's
-// removed-node mask, which is exactly what the fitness kernels consume, so no
-// separate mask-building pass runs per generation.  Every random decision is
+// One workgroup builds one individual; its membership bit set over the nodes
+// lives in LDS while the row is built, and the finished row is written out
+// sorted for the fitness kernels.  Every random decision is
 // a Philox draw keyed by (seed, generation, individual, slot): the result is a
 // pure function of the seed and does not depend on the launch geometry.
 #include <algorithm>
@@ -24,7 +23,6 @@ struct OpArgs {
     const int32_t *pop;   // [P][k] current population, rows ascending
     const int64_t *fit;   // [P]   ordered by (PC, position)
     int32_t *children;    // [L][k] out
-    uint32_t *masks;      // [L][W] out: removed-node bit sets of the children
     int32_t *flag;        // [1]   attempts exhausted
     uint64_t seed, t_pc, t_pm;
     uint32_t gen;
@@ -92,8 +90,6 @@ __device__ void write_out(const OpLds &l, const OpArgs &a, int32_t idx)
 {
     int32_t *dst = a.children + (int64_t)idx * a.k;
     for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) dst[j] = l.row[j];
-    uint32_t *m = a.masks + (int64_t)idx * a.W;
-    for (int32_t w = threadIdx.x; w < a.W; w += blockDim.x) m[w] = l.U[w];
 }
 
 // Initial individual i (eq. 2): slot j takes the first INIT draw that is not
@@ -277,7 +273,6 @@ OpArgs make_args(gapa_ga *ga, const int32_t *pop, const int64_t *fit, uint32_t g
     a.pop = pop;
     a.fit = fit;
     a.children = ga->children.as<int32_t>();
-    a.masks = ga->masks.as<uint32_t>();
     a.flag = ga->flag.as<int32_t>();
     a.seed = ga->params.seed;
     a.t_pc = ga->t_pc;
@@ -346,8 +341,8 @@ int ga_init_population(gapa_ga *ga, hipStream_t s)
         hipLaunchKernelGGL(k_init, dim3(P), dim3(kOpBlock), ga->op_lds_bytes, s, a);
     }
     GAPA_HIP(hipGetLastError());
-    int rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), P, ga->child_fit.as<int64_t>(), nullptr, ga->ws,
-                        &ga->timer, s);
+    int rc = eval_genes(ga->graph, ga->children.as<int32_t>(), P, ga->params.k, true, ga->child_fit.as<int64_t>(), nullptr,
+                        ga->flag.as<int32_t>() + 1, ga->ws, &ga->timer, s);
     if (rc != GAPA_OK) return rc;
     return rank_and_gather(ga, nullptr, nullptr, 0, P, s);
 }
@@ -364,8 +359,8 @@ int ga_generation(gapa_ga *ga, hipStream_t s)
         hipLaunchKernelGGL(k_offspring, dim3(L), dim3(kOpBlock), ga->op_lds_bytes, s, a);
     }
     GAPA_HIP(hipGetLastError());
-    int rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), L, ga->child_fit.as<int64_t>(), nullptr, ga->ws,
-                        &ga->timer, s);
+    int rc = eval_genes(ga->graph, ga->children.as<int32_t>(), L, ga->params.k, true, ga->child_fit.as<int64_t>(), nullptr,
+                        ga->flag.as<int32_t>() + 1, ga->ws, &ga->timer, s);
     if (rc != GAPA_OK) return rc;
     rc = rank_and_gather(ga, fit, pop, P, L, s);
     if (rc != GAPA_OK) return rc;

@@ -76,7 +76,15 @@ struct TimedScope {
 // Scratch for the batched fitness of one chunk of individuals.
 struct FitnessWorkspace {
     DevBuf parent;   // int32 [B][n]  union-find parents
-    DevBuf count;    // int32 [B][n]  component sizes at roots
+    DevBuf count;    // int32 [B][n]  component sizes at roots (union-find path)
+    DevBuf dead;     // uint32 [n][Wd] removed bits, node-major (bit-parallel path)
+    DevBuf reach;    // uint32 [n][Wd] root-component bits
+    DevBuf ucount;   // int32 [B][n]  set sizes of the leftover union-find, kept zero
+    DevBuf pairs;    // int64 [B * n_noniso] pending (individual, node) keys
+    DevBuf worklist; // int32 [n_noniso] nodes still pending after the ordered sweep
+    DevBuf small;    // int32 roots, root-set sizes, counters, count partials
+    int32_t *stats_ctr = nullptr;  // device counters of the last bit-parallel chunk
+    int32_t stats_B = 0;
     DevBuf masks;    // uint32 [P][W] removed-node bit sets (eval_population)
     DevBuf genes;    // int32 [P][k]  staged host genes
     DevBuf fitness;  // int64 [P]
@@ -94,6 +102,12 @@ struct gapa_graph {
     int32_t *d_row_ptr = nullptr;
     int32_t *d_col = nullptr;
     int32_t *d_src = nullptr;   // source node of every CSR entry (COO rows)
+    int32_t *d_order = nullptr; // [n] nodes by (degree desc, id)
+    int32_t *d_colD = nullptr;  // [nnz] each neighbour list by (degree desc, id)
+    int32_t *d_band_v = nullptr;  // [n_noniso] non-isolated nodes by (BFS level, id)
+    std::vector<int32_t> band_off;  // host: band b is d_band_v[band_off[b], band_off[b+1])
+    int32_t n_noniso = 0;       // nodes with at least one edge
+    int32_t algorithm = 0;      // 0: bit-parallel sweeps, 1: edge-parallel union-find
     gapa::FitnessWorkspace ws;
     gapa::KernelTimer timer;
     bool failed = false;
@@ -101,10 +115,17 @@ struct gapa_graph {
 
 namespace gapa {
 
-// Fitness of P individuals given as removed-node bit sets masks[P][W] (device).
-// Writes fitness[P] (int64) and, if mcn != nullptr, mcn[P] (int32).
-int eval_masks(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,
-               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+// Fitness of P individuals given as gene rows genes[P][k] (device, node ids;
+// a repeated id in a row is one removal).  Writes fitness[P] (int64) and, if
+// mcn != nullptr, mcn[P] (int32); a gene outside [0, n) sets flag[0] and is
+// ignored.  Runs the graph's selected algorithm.
+// `distinct`: every row is known to hold distinct ids (the GA's rows).
+int eval_genes(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, bool distinct, int64_t *fitness,
+               int32_t *mcn, int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+int eval_genes_bits(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, bool distinct, int64_t *fitness,
+                    int32_t *mcn, int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,
+                         FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
 
 // Fills count 32-bit words at p with value (a kernel, not a memset node).
 int launch_fill_u32(void *p, uint32_t value, int64_t count, hipStream_t s);
@@ -144,7 +165,6 @@ struct gapa_ga {
     gapa::DevBuf fit[2];          // int64 [P]
     gapa::DevBuf children;        // int32 [lambda][k]
     gapa::DevBuf child_fit;       // int64 [lambda]
-    gapa::DevBuf masks;           // uint32 [max(P, lambda)][W]
     gapa::DevBuf src;             // int32 [P] elitism: source tag of each kept row
     gapa::DevBuf flag;            // int32 [4] device error flags
     gapa::FitnessWorkspace ws;

@@ -38,12 +38,13 @@ GAPA_E_STATE = 7
 GAPA_DEVICE_PTRS = 1 << 0
 GAPA_TRUST_INPUT = 1 << 1
 GAPA_WANT_MCN = 1 << 2
+GAPA_UNIONFIND = 1 << 3
 
 EXPORTED = (
     "gapa_graph_create", "gapa_graph_destroy", "gapa_eval_population",
     "gapa_ga_create", "gapa_generation_step", "gapa_best", "gapa_get_population", "gapa_ga_destroy",
     "gapa_graph_set_timing", "gapa_graph_kernel_times", "gapa_ga_set_timing", "gapa_ga_kernel_times",
-    "gapa_last_error", "gapa_version",
+    "gapa_graph_fitness_stats", "gapa_ga_fitness_stats", "gapa_last_error", "gapa_version",
 )
 
 
@@ -88,6 +89,8 @@ def lib() -> C.CDLL:
         f.argtypes = [vp, C.c_int32]
     for f in (L.gapa_graph_kernel_times, L.gapa_ga_kernel_times):
         f.argtypes = [vp, C.POINTER(gapa_kernel_time), C.c_int32, i32p]
+    for f in (L.gapa_graph_fitness_stats, L.gapa_ga_fitness_stats):
+        f.argtypes = [vp, i64p]
     L.gapa_last_error.restype = C.c_char_p
     L.gapa_version.restype = C.c_char_p
     _lib = L
@@ -161,6 +164,12 @@ def gapa_eval_population(h, genes, fitness=None, mcn=None, flags: int = 0, strea
     return (fitness, mcn) if flags & GAPA_WANT_MCN else fitness
 
 
+def _fitness_stats(fn, h) -> dict:
+    out = (C.c_int64 * 4)()
+    _check(fn(h, out))
+    return {"chunk": out[0], "pending_nodes": out[1], "leftover_pairs": out[2], "changing_sweeps": out[3]}
+
+
 def _kernel_times(fn, h) -> dict:
     cap = 64
     arr = (gapa_kernel_time * cap)()
@@ -172,13 +181,14 @@ def _kernel_times(fn, h) -> dict:
 class Graph:
     """A CSR graph resident on the current HIP device."""
 
-    def __init__(self, n: int, row_ptr, col_idx, trust: bool = False):
+    def __init__(self, n: int, row_ptr, col_idx, trust: bool = False, unionfind: bool = False):
         self.n = int(n)
-        self.handle = gapa_graph_create(self.n, row_ptr, col_idx, GAPA_TRUST_INPUT if trust else 0)
+        flags = (GAPA_TRUST_INPUT if trust else 0) | (GAPA_UNIONFIND if unionfind else 0)
+        self.handle = gapa_graph_create(self.n, row_ptr, col_idx, flags)
 
     @classmethod
-    def from_csr(cls, g, trust: bool = False) -> "Graph":
-        return cls(g.n, g.row_ptr, g.col_idx, trust)
+    def from_csr(cls, g, trust: bool = False, unionfind: bool = False) -> "Graph":
+        return cls(g.n, g.row_ptr, g.col_idx, trust, unionfind)
 
     def eval(self, genes, want_mcn: bool = False, trust: bool = False, stream=None):
         flags = (GAPA_WANT_MCN if want_mcn else 0) | (GAPA_TRUST_INPUT if trust else 0)
@@ -189,6 +199,9 @@ class Graph:
 
     def kernel_times(self) -> dict:
         return _kernel_times(lib().gapa_graph_kernel_times, self.handle)
+
+    def fitness_stats(self) -> dict:
+        return _fitness_stats(lib().gapa_graph_fitness_stats, self.handle)
 
     def close(self):
         if self.handle:
@@ -257,6 +270,9 @@ class GA:
 
     def kernel_times(self) -> dict:
         return _kernel_times(lib().gapa_ga_kernel_times, self.handle)
+
+    def fitness_stats(self) -> dict:
+        return _fitness_stats(lib().gapa_ga_fitness_stats, self.handle)
 
     def close(self):
         if self.handle:

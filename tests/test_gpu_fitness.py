@@ -20,9 +20,12 @@ def gp():
     return gapa
 
 
-def check(gp, g, pop, want_mcn=True, graph=None):
-    graph = graph or gp.Graph.from_csr(g)
-    print(f"eval n={g.n} nnz={g.nnz} P={pop.shape[0]} k={pop.shape[1]}", flush=True)
+ALGOS = ["bits", "unionfind"]
+
+
+def check(gp, g, pop, want_mcn=True, graph=None, algo="bits"):
+    graph = graph or gp.Graph.from_csr(g, unionfind=(algo == "unionfind"))
+    print(f"eval {algo} n={g.n} nnz={g.nnz} P={pop.shape[0]} k={pop.shape[1]}", flush=True)
     F, M = graph.eval(pop, want_mcn=True)
     Fo, Mo = O.eval_population(g, pop, want_mcn=True)
     assert np.array_equal(F, Fo), np.nonzero(F != Fo)[0][:10]
@@ -31,9 +34,10 @@ def check(gp, g, pop, want_mcn=True, graph=None):
     return F
 
 
-def test_ba200_random_populations(gp, ba200):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_ba200_random_populations(gp, ba200, algo):
     for seed in range(3):
-        check(gp, ba200, inputs.random_population(ba200.n, 10, 32, seed=seed))
+        check(gp, ba200, inputs.random_population(ba200.n, 10, 32, seed=seed), algo=algo)
 
 
 def test_ba10k_random_and_hub_biased(gp, ba10k):
@@ -42,15 +46,32 @@ def test_ba10k_random_and_hub_biased(gp, ba10k):
     check(gp, ba10k, inputs.hub_biased_population(ba10k, 100, 64, seed=5, hub_frac=0.9), graph=graph)
 
 
-def test_cl200k_sample_spans_chunks(gp, cl200k):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_cl200k_sample_spans_chunks(gp, cl200k, algo):
     # 400 individuals at n = 200k run as more than one chunk of the union-find workspace
-    graph = gp.Graph.from_csr(cl200k)
+    graph = gp.Graph.from_csr(cl200k, unionfind=(algo == "unionfind"))
     pop = np.concatenate([inputs.random_population(cl200k.n, 2000, 200, seed=6),
                           inputs.hub_biased_population(cl200k, 2000, 200, seed=7, hub_frac=0.8)])
     check(gp, cl200k, pop, graph=graph)
 
 
-def test_small_graph_families_ragged_sizes(gp):
+def test_cl200k_full_population_hub_heavy(gp, cl200k):
+    # the benchmark's shape: 1024 individuals at once; rows that remove most of
+    # the top hubs fragment the graph and leave work for the leftover pass
+    graph = gp.Graph.from_csr(cl200k)
+    pop = np.concatenate([inputs.hub_biased_population(cl200k, 2000, 512, seed=8, hub_frac=1.0),
+                          inputs.random_population(cl200k.n, 2000, 512, seed=9)])
+    check(gp, cl200k, pop, graph=graph)
+
+
+def test_many_chunks_and_padding(gp, ba10k):
+    graph = gp.Graph.from_csr(ba10k)
+    for P in (1, 31, 33, 1025, 2100):
+        check(gp, ba10k, inputs.random_population(ba10k.n, 100, P, seed=P), graph=graph)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_small_graph_families_ragged_sizes(gp, algo):
     rng = np.random.default_rng(0)
     graphs = [
         inputs.barabasi_albert(1000, 1, seed=1),        # tree
@@ -64,12 +85,13 @@ def test_small_graph_families_ragged_sizes(gp):
         for k in (0, 1, max(1, g.n // 20), g.n // 2):
             P = int(rng.integers(1, 40))
             pop = inputs.random_population(g.n, k, P, seed=int(rng.integers(1 << 30))) if k else np.zeros((P, 0), np.int32)
-            check(gp, g, pop)
+            check(gp, g, pop, algo=algo)
 
 
-def test_edge_cases(gp):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_edge_cases(gp, algo):
     g = inputs.erdos_renyi(200, 3.0, seed=9)
-    graph = gp.Graph.from_csr(g)
+    graph = gp.Graph.from_csr(g, unionfind=(algo == "unionfind"))
     # everything removed, duplicates in a row (set semantics), a single row
     allrm = np.arange(200, dtype=np.int32)[None, :]
     check(gp, g, allrm, graph=graph)
@@ -78,9 +100,25 @@ def test_edge_cases(gp):
     assert F[0] == O.pc(g, [5, 7])[0]
     # edgeless graph and one-node graph
     e = inputs.csr_from_edges(50, np.array([], dtype=int), np.array([], dtype=int))
-    check(gp, e, inputs.random_population(50, 5, 3, seed=1))
+    check(gp, e, inputs.random_population(50, 5, 3, seed=1), algo=algo)
     one = inputs.csr_from_edges(1, np.array([], dtype=int), np.array([], dtype=int))
-    check(gp, one, np.zeros((2, 0), np.int32))
+    check(gp, one, np.zeros((2, 0), np.int32), algo=algo)
+    # a long path: the ordered sweep cannot settle it, the leftover pass must
+    p = inputs.csr_from_edges(3000, np.arange(2999), np.arange(1, 3000))
+    check(gp, p, inputs.random_population(3000, 30, 40, seed=3), algo=algo)
+    check(gp, p, np.zeros((3, 0), np.int32), algo=algo)
+    # disjoint cliques plus isolated nodes; only isolated survivors in some rows
+    us, vs, off = [], [], 0
+    for size in (7, 1, 12, 3, 1, 1, 30):
+        u, v = np.triu_indices(size, 1)
+        us.append(u + off)
+        vs.append(v + off)
+        off += size
+    cl = inputs.csr_from_edges(off, np.concatenate(us), np.concatenate(vs))
+    deg = cl.degrees()
+    noniso = np.nonzero(deg > 0)[0].astype(np.int32)
+    check(gp, cl, np.stack([noniso, noniso]), algo=algo)
+    check(gp, cl, inputs.random_population(off, 20, 16, seed=4), algo=algo)
     # P = 0 is a no-op
     assert graph.eval(np.zeros((0, 3), np.int32)).shape == (0,)
 
