@@ -560,6 +560,7 @@ int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **
     if (rc == GAPA_OK) rc = ga->children.reserve((size_t)rows * k * 4);
     if (rc == GAPA_OK) rc = ga->child_fit.reserve((size_t)rows * 8);
     if (rc == GAPA_OK) rc = ga->src.reserve((size_t)P * 4);
+    if (rc == GAPA_OK) rc = ga->rank.reserve((size_t)(P + lambda) * 4);
     if (rc == GAPA_OK) rc = ga->flag.reserve(16);
     if (rc != GAPA_OK) return fail(rc);
     if ((rc = ga_prepare_kernels(lds)) != GAPA_OK) return fail(rc);
@@ -669,7 +670,7 @@ int gapa_ga_destroy(gapa_ga *ga)
         DeviceGuard dg(ga->graph->device);
         (void)hipDeviceSynchronize();
         for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit, &ga->src,
-                        &ga->flag})
+                        &ga->rank, &ga->flag})
             b->release();
         release_workspace(ga->ws);
     }

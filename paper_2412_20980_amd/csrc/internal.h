@@ -143,6 +143,13 @@ int ga_prepare_kernels(size_t lds);
 
 int ga_init_population(gapa_ga *ga, hipStream_t s);
 int ga_generation(gapa_ga *ga, hipStream_t s);
+int ga_launch_init(gapa_ga *ga, hipStream_t s);
+int ga_launch_offspring(gapa_ga *ga, uint32_t gen, int32_t count, hipStream_t s);
+// Elitism over the npar current parents (f_par / par_rows; 0 at generation 0)
+// and npool evaluated offspring (f_pool[q] is the fitness of child pool[q], or
+// of child q when pool is NULL); writes the next population buffer.
+int ga_rank_and_gather(gapa_ga *ga, const int64_t *f_par, const int32_t *par_rows, int32_t npar,
+                       const int64_t *f_pool, const int32_t *pool, int32_t npool, hipStream_t s);
 
 // Error reporting for HIP calls.
 int hip_fail(hipError_t e, const char *what);
@@ -166,6 +173,7 @@ struct gapa_ga {
     gapa::DevBuf children;        // int32 [lambda][k]
     gapa::DevBuf child_fit;       // int64 [lambda]
     gapa::DevBuf src;             // int32 [P] elitism: source tag of each kept row
+    gapa::DevBuf rank;            // int32 [P + lambda] elitism: offspring below each key
     gapa::DevBuf flag;            // int32 [4] device error flags
     gapa::FitnessWorkspace ws;
     gapa::KernelTimer timer;
