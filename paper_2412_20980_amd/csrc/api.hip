@@ -2,6 +2,7 @@
 // device buffers, streams, error reporting and kernel timing around the
 // fitness and genetic-operator kernels.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -218,6 +219,7 @@ int validate_graph(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci)
 //            bands; nodes no source reaches form the last band.
 constexpr int kSources = 64;
 constexpr int kMaxBands = 24;
+constexpr int kMinBand = 4096;
 
 void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, std::vector<int32_t> &order,
                      std::vector<int32_t> &colD, std::vector<int32_t> &band_v, std::vector<int32_t> &band_off)
@@ -260,14 +262,34 @@ void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, std::vecto
         }
     std::sort(band_v.begin(), band_v.end(),
               [&](int32_t a, int32_t b) { return level[a] != level[b] ? level[a] < level[b] : a < b; });
+    // Bands: level 0 (the sources) alone; later levels joined until a band
+    // holds kMinBand nodes, so that sparse tail levels do not each cost a
+    // launch; at most kMaxBands bands.
     const int32_t nlev = unreached + 1;
-    const int32_t nb = std::min<int32_t>(nlev, kMaxBands);
+    std::vector<int32_t> lev_count(nlev, 0);
+    for (int32_t v : band_v) ++lev_count[level[v]];
     band_off.assign(1, 0);
-    size_t pos = 0;
-    for (int32_t b = 0; b < nb; ++b) {
-        const int32_t lev_end = (int32_t)(((int64_t)(b + 1) * nlev) / nb);  // levels [.., lev_end)
-        while (pos < band_v.size() && level[band_v[pos]] < lev_end) ++pos;
-        band_off.push_back((int32_t)pos);
+    int32_t acc = 0, cur = 0;
+    for (int32_t lv2 = 0; lv2 < nlev; ++lv2) {
+        acc += lev_count[lv2];
+        cur += lev_count[lv2];
+        if (lv2 == 0 || cur >= kMinBand) {
+            band_off.push_back(acc);
+            cur = 0;
+        }
+    }
+    if (band_off.back() != acc) band_off.push_back(acc);
+    while ((int32_t)band_off.size() - 1 > kMaxBands) {  // merge the two smallest neighbours
+        size_t best = 1;
+        int32_t best_size = INT32_MAX;
+        for (size_t b = 1; b + 1 < band_off.size(); ++b) {
+            const int32_t sz = band_off[b + 1] - band_off[b - 1];
+            if (sz < best_size) {
+                best_size = sz;
+                best = b;
+            }
+        }
+        band_off.erase(band_off.begin() + best);
     }
 }
 
@@ -280,7 +302,7 @@ void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, std::vecto
 void release_workspace(FitnessWorkspace &w)
 {
     for (DevBuf *b : {&w.parent, &w.count, &w.dead, &w.reach, &w.ucount, &w.pairs, &w.worklist, &w.small, &w.masks,
-                      &w.genes, &w.fitness, &w.mcn, &w.flag})
+                      &w.alive, &w.genes, &w.fitness, &w.mcn, &w.flag})
         b->release();
     w.stats_ctr = nullptr;
 }
@@ -355,6 +377,9 @@ int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int3
     std::vector<int32_t> order, colD, band_v;
     graph_orderings(n, row_ptr, col_idx, order, colD, band_v, g->band_off);
     g->n_noniso = (int32_t)band_v.size();
+    std::vector<uint32_t> noniso_bits((size_t)g->words, 0u);
+    for (int32_t v = 0; v < n; ++v)
+        if (row_ptr[v + 1] > row_ptr[v]) noniso_bits[v >> 5] |= 1u << (v & 31);
     auto fail = [&](int rc) {
         gapa_graph_destroy(g);
         return rc;
@@ -382,6 +407,9 @@ int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int3
     }
     if ((e = hipMemcpy(g->d_order, order.data(), (size_t)n * 4, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(hip_fail(e, "hipMemcpy"));
+    if ((e = hipMalloc(&g->d_noniso, (size_t)g->words * 4)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMemcpy(g->d_noniso, noniso_bits.data(), (size_t)g->words * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_fail(e, "hipMemcpy"));
     if (!band_v.empty() &&
         (e = hipMemcpy(g->d_band_v, band_v.data(), band_v.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(hip_fail(e, "hipMemcpy"));
@@ -399,6 +427,7 @@ int gapa_graph_destroy(gapa_graph *g)
         if (g->d_col) (void)hipFree(g->d_col);
         for (int32_t *p : {g->d_src, g->d_colD, g->d_order, g->d_band_v})
             if (p) (void)hipFree(p);
+        if (g->d_noniso) (void)hipFree(g->d_noniso);
         release_workspace(g->ws);
     }
     delete g;
@@ -457,7 +486,7 @@ int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t
         d_mcn = want_mcn ? w.mcn.as<int32_t>() : nullptr;
     }
     if ((rc = launch_fill_u32(w.flag.ptr, 0u, 4, s)) != GAPA_OK) return fail_handle(&g->failed, rc);
-    if ((rc = eval_genes(g, d_genes, P, k, false, d_fit, d_mcn, w.flag.as<int32_t>(), w, &g->timer, s)) != GAPA_OK)
+    if ((rc = eval_genes(g, d_genes, P, k, d_fit, d_mcn, w.flag.as<int32_t>(), w, &g->timer, s)) != GAPA_OK)
         return fail_handle(&g->failed, rc);
     if (dev_ptrs && trust) return GAPA_OK;
     int32_t hflag[4] = {0, 0, 0, 0};
@@ -559,6 +588,8 @@ int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **
     }
     if (rc == GAPA_OK) rc = ga->children.reserve((size_t)rows * k * 4);
     if (rc == GAPA_OK) rc = ga->child_fit.reserve((size_t)rows * 8);
+    if (rc == GAPA_OK) rc = ga->masks.reserve((size_t)rows * g->words * 4);
+    if (rc == GAPA_OK) rc = ga->alive.reserve((size_t)rows * 4);
     if (rc == GAPA_OK) rc = ga->src.reserve((size_t)P * 4);
     if (rc == GAPA_OK) rc = ga->rank.reserve((size_t)(P + lambda) * 4);
     if (rc == GAPA_OK) rc = ga->flag.reserve(16);
@@ -669,8 +700,8 @@ int gapa_ga_destroy(gapa_ga *ga)
     {
         DeviceGuard dg(ga->graph->device);
         (void)hipDeviceSynchronize();
-        for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit, &ga->src,
-                        &ga->rank, &ga->flag})
+        for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit,
+                        &ga->masks, &ga->alive, &ga->src, &ga->rank, &ga->flag})
             b->release();
         release_workspace(ga->ws);
     }

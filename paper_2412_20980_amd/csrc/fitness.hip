@@ -58,6 +58,44 @@ __device__ __forceinline__ void unite(int32_t *parent, int32_t a, int32_t b)
     }
 }
 
+// Removed-node bit set of each row of genes, built in LDS and written out,
+// plus the row's count of surviving non-isolated nodes.  One block per row.
+__global__ void k_mask_build_lds(const int32_t *__restrict__ genes, int32_t k, int32_t n, int32_t W,
+                                 const uint32_t *__restrict__ noniso, int32_t n_noniso, uint32_t *__restrict__ masks,
+                                 int32_t *__restrict__ alive, int32_t *__restrict__ flag)
+{
+    extern __shared__ uint32_t U[];
+    __shared__ int32_t part[kBlock / 64];
+    const int32_t i = blockIdx.x;
+    for (int32_t w = threadIdx.x; w < W; w += blockDim.x) U[w] = 0u;
+    __syncthreads();
+    const int32_t *row = genes + (int64_t)i * k;
+    for (int32_t j = threadIdx.x; j < k; j += blockDim.x) {
+        const int32_t v = row[j];
+        if (v < 0 || v >= n) {
+            atomicOr(flag, 1);
+            continue;
+        }
+        atomicOr(U + (v >> 5), 1u << (v & 31));
+    }
+    __syncthreads();
+    uint32_t *m = masks + (int64_t)i * W;
+    int32_t gone = 0;
+    for (int32_t w = threadIdx.x; w < W; w += blockDim.x) {
+        m[w] = U[w];
+        gone += __popc(U[w] & noniso[w]);
+    }
+    for (int off = 32; off > 0; off >>= 1) gone += __shfl_down(gone, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = gone;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += part[q];
+        alive[i] = n_noniso - t;
+    }
+}
+
+// Same with the bit set built in global memory (bit sets too large for LDS).
 __global__ void k_mask_build(const int32_t *__restrict__ genes, int32_t k, int32_t n, int32_t W,
                              uint32_t *__restrict__ masks, int32_t *__restrict__ flag)
 {
@@ -73,6 +111,24 @@ __global__ void k_mask_build(const int32_t *__restrict__ genes, int32_t k, int32
             continue;
         }
         atomicOr(m + (v >> 5), 1u << (v & 31));
+    }
+}
+
+__global__ void k_mask_alive(const uint32_t *__restrict__ masks, int32_t W, const uint32_t *__restrict__ noniso,
+                             int32_t n_noniso, int32_t *__restrict__ alive)
+{
+    __shared__ int32_t part[kBlock / 64];
+    const int32_t i = blockIdx.x;
+    const uint32_t *m = masks + (int64_t)i * W;
+    int32_t gone = 0;
+    for (int32_t w = threadIdx.x; w < W; w += blockDim.x) gone += __popc(m[w] & noniso[w]);
+    for (int off = 32; off > 0; off >>= 1) gone += __shfl_down(gone, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = gone;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += part[q];
+        alive[i] = n_noniso - t;
     }
 }
 
@@ -172,28 +228,44 @@ int launch_fill_u32(void *p, uint32_t value, int64_t count, hipStream_t s)
     return GAPA_OK;
 }
 
-int launch_mask_build(const int32_t *genes, int32_t P, int32_t k, int32_t n, int32_t W, uint32_t *masks,
-                      int32_t *flag, hipStream_t s)
+int launch_mask_build(const int32_t *genes, int32_t P, int32_t k, int32_t n, int32_t W, const uint32_t *noniso,
+                      int32_t n_noniso, uint32_t *masks, int32_t *alive, int32_t *flag, hipStream_t s)
 {
     if (P <= 0) return GAPA_OK;
-    hipLaunchKernelGGL(k_mask_build, dim3(P), dim3(kBlock), 0, s, genes, k, n, W, masks, flag);
+    const size_t lds = (size_t)W * 4;
+    if (lds <= 64 * 1024) {
+        hipLaunchKernelGGL(k_mask_build_lds, dim3(P), dim3(kBlock), lds, s, genes, k, n, W, noniso, n_noniso, masks,
+                           alive, flag);
+    } else {
+        hipLaunchKernelGGL(k_mask_build, dim3(P), dim3(kBlock), 0, s, genes, k, n, W, masks, flag);
+        hipLaunchKernelGGL(k_mask_alive, dim3(P), dim3(kBlock), 0, s, masks, W, noniso, n_noniso, alive);
+    }
     GAPA_HIP(hipGetLastError());
     return GAPA_OK;
 }
 
-int eval_genes(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, bool distinct, int64_t *fitness,
-               int32_t *mcn, int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
+int eval_masks(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness, int32_t *mcn,
+               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
 {
     if (P <= 0) return GAPA_OK;
-    if (g->algorithm != 1) return eval_genes_bits(g, genes, P, k, distinct, fitness, mcn, flag, ws, timer, s);
+    if (g->algorithm == 1) return eval_masks_unionfind(g, masks, P, fitness, mcn, ws, timer, s);
+    return eval_masks_bits(g, masks, alive, P, fitness, mcn, ws, timer, s);
+}
+
+int eval_genes(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int64_t *fitness, int32_t *mcn,
+               int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
+{
+    if (P <= 0) return GAPA_OK;
     int rc;
     if ((rc = ws.masks.reserve((size_t)P * g->words * 4)) != GAPA_OK) return rc;
+    if ((rc = ws.alive.reserve((size_t)P * 4)) != GAPA_OK) return rc;
     {
         TimedScope ts(timer, "mask_build", s);
-        if ((rc = launch_mask_build(genes, P, k, g->n, g->words, ws.masks.as<uint32_t>(), flag, s)) != GAPA_OK)
+        if ((rc = launch_mask_build(genes, P, k, g->n, g->words, g->d_noniso, g->n_noniso, ws.masks.as<uint32_t>(),
+                                    ws.alive.as<int32_t>(), flag, s)) != GAPA_OK)
             return rc;
     }
-    return eval_masks_unionfind(g, ws.masks.as<uint32_t>(), P, fitness, mcn, ws, timer, s);
+    return eval_masks(g, ws.masks.as<uint32_t>(), ws.alive.as<int32_t>(), P, fitness, mcn, ws, timer, s);
 }
 
 int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,

@@ -32,8 +32,8 @@ namespace gapa {
 namespace {
 
 constexpr int kBlk = 256;
-constexpr int kSweepGrid = 1024;  // blocks of the grid-stride worklist kernels
-constexpr int kSweeps = 6;        // follow-up sweeps over the pending nodes
+constexpr int kSweepGrid = 4096;  // blocks of the grid-stride worklist kernels
+constexpr int kSweeps = 4;        // follow-up sweeps over the pending nodes
 
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p)
 {
@@ -55,68 +55,100 @@ __device__ __forceinline__ uint64_t group_mask(int Wd)
     return ones << (lane & ~(Wd - 1));
 }
 
-// dead rows of a chunk start as "padding removes everything": bits of
-// individuals past B_real set, the rest clear.
-__global__ void k_dead_init(uint32_t *__restrict__ dead, int64_t words, int32_t Wd, int32_t B_real)
+// dead rows from per-individual removed-node bit sets masks[B_real][W]: a
+// block takes kTileWords node words (32 * kTileWords nodes) of every
+// individual of the chunk, stages them in LDS (rows of kTileWords words are
+// contiguous in global memory), transposes each 32 x 32 bit block with
+// ballots, and writes the tile's dead rows, which are one contiguous range of
+// the node-major array.  The same range of reach rows is cleared.
+// Individuals past B_real are padding and remove every node.
+constexpr int kTileWords = 8;
+
+// 32 x 32 bit-matrix transpose across the 32 lanes of a half-wave: lane r
+// holds row r (bit c = entry (r, c)); afterwards lane c holds column c (bit r =
+// entry (r, c)).  Five rounds swap the off-diagonal blocks of 16, 8, 4, 2 and 1
+// bits between lanes r and r ^ j.
+__device__ __forceinline__ uint32_t transpose32(uint32_t x, int l32)
 {
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < words; x += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t w = (int32_t)(x & (Wd - 1));
-        const int32_t first = w * 32;
-        uint32_t pad = 0;
-        if (B_real <= first) pad = 0xFFFFFFFFu;
-        else if (B_real < first + 32) pad = ~((1u << (B_real - first)) - 1u);
-        dead[x] = pad;
+    const uint32_t masks[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+        const int j = 16 >> s;
+        const uint32_t m = masks[s];
+        const uint32_t y = __shfl_xor(x, j, 64);
+        x = (l32 & j) ? (((y >> j) & m) | (x & ~m)) : ((x & m) | ((y & m) << j));
     }
+    return x;
 }
 
-// One block per individual i: sets i's bit in the dead row of each of its
-// genes (eq. 13's batched perturbation), and counts its distinct removed
-// non-isolated nodes: alive_noniso[i] = n_noniso - that count.  Genes outside
-// [0, n) raise flag[0] and are skipped.  kDistinct: the caller guarantees
-// distinct ids per row (the GA's rows), so each gene counts once.
-template <bool kDistinct>
-__global__ __launch_bounds__(kBlk) void k_dead_scatter(const int32_t *__restrict__ genes, int32_t k, int32_t n,
-                                                       int32_t Wd, const int32_t *__restrict__ row_ptr,
-                                                       int32_t n_noniso, uint32_t *__restrict__ dead,
-                                                       int32_t *__restrict__ alive_noniso, int32_t *__restrict__ flag)
+__global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restrict__ masks, int32_t W, int32_t B_real,
+                                                         int32_t log_wd, int32_t n, uint32_t *__restrict__ dead,
+                                                         uint32_t *__restrict__ reach)
 {
-    __shared__ int32_t part[kBlk / 64];
-    const int32_t i = blockIdx.x;
-    const int32_t w = i >> 5;
-    const uint32_t bit = 1u << (i & 31);
-    const int32_t *row = genes + (int64_t)i * k;
-    int32_t cnt = 0;
-    for (int32_t j = threadIdx.x; j < k; j += blockDim.x) {
-        const int32_t v = row[j];
-        if (v < 0 || v >= n) {
-            atomicOr(flag, 1);
-            continue;
-        }
-        if (kDistinct) {
-            // rows known to hold distinct ids: no need for the old value
-            atomicOr(dead + (int64_t)v * Wd + w, bit);
-            if (row_ptr[v + 1] > row_ptr[v]) ++cnt;
-        } else {
-            const uint32_t old = atomicOr(dead + (int64_t)v * Wd + w, bit);
-            if (!(old & bit) && row_ptr[v + 1] > row_ptr[v]) ++cnt;
-        }
+    // One LDS buffer serves first as the input tile [B][kTileWords] and then as
+    // the output tile [32 * kTileWords nodes][Wd]; rows are padded by one word
+    // so that column walks spread over the LDS banks.
+    constexpr int kIn = kTileWords + 1;
+    __shared__ uint32_t tile[32 * 32 * kIn];
+    const int32_t Wd = 1 << log_wd;
+    const int32_t B = Wd * 32;
+    const int32_t Wo = Wd + 1;
+    const int32_t j0 = blockIdx.x * kTileWords;
+    // all loads of a thread are issued before any LDS store: they are
+    // independent, so they are in flight together
+    constexpr int kLoads = 32 * 32 * kTileWords / kBlk;
+    uint32_t vals[kLoads];
+#pragma unroll
+    for (int r = 0; r < kLoads; ++r) {
+        const int32_t x = threadIdx.x + r * kBlk;
+        const int32_t b = x / kTileWords, jj = x % kTileWords;
+        vals[r] = (x < B * kTileWords && b < B_real && j0 + jj < W) ? masks[(int64_t)b * W + j0 + jj] : 0xFFFFFFFFu;
     }
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+#pragma unroll
+    for (int r = 0; r < kLoads; ++r) {
+        const int32_t x = threadIdx.x + r * kBlk;
+        if (x < B * kTileWords) tile[(x / kTileWords) * kIn + (x % kTileWords)] = vals[r];
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t s = 0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += part[q];
-        alive_noniso[i] = n_noniso - s;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+    // (node word jj, individual word w) 32 x 32 blocks, one per half-wave pass
+    const int32_t combos = kTileWords * Wd;
+    uint32_t res[kTileWords * 32 / 8];
+#pragma unroll
+    for (int it = 0; it < kTileWords * 32 / 8; ++it) {
+        const int32_t cc = (it * nw + wv) * 2 + half;
+        const bool ok = cc < combos;
+        const int32_t jj = cc >> log_wd, w = cc & (Wd - 1);
+        const uint32_t x = ok ? tile[(w * 32 + l32) * kIn + jj] : 0u;
+        res[it] = transpose32(x, l32);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kTileWords * 32 / 8; ++it) {
+        const int32_t cc = (it * nw + wv) * 2 + half;
+        if (cc < combos) tile[((cc >> log_wd) * 32 + l32) * Wo + (cc & (Wd - 1))] = res[it];
+    }
+    __syncthreads();
+    const int64_t v0 = (int64_t)j0 * 32;
+    const int32_t rows = (int32_t)min((int64_t)32 * kTileWords, (int64_t)n - v0);
+    for (int32_t x = threadIdx.x; x < (rows << log_wd); x += blockDim.x) {
+        dead[v0 * Wd + x] = tile[(x >> log_wd) * Wo + (x & (Wd - 1))];
+        reach[v0 * Wd + x] = 0u;
     }
 }
 
 // Root of each individual: the first surviving node in (degree desc, id)
-// order; its reach bit is set.  No survivor: root = -1.
+// order; its reach bit is set and its union-find entry initialised.  No
+// survivor: root = -1.  Also clears the individual's outputs and counters and
+// the chunk's counters (ctr[2] is the "sweep 0 changed" flag, set).
 __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restrict__ order, int32_t n, int32_t Wd,
-                       int32_t B_real, int32_t *__restrict__ root, uint32_t *__restrict__ reach)
+                       int32_t B_real, int32_t *__restrict__ root, uint32_t *__restrict__ reach,
+                       int32_t *__restrict__ parent, int32_t *__restrict__ other, int32_t *__restrict__ ctr,
+                       unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 64) ctr[i] = i == 2 ? 1 : 0;
     if (i >= B_real) return;
     const int32_t w = i >> 5;
     const uint32_t bit = 1u << (i & 31);
@@ -129,7 +161,13 @@ __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restr
         }
     }
     root[i] = r;
-    if (r >= 0) atomicOr(reach + (int64_t)r * Wd + w, bit);
+    other[i] = 0;
+    fitness[i] = 0ull;
+    if (mcn) mcn[i] = 0;
+    if (r >= 0) {
+        atomicOr(reach + (int64_t)r * Wd + w, bit);
+        parent[(int64_t)i * n + r] = r;
+    }
 }
 
 // Pull for one node by its lane group: OR the neighbours' reach rows (in
@@ -199,9 +237,11 @@ __device__ __forceinline__ int32_t block_reserve(int32_t mine, int32_t *counter,
     return *s_base;
 }
 
-constexpr int kCompactRange = 256;  // input items per compaction block
+constexpr int kCompactRange = 64;   // input items per compaction block
 
-// Nodes still pending after the ordered sweep -> worklist.
+// Nodes still pending after the ordered sweep -> worklist.  A block owns
+// kCompactRange nodes; every thread issues the loads of all its (node, word)
+// entries before testing any of them.
 __global__ __launch_bounds__(kBlk) void k_collect_pending(const int32_t *__restrict__ band_v, int32_t count,
                                                           int32_t Wd, const uint32_t *__restrict__ dead,
                                                           const uint32_t *__restrict__ reach,
@@ -214,14 +254,26 @@ __global__ __launch_bounds__(kBlk) void k_collect_pending(const int32_t *__restr
     const int32_t gpb = blockDim.x / Wd;
     const int32_t r0 = blockIdx.x * kCompactRange, r1 = min(count, r0 + kCompactRange);
     if (threadIdx.x == 0) s_off = 0;
+    // iterations: kCompactRange / gpb = kCompactRange * Wd / kBlk <= kIter
+    constexpr int kIter = kCompactRange * 32 / kBlk;
+    uint32_t pend[kIter];
+    int32_t vv[kIter];
+    const int32_t iters = (kCompactRange + gpb - 1) / gpb;
+#pragma unroll
+    for (int it = 0; it < kIter; ++it) {
+        const int32_t idx = r0 + it * gpb + (int32_t)(threadIdx.x / Wd);
+        vv[it] = (it < iters && idx < r1) ? band_v[idx] : -1;
+    }
+#pragma unroll
+    for (int it = 0; it < kIter; ++it) {
+        const int32_t v = vv[it];
+        pend[it] = v >= 0 ? (~dead[(int64_t)v * Wd + w] & ~reach[(int64_t)v * Wd + w]) : 0u;
+    }
     __syncthreads();
-    for (int32_t idx0 = r0; idx0 < r1; idx0 += gpb) {
-        const int32_t idx = idx0 + (int32_t)(threadIdx.x / Wd);
-        const bool valid = idx < r1;
-        const int32_t v = valid ? band_v[idx] : 0;
-        const uint32_t pend = valid ? (~dead[(int64_t)v * Wd + w] & ~reach[(int64_t)v * Wd + w]) : 0u;
-        const bool any = (__ballot(pend != 0) & gmask) != 0;
-        if (valid && any && w == 0) s_list[atomicAdd(&s_off, 1)] = v;
+#pragma unroll
+    for (int it = 0; it < kIter; ++it) {
+        const bool any = (__ballot(pend[it] != 0) & gmask) != 0;
+        if (vv[it] >= 0 && any && w == 0) s_list[atomicAdd(&s_off, 1)] = vv[it];
     }
     __syncthreads();
     const int32_t found = s_off;
@@ -252,46 +304,86 @@ __global__ void k_pull_worklist(const int32_t *__restrict__ worklist, const int3
         if (__ballot(valid) == 0) continue;
         if (valid) any_gain |= pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach);
     }
-    if (__ballot(any_gain) != 0 && lane == 0) atomicOr(changed + s, 1);
+    // one flag for the whole grid: set it with a plain store, and only if no
+    // other wave has (same-address atomics from every wave would serialise)
+    if (__ballot(any_gain) != 0 && lane == 0 && ld_relaxed(changed + s) == 0)
+        __hip_atomic_store(changed + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// (individual, node) pairs still pending -> pair list; parent[i][v] = v.
+// Pending (individual, node) pairs.  A pending node with no surviving
+// neighbour is a component of its own: it is only counted (per block, into
+// one partial row of single_part, which k_root_final adds to other[i]).
+// The rest go to the pair list for the union-find (parent[i][v] = v).
 // Padding individuals remove every node, so their bits are never pending.
 // Each block owns kCompactRange worklist entries: one pass counts, one global
 // atomic reserves, a second pass writes.
+__device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t gmask,
+                                              const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
+                                              const uint32_t *__restrict__ dead, const uint32_t *__restrict__ reach,
+                                              bool valid, uint32_t &single, uint32_t &multi)
+{
+    const uint32_t pend = valid ? (~dead[(int64_t)v * Wd + w] & ~reach[(int64_t)v * Wd + w]) : 0u;
+    uint32_t nb = 0;
+    if ((__ballot(pend != 0) & gmask) != 0) {
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            nb |= ~dead[(int64_t)colD[e] * Wd + w];
+            if ((__ballot((nb & pend) != pend) & gmask) == 0) break;
+        }
+    }
+    single = pend & ~nb;
+    multi = pend & nb;
+}
+
 __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restrict__ worklist,
                                                         const int32_t *__restrict__ wl_count, int32_t Wd, int32_t n,
+                                                        const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ colD,
                                                         const uint32_t *__restrict__ dead,
                                                         const uint32_t *__restrict__ reach, int64_t *__restrict__ pairs,
-                                                        int32_t *__restrict__ pair_count, int32_t *__restrict__ parent)
+                                                        int32_t *__restrict__ pair_count, int32_t *__restrict__ parent,
+                                                        int32_t *__restrict__ single_part)
 {
     __shared__ int32_t s_tot, s_base, s_off;
+    __shared__ int32_t s_single[1024];
     const int w = threadIdx.x & (Wd - 1);
+    const uint64_t gmask = group_mask(Wd);
     const int32_t gpb = blockDim.x / Wd;
+    const int32_t B = Wd * 32;
     const int32_t count = *wl_count;
+    if ((int64_t)blockIdx.x * kCompactRange >= count) return;  // no range: no partial row (see k_root_final)
+    for (int32_t t = threadIdx.x; t < B; t += blockDim.x) s_single[t] = 0;
+    __syncthreads();
     for (int32_t r0 = blockIdx.x * kCompactRange; r0 < count; r0 += gridDim.x * kCompactRange) {
         const int32_t r1 = min(count, r0 + kCompactRange);
         int32_t mine = 0;
-        for (int32_t idx = r0 + (int32_t)(threadIdx.x / Wd); idx < r1; idx += gpb) {
-            const int32_t v = worklist[idx];
-            mine += __popc(~dead[(int64_t)v * Wd + w] & ~reach[(int64_t)v * Wd + w]);
+        for (int32_t idx0 = r0; idx0 < r1; idx0 += gpb) {
+            const int32_t idx = idx0 + (int32_t)(threadIdx.x / Wd);
+            const bool valid = idx < r1;
+            const int32_t v = valid ? worklist[idx] : 0;
+            uint32_t single, multi;
+            pending_split(v, Wd, w, gmask, row_ptr, colD, dead, reach, valid, single, multi);
+            mine += __popc(multi);
+            for (; single; single &= single - 1) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
         }
         const int32_t base = block_reserve(mine, pair_count, &s_tot, &s_base, &s_off);
-        for (int32_t idx = r0 + (int32_t)(threadIdx.x / Wd); idx < r1; idx += gpb) {
-            const int32_t v = worklist[idx];
-            uint32_t pend = ~dead[(int64_t)v * Wd + w] & ~reach[(int64_t)v * Wd + w];
-            if (!pend) continue;
-            int32_t q = base + atomicAdd(&s_off, __popc(pend));
-            while (pend) {
-                const int t = __ffs(pend) - 1;
-                pend &= pend - 1;
-                const int64_t key = (int64_t)(w * 32 + t) * n + v;
+        for (int32_t idx0 = r0; idx0 < r1; idx0 += gpb) {
+            const int32_t idx = idx0 + (int32_t)(threadIdx.x / Wd);
+            const bool valid = idx < r1;
+            const int32_t v = valid ? worklist[idx] : 0;
+            uint32_t single, multi;
+            pending_split(v, Wd, w, gmask, row_ptr, colD, dead, reach, valid, single, multi);
+            if (!multi) continue;
+            int32_t q = base + atomicAdd(&s_off, __popc(multi));
+            for (; multi; multi &= multi - 1) {
+                const int64_t key = (int64_t)(w * 32 + __ffs(multi) - 1) * n + v;
                 pairs[q++] = key;
                 parent[key] = v;
             }
         }
         __syncthreads();
     }
+    // singleton counts of this block: one partial row, summed by k_root_final
+    for (int32_t t = threadIdx.x; t < B; t += blockDim.x) single_part[(int64_t)blockIdx.x * B + t] = s_single[t];
 }
 
 __device__ __forceinline__ int32_t uf_find(int32_t *parent, int32_t x)
@@ -323,11 +415,6 @@ __device__ __forceinline__ void uf_unite(int32_t *parent, int32_t a, int32_t b)
     }
 }
 
-__global__ void k_root_init(const int32_t *__restrict__ root, int32_t B_real, int32_t n, int32_t *__restrict__ parent)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < B_real && root[i] >= 0) parent[(int64_t)i * n + root[i]] = root[i];
-}
 
 // Union over the surviving edges of each pending pair: a surviving neighbour
 // that is reached joins the root's set; a pending one (each such edge once,
@@ -368,13 +455,6 @@ __global__ void k_pairs_count(const int64_t *__restrict__ pairs, const int32_t *
     }
 }
 
-__global__ void k_root_rep(const int32_t *__restrict__ root, int32_t B_real, int32_t n, int32_t *__restrict__ parent,
-                           int32_t *__restrict__ rep)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B_real) return;
-    rep[i] = root[i] >= 0 ? uf_find(parent + (int64_t)i * n, root[i]) : -1;
-}
 
 __device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit, int32_t *mcn)
 {
@@ -386,7 +466,7 @@ __device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit
 // other than the root's representative): counted, and their sizes summed into
 // other[i].  Their counters are cleared for reuse.
 __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, int32_t n,
-                               const int32_t *__restrict__ parent, const int32_t *__restrict__ rep,
+                               int32_t *__restrict__ parent, const int32_t *__restrict__ root,
                                int32_t *__restrict__ ucount, int32_t *__restrict__ other,
                                unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn)
 {
@@ -395,7 +475,7 @@ __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t 
         const int64_t key = pairs[q];
         const int32_t i = (int32_t)(key / n);
         const int32_t v = (int32_t)(key - (int64_t)i * n);
-        if (parent[key] != v || v == rep[i]) continue;
+        if (parent[key] != v || v == uf_find(parent + (int64_t)i * n, root[i])) continue;
         const int32_t s = ucount[key];
         ucount[key] = 0;
         atomicAdd(other + i, s);
@@ -406,7 +486,26 @@ __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t 
 // The root's component: every surviving non-isolated node not in another
 // component (an isolated root means every non-isolated node is removed and
 // the component is the root alone).
-__global__ void k_root_final(const int32_t *__restrict__ root, const int32_t *__restrict__ rep,
+// Adds the singleton partial rows of the collect blocks that owned a range to
+// other[i]: block (x, y) sums rows [64 y, 64 y + 64) for individuals
+// [64 x, 64 x + 64), loads unrolled, then one atomic per individual.
+constexpr int kSumRows = 64;
+
+__global__ void k_single_sum(const int32_t *__restrict__ single_part, const int32_t *__restrict__ wl_count,
+                             int32_t nparts, int32_t B, int32_t *__restrict__ other)
+{
+    const int32_t i = blockIdx.x * 64 + threadIdx.x;
+    const int32_t used = min(nparts, (*wl_count + kCompactRange - 1) / kCompactRange);
+    const int32_t b0 = blockIdx.y * kSumRows;
+    if (i >= B || b0 >= used) return;
+    const int32_t b1 = min(used, b0 + kSumRows);
+    int32_t acc = 0;
+#pragma unroll 16
+    for (int32_t b = b0; b < b1; ++b) acc += single_part[(int64_t)b * B + i];
+    if (acc) atomicAdd(other + i, acc);
+}
+
+__global__ void k_root_final(const int32_t *__restrict__ root, int32_t *__restrict__ parent,
                              const int32_t *__restrict__ alive_noniso, const int32_t *__restrict__ other,
                              const int32_t *__restrict__ row_ptr, int32_t B_real, int32_t n,
                              int32_t *__restrict__ ucount, unsigned long long *__restrict__ fitness,
@@ -415,18 +514,18 @@ __global__ void k_root_final(const int32_t *__restrict__ root, const int32_t *__
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B_real || root[i] < 0) return;
     const int32_t r = root[i];
-    ucount[(int64_t)i * n + rep[i]] = 0;
+    ucount[(int64_t)i * n + uf_find(parent + (int64_t)i * n, r)] = 0;
     const int64_t s = row_ptr[r + 1] > row_ptr[r] ? (int64_t)alive_noniso[i] - other[i] : 1;
     add_component(s, fitness + i, mcn ? mcn + i : nullptr);
 }
 
 }  // namespace
 
-int eval_genes_bits(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, bool distinct, int64_t *fitness,
-                    int32_t *mcn, int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
+int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
+                    int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
 {
     if (P <= 0) return GAPA_OK;
-    const int32_t n = g->n;
+    const int32_t n = g->n, W = g->words;
     // chunk width: 32 * Wd individuals, Wd a power of two <= 32
     int32_t Wd = 1;
     while (Wd < 32 && Wd * 32 < P) Wd <<= 1;
@@ -442,11 +541,12 @@ int eval_genes_bits(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, b
     const int64_t max_pairs = (int64_t)B * std::max(g->n_noniso, 1);
     if ((rc = ws.pairs.reserve((size_t)max_pairs * 8)) != GAPA_OK) return rc;
     if ((rc = ws.worklist.reserve((size_t)std::max(g->n_noniso, 1) * 4)) != GAPA_OK) return rc;
-    if ((rc = ws.small.reserve((size_t)(4 * B + 64) * 4)) != GAPA_OK) return rc;
+    if ((rc = ws.small.reserve((size_t)(2 * B + 64 + (size_t)kSweepGrid * B) * 4)) != GAPA_OK) return rc;
     int32_t *root = ws.small.as<int32_t>();
-    int32_t *alive = root + B, *other = root + 2 * B, *rep = root + 3 * B;
-    int32_t *ctr = root + 4 * B;  // [0] worklist count, [1] pair count, [2..] changed flags
+    int32_t *other = root + B;
+    int32_t *ctr = root + 2 * B;  // [0] worklist count, [1] pair count, [2..] changed flags
     int32_t *wl_count = ctr, *pair_count = ctr + 1, *changed = ctr + 2;
+    int32_t *single_part = ctr + 64;  // [kSweepGrid][B] singleton counts per collect block
     ws.stats_ctr = ctr;
     ws.stats_B = B;
     uint32_t *dead = ws.dead.as<uint32_t>(), *reach = ws.reach.as<uint32_t>();
@@ -454,34 +554,25 @@ int eval_genes_bits(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, b
     int64_t *pairs = ws.pairs.as<int64_t>();
     int32_t *worklist = ws.worklist.as<int32_t>();
 
-    if ((rc = launch_fill_u32(fitness, 0u, (int64_t)P * 2, s)) != GAPA_OK) return rc;
-    if (mcn && (rc = launch_fill_u32(mcn, 0u, P, s)) != GAPA_OK) return rc;
-
     const int32_t nb = (int32_t)g->band_off.size() - 1;
     const int32_t noniso = g->n_noniso;
-    const int64_t rows = (int64_t)n * Wd;
-    const int row_blocks = (int)std::min<int64_t>((rows + kBlk - 1) / kBlk, 8192);
     for (int32_t c0 = 0; c0 < P; c0 += B) {
         const int32_t Br = std::min(B, P - c0);
         unsigned long long *fit = reinterpret_cast<unsigned long long *>(fitness + c0);
         int32_t *mc = mcn ? mcn + c0 : nullptr;
+        const int32_t *al = alive + c0;
         {
-            TimedScope ts(timer, "k_dead_scatter", s);
-            if ((rc = launch_fill_u32(reach, 0u, rows, s)) != GAPA_OK) return rc;
-            if ((rc = launch_fill_u32(ctr, 0u, 64, s)) != GAPA_OK) return rc;
-            if ((rc = launch_fill_u32(other, 0u, B, s)) != GAPA_OK) return rc;
-            if ((rc = launch_fill_u32(changed, 1u, 1, s)) != GAPA_OK) return rc;
-            hipLaunchKernelGGL(k_dead_init, dim3(row_blocks), dim3(kBlk), 0, s, dead, rows, Wd, Br);
-            if (distinct)
-                hipLaunchKernelGGL(k_dead_scatter<true>, dim3(Br), dim3(kBlk), 0, s, genes + (int64_t)c0 * k, k, n, Wd,
-                                   g->d_row_ptr, noniso, dead, alive, flag);
-            else
-                hipLaunchKernelGGL(k_dead_scatter<false>, dim3(Br), dim3(kBlk), 0, s, genes + (int64_t)c0 * k, k, n,
-                                   Wd, g->d_row_ptr, noniso, dead, alive, flag);
+            TimedScope ts(timer, "k_dead_transpose", s);
+            int32_t log_wd = 0;
+            while ((1 << log_wd) < Wd) ++log_wd;
+            hipLaunchKernelGGL(k_dead_transpose, dim3((W + kTileWords - 1) / kTileWords), dim3(kBlk), 0, s,
+                               masks + (int64_t)c0 * W, W, Br, log_wd, n, dead, reach);
         }
         {
             TimedScope ts(timer, "k_seed", s);
-            hipLaunchKernelGGL(k_seed, dim3((Br + 63) / 64), dim3(64), 0, s, dead, g->d_order, n, Wd, Br, root, reach);
+            const int32_t th = std::max(Br, 64);
+            hipLaunchKernelGGL(k_seed, dim3((th + 63) / 64), dim3(64), 0, s, dead, g->d_order, n, Wd, Br, root, reach,
+                               parent, other, ctr, fit, mc);
         }
         {
             TimedScope ts(timer, "k_pull_band", s);
@@ -507,9 +598,8 @@ int eval_genes_bits(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, b
         }
         {
             TimedScope ts(timer, "k_collect_pairs", s);
-            hipLaunchKernelGGL(k_collect_pairs, dim3(kSweepGrid), dim3(kBlk), 0, s, worklist, wl_count, Wd, n, dead,
-                               reach, pairs, pair_count, parent);
-            hipLaunchKernelGGL(k_root_init, dim3((Br + 63) / 64), dim3(64), 0, s, root, Br, n, parent);
+            hipLaunchKernelGGL(k_collect_pairs, dim3(kSweepGrid), dim3(kBlk), 0, s, worklist, wl_count, Wd, n,
+                               g->d_row_ptr, g->d_colD, dead, reach, pairs, pair_count, parent, single_part);
         }
         {
             TimedScope ts(timer, "k_pairs_hook", s);
@@ -519,13 +609,17 @@ int eval_genes_bits(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, b
         {
             TimedScope ts(timer, "k_pairs_count", s);
             hipLaunchKernelGGL(k_pairs_count, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, n, parent, ucount);
-            hipLaunchKernelGGL(k_root_rep, dim3((Br + 63) / 64), dim3(64), 0, s, root, Br, n, parent, rep);
         }
         {
             TimedScope ts(timer, "k_pairs_reduce", s);
-            hipLaunchKernelGGL(k_pairs_reduce, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, n, parent, rep,
+            hipLaunchKernelGGL(k_pairs_reduce, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, n, parent, root,
                                ucount, other, fit, mc);
-            hipLaunchKernelGGL(k_root_final, dim3((Br + 63) / 64), dim3(64), 0, s, root, rep, alive, other,
+        }
+        {
+            TimedScope ts(timer, "k_root_final", s);
+            hipLaunchKernelGGL(k_single_sum, dim3((B + 63) / 64, (kSweepGrid + kSumRows - 1) / kSumRows), dim3(64), 0, s,
+                               single_part, wl_count, kSweepGrid, B, other);
+            hipLaunchKernelGGL(k_root_final, dim3((Br + 63) / 64), dim3(64), 0, s, root, parent, al, other,
                                g->d_row_ptr, Br, n, ucount, fit, mc);
         }
         GAPA_HIP(hipGetLastError());

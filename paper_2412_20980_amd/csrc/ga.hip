@@ -20,25 +20,27 @@ namespace gapa {
 namespace {
 
 constexpr int kOpBlock = 256;
-constexpr int kRankTile = 256;
+constexpr int kRankTile = 64;
 
 struct OpArgs {
-    const int32_t *pop;   // [P][k] current population, rows ascending
-    const int64_t *fit;   // [P]   ordered by (PC, position)
-    int32_t *children;    // [L][k] out
-    int32_t *flag;        // [1]   attempts exhausted
+    const int32_t *pop;     // [P][k] current population, rows ascending
+    const int64_t *fit;     // [P]   ordered by (PC, position)
+    const uint32_t *noniso; // [W]   bit v set: v has an edge
+    int32_t *children;      // [L][k] out: rows ascending
+    uint32_t *masks;        // [L][W] out: removed-node bit set of each child
+    int32_t *alive;         // [L]   out: surviving non-isolated nodes
+    int32_t *flag;          // [1]   attempts exhausted
     uint64_t seed, t_pc, t_pm;
     uint32_t gen;
-    int32_t P, k, n, W, K2, KW, T;
+    int32_t P, k, n, W, KW, T, n_noniso;
 };
 
-// LDS of one operator block: membership bits over the nodes, the row (padded
-// to a power of two for the sort), first-attempt candidates per slot, and
-// three bit sets over the slots.
+// LDS of one operator block: membership bits over the nodes, the row by slot,
+// a list of slots, and three bit sets over the slots.
 struct OpLds {
     uint32_t *U;          // [W]
-    int32_t *row;         // [K2]
-    int32_t *cand;        // [k]
+    int32_t *row;         // [k]
+    int32_t *list;        // [k]
     uint32_t *from_donor; // [KW]
     uint32_t *dup;        // [KW]
     uint32_t *mut;        // [KW]
@@ -49,8 +51,8 @@ __device__ __forceinline__ OpLds carve(uint32_t *smem, const OpArgs &a)
     OpLds l;
     l.U = smem;
     l.row = reinterpret_cast<int32_t *>(smem + a.W);
-    l.cand = l.row + a.K2;
-    l.from_donor = reinterpret_cast<uint32_t *>(l.cand + a.k);
+    l.list = l.row + a.k;
+    l.from_donor = reinterpret_cast<uint32_t *>(l.list + a.k);
     l.dup = l.from_donor + a.KW;
     l.mut = l.dup + a.KW;
     return l;
@@ -79,38 +81,143 @@ __device__ int32_t first_non_member(const uint32_t *U, uint32_t u, uint32_t t0, 
     return (int32_t)u;
 }
 
-// Ascending bitonic sort of K2 (a power of two) ints in LDS by the whole block.
-__device__ void block_sort(int32_t *a, int32_t K2)
+// Slots whose bit is set in bits[0 .. ceil(k/32)), ascending, into list[];
+// returns how many.  Run by one whole wave.
+__device__ int32_t wave_list_slots(const uint32_t *bits, int32_t k, int32_t *list)
 {
-    for (int32_t size = 2; size <= K2; size <<= 1) {
-        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int32_t i = threadIdx.x; i < (K2 >> 1); i += blockDim.x) {
-                const int32_t lo = 2 * i - (i & (stride - 1));
-                const int32_t hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const int32_t x = a[lo], y = a[hi];
-                if ((x > y) == up) {
-                    a[lo] = y;
-                    a[hi] = x;
+    const int lane = threadIdx.x & 63;
+    int32_t count = 0;
+    for (int32_t j0 = 0; j0 < k; j0 += 64) {
+        const int32_t j = j0 + lane;
+        const bool on = j < k && ((bits[j >> 5] >> (j & 31)) & 1u);
+        const uint64_t mask = __ballot(on);
+        if (on) list[count + __popcll(mask & ((1ull << lane) - 1ull))] = j;
+        count += __popcll(mask);
+    }
+    return count;
+}
+
+// The defining rule, in slot order: slot list[a] (a = 0, 1, ...) takes the
+// first draw (slot, ind, gen, stream | t), t = 0, 1, ..., that is not in the
+// membership set U; U gains it and, with `swap`, loses the slot's previous
+// value.  One wave resolves 64 slots at a time: every lane takes its attempt
+// 0, and lane l's draw is accepted if it is not a member given the lanes
+// before it (not in U unless an earlier lane freed it, and not taken by an
+// earlier lane).  All lanes before the first rejected one are committed at
+// once; the rejected one is resolved alone with further attempts, exactly as
+// the sequential rule would; the next batch starts after it.
+__device__ void wave_draw_in_order(const OpLds &l, const OpArgs &a, const int32_t *list, int32_t count, bool swap,
+                                   uint32_t ind, uint32_t gen, uint32_t stream)
+{
+    const int lane = threadIdx.x & 63;
+    int32_t pos = 0;
+    while (pos < count) {
+        const int32_t nvalid = min(64, count - pos);
+        const bool valid = lane < nvalid;
+        const int32_t j = valid ? (list ? list[pos + lane] : pos + lane) : 0;
+        const uint32_t c = valid ? bounded(draw(a.seed, j, ind, gen, stream, 0).w0, a.n) : 0xFFFFFFFFu;
+        const int32_t old = (valid && swap) ? l.row[j] : -1;
+        const bool in_u = valid && lds_test(l.U, c);
+        bool taken = false, freed = false;
+        // q is uniform across the wave: lane q's values are read with readlane
+        for (int q = 0; q < nvalid; ++q) {
+            const uint32_t cq = (uint32_t)__builtin_amdgcn_readlane((int)c, q);
+            const int32_t oq = __builtin_amdgcn_readlane(old, q);
+            if (q < lane) {
+                taken |= cq == c;
+                freed |= oq == (int32_t)c;
+            }
+        }
+        const bool reject = valid && ((in_u && !freed) || taken);
+        const uint64_t rej = __ballot(reject);
+        const int32_t f = rej ? (int32_t)__ffsll((unsigned long long)rej) - 1 : nvalid;
+        if (swap && lane < f) atomicAnd(&l.U[old >> 5], ~(1u << (old & 31)));
+        if (lane < f) {
+            atomicOr(&l.U[c >> 5], 1u << (c & 31));
+            l.row[j] = (int32_t)c;
+        }
+        if (f < nvalid) {
+            if (lane == f) {
+                const int32_t u = first_non_member(l.U, c, 0, a.seed, j, ind, gen, stream, a.n);
+                if (u < 0) {
+                    atomicOr(a.flag, 1);
+                } else {
+                    if (swap) l.U[old >> 5] &= ~(1u << (old & 31));
+                    lds_set(l.U, u);
+                    l.row[j] = u;
                 }
             }
-            __syncthreads();
+            pos += f + 1;
+        } else {
+            pos += nvalid;
         }
     }
+}
+
+// Exclusive prefix sum over the block (blockDim.x <= 1024, a multiple of 64);
+// also returns the block total.  Every thread must call it.
+__device__ int32_t block_exclusive_scan(int32_t x, int32_t *total)
+{
+    __shared__ int32_t s_wave[16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) s_wave[wv] = incl;
+    __syncthreads();
+    int32_t before = 0, sum = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+        if (q < wv) before += s_wave[q];
+        sum += s_wave[q];
+    }
+    __syncthreads();
+    *total = sum;
+    return before + incl - x;
 }
 
 __device__ void clear_lds(const OpLds &l, const OpArgs &a)
 {
     for (int32_t w = threadIdx.x; w < a.W; w += blockDim.x) l.U[w] = 0u;
     for (int32_t w = threadIdx.x; w < a.KW; w += blockDim.x) l.from_donor[w] = l.dup[w] = l.mut[w] = 0u;
-    for (int32_t j = a.k + threadIdx.x; j < a.K2; j += blockDim.x) l.row[j] = INT_MAX;
 }
 
-__device__ void sort_and_write(const OpLds &l, const OpArgs &a, int32_t idx)
+// The finished individual leaves as its membership bit set (the removed-node
+// mask the fitness kernels consume), its row in ascending order (the set bits
+// enumerated in order: each thread owns a contiguous run of words, a block
+// scan of their popcounts gives its output offset) and its count of
+// surviving non-isolated nodes.
+__device__ void emit(const OpLds &l, const OpArgs &a, int32_t idx)
 {
-    block_sort(l.row, a.K2);
+    __syncthreads();
+    uint32_t *m = a.masks + (int64_t)idx * a.W;
+    int32_t gone = 0;
+    for (int32_t w = threadIdx.x; w < a.W; w += blockDim.x) {
+        const uint32_t x = l.U[w];
+        m[w] = x;
+        gone += __popc(x & a.noniso[w]);
+    }
+    const int32_t per = (a.W + blockDim.x - 1) / blockDim.x;
+    const int32_t w0 = min(a.W, (int32_t)threadIdx.x * per), w1 = min(a.W, w0 + per);
+    int32_t cnt = 0;
+    for (int32_t w = w0; w < w1; ++w) cnt += __popc(l.U[w]);
+    int32_t total = 0, gone_total = 0;
+    (void)block_exclusive_scan(gone, &gone_total);
+    int32_t off = block_exclusive_scan(cnt, &total);
+    // the sorted row is staged in LDS (the slot list is free by now) and
+    // written out coalesced
+    for (int32_t w = w0; w < w1; ++w)
+        for (uint32_t bits = l.U[w]; bits; bits &= bits - 1)
+            if (off < a.k) l.list[off++] = w * 32 + __ffs(bits) - 1;
+    __syncthreads();
     int32_t *dst = a.children + (int64_t)idx * a.k;
-    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) dst[j] = l.row[j];
+    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) dst[j] = l.list[j];
+    if (threadIdx.x == 0) {
+        a.alive[idx] = a.n_noniso - gone_total;
+        if (total != a.k) atomicOr(a.flag, 1);
+    }
 }
 
 // Initial individual i (eq. 2): slot j takes the first INIT draw that is not
@@ -121,23 +228,9 @@ __global__ __launch_bounds__(kOpBlock) void k_init(OpArgs a)
     const OpLds l = carve(smem, a);
     const int32_t i = blockIdx.x;
     clear_lds(l, a);
-    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x)
-        l.cand[j] = (int32_t)bounded(draw(a.seed, j, i, 0, kStreamInit, 0).w0, a.n);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int32_t j = 0; j < a.k; ++j) {
-            const int32_t u = first_non_member(l.U, l.cand[j], 0, a.seed, j, i, 0, kStreamInit, a.n);
-            if (u < 0) {
-                atomicOr(a.flag, 1);
-                l.row[j] = 0;
-                continue;
-            }
-            lds_set(l.U, u);
-            l.row[j] = u;
-        }
-    }
-    __syncthreads();
-    sort_and_write(l, a, i);
+    if (threadIdx.x < 64) wave_draw_in_order(l, a, nullptr, a.k, false, i, 0, kStreamInit);
+    emit(l, a, i);
 }
 
 // Offspring o of generation gen >= 1.
@@ -183,10 +276,7 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs a)
         l.row[j] = c;
         if (take) atomicOr(&l.from_donor[j >> 5], 1u << (j & 31));
         else atomicOr(&l.U[c >> 5], 1u << (c & 31));
-        if ((uint64_t)x.w1 < a.t_pm) {
-            atomicOr(&l.mut[j >> 5], 1u << (j & 31));
-            l.cand[j] = (int32_t)bounded(draw(a.seed, j, o, a.gen, kStreamMutate, 0).w0, a.n);
-        }
+        if ((uint64_t)x.w1 < a.t_pm) atomicOr(&l.mut[j >> 5], 1u << (j & 31));
     }
     __syncthreads();
 
@@ -212,37 +302,14 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs a)
     }
     __syncthreads();
 
-    if (threadIdx.x == 0) {
-        for (int32_t q = 0; q < a.KW; ++q) {
-            for (uint32_t bits = l.dup[q]; bits; bits &= bits - 1) {
-                const int32_t j = q * 32 + __ffs(bits) - 1;
-                const uint32_t u0 = bounded(draw(a.seed, j, o, a.gen, kStreamRepair, 0).w0, a.n);
-                const int32_t u = first_non_member(l.U, u0, 0, a.seed, j, o, a.gen, kStreamRepair, a.n);
-                if (u < 0) {
-                    atomicOr(a.flag, 1);
-                    continue;
-                }
-                lds_set(l.U, u);
-                l.row[j] = u;
-            }
-        }
-        for (int32_t q = 0; q < a.KW; ++q) {
-            for (uint32_t bits = l.mut[q]; bits; bits &= bits - 1) {
-                const int32_t j = q * 32 + __ffs(bits) - 1;
-                const int32_t u = first_non_member(l.U, l.cand[j], 0, a.seed, j, o, a.gen, kStreamMutate, a.n);
-                if (u < 0) {
-                    atomicOr(a.flag, 1);
-                    continue;
-                }
-                const int32_t old = l.row[j];
-                l.U[old >> 5] &= ~(1u << (old & 31));
-                lds_set(l.U, u);
-                l.row[j] = u;
-            }
-        }
+    // repair, then mutation, each in ascending slot order (one wave)
+    if (threadIdx.x < 64) {
+        const int32_t nd = wave_list_slots(l.dup, a.k, l.list);
+        wave_draw_in_order(l, a, l.list, nd, false, o, a.gen, kStreamRepair);
+        const int32_t nm = wave_list_slots(l.mut, a.k, l.list);
+        wave_draw_in_order(l, a, l.list, nm, true, o, a.gen, kStreamMutate);
     }
-    __syncthreads();
-    sort_and_write(l, a, o);
+    emit(l, a, o);
 }
 
 // Elitism (eq. 10-11) as a merge by ranks.  Keys: parents (PC, tag r) for the
@@ -259,6 +326,7 @@ __global__ __launch_bounds__(kRankTile) void k_rank_count(const int64_t *__restr
 {
     __shared__ int64_t tf[kRankTile];
     __shared__ int32_t tt[kRankTile];
+    // blockDim.x == kRankTile
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t q0 = blockIdx.y * kRankTile;
     const int32_t q = q0 + threadIdx.x;
@@ -325,7 +393,10 @@ OpArgs make_args(gapa_ga *ga, const int32_t *pop, const int64_t *fit, uint32_t g
     OpArgs a;
     a.pop = pop;
     a.fit = fit;
+    a.noniso = g->d_noniso;
     a.children = ga->children.as<int32_t>();
+    a.masks = ga->masks.as<uint32_t>();
+    a.alive = ga->alive.as<int32_t>();
     a.flag = ga->flag.as<int32_t>();
     a.seed = ga->params.seed;
     a.t_pc = ga->t_pc;
@@ -335,11 +406,9 @@ OpArgs make_args(gapa_ga *ga, const int32_t *pop, const int64_t *fit, uint32_t g
     a.k = ga->params.k;
     a.n = g->n;
     a.W = g->words;
-    int32_t K2 = 1;
-    while (K2 < a.k) K2 <<= 1;
-    a.K2 = K2;
     a.KW = (a.k + 31) / 32;
     a.T = ga->params.tournament;
+    a.n_noniso = g->n_noniso;
     return a;
 }
 
@@ -375,10 +444,8 @@ int ga_rank_and_gather(gapa_ga *ga, const int64_t *f_par, const int32_t *par_row
 size_t ga_op_lds_bytes(int32_t n, int32_t k)
 {
     const size_t W = ((size_t)n + 31) / 32;
-    size_t K2 = 1;
-    while (K2 < (size_t)k) K2 <<= 1;
     const size_t KW = ((size_t)k + 31) / 32;
-    return 4 * (W + K2 + (size_t)k + 3 * KW);
+    return 4 * (W + 2 * (size_t)k + 3 * KW);
 }
 
 int ga_prepare_kernels(size_t lds)
@@ -415,8 +482,8 @@ int ga_init_population(gapa_ga *ga, hipStream_t s)
     const int32_t P = ga->params.pop;
     int rc = ga_launch_init(ga, s);
     if (rc != GAPA_OK) return rc;
-    rc = eval_genes(ga->graph, ga->children.as<int32_t>(), P, ga->params.k, true, ga->child_fit.as<int64_t>(),
-                    nullptr, ga->flag.as<int32_t>() + 1, ga->ws, &ga->timer, s);
+    rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(), P, ga->child_fit.as<int64_t>(),
+                    nullptr, ga->ws, &ga->timer, s);
     if (rc != GAPA_OK) return rc;
     return ga_rank_and_gather(ga, nullptr, nullptr, 0, ga->child_fit.as<int64_t>(), nullptr, P, s);
 }
@@ -427,8 +494,8 @@ int ga_generation(gapa_ga *ga, hipStream_t s)
     const uint32_t gen = (uint32_t)(ga->generation + 1);
     int rc = ga_launch_offspring(ga, gen, L, s);
     if (rc != GAPA_OK) return rc;
-    rc = eval_genes(ga->graph, ga->children.as<int32_t>(), L, ga->params.k, true, ga->child_fit.as<int64_t>(),
-                    nullptr, ga->flag.as<int32_t>() + 1, ga->ws, &ga->timer, s);
+    rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(), L, ga->child_fit.as<int64_t>(),
+                    nullptr, ga->ws, &ga->timer, s);
     if (rc != GAPA_OK) return rc;
     rc = ga_rank_and_gather(ga, ga->fit[ga->cur].as<int64_t>(), ga->pop[ga->cur].as<int32_t>(), P,
                             ga->child_fit.as<int64_t>(), nullptr, L, s);

@@ -86,6 +86,7 @@ struct FitnessWorkspace {
     int32_t *stats_ctr = nullptr;  // device counters of the last bit-parallel chunk
     int32_t stats_B = 0;
     DevBuf masks;    // uint32 [P][W] removed-node bit sets (eval_population)
+    DevBuf alive;    // int32 [P]    surviving non-isolated nodes (eval_population)
     DevBuf genes;    // int32 [P][k]  staged host genes
     DevBuf fitness;  // int64 [P]
     DevBuf mcn;      // int32 [P]
@@ -105,6 +106,7 @@ struct gapa_graph {
     int32_t *d_order = nullptr; // [n] nodes by (degree desc, id)
     int32_t *d_colD = nullptr;  // [nnz] each neighbour list by (degree desc, id)
     int32_t *d_band_v = nullptr;  // [n_noniso] non-isolated nodes by (BFS level, id)
+    uint32_t *d_noniso = nullptr; // [words] bit v set: v has at least one edge
     std::vector<int32_t> band_off;  // host: band b is d_band_v[band_off[b], band_off[b+1])
     int32_t n_noniso = 0;       // nodes with at least one edge
     int32_t algorithm = 0;      // 0: bit-parallel sweeps, 1: edge-parallel union-find
@@ -115,24 +117,28 @@ struct gapa_graph {
 
 namespace gapa {
 
-// Fitness of P individuals given as gene rows genes[P][k] (device, node ids;
-// a repeated id in a row is one removal).  Writes fitness[P] (int64) and, if
-// mcn != nullptr, mcn[P] (int32); a gene outside [0, n) sets flag[0] and is
-// ignored.  Runs the graph's selected algorithm.
-// `distinct`: every row is known to hold distinct ids (the GA's rows).
-int eval_genes(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, bool distinct, int64_t *fitness,
-               int32_t *mcn, int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
-int eval_genes_bits(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, bool distinct, int64_t *fitness,
-                    int32_t *mcn, int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+// Fitness of P individuals given as removed-node bit sets masks[P][W]
+// (device) with alive[P] = surviving non-isolated nodes of each.  Writes
+// fitness[P] (int64) and, if mcn != nullptr, mcn[P] (int32).  Runs the graph's
+// selected algorithm.
+int eval_masks(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness, int32_t *mcn,
+               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
+                    int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
 int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,
                          FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+// Same from gene rows genes[P][k] (device node ids; a repeated id in a row is
+// one removal); a gene outside [0, n) sets flag[0] and is ignored.
+int eval_genes(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int64_t *fitness, int32_t *mcn,
+               int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
 
 // Fills count 32-bit words at p with value (a kernel, not a memset node).
 int launch_fill_u32(void *p, uint32_t value, int64_t count, hipStream_t s);
 
-// genes[P][k] (device) -> masks[P][W]; out-of-range genes raise flag[0].
-int launch_mask_build(const int32_t *genes, int32_t P, int32_t k, int32_t n, int32_t W, uint32_t *masks,
-                      int32_t *flag, hipStream_t s);
+// genes[P][k] (device) -> masks[P][W] and alive[P]; out-of-range genes
+// raise flag[0].
+int launch_mask_build(const int32_t *genes, int32_t P, int32_t k, int32_t n, int32_t W, const uint32_t *noniso,
+                      int32_t n_noniso, uint32_t *masks, int32_t *alive, int32_t *flag, hipStream_t s);
 
 // ------------------------------------------------------------------- GA -----
 
@@ -172,6 +178,8 @@ struct gapa_ga {
     gapa::DevBuf fit[2];          // int64 [P]
     gapa::DevBuf children;        // int32 [lambda][k]
     gapa::DevBuf child_fit;       // int64 [lambda]
+    gapa::DevBuf masks;           // uint32 [max(P, lambda)][W] removed-node bit sets
+    gapa::DevBuf alive;           // int32 [max(P, lambda)] surviving non-isolated nodes
     gapa::DevBuf src;             // int32 [P] elitism: source tag of each kept row
     gapa::DevBuf rank;            // int32 [P + lambda] elitism: offspring below each key
     gapa::DevBuf flag;            // int32 [4] device error flags
