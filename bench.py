@@ -1,6 +1,7 @@
 """Benchmark: GA generations of critical node detection on one MI355X.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+  python bench.py --copy-calibration      # plain 1 GiB copies, for counter scaling
 
 A step is one whole generation of the method on the device: tournament
 selection, crossover with repair, mutation, batched exact fitness of all
@@ -8,10 +9,23 @@ offspring and elitism.  The default workload is the 200k-node Chung-Lu
 power-law graph (gamma 2.5, mean degree 10), budget k = 2000, population 1024,
 1024 offspring per generation.  Inputs are resident in HBM before timing
 starts.  Prints one JSON line.
+
+Roofline: the batched fitness of one chunk of individuals (up to 1024) is the
+measured unit ("fitness_pass": removed-node bit sets, then the fixed sequence
+of component kernels, then PC).  Its algorithmic bytes are B_eval per
+evaluated individual (CSR row pointers and columns, the removed-node bit set,
+one label written and read per node, the int64 result); its duration is taken
+with HIP events on the launch stream around K passes over the GA's current
+population.
+Measured HBM traffic comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled
+by the same counters on a plain copy (profiles/fitness_traffic.json), and is
+reported only while the kernel sources still match the ones profiled.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
@@ -22,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "population fitness evals/s + HBM GB/s at n=200k; time-to-target PC surrogate vs plain"
 
 
 def algorithmic_bytes_per_eval(n: int, nnz: int) -> int:
@@ -31,20 +46,26 @@ def algorithmic_bytes_per_eval(n: int, nnz: int) -> int:
     return 4 * (n + 1) + 4 * nnz + 4 * math.ceil(n / 32) + 8 * n + 8
 
 
-def kernel_unit_bytes(name: str, n: int, nnz: int) -> int | None:
-    """Algorithmic bytes per individual of each fitness kernel."""
-    W = math.ceil(n / 32)
-    table = {
-        # edge-parallel union-find: COO rows + columns, mask bits of both
-        # endpoints (one bit set per individual), parent array read and written
-        "cc_hook": 8 * nnz + 4 * W + 8 * n,
-        "cc_count": 4 * W + 4 * n + 4 * n,
-        "cc_init": 4 * n,
-        "cc_reduce": 4 * n,
-    }
-    if name.startswith("k_"):
-        return algorithmic_bytes_per_eval(n, nnz)
-    return table.get(name)
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2412_20980_amd", "csrc", "*"))):
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per fitness pass from the committed counter summary, or None
+    when it is missing or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "fitness_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("workload") != workload or t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t
 
 
 def cpu_baseline(w, budget_s: float = 12.0):
@@ -63,8 +84,20 @@ def cpu_baseline(w, budget_s: float = 12.0):
         evals += w.offspring or w.pop
     dt = time.perf_counter() - t0
     return {"value": evals / dt, "unit": "fitness evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle GA on the same graph: generation 0 + {gens} generations "
-                      f"({evals} BFS fitness evaluations, operators included), {dt:.1f} s wall"}
+            "sample": f"oracle GA (C, OpenMP over individuals) on the same graph: generation 0 + {gens} "
+                      f"generations, {evals} BFS fitness evaluations with operators and elitism, {dt:.1f} s wall"}
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28  # 2^28 float32 = 1 GiB
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 4 * n, "copies": 3}), flush=True)
 
 
 def main():
@@ -75,6 +108,7 @@ def main():
     ap.add_argument("--workload", default="cl200k_k2000_p1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build evaluates one GPU's share of the population "
@@ -82,10 +116,14 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2412_20980_amd import gapa, inputs
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    from paper_2412_20980_amd import gapa, inputs
+
     w = inputs.workload(args.workload)
     g = w.graph
     lam = w.offspring or w.pop
@@ -104,25 +142,40 @@ def main():
     dt = time.perf_counter() - t0
     _, best_f, gen_count = ga.best()
 
-    # kernel durations: HIP events recorded by the library around each
-    # launch, on the stream the kernels run on, over a second pass of K steps
-    ga.set_timing(True)
+    # operator-kernel and elitism durations: HIP events the library records
+    # around those single kernels on the launch stream
+    ga.set_timing(1)
     ga.step(args.steps, stream=stream)
     torch.cuda.synchronize()
-    times = ga.kernel_times()
-    ga.set_timing(False)
-    fit_kernels = {k: v for k, v in times.items() if kernel_unit_bytes(k, g.n, g.nnz) is not None}
-    dom = max(fit_kernels.items(), key=lambda kv: kv[1][1])
-    name, (launches, total_ms) = dom
-    avg_ms = total_ms / launches
-    evaluated = lam * args.steps
-    per_launch_inds = evaluated / launches
-    unit = kernel_unit_bytes(name, g.n, g.nnz)
-    achieved = unit * per_launch_inds / (avg_ms * 1e-3) / 1e9
+    passes = ga.kernel_times()
+    ga.set_timing(0)
+    stats = ga.fitness_stats()
+
+    # batched-fitness pass: HIP events on the launch stream around K passes
+    # over the GA's current population (1024 evolved individuals, device
+    # resident); one pass = removed-node bit sets + components + PC
+    pop_now, _ = ga.population()
+    genes = torch.from_numpy(pop_now).to("cuda")
+    fit = torch.empty(genes.shape[0], dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        gapa.gapa_eval_population(graph.handle, genes, fitness=fit, flags=gapa.GAPA_TRUST_INPUT, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        gapa.gapa_eval_population(graph.handle, genes, fitness=fit, flags=gapa.GAPA_TRUST_INPUT, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    avg_ms = ev0.elapsed_time(ev1) / args.steps
+    f_launches = args.steps
+    per_launch = genes.shape[0]
+    unit_bytes = algorithmic_bytes_per_eval(g.n, g.nnz)
+    achieved = unit_bytes * per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(w.name)
 
     evals_per_s = lam * args.steps / dt
     out = {
-        "metric": "population fitness evals/s + HBM GB/s at n=200k; time-to-target PC surrogate vs plain",
+        "metric": METRIC,
         "value": evals_per_s,
         "unit": "fitness evals/s",
         "n_gpus": 1,
@@ -137,13 +190,15 @@ def main():
         "config": {"workload": w.name, "graph": g.name, "n": g.n, "m": g.m, "k": w.k, "pop": w.pop,
                    "offspring": lam, "pc": w.pc, "pm": w.pm, "tournament": w.tournament,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_ms": avg_ms, "launches": launches,
-                     "algorithmic_bytes_per_individual": unit, "individuals_per_launch": per_launch_inds},
-        "effective_eval_GBs": evals_per_s * algorithmic_bytes_per_eval(g.n, g.nnz) / 1e9,
-        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(times.items())},
-        "fitness_stats": ga.fitness_stats(),
+        "roofline": {"bound": "hbm", "kernel": "fitness_pass", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["bytes_per_pass"] if traffic else None,
+                     "traffic_GBs": traffic["bytes_per_pass"] / (avg_ms * 1e-3) / 1e9 if traffic else None,
+                     "avg_launch_ms": avg_ms, "launches": f_launches,
+                     "algorithmic_bytes_per_unit": unit_bytes, "units_per_launch": per_launch},
+        "operator_ms_per_step": {k: v[1] / args.steps for k, v in sorted(passes.items()) if k != "fitness_pass"},
+        "fitness_stats": stats,
+        "kernel_source_sha256": kernel_source_hash(),
         "best_pc": best_f,
         "generation": gen_count,
     }

@@ -154,11 +154,15 @@ GAPA_API int gapa_ga_destroy(gapa_ga *ga);
  * Diagnostics
  * ------------------------------------------------------------------------- */
 
-/* Kernel timing: while enabled on a handle, the library brackets the launches
- * of each kernel with HIP events on the launch stream.  gapa_kernel_times
- * fills up to `cap` entries with the kernel name, launch count and summed
- * milliseconds (it waits for outstanding work) and returns the number of
- * entries through *count.  Names stay valid until the handle is destroyed. */
+/* Kernel timing: `enable` 1 brackets whole passes with HIP events on their
+ * launch stream ("fitness_pass": the batched fitness of one chunk of up to
+ * 1024 individuals; "ga_offspring", "ga_init": the operator kernel;
+ * "elitism"); 2 also brackets every kernel launch inside them (the extra
+ * events add gaps, so pass totals are exact only at 1); 0 disables.
+ * gapa_*_kernel_times fills up to `cap` entries with the scope name, count
+ * and summed milliseconds (it waits for outstanding work) and returns the
+ * number of entries through *count.  Names stay valid until the handle is
+ * destroyed. */
 typedef struct gapa_kernel_time {
     const char *name;
     int64_t launches;

@@ -79,17 +79,21 @@ void KernelTimer::begin(const char *name, hipStream_t s)
     p.name = name;
     p.a = take();
     p.b = take();
-    if (!p.a || !p.b) return;
+    if (!p.a || !p.b) {
+        open_.push_back(SIZE_MAX);
+        return;
+    }
     (void)hipEventRecord(p.a, s);
     pending_.push_back(p);
-    open_ = &pending_.back();
+    open_.push_back(pending_.size() - 1);
 }
 
 void KernelTimer::end(hipStream_t s)
 {
-    if (!open_) return;
-    (void)hipEventRecord(open_->b, s);
-    open_ = nullptr;
+    if (open_.empty()) return;
+    const size_t i = open_.back();
+    open_.pop_back();
+    if (i != SIZE_MAX) (void)hipEventRecord(pending_[i].b, s);
 }
 
 int KernelTimer::collect(gapa_kernel_time *out, int cap, int *count)
@@ -120,6 +124,7 @@ int KernelTimer::collect(gapa_kernel_time *out, int cap, int *count)
     if (count) *count = (int)totals_.size();
     return GAPA_OK;
 }
+
 
 KernelTimer::~KernelTimer()
 {
@@ -520,7 +525,8 @@ int gapa_ga_fitness_stats(gapa_ga *ga, int64_t out[4])
 int gapa_graph_set_timing(gapa_graph *g, int32_t enable)
 {
     if (!g) return GAPA_E_INVALID_ARG;
-    g->timer.enabled = enable != 0;
+    if (enable < 0 || enable > 2) return GAPA_E_INVALID_ARG;
+    g->timer.level = enable;
     return GAPA_OK;
 }
 
@@ -712,7 +718,8 @@ int gapa_ga_destroy(gapa_ga *ga)
 int gapa_ga_set_timing(gapa_ga *ga, int32_t enable)
 {
     if (!ga) return GAPA_E_INVALID_ARG;
-    ga->timer.enabled = enable != 0;
+    if (enable < 0 || enable > 2) return GAPA_E_INVALID_ARG;
+    ga->timer.level = enable;
     return GAPA_OK;
 }
 

@@ -289,6 +289,7 @@ int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_
     int32_t *count = ws.count.as<int32_t>();
     for (int32_t c0 = 0; c0 < P; c0 += B) {
         const int32_t nb = std::min(B, P - c0);
+        TimedScope pass(timer, "fitness_pass", s, 1);
         const uint32_t *m = masks + (int64_t)c0 * W;
         const dim3 gv((n + kBlock - 1) / kBlock, nb);
         {

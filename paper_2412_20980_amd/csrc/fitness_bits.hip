@@ -561,6 +561,7 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         unsigned long long *fit = reinterpret_cast<unsigned long long *>(fitness + c0);
         int32_t *mc = mcn ? mcn + c0 : nullptr;
         const int32_t *al = alive + c0;
+        TimedScope pass(timer, "fitness_pass", s, 1);
         {
             TimedScope ts(timer, "k_dead_transpose", s);
             int32_t log_wd = 0;

@@ -423,6 +423,7 @@ int ga_rank_and_gather(gapa_ga *ga, const int64_t *f_par, const int32_t *par_row
     int32_t *pos = ga->rank.as<int32_t>();
     int rc;
     if ((rc = launch_fill_u32(pos, 0u, total, s)) != GAPA_OK) return rc;
+    TimedScope pass(&ga->timer, "elitism", s, 1);
     {
         TimedScope ts(&ga->timer, "elitism_rank", s);
         const dim3 grid((total + kRankTile - 1) / kRankTile, (npool + kRankTile - 1) / kRankTile);
@@ -462,7 +463,7 @@ int ga_prepare_kernels(size_t lds)
 int ga_launch_init(gapa_ga *ga, hipStream_t s)
 {
     OpArgs a = make_args(ga, nullptr, nullptr, 0);
-    TimedScope ts(&ga->timer, "ga_init", s);
+    TimedScope ts(&ga->timer, "ga_init", s, 1);
     hipLaunchKernelGGL(k_init, dim3(ga->params.pop), dim3(kOpBlock), ga->op_lds_bytes, s, a);
     GAPA_HIP(hipGetLastError());
     return GAPA_OK;
@@ -471,7 +472,7 @@ int ga_launch_init(gapa_ga *ga, hipStream_t s)
 int ga_launch_offspring(gapa_ga *ga, uint32_t gen, int32_t count, hipStream_t s)
 {
     OpArgs a = make_args(ga, ga->pop[ga->cur].as<int32_t>(), ga->fit[ga->cur].as<int64_t>(), gen);
-    TimedScope ts(&ga->timer, "ga_offspring", s);
+    TimedScope ts(&ga->timer, "ga_offspring", s, 1);
     hipLaunchKernelGGL(k_offspring, dim3(count), dim3(kOpBlock), ga->op_lds_bytes, s, a);
     GAPA_HIP(hipGetLastError());
     return GAPA_OK;

@@ -35,11 +35,14 @@ struct DevBuf {
 
 // ---------------------------------------------------------------- timing ----
 
-// While enabled, each named kernel launch is bracketed by a pair of HIP
-// events recorded on its stream; totals are folded in on collect().
+// While enabled, named scopes are bracketed by a pair of HIP events recorded
+// on their stream; totals are folded in on collect().  Level 1 times whole
+// passes (the batched fitness of a chunk, the operator kernel, elitism);
+// level 2 also times every kernel launch inside them (the extra events add
+// gaps between kernels, so pass totals are only exact at level 1).
 class KernelTimer {
 public:
-    bool enabled = false;
+    int level = 0;
     void begin(const char *name, hipStream_t s);
     void end(hipStream_t s);
     int collect(gapa_kernel_time *out, int cap, int *count);
@@ -54,20 +57,22 @@ private:
     std::vector<hipEvent_t> free_;
     std::map<std::string, std::pair<int64_t, double>> totals_;
     std::vector<std::string> names_;  // stable storage for returned names
+    std::vector<size_t> open_;        // indices into pending_ of open scopes
     hipEvent_t take();
-    Pending *open_ = nullptr;
 };
 
 struct TimedScope {
     KernelTimer *t;
     hipStream_t s;
-    TimedScope(KernelTimer *timer, const char *name, hipStream_t stream) : t(timer), s(stream)
+    bool on;
+    TimedScope(KernelTimer *timer, const char *name, hipStream_t stream, int level = 2)
+        : t(timer), s(stream), on(timer && timer->level >= level)
     {
-        if (t && t->enabled) t->begin(name, s);
+        if (on) t->begin(name, s);
     }
     ~TimedScope()
     {
-        if (t && t->enabled) t->end(s);
+        if (on) t->end(s);
     }
 };
 
