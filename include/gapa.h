@@ -51,6 +51,7 @@ extern "C" {
 
 typedef struct gapa_graph gapa_graph;
 typedef struct gapa_ga gapa_ga;
+typedef struct gapa_batch gapa_batch;
 
 typedef enum gapa_status {
     GAPA_OK = 0,
@@ -69,9 +70,14 @@ enum {
                                    is asynchronous on `stream`                  */
     GAPA_TRUST_INPUT = 1u << 1, /* skip host-side validation                    */
     GAPA_WANT_MCN = 1u << 2,    /* also compute the largest component size      */
-    GAPA_UNIONFIND = 1u << 3    /* gapa_graph_create: evaluate with edge-parallel
+    GAPA_UNIONFIND = 1u << 3,   /* gapa_graph_create: evaluate with edge-parallel
                                    union-find instead of bit-parallel sweeps
                                    (same results, slower; a cross-check)        */
+    GAPA_GRAPH_REPLAY = 1u << 4 /* gapa_params.flags: record one generation's
+                                   launches as a HIP graph once and replay it
+                                   (same results; fewer launch gaps).  Kernel
+                                   timing, when enabled, runs generations
+                                   eagerly instead.                             */
 };
 
 /* ---------------------------------------------------------------------------
@@ -124,7 +130,7 @@ typedef struct gapa_params {
     uint64_t seed;
     double pc;
     double pm;
-    uint32_t flags;   /* reserved, 0 */
+    uint32_t flags;   /* 0 or GAPA_GRAPH_REPLAY */
     int32_t reserved; /* 0 */
 } gapa_params;
 
@@ -151,6 +157,35 @@ GAPA_API int gapa_get_population(gapa_ga *ga, int32_t *genes_out, int64_t *fitne
 GAPA_API int gapa_ga_destroy(gapa_ga *ga);
 
 /* ---------------------------------------------------------------------------
+ * Batch of independent GAs (Section III-D runs several GA processes side by
+ * side in its M and MNM modes; here many independent instances share each
+ * device pass instead).
+ *
+ * count      1 <= count <= 4096 instances
+ * graphs     [count] graph handles on the current device (the same handle may
+ *            appear several times); each must outlive the batch.  Their
+ *            disjoint union is built once on the device (sum of n <= 2^30).
+ * params     [count] parameters as for gapa_ga_create, per instance
+ *            (max(pop, offspring) <= 1024 for each; flags 0 or
+ *            GAPA_GRAPH_REPLAY, taken from params[0] for the whole batch)
+ *
+ * Instance b evolves exactly as gapa_ga_create(graphs[b], &params[b]) and
+ * its generation steps would alone: same draws, same populations, same
+ * fitness, generation by generation.  One generation of the batch is one
+ * operator launch over all instances' offspring, one bit-parallel fitness
+ * pass over all of them and one elitism launch.  Enqueue semantics and
+ * host-pointer waits are those of the single-GA calls; idx selects an
+ * instance (0 <= idx < count).
+ * ------------------------------------------------------------------------- */
+GAPA_API int gapa_batch_create(int32_t count, gapa_graph *const *graphs, const gapa_params *params, void *stream,
+                               gapa_batch **out);
+GAPA_API int gapa_batch_step(gapa_batch *b, int32_t n_generations, void *stream);
+GAPA_API int gapa_batch_best(gapa_batch *b, int32_t idx, int32_t *genes_out, int64_t *fitness_out,
+                             int64_t *generation_out);
+GAPA_API int gapa_batch_get_population(gapa_batch *b, int32_t idx, int32_t *genes_out, int64_t *fitness_out);
+GAPA_API int gapa_batch_destroy(gapa_batch *b);
+
+/* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */
 
@@ -173,6 +208,8 @@ GAPA_API int gapa_graph_set_timing(gapa_graph *g, int32_t enable);
 GAPA_API int gapa_graph_kernel_times(gapa_graph *g, gapa_kernel_time *out, int32_t cap, int32_t *count);
 GAPA_API int gapa_ga_set_timing(gapa_ga *ga, int32_t enable);
 GAPA_API int gapa_ga_kernel_times(gapa_ga *ga, gapa_kernel_time *out, int32_t cap, int32_t *count);
+GAPA_API int gapa_batch_set_timing(gapa_batch *b, int32_t enable);
+GAPA_API int gapa_batch_kernel_times(gapa_batch *b, gapa_kernel_time *out, int32_t cap, int32_t *count);
 
 /* Counters of the last chunk the bit-parallel fitness evaluated on a handle
  * (waits for outstanding work): out[0] individuals per chunk, out[1] nodes

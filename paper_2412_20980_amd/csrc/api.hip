@@ -216,61 +216,69 @@ int validate_graph(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci)
     return GAPA_OK;
 }
 
-// Host-side orderings used by the bit-parallel fitness kernels:
-//   order  - all nodes by (degree desc, id): root candidates;
+// Host-side orderings used by the bit-parallel fitness kernels.  The graph
+// may be a disjoint union of instances (node ranges [voff[b], voff[b+1]));
+// everything is computed per instance and only the bands are shared.
+//   order  - the nodes of each instance by (degree desc, id): root candidates;
 //   colD   - each neighbour list by (degree desc, id): hubs are read first;
-//   bands  - non-isolated nodes by breadth-first level from the highest-degree
-//            nodes of G (multi-source), levels merged into at most kMaxBands
-//            bands; nodes no source reaches form the last band.
+//   bands  - non-isolated nodes by breadth-first level from the kSources
+//            highest-degree nodes of their instance (multi-source); level l
+//            of every instance falls in the same band; levels are merged
+//            into at most kMaxBands bands; nodes no source reaches take the
+//            level after their instance's last one.
 constexpr int kSources = 64;
 constexpr int kMaxBands = 24;
 constexpr int kMinBand = 4096;
 
-void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, std::vector<int32_t> &order,
-                     std::vector<int32_t> &colD, std::vector<int32_t> &band_v, std::vector<int32_t> &band_off)
+void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, const std::vector<int32_t> &voff,
+                     std::vector<int32_t> &order, std::vector<int32_t> &colD, std::vector<int32_t> &band_v,
+                     std::vector<int32_t> &band_off)
 {
     std::vector<int32_t> deg(n);
     for (int32_t v = 0; v < n; ++v) deg[v] = rp[v + 1] - rp[v];
     auto by_degree = [&](int32_t a, int32_t b) { return deg[a] != deg[b] ? deg[a] > deg[b] : a < b; };
     order.resize(n);
     for (int32_t v = 0; v < n; ++v) order[v] = v;
-    std::sort(order.begin(), order.end(), by_degree);
     colD.assign(ci, ci + rp[n]);
     for (int32_t v = 0; v < n; ++v) std::sort(colD.begin() + rp[v], colD.begin() + rp[v + 1], by_degree);
 
     std::vector<int32_t> level(n, -1);
     std::vector<int32_t> frontier, next;
-    for (int32_t p = 0; p < n && (int)frontier.size() < kSources; ++p) {
-        const int32_t v = order[p];
-        if (deg[v] == 0) break;
-        level[v] = 0;
-        frontier.push_back(v);
+    int32_t nlev = 1;
+    for (size_t b = 0; b + 1 < voff.size(); ++b) {
+        const int32_t v0 = voff[b], v1 = voff[b + 1];
+        std::sort(order.begin() + v0, order.begin() + v1, by_degree);
+        frontier.clear();
+        for (int32_t p = v0; p < v1 && (int)frontier.size() < kSources; ++p) {
+            const int32_t v = order[p];
+            if (deg[v] == 0) break;
+            level[v] = 0;
+            frontier.push_back(v);
+        }
+        int32_t lv = 0;
+        while (!frontier.empty()) {
+            next.clear();
+            for (int32_t v : frontier)
+                for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+                    if (level[ci[e]] < 0) {
+                        level[ci[e]] = lv + 1;
+                        next.push_back(ci[e]);
+                    }
+            frontier.swap(next);
+            ++lv;
+        }
+        for (int32_t v = v0; v < v1; ++v)  // non-isolated nodes no source reaches
+            if (deg[v] > 0 && level[v] < 0) level[v] = lv;
+        nlev = std::max(nlev, lv + 1);
     }
-    int32_t lv = 0;
-    while (!frontier.empty()) {
-        next.clear();
-        for (int32_t v : frontier)
-            for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
-                if (level[ci[e]] < 0) {
-                    level[ci[e]] = lv + 1;
-                    next.push_back(ci[e]);
-                }
-        frontier.swap(next);
-        ++lv;
-    }
-    const int32_t unreached = lv;  // non-isolated nodes no source reaches
     band_v.clear();
     for (int32_t v = 0; v < n; ++v)
-        if (deg[v] > 0) {
-            if (level[v] < 0) level[v] = unreached;
-            band_v.push_back(v);
-        }
+        if (deg[v] > 0) band_v.push_back(v);
     std::sort(band_v.begin(), band_v.end(),
               [&](int32_t a, int32_t b) { return level[a] != level[b] ? level[a] < level[b] : a < b; });
     // Bands: level 0 (the sources) alone; later levels joined until a band
     // holds kMinBand nodes, so that sparse tail levels do not each cost a
     // launch; at most kMaxBands bands.
-    const int32_t nlev = unreached + 1;
     std::vector<int32_t> lev_count(nlev, 0);
     for (int32_t v : band_v) ++lev_count[level[v]];
     band_off.assign(1, 0);
@@ -333,39 +341,11 @@ int fail_handle(bool *failed, int rc)
     return rc;
 }
 
-}  // namespace
-}  // namespace gapa
-
-using namespace gapa;
-
-extern "C" {
-
-const char *gapa_last_error(void)
+// Device copy of a validated CSR and its orderings; voff splits the nodes
+// into instances (a single graph: {0, n}).
+int graph_build(int dev, int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                const std::vector<int32_t> &voff, int algorithm, gapa_graph **out)
 {
-    return g_last_error.c_str();
-}
-
-const char *gapa_version(void)
-{
-    return "gapa-mi355x 0.1 (gfx950)";
-}
-
-int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, uint32_t flags,
-                      gapa_graph **out)
-{
-    g_last_error.clear();
-    if (!out) {
-        set_error("out is NULL");
-        return GAPA_E_INVALID_ARG;
-    }
-    *out = nullptr;
-    if (n < 1 || n > (1 << 30) || nnz < 0 || nnz >= (1ll << 31) || !row_ptr || (nnz > 0 && !col_idx)) {
-        set_error("invalid graph sizes or pointers (n=%d, nnz=%lld)", n, (long long)nnz);
-        return GAPA_E_INVALID_ARG;
-    }
-    if (!(flags & GAPA_TRUST_INPUT)) API_TRY(validate_graph(n, nnz, row_ptr, col_idx));
-    int dev = 0;
-    API_TRY(check_device(&dev));
     gapa_graph *g = new (std::nothrow) gapa_graph();
     if (!g) {
         set_error("host allocation failed");
@@ -375,12 +355,12 @@ int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int3
     g->n = n;
     g->nnz = nnz;
     g->words = (n + 31) / 32;
-    g->algorithm = (flags & GAPA_UNIONFIND) ? 1 : 0;
+    g->algorithm = algorithm;
     std::vector<int32_t> src((size_t)std::max<int64_t>(nnz, 1));
     for (int32_t v = 0; v < n; ++v)
         for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) src[e] = v;
     std::vector<int32_t> order, colD, band_v;
-    graph_orderings(n, row_ptr, col_idx, order, colD, band_v, g->band_off);
+    graph_orderings(n, row_ptr, col_idx, voff, order, colD, band_v, g->band_off);
     g->n_noniso = (int32_t)band_v.size();
     std::vector<uint32_t> noniso_bits((size_t)g->words, 0u);
     for (int32_t v = 0; v < n; ++v)
@@ -420,6 +400,43 @@ int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int3
         return fail(hip_fail(e, "hipMemcpy"));
     *out = g;
     return GAPA_OK;
+}
+
+}  // namespace
+}  // namespace gapa
+
+using namespace gapa;
+
+extern "C" {
+
+const char *gapa_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+const char *gapa_version(void)
+{
+    return "gapa-mi355x 0.1 (gfx950)";
+}
+
+int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, uint32_t flags,
+                      gapa_graph **out)
+{
+    g_last_error.clear();
+    if (!out) {
+        set_error("out is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (n < 1 || n > (1 << 30) || nnz < 0 || nnz >= (1ll << 31) || !row_ptr || (nnz > 0 && !col_idx)) {
+        set_error("invalid graph sizes or pointers (n=%d, nnz=%lld)", n, (long long)nnz);
+        return GAPA_E_INVALID_ARG;
+    }
+    if (!(flags & GAPA_TRUST_INPUT)) API_TRY(validate_graph(n, nnz, row_ptr, col_idx));
+    int dev = 0;
+    API_TRY(check_device(&dev));
+    return graph_build(dev, n, nnz, row_ptr, col_idx, std::vector<int32_t>{0, n}, (flags & GAPA_UNIONFIND) ? 1 : 0,
+                       out);
 }
 
 int gapa_graph_destroy(gapa_graph *g)
@@ -542,104 +559,187 @@ int gapa_graph_kernel_times(gapa_graph *g, gapa_kernel_time *out, int32_t cap, i
 
 // ---------------------------------------------------------------------- GA ---
 
-int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **out)
+}  // extern "C"
+
+namespace gapa {
+namespace {
+
+bool params_ok(const gapa_params *p, int32_t n)
 {
-    g_last_error.clear();
-    if (!out || !g || !p) {
-        set_error("NULL argument");
-        return GAPA_E_INVALID_ARG;
+    return p->k >= 1 && p->k <= n / 2 && p->pop >= 1 && p->tournament >= 1 && p->tournament <= 64 &&
+           p->offspring >= 0 && p->pc >= 0.0 && p->pc <= 1.0 && p->pm >= 0.0 && p->pm <= 1.0 &&
+           (p->flags & ~(uint32_t)GAPA_GRAPH_REPLAY) == 0 && p->reserved == 0;
+}
+
+// Fills the instance table and sizes every buffer of a GA over `count`
+// instances; instance b has parameters p[b], n[b] nodes, n_noniso[b]
+// non-isolated nodes; slot_stride > 0 puts instance b's slots at
+// b * slot_stride (a batch), 0 keeps them contiguous from 0 (one GA).
+int ga_allocate(gapa_ga *ga, int32_t count, const gapa_params *p, const int32_t *n, const int32_t *n_noniso,
+                int32_t slot_stride)
+{
+    ga->count = count;
+    ga->params = p[0];
+    ga->lambda = p[0].offspring > 0 ? p[0].offspring : p[0].pop;
+    ga->t_pc = bernoulli_threshold(p[0].pc);
+    ga->t_pm = bernoulli_threshold(p[0].pm);
+    ga->use_graph = (p[0].flags & GAPA_GRAPH_REPLAY) != 0;
+    ga->hinst.assign(count, GaInst{});
+    int64_t pop_el = 0, child_el = 0, mask_w = 0;
+    int32_t fit_n = 0, rank_n = 0, noniso_w = 0, slots = 0;
+    size_t lds = 0;
+    for (int32_t b = 0; b < count; ++b) {
+        GaInst &I = ga->hinst[b];
+        const int32_t L = p[b].offspring > 0 ? p[b].offspring : p[b].pop;
+        const int32_t R = std::max(p[b].pop, L);
+        I.P = p[b].pop;
+        I.L = L;
+        I.k = p[b].k;
+        I.n = n[b];
+        I.W = (n[b] + 31) / 32;
+        I.KW = (p[b].k + 31) / 32;
+        I.T = p[b].tournament;
+        I.n_noniso = n_noniso[b];
+        I.seed = p[b].seed;
+        I.t_pc = bernoulli_threshold(p[b].pc);
+        I.t_pm = bernoulli_threshold(p[b].pm);
+        I.pop_off = pop_el;
+        I.child_off = child_el;
+        I.mask_off = mask_w;
+        I.fit_off = fit_n;
+        I.slot_off = slot_stride > 0 ? b * slot_stride : slots;
+        I.rank_off = rank_n;
+        I.noniso_off = noniso_w;
+        pop_el += (int64_t)I.P * I.k;
+        child_el += (int64_t)R * I.k;
+        mask_w += (int64_t)R * I.W;
+        fit_n += I.P;
+        rank_n += I.P + L;
+        noniso_w += I.W;
+        slots += R;
+        ga->max_pop = std::max(ga->max_pop, I.P);
+        ga->max_lambda = std::max(ga->max_lambda, L);
+        ga->max_pop_lambda = std::max(ga->max_pop_lambda, I.P + L);
+        lds = std::max(lds, ga_op_lds_bytes(n[b], p[b].k));
     }
-    *out = nullptr;
-    if (g->failed) {
-        set_error("graph handle is in a failed state");
-        return GAPA_E_STATE;
-    }
-    const int32_t lambda = p->offspring > 0 ? p->offspring : p->pop;
-    if (p->k < 1 || p->k > g->n / 2 || p->pop < 1 || p->tournament < 1 || p->tournament > 64 || p->offspring < 0 ||
-        !(p->pc >= 0.0 && p->pc <= 1.0) || !(p->pm >= 0.0 && p->pm <= 1.0) || p->flags != 0) {
-        set_error("invalid GA parameters (need 1 <= k <= n/2, pop >= 1, 1 <= T <= 64, pc, pm in [0, 1])");
-        return GAPA_E_INVALID_ARG;
-    }
-    if ((int64_t)p->pop * p->k >= (1ll << 31) || (int64_t)lambda * p->k >= (1ll << 31)) {
+    if (slot_stride > 0) slots = count * slot_stride;
+    ga->rank_total = rank_n;
+    ga->op_lds_bytes = lds;
+    if (pop_el >= (1ll << 31) || child_el >= (1ll << 31)) {
         set_error("population too large");
         return GAPA_E_INVALID_ARG;
     }
-    const size_t lds = ga_op_lds_bytes(g->n, p->k);
     if (lds > 160 * 1024) {
-        set_error("n = %d and k = %d need %zu bytes of LDS for the operator kernels (limit 160 KiB)", g->n, p->k, lds);
+        set_error("n and k need %zu bytes of LDS for the operator kernels (limit 160 KiB)", lds);
         return GAPA_E_INVALID_ARG;
     }
-    DeviceGuard dg(g->device);
-    gapa_ga *ga = new (std::nothrow) gapa_ga();
-    if (!ga) {
-        set_error("host allocation failed");
-        return GAPA_E_OOM;
-    }
-    ga->graph = g;
-    ga->params = *p;
-    ga->lambda = lambda;
-    ga->t_pc = bernoulli_threshold(p->pc);
-    ga->t_pm = bernoulli_threshold(p->pm);
-    ga->op_lds_bytes = lds;
-    const int32_t P = p->pop, k = p->k;
-    const int32_t rows = std::max(P, lambda);
     int rc = GAPA_OK;
-    auto fail = [&](int code) {
-        gapa_ga_destroy(ga);
-        return code;
-    };
     for (int i = 0; i < 2 && rc == GAPA_OK; ++i) {
-        rc = ga->pop[i].reserve((size_t)P * k * 4);
-        if (rc == GAPA_OK) rc = ga->fit[i].reserve((size_t)P * 8);
+        rc = ga->pop[i].reserve((size_t)pop_el * 4);
+        if (rc == GAPA_OK) rc = ga->fit[i].reserve((size_t)fit_n * 8);
     }
-    if (rc == GAPA_OK) rc = ga->children.reserve((size_t)rows * k * 4);
-    if (rc == GAPA_OK) rc = ga->child_fit.reserve((size_t)rows * 8);
-    if (rc == GAPA_OK) rc = ga->masks.reserve((size_t)rows * g->words * 4);
-    if (rc == GAPA_OK) rc = ga->alive.reserve((size_t)rows * 4);
-    if (rc == GAPA_OK) rc = ga->src.reserve((size_t)P * 4);
-    if (rc == GAPA_OK) rc = ga->rank.reserve((size_t)(P + lambda) * 4);
+    if (rc == GAPA_OK) rc = ga->children.reserve((size_t)child_el * 4);
+    if (rc == GAPA_OK) rc = ga->child_fit.reserve((size_t)slots * 8);
+    if (rc == GAPA_OK) rc = ga->masks.reserve((size_t)mask_w * 4);
+    if (rc == GAPA_OK) rc = ga->alive.reserve((size_t)slots * 4);
+    if (rc == GAPA_OK) rc = ga->src.reserve((size_t)fit_n * 4);
+    if (rc == GAPA_OK) rc = ga->rank.reserve((size_t)rank_n * 4);
     if (rc == GAPA_OK) rc = ga->flag.reserve(16);
-    if (rc != GAPA_OK) return fail(rc);
-    if ((rc = ga_prepare_kernels(lds)) != GAPA_OK) return fail(rc);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((rc = launch_fill_u32(ga->flag.ptr, 0u, 4, s)) != GAPA_OK) return fail(rc);
-    if ((rc = ga_init_population(ga, s)) != GAPA_OK) return fail(rc);
-    ga->last_stream = s;
-    *out = ga;
+    if (rc == GAPA_OK) rc = ga->gen_ctr.reserve(16);
+    if (rc == GAPA_OK) rc = ga->inst.reserve(sizeof(GaInst) * count);
+    if (rc != GAPA_OK) return rc;
+    GAPA_HIP(hipMemcpy(ga->inst.ptr, ga->hinst.data(), sizeof(GaInst) * count, hipMemcpyHostToDevice));
+    return ga_prepare_kernels(lds);
+}
+
+template <class T> int upload(DevBuf &buf, const std::vector<T> &v)
+{
+    int rc = buf.reserve(std::max<size_t>(v.size(), 1) * sizeof(T));
+    if (rc != GAPA_OK) return rc;
+    if (!v.empty()) GAPA_HIP(hipMemcpy(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return GAPA_OK;
 }
 
-int gapa_generation_step(gapa_ga *ga, int32_t n_generations, void *stream)
+void release_graphs(gapa_ga *ga)
 {
-    g_last_error.clear();
-    if (!ga || n_generations < 0) {
-        set_error("invalid arguments");
-        return GAPA_E_INVALID_ARG;
+    for (int c = 0; c < 2; ++c) {
+        if (ga->execs[c]) (void)hipGraphExecDestroy(ga->execs[c]);
+        if (ga->graphs[c]) (void)hipGraphDestroy(ga->graphs[c]);
+        ga->execs[c] = nullptr;
+        ga->graphs[c] = nullptr;
     }
+}
+
+// Records one generation starting from population buffer c as a HIP graph.
+// The host-side counters are restored afterwards: nothing ran.
+int capture_generation(gapa_ga *ga, int c)
+{
+    if (!ga->cap_stream) GAPA_HIP(hipStreamCreateWithFlags(&ga->cap_stream, hipStreamNonBlocking));
+    const int64_t gen = ga->generation;
+    GAPA_HIP(hipStreamBeginCapture(ga->cap_stream, hipStreamCaptureModeRelaxed));
+    const int rc = ga_generation(ga, ga->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(ga->cap_stream, &graph);
+    ga->cur = c;
+    ga->generation = gen;
+    if (rc != GAPA_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc != GAPA_OK ? rc : hip_fail(e, "hipStreamEndCapture");
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e2, "hipGraphInstantiate");
+    }
+    ga->graphs[c] = graph;
+    ga->execs[c] = exec;
+    return GAPA_OK;
+}
+
+int ga_run(gapa_ga *ga, int32_t n_generations, hipStream_t s)
+{
+    for (int32_t i = 0; i < n_generations; ++i) {
+        if (!(ga->use_graph && ga->warm && ga->timer.level == 0)) {
+            const int rc = ga_generation(ga, s);
+            if (rc != GAPA_OK) return rc;
+            ga->warm = true;  // every buffer of a generation has its final size
+            continue;
+        }
+        const int c = ga->cur;
+        if (!ga->execs[c]) {
+            const int rc = capture_generation(ga, c);
+            if (rc != GAPA_OK) return rc;
+        }
+        GAPA_HIP(hipGraphLaunch(ga->execs[c], s));
+        ga->cur = 1 - c;
+        ga->generation += 1;
+    }
+    return GAPA_OK;
+}
+
+int ga_step_checked(gapa_ga *ga, int32_t n_generations, hipStream_t s)
+{
     if (ga->failed) {
         set_error("GA handle is in a failed state");
         return GAPA_E_STATE;
     }
-    if (ga->generation + n_generations >= (1ll << 32) - 1) {
-        set_error("generation counter would exceed 2^32 - 1");
+    if (n_generations < 0 || ga->generation + n_generations >= (1ll << 32) - 1) {
+        set_error("invalid generation count (the counter must stay below 2^32 - 1)");
         return GAPA_E_INVALID_ARG;
     }
     DeviceGuard dg(ga->graph->device);
-    hipStream_t s = static_cast<hipStream_t>(stream);
     if (s != ga->last_stream) {
         // order this call after work enqueued earlier on another stream
         hipError_t e = hipStreamSynchronize(ga->last_stream);
         if (e != hipSuccess) return fail_handle(&ga->failed, hip_fail(e, "hipStreamSynchronize"));
         ga->last_stream = s;
     }
-    for (int32_t i = 0; i < n_generations; ++i) {
-        int rc = ga_generation(ga, s);
-        if (rc != GAPA_OK) return fail_handle(&ga->failed, rc);
-    }
-    return GAPA_OK;
+    const int rc = ga_run(ga, n_generations, s);
+    return rc == GAPA_OK ? rc : fail_handle(&ga->failed, rc);
 }
 
-static int ga_sync_check(gapa_ga *ga)
+int ga_sync_check(gapa_ga *ga)
 {
     int32_t hflag[4] = {0, 0, 0, 0};
     hipError_t e = hipMemcpyAsync(hflag, ga->flag.ptr, 16, hipMemcpyDeviceToHost, ga->last_stream);
@@ -653,6 +753,104 @@ static int ga_sync_check(gapa_ga *ga)
     return GAPA_OK;
 }
 
+// Rows of instance b (all P, or only the best with best_only) to the host.
+int ga_copy_out(gapa_ga *ga, int32_t b, bool best_only, int32_t *genes_out, int64_t *fitness_out)
+{
+    if (ga->failed) {
+        set_error("GA handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    DeviceGuard dg(ga->graph->device);
+    const GaInst &I = ga->hinst[b];
+    const int32_t rows = best_only ? 1 : I.P;
+    hipStream_t s = ga->last_stream;
+    hipError_t e = hipSuccess;
+    if (genes_out)
+        e = hipMemcpyAsync(genes_out, ga->pop[ga->cur].as<int32_t>() + I.pop_off, (size_t)rows * I.k * 4,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && fitness_out)
+        e = hipMemcpyAsync(fitness_out, ga->fit[ga->cur].as<int64_t>() + I.fit_off, (size_t)rows * 8,
+                           hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail_handle(&ga->failed, hip_fail(e, "population copy"));
+    return ga_sync_check(ga);
+}
+
+void ga_release(gapa_ga *ga)
+{
+    (void)hipDeviceSynchronize();
+    release_graphs(ga);
+    if (ga->cap_stream) (void)hipStreamDestroy(ga->cap_stream);
+    ga->cap_stream = nullptr;
+    for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit, &ga->masks,
+                    &ga->alive, &ga->src, &ga->rank, &ga->flag, &ga->gen_ctr, &ga->inst, &ga->noniso_buf,
+                    &ga->tab_voff, &ga->tab_live_init, &ga->tab_live_gen, &ga->tab_moff, &ga->tab_node_inst,
+                    &ga->tab_tiles})
+        b->release();
+    release_workspace(ga->ws);
+}
+
+int ga_collect_times(gapa_ga *ga, gapa_kernel_time *out, int32_t cap, int32_t *count)
+{
+    DeviceGuard dg(ga->graph->device);
+    int c = 0;
+    int rc = ga->timer.collect(out, cap, &c);
+    if (count) *count = c;
+    return rc;
+}
+
+}  // namespace
+}  // namespace gapa
+
+extern "C" {
+
+int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **out)
+{
+    g_last_error.clear();
+    if (!out || !g || !p) {
+        set_error("NULL argument");
+        return GAPA_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (g->failed) {
+        set_error("graph handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    if (!params_ok(p, g->n)) {
+        set_error("invalid GA parameters (need 1 <= k <= n/2, pop >= 1, 1 <= T <= 64, pc, pm in [0, 1], "
+                  "flags 0 or GAPA_GRAPH_REPLAY)");
+        return GAPA_E_INVALID_ARG;
+    }
+    DeviceGuard dg(g->device);
+    gapa_ga *ga = new (std::nothrow) gapa_ga();
+    if (!ga) {
+        set_error("host allocation failed");
+        return GAPA_E_OOM;
+    }
+    ga->graph = g;
+    auto fail = [&](int code) {
+        gapa_ga_destroy(ga);
+        return code;
+    };
+    int rc = ga_allocate(ga, 1, p, &g->n, &g->n_noniso, 0);
+    if (rc != GAPA_OK) return fail(rc);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = launch_fill_u32(ga->flag.ptr, 0u, 4, s)) != GAPA_OK) return fail(rc);
+    if ((rc = ga_init_population(ga, s)) != GAPA_OK) return fail(rc);
+    ga->last_stream = s;
+    *out = ga;
+    return GAPA_OK;
+}
+
+int gapa_generation_step(gapa_ga *ga, int32_t n_generations, void *stream)
+{
+    g_last_error.clear();
+    if (!ga) {
+        set_error("GA is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    return ga_step_checked(ga, n_generations, static_cast<hipStream_t>(stream));
+}
+
 int gapa_best(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out, int64_t *generation_out)
 {
     g_last_error.clear();
@@ -660,22 +858,9 @@ int gapa_best(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out, int64_t *ge
         set_error("GA is NULL");
         return GAPA_E_INVALID_ARG;
     }
-    if (ga->failed) {
-        set_error("GA handle is in a failed state");
-        return GAPA_E_STATE;
-    }
-    DeviceGuard dg(ga->graph->device);
-    hipStream_t s = ga->last_stream;
-    hipError_t e = hipSuccess;
-    if (genes_out)
-        e = hipMemcpyAsync(genes_out, ga->pop[ga->cur].ptr, (size_t)ga->params.k * 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && fitness_out)
-        e = hipMemcpyAsync(fitness_out, ga->fit[ga->cur].ptr, 8, hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return fail_handle(&ga->failed, hip_fail(e, "gapa_best copy"));
-    int rc = ga_sync_check(ga);
-    if (rc != GAPA_OK) return rc;
-    if (generation_out) *generation_out = ga->generation;
-    return GAPA_OK;
+    const int rc = ga_copy_out(ga, 0, true, genes_out, fitness_out);
+    if (rc == GAPA_OK && generation_out) *generation_out = ga->generation;
+    return rc;
 }
 
 int gapa_get_population(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out)
@@ -685,19 +870,7 @@ int gapa_get_population(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out)
         set_error("GA is NULL");
         return GAPA_E_INVALID_ARG;
     }
-    if (ga->failed) {
-        set_error("GA handle is in a failed state");
-        return GAPA_E_STATE;
-    }
-    DeviceGuard dg(ga->graph->device);
-    hipStream_t s = ga->last_stream;
-    const int32_t P = ga->params.pop, k = ga->params.k;
-    hipError_t e = hipSuccess;
-    if (genes_out) e = hipMemcpyAsync(genes_out, ga->pop[ga->cur].ptr, (size_t)P * k * 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && fitness_out)
-        e = hipMemcpyAsync(fitness_out, ga->fit[ga->cur].ptr, (size_t)P * 8, hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return fail_handle(&ga->failed, hip_fail(e, "gapa_get_population copy"));
-    return ga_sync_check(ga);
+    return ga_copy_out(ga, 0, false, genes_out, fitness_out);
 }
 
 int gapa_ga_destroy(gapa_ga *ga)
@@ -705,11 +878,7 @@ int gapa_ga_destroy(gapa_ga *ga)
     if (!ga) return GAPA_OK;
     {
         DeviceGuard dg(ga->graph->device);
-        (void)hipDeviceSynchronize();
-        for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit,
-                        &ga->masks, &ga->alive, &ga->src, &ga->rank, &ga->flag})
-            b->release();
-        release_workspace(ga->ws);
+        ga_release(ga);
     }
     delete ga;
     return GAPA_OK;
@@ -726,11 +895,204 @@ int gapa_ga_set_timing(gapa_ga *ga, int32_t enable)
 int gapa_ga_kernel_times(gapa_ga *ga, gapa_kernel_time *out, int32_t cap, int32_t *count)
 {
     if (!ga) return GAPA_E_INVALID_ARG;
-    DeviceGuard dg(ga->graph->device);
-    int c = 0;
-    int rc = ga->timer.collect(out, cap, &c);
-    if (count) *count = c;
+    return ga_collect_times(ga, out, cap, count);
+}
+
+// ------------------------------------------------------------------- batch ---
+
+int gapa_batch_create(int32_t count, gapa_graph *const *graphs, const gapa_params *params, void *stream,
+                      gapa_batch **out)
+{
+    g_last_error.clear();
+    if (!out || !graphs || !params) {
+        set_error("NULL argument");
+        return GAPA_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (count < 1 || count > 4096) {
+        set_error("count = %d, need 1 <= count <= 4096", count);
+        return GAPA_E_INVALID_ARG;
+    }
+    std::vector<int32_t> ns(count), nonisos(count), voff(count + 1, 0);
+    std::vector<int64_t> eoff(count + 1, 0);
+    int32_t slots_needed = 1;
+    for (int32_t b = 0; b < count; ++b) {
+        const gapa_graph *g = graphs[b];
+        if (!g || g->failed || g->device != graphs[0]->device) {
+            set_error("graph %d is NULL, failed or on another device", b);
+            return GAPA_E_INVALID_ARG;
+        }
+        const gapa_params &p = params[b];
+        if (!params_ok(&p, g->n) || p.flags != params[0].flags) {
+            set_error("invalid GA parameters of instance %d", b);
+            return GAPA_E_INVALID_ARG;
+        }
+        const int32_t L = p.offspring > 0 ? p.offspring : p.pop;
+        if (std::max(p.pop, L) > 1024) {
+            set_error("instance %d: max(pop, offspring) = %d exceeds 1024", b, std::max(p.pop, L));
+            return GAPA_E_INVALID_ARG;
+        }
+        slots_needed = std::max(slots_needed, std::max(p.pop, L));
+        ns[b] = g->n;
+        nonisos[b] = g->n_noniso;
+        if ((int64_t)voff[b] + g->n > (1 << 30) || eoff[b] + g->nnz >= (1ll << 31)) {
+            set_error("the union of the instance graphs is too large");
+            return GAPA_E_INVALID_ARG;
+        }
+        voff[b + 1] = voff[b] + g->n;
+        eoff[b + 1] = eoff[b] + g->nnz;
+    }
+    int32_t bseg = 32;
+    while (bseg < slots_needed) bseg <<= 1;
+    DeviceGuard dg(graphs[0]->device);
+    gapa_batch *bt = new (std::nothrow) gapa_batch();
+    if (!bt || !(bt->ga = new (std::nothrow) gapa_ga())) {
+        delete bt;
+        set_error("host allocation failed");
+        return GAPA_E_OOM;
+    }
+    auto fail = [&](int code) {
+        gapa_batch_destroy(bt);
+        return code;
+    };
+    gapa_ga *ga = bt->ga;
+    hipError_t e;
+    int rc;
+    if (count == 1) {
+        ga->graph = graphs[0];
+    } else {
+        // the disjoint union of the instance graphs: instance b's node v is
+        // node voff[b] + v
+        const int32_t N = voff[count];
+        const int64_t M = eoff[count];
+        std::vector<int32_t> rp((size_t)N + 1), ci((size_t)std::max<int64_t>(M, 1)), tmp_rp;
+        for (int32_t b = 0; b < count; ++b) {
+            const gapa_graph *g = graphs[b];
+            tmp_rp.resize((size_t)g->n + 1);
+            if ((e = hipMemcpy(tmp_rp.data(), g->d_row_ptr, ((size_t)g->n + 1) * 4, hipMemcpyDeviceToHost)) !=
+                hipSuccess)
+                return fail(hip_fail(e, "hipMemcpy"));
+            for (int32_t v = 0; v < g->n; ++v) rp[voff[b] + v] = (int32_t)(eoff[b] + tmp_rp[v]);
+            if (g->nnz > 0) {
+                int32_t *dst = ci.data() + eoff[b];
+                if ((e = hipMemcpy(dst, g->d_col, (size_t)g->nnz * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+                    return fail(hip_fail(e, "hipMemcpy"));
+                for (int64_t q = 0; q < g->nnz; ++q) dst[q] += voff[b];
+            }
+        }
+        rp[N] = (int32_t)M;
+        if ((rc = graph_build(graphs[0]->device, N, M, rp.data(), ci.data(), voff, 0, &bt->super)) != GAPA_OK)
+            return fail(rc);
+        ga->graph = bt->super;
+    }
+    if ((rc = ga_allocate(ga, count, params, ns.data(), nonisos.data(), count > 1 ? bseg : 0)) != GAPA_OK)
+        return fail(rc);
+    if (count > 1) {
+        // per-instance non-isolated bit sets, in local ids
+        int64_t words = 0;
+        for (int32_t b = 0; b < count; ++b) words += (ns[b] + 31) / 32;
+        if ((rc = ga->noniso_buf.reserve((size_t)words * 4)) != GAPA_OK) return fail(rc);
+        ga->noniso = ga->noniso_buf.as<uint32_t>();
+        for (int32_t b = 0; b < count; ++b)
+            if ((e = hipMemcpy(ga->noniso + ga->hinst[b].noniso_off, graphs[b]->d_noniso,
+                               (size_t)((ns[b] + 31) / 32) * 4, hipMemcpyDeviceToDevice)) != hipSuccess)
+                return fail(hip_fail(e, "hipMemcpy"));
+        // instance tables of the fitness pass
+        std::vector<int32_t> live_init(count), live_gen(count), node_inst((size_t)voff[count]), tiles;
+        std::vector<int64_t> moff(count);
+        for (int32_t b = 0; b < count; ++b) {
+            const GaInst &I = ga->hinst[b];
+            live_init[b] = I.P;
+            live_gen[b] = I.L;
+            moff[b] = I.mask_off;
+            for (int32_t v = voff[b]; v < voff[b + 1]; ++v) node_inst[v] = b;
+            for (int32_t j0 = 0; j0 < I.W; j0 += 8) {
+                tiles.push_back(b);
+                tiles.push_back(j0);
+            }
+        }
+        if ((rc = upload(ga->tab_voff, voff)) != GAPA_OK || (rc = upload(ga->tab_live_init, live_init)) != GAPA_OK ||
+            (rc = upload(ga->tab_live_gen, live_gen)) != GAPA_OK || (rc = upload(ga->tab_moff, moff)) != GAPA_OK ||
+            (rc = upload(ga->tab_node_inst, node_inst)) != GAPA_OK || (rc = upload(ga->tab_tiles, tiles)) != GAPA_OK)
+            return fail(rc);
+        InstTable t;
+        t.count = count;
+        t.bseg = bseg;
+        t.voff = ga->tab_voff.as<int32_t>();
+        t.moff = ga->tab_moff.as<int64_t>();
+        t.node_inst = ga->tab_node_inst.as<int32_t>();
+        t.tiles = ga->tab_tiles.as<int32_t>();
+        t.ntiles = (int32_t)(tiles.size() / 2);
+        ga->tab_init = t;
+        ga->tab_init.live = ga->tab_live_init.as<int32_t>();
+        ga->tab_gen = t;
+        ga->tab_gen.live = ga->tab_live_gen.as<int32_t>();
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = launch_fill_u32(ga->flag.ptr, 0u, 4, s)) != GAPA_OK) return fail(rc);
+    if ((rc = ga_init_population(ga, s)) != GAPA_OK) return fail(rc);
+    ga->last_stream = s;
+    *out = bt;
+    return GAPA_OK;
+}
+
+int gapa_batch_step(gapa_batch *b, int32_t n_generations, void *stream)
+{
+    g_last_error.clear();
+    if (!b) {
+        set_error("batch is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    return ga_step_checked(b->ga, n_generations, static_cast<hipStream_t>(stream));
+}
+
+int gapa_batch_best(gapa_batch *b, int32_t idx, int32_t *genes_out, int64_t *fitness_out, int64_t *generation_out)
+{
+    g_last_error.clear();
+    if (!b || idx < 0 || idx >= b->ga->count) {
+        set_error("batch is NULL or index out of range");
+        return GAPA_E_INVALID_ARG;
+    }
+    const int rc = ga_copy_out(b->ga, idx, true, genes_out, fitness_out);
+    if (rc == GAPA_OK && generation_out) *generation_out = b->ga->generation;
     return rc;
+}
+
+int gapa_batch_get_population(gapa_batch *b, int32_t idx, int32_t *genes_out, int64_t *fitness_out)
+{
+    g_last_error.clear();
+    if (!b || idx < 0 || idx >= b->ga->count) {
+        set_error("batch is NULL or index out of range");
+        return GAPA_E_INVALID_ARG;
+    }
+    return ga_copy_out(b->ga, idx, false, genes_out, fitness_out);
+}
+
+int gapa_batch_set_timing(gapa_batch *b, int32_t enable)
+{
+    if (!b) return GAPA_E_INVALID_ARG;
+    return gapa_ga_set_timing(b->ga, enable);
+}
+
+int gapa_batch_kernel_times(gapa_batch *b, gapa_kernel_time *out, int32_t cap, int32_t *count)
+{
+    if (!b) return GAPA_E_INVALID_ARG;
+    return ga_collect_times(b->ga, out, cap, count);
+}
+
+int gapa_batch_destroy(gapa_batch *b)
+{
+    if (!b) return GAPA_OK;
+    if (b->ga) {
+        if (b->ga->graph) {
+            DeviceGuard dg(b->ga->graph->device);
+            ga_release(b->ga);
+        }
+        delete b->ga;
+    }
+    gapa_graph_destroy(b->super);
+    delete b;
+    return GAPA_OK;
 }
 
 }  // extern "C"

@@ -245,8 +245,12 @@ int launch_mask_build(const int32_t *genes, int32_t P, int32_t k, int32_t n, int
 }
 
 int eval_masks(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness, int32_t *mcn,
-               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
+               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it)
 {
+    if (it && it->count > 1) {
+        if (g->algorithm != 0) return GAPA_E_INVALID_ARG;
+        return eval_masks_bits(g, masks, alive, P, fitness, mcn, ws, timer, s, it);
+    }
     if (P <= 0) return GAPA_OK;
     if (g->algorithm == 1) return eval_masks_unionfind(g, masks, P, fitness, mcn, ws, timer, s);
     return eval_masks_bits(g, masks, alive, P, fitness, mcn, ws, timer, s);

@@ -55,6 +55,54 @@ __device__ __forceinline__ uint64_t group_mask(int Wd)
     return ones << (lane & ~(Wd - 1));
 }
 
+}  // namespace
+
+// Instances evaluated in one bit-parallel pass.  Instance b owns the nodes
+// [voff(b), voff(b+1)) of the graph (a disjoint union when several graphs are
+// batched) and the individual slots [b*bseg, (b+1)*bseg): bit i of a node's
+// row belongs to slot b*bseg + i.  live(b) slots are in use; the others are
+// padding that removes every node.  Genes and masks of an instance use its
+// local node ids (node - voff(b)); the removed-node bit set of its slot i
+// starts at word moff(b) + i * W_b of the mask array.  The leftover
+// union-find of slot (b, i) works on local ids in the block of n_b entries
+// at bseg * voff(b) + i * n_b.  With count == 1 the arrays are unused and the
+// one instance is all n1 nodes with live1 slots in use.
+struct Insts {
+    int32_t count;
+    int32_t bseg;              // slots per instance, 32 * Wd
+    int32_t n1, live1;         // count == 1
+    const int32_t *voff;       // [count + 1]
+    const int32_t *live;       // [count]
+    const int64_t *moff;       // [count]
+    const int32_t *node_inst;  // [n]: instance of each node
+    const int32_t *tiles;      // (instance, first node word) of each transpose tile
+};
+
+namespace {
+
+__device__ __forceinline__ int32_t i_voff(const Insts &I, int32_t b)
+{
+    return I.count == 1 ? (b ? I.n1 : 0) : I.voff[b];
+}
+
+__device__ __forceinline__ int32_t i_live(const Insts &I, int32_t b)
+{
+    return I.count == 1 ? I.live1 : I.live[b];
+}
+
+__device__ __forceinline__ int32_t inst_of_node(const Insts &I, int32_t v)
+{
+    return I.count == 1 ? 0 : I.node_inst[v];
+}
+
+// Start of the union-find block of slot gi.
+__device__ __forceinline__ int64_t uf_block(const Insts &I, int32_t gi)
+{
+    const int32_t b = gi / I.bseg;
+    const int32_t v0 = i_voff(I, b);
+    return (int64_t)I.bseg * v0 + (int64_t)(gi - b * I.bseg) * (i_voff(I, b + 1) - v0);
+}
+
 // dead rows from per-individual removed-node bit sets masks[B_real][W]: a
 // block takes kTileWords node words (32 * kTileWords nodes) of every
 // individual of the chunk, stages them in LDS (rows of kTileWords words are
@@ -81,10 +129,19 @@ __device__ __forceinline__ uint32_t transpose32(uint32_t x, int l32)
     return x;
 }
 
-__global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restrict__ masks, int32_t W, int32_t B_real,
-                                                         int32_t log_wd, int32_t n, uint32_t *__restrict__ dead,
+__global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restrict__ masks, const Insts I,
+                                                         int32_t log_wd, uint32_t *__restrict__ dead,
                                                          uint32_t *__restrict__ reach)
 {
+    // this tile: instance b, its node words [j0, j0 + kTileWords)
+    const int32_t b = I.count == 1 ? 0 : I.tiles[2 * blockIdx.x];
+    const int32_t j0 = I.count == 1 ? blockIdx.x * kTileWords : I.tiles[2 * blockIdx.x + 1];
+    const int32_t vb = i_voff(I, b);
+    const int32_t nb = i_voff(I, b + 1) - vb;
+    const int32_t W = (nb + 31) / 32;
+    const int32_t B_real = i_live(I, b);
+    const int64_t mstride = W;
+    if (I.count > 1) masks += I.moff[b];
     // One LDS buffer serves first as the input tile [B][kTileWords] and then as
     // the output tile [32 * kTileWords nodes][Wd]; rows are padded by one word
     // so that column walks spread over the LDS banks.
@@ -93,7 +150,6 @@ __global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restr
     const int32_t Wd = 1 << log_wd;
     const int32_t B = Wd * 32;
     const int32_t Wo = Wd + 1;
-    const int32_t j0 = blockIdx.x * kTileWords;
     // all loads of a thread are issued before any LDS store: they are
     // independent, so they are in flight together
     constexpr int kLoads = 32 * 32 * kTileWords / kBlk;
@@ -101,8 +157,9 @@ __global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restr
 #pragma unroll
     for (int r = 0; r < kLoads; ++r) {
         const int32_t x = threadIdx.x + r * kBlk;
-        const int32_t b = x / kTileWords, jj = x % kTileWords;
-        vals[r] = (x < B * kTileWords && b < B_real && j0 + jj < W) ? masks[(int64_t)b * W + j0 + jj] : 0xFFFFFFFFu;
+        const int32_t ind = x / kTileWords, jj = x % kTileWords;
+        vals[r] = (x < B * kTileWords && ind < B_real && j0 + jj < W) ? masks[(int64_t)ind * mstride + j0 + jj]
+                                                                     : 0xFFFFFFFFu;
     }
 #pragma unroll
     for (int r = 0; r < kLoads; ++r) {
@@ -130,43 +187,48 @@ __global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restr
         if (cc < combos) tile[((cc >> log_wd) * 32 + l32) * Wo + (cc & (Wd - 1))] = res[it];
     }
     __syncthreads();
-    const int64_t v0 = (int64_t)j0 * 32;
-    const int32_t rows = (int32_t)min((int64_t)32 * kTileWords, (int64_t)n - v0);
+    const int64_t v0 = vb + (int64_t)j0 * 32;
+    const int32_t rows = min(32 * kTileWords, nb - j0 * 32);
     for (int32_t x = threadIdx.x; x < (rows << log_wd); x += blockDim.x) {
         dead[v0 * Wd + x] = tile[(x >> log_wd) * Wo + (x & (Wd - 1))];
         reach[v0 * Wd + x] = 0u;
     }
 }
 
-// Root of each individual: the first surviving node in (degree desc, id)
-// order; its reach bit is set and its union-find entry initialised.  No
-// survivor: root = -1.  Also clears the individual's outputs and counters and
-// the chunk's counters (ctr[2] is the "sweep 0 changed" flag, set).
-__global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restrict__ order, int32_t n, int32_t Wd,
-                       int32_t B_real, int32_t *__restrict__ root, uint32_t *__restrict__ reach,
-                       int32_t *__restrict__ parent, int32_t *__restrict__ other, int32_t *__restrict__ ctr,
-                       unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn)
+// Root of each slot: the first surviving node of its instance in (degree
+// desc, id) order; its reach bit is set and its union-find entry initialised.
+// No survivor (or a padding slot): root = -1.  Also clears the slot's outputs
+// and counters and the pass's counters (ctr[2] is the "sweep 0 changed"
+// flag, set).
+__global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restrict__ order, const Insts I, int32_t Wd,
+                       int32_t *__restrict__ root, uint32_t *__restrict__ reach, int32_t *__restrict__ parent,
+                       int32_t *__restrict__ other, int32_t *__restrict__ ctr, unsigned long long *__restrict__ fitness,
+                       int32_t *__restrict__ mcn)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 64) ctr[i] = i == 2 ? 1 : 0;
-    if (i >= B_real) return;
+    const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi < 64) ctr[gi] = gi == 2 ? 1 : 0;
+    if (gi >= I.count * I.bseg) return;
+    const int32_t b = gi / I.bseg, i = gi - b * I.bseg;
+    root[gi] = -1;
+    other[gi] = 0;
+    if (i >= i_live(I, b)) return;
+    fitness[gi] = 0ull;
+    if (mcn) mcn[gi] = 0;
     const int32_t w = i >> 5;
     const uint32_t bit = 1u << (i & 31);
+    const int32_t p0 = i_voff(I, b), p1 = i_voff(I, b + 1);
     int32_t r = -1;
-    for (int32_t p = 0; p < n; ++p) {
+    for (int32_t p = p0; p < p1; ++p) {
         const int32_t v = order[p];
         if (!(dead[(int64_t)v * Wd + w] & bit)) {
             r = v;
             break;
         }
     }
-    root[i] = r;
-    other[i] = 0;
-    fitness[i] = 0ull;
-    if (mcn) mcn[i] = 0;
+    root[gi] = r;
     if (r >= 0) {
         atomicOr(reach + (int64_t)r * Wd + w, bit);
-        parent[(int64_t)i * n + r] = r;
+        parent[uf_block(I, gi) + (r - p0)] = r - p0;
     }
 }
 
@@ -312,7 +374,8 @@ __global__ void k_pull_worklist(const int32_t *__restrict__ worklist, const int3
 
 // Pending (individual, node) pairs.  A pending node with no surviving
 // neighbour is a component of its own: it is only counted (per block, into
-// one partial row of single_part, which k_root_final adds to other[i]).
+// one partial row of single_part, which k_single_sum adds to other[i]; with
+// several instances directly into other[i]).
 // The rest go to the pair list for the union-find (parent[i][v] = v).
 // Padding individuals remove every node, so their bits are never pending.
 // Each block owns kCompactRange worklist entries: one pass counts, one global
@@ -335,22 +398,25 @@ __device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t
 }
 
 __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restrict__ worklist,
-                                                        const int32_t *__restrict__ wl_count, int32_t Wd, int32_t n,
+                                                        const int32_t *__restrict__ wl_count, int32_t Wd, const Insts I,
                                                         const int32_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ colD,
                                                         const uint32_t *__restrict__ dead,
                                                         const uint32_t *__restrict__ reach, int64_t *__restrict__ pairs,
                                                         int32_t *__restrict__ pair_count, int32_t *__restrict__ parent,
-                                                        int32_t *__restrict__ single_part)
+                                                        int32_t *__restrict__ single_part, int32_t *__restrict__ other)
 {
     __shared__ int32_t s_tot, s_base, s_off;
     __shared__ int32_t s_single[1024];
     const int w = threadIdx.x & (Wd - 1);
     const uint64_t gmask = group_mask(Wd);
     const int32_t gpb = blockDim.x / Wd;
-    const int32_t B = Wd * 32;
+    // singleton counts: per-block LDS counters written as a partial row when
+    // all slots fit (one instance), else global atomics per slot
+    const int32_t B = I.count * I.bseg;
+    const bool lds_singles = I.count == 1;
     const int32_t count = *wl_count;
-    if ((int64_t)blockIdx.x * kCompactRange >= count) return;  // no range: no partial row (see k_root_final)
+    if ((int64_t)blockIdx.x * kCompactRange >= count) return;  // no range: no partial row (see k_single_sum)
     for (int32_t t = threadIdx.x; t < B; t += blockDim.x) s_single[t] = 0;
     __syncthreads();
     for (int32_t r0 = blockIdx.x * kCompactRange; r0 < count; r0 += gridDim.x * kCompactRange) {
@@ -363,7 +429,11 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restric
             uint32_t single, multi;
             pending_split(v, Wd, w, gmask, row_ptr, colD, dead, reach, valid, single, multi);
             mine += __popc(multi);
-            for (; single; single &= single - 1) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
+            const int32_t gbase = inst_of_node(I, v) * I.bseg + w * 32;
+            for (; single; single &= single - 1) {
+                if (lds_singles) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
+                else atomicAdd(other + gbase + __ffs(single) - 1, 1);
+            }
         }
         const int32_t base = block_reserve(mine, pair_count, &s_tot, &s_base, &s_off);
         for (int32_t idx0 = r0; idx0 < r1; idx0 += gpb) {
@@ -374,16 +444,19 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restric
             pending_split(v, Wd, w, gmask, row_ptr, colD, dead, reach, valid, single, multi);
             if (!multi) continue;
             int32_t q = base + atomicAdd(&s_off, __popc(multi));
+            const int32_t b = inst_of_node(I, v);
+            const int32_t vl = v - i_voff(I, b);
             for (; multi; multi &= multi - 1) {
-                const int64_t key = (int64_t)(w * 32 + __ffs(multi) - 1) * n + v;
-                pairs[q++] = key;
-                parent[key] = v;
+                const int32_t gi = b * I.bseg + w * 32 + __ffs(multi) - 1;
+                pairs[q++] = ((int64_t)gi << 32) | (uint32_t)v;
+                parent[uf_block(I, gi) + vl] = vl;
             }
         }
         __syncthreads();
     }
-    // singleton counts of this block: one partial row, summed by k_root_final
-    for (int32_t t = threadIdx.x; t < B; t += blockDim.x) single_part[(int64_t)blockIdx.x * B + t] = s_single[t];
+    // singleton counts of this block: one partial row, summed by k_single_sum
+    if (lds_singles)
+        for (int32_t t = threadIdx.x; t < B; t += blockDim.x) single_part[(int64_t)blockIdx.x * B + t] = s_single[t];
 }
 
 __device__ __forceinline__ int32_t uf_find(int32_t *parent, int32_t x)
@@ -416,10 +489,10 @@ __device__ __forceinline__ void uf_unite(int32_t *parent, int32_t a, int32_t b)
 }
 
 
-// Union over the surviving edges of each pending pair: a surviving neighbour
-// that is reached joins the root's set; a pending one (each such edge once,
-// from its smaller end) is united with it.
-__global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, int32_t n,
+// Union over the surviving edges of each pending pair (key: slot << 32 |
+// node): a surviving neighbour that is reached joins the root's set; a
+// pending one (each such edge once, from its smaller end) is united with it.
+__global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, const Insts I,
                              int32_t Wd, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                              const uint32_t *__restrict__ dead, const uint32_t *__restrict__ reach,
                              const int32_t *__restrict__ root, int32_t *__restrict__ parent)
@@ -427,34 +500,34 @@ __global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const int32_t *_
     const int32_t count = *pair_count;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t key = pairs[q];
-        const int32_t i = (int32_t)(key / n);
-        const int32_t v = (int32_t)(key - (int64_t)i * n);
+        const int32_t gi = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
+        const int32_t b = gi / I.bseg, i = gi - b * I.bseg;
+        const int32_t off = i_voff(I, b);
         const int32_t w = i >> 5;
         const uint32_t bit = 1u << (i & 31);
-        int32_t *pi = parent + (int64_t)i * n;
+        int32_t *pi = parent + uf_block(I, gi);
         for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
             const int32_t u = col[e];
             if (dead[(int64_t)u * Wd + w] & bit) continue;
-            if (reach[(int64_t)u * Wd + w] & bit) uf_unite(pi, v, root[i]);
-            else if (v < u) uf_unite(pi, v, u);
+            if (reach[(int64_t)u * Wd + w] & bit) uf_unite(pi, v - off, root[gi] - off);
+            else if (v < u) uf_unite(pi, v - off, u - off);
         }
     }
 }
 
 // Pending nodes counted at the representative of their set.
-__global__ void k_pairs_count(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, int32_t n,
+__global__ void k_pairs_count(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, const Insts I,
                               int32_t *__restrict__ parent, int32_t *__restrict__ ucount)
 {
     const int32_t count = *pair_count;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t key = pairs[q];
-        const int32_t i = (int32_t)(key / n);
-        const int32_t v = (int32_t)(key - (int64_t)i * n);
-        const int32_t r = uf_find(parent + (int64_t)i * n, v);
-        atomicAdd(ucount + (int64_t)i * n + r, 1);
+        const int32_t gi = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
+        const int64_t blk = uf_block(I, gi);
+        const int32_t r = uf_find(parent + blk, v - i_voff(I, gi / I.bseg));
+        atomicAdd(ucount + blk + r, 1);
     }
 }
-
 
 __device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit, int32_t *mcn)
 {
@@ -464,8 +537,8 @@ __device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit
 
 // Components made only of pending nodes (set representative is a pending node
 // other than the root's representative): counted, and their sizes summed into
-// other[i].  Their counters are cleared for reuse.
-__global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, int32_t n,
+// other[gi].  Their counters are cleared for reuse.
+__global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, const Insts I,
                                int32_t *__restrict__ parent, const int32_t *__restrict__ root,
                                int32_t *__restrict__ ucount, int32_t *__restrict__ other,
                                unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn)
@@ -473,19 +546,18 @@ __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t 
     const int32_t count = *pair_count;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t key = pairs[q];
-        const int32_t i = (int32_t)(key / n);
-        const int32_t v = (int32_t)(key - (int64_t)i * n);
-        if (parent[key] != v || v == uf_find(parent + (int64_t)i * n, root[i])) continue;
-        const int32_t s = ucount[key];
-        ucount[key] = 0;
-        atomicAdd(other + i, s);
-        add_component(s, fitness + i, mcn ? mcn + i : nullptr);
+        const int32_t gi = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
+        const int32_t off = i_voff(I, gi / I.bseg);
+        const int64_t blk = uf_block(I, gi);
+        const int32_t vl = v - off;
+        if (parent[blk + vl] != vl || vl == uf_find(parent + blk, root[gi] - off)) continue;
+        const int32_t s = ucount[blk + vl];
+        ucount[blk + vl] = 0;
+        atomicAdd(other + gi, s);
+        add_component(s, fitness + gi, mcn ? mcn + gi : nullptr);
     }
 }
 
-// The root's component: every surviving non-isolated node not in another
-// component (an isolated root means every non-isolated node is removed and
-// the component is the root alone).
 // Adds the singleton partial rows of the collect blocks that owned a range to
 // other[i]: block (x, y) sums rows [64 y, 64 y + 64) for individuals
 // [64 x, 64 x + 64), loads unrolled, then one atomic per individual.
@@ -505,31 +577,38 @@ __global__ void k_single_sum(const int32_t *__restrict__ single_part, const int3
     if (acc) atomicAdd(other + i, acc);
 }
 
-__global__ void k_root_final(const int32_t *__restrict__ root, int32_t *__restrict__ parent,
+__global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, int32_t *__restrict__ parent,
                              const int32_t *__restrict__ alive_noniso, const int32_t *__restrict__ other,
-                             const int32_t *__restrict__ row_ptr, int32_t B_real, int32_t n,
-                             int32_t *__restrict__ ucount, unsigned long long *__restrict__ fitness,
-                             int32_t *__restrict__ mcn)
+                             const int32_t *__restrict__ row_ptr, int32_t *__restrict__ ucount,
+                             unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B_real || root[i] < 0) return;
-    const int32_t r = root[i];
-    ucount[(int64_t)i * n + uf_find(parent + (int64_t)i * n, r)] = 0;
-    const int64_t s = row_ptr[r + 1] > row_ptr[r] ? (int64_t)alive_noniso[i] - other[i] : 1;
-    add_component(s, fitness + i, mcn ? mcn + i : nullptr);
+    const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= I.count * I.bseg || root[gi] < 0) return;
+    const int32_t r = root[gi];
+    const int32_t off = i_voff(I, gi / I.bseg);
+    const int64_t blk = uf_block(I, gi);
+    ucount[blk + uf_find(parent + blk, r - off)] = 0;
+    const int64_t s = row_ptr[r + 1] > row_ptr[r] ? (int64_t)alive_noniso[gi] - other[gi] : 1;
+    add_component(s, fitness + gi, mcn ? mcn + gi : nullptr);
 }
 
 }  // namespace
 
 int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
-                    int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
+                    int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it)
 {
-    if (P <= 0) return GAPA_OK;
+    const bool multi = it && it->count > 1;
+    if (!multi && P <= 0) return GAPA_OK;
     const int32_t n = g->n, W = g->words;
-    // chunk width: 32 * Wd individuals, Wd a power of two <= 32
+    // chunk width: 32 * Wd slots per instance, Wd a power of two <= 32
     int32_t Wd = 1;
-    while (Wd < 32 && Wd * 32 < P) Wd <<= 1;
+    if (multi) Wd = it->bseg / 32;
+    else
+        while (Wd < 32 && Wd * 32 < P) Wd <<= 1;
+    int32_t log_wd = 0;
+    while ((1 << log_wd) < Wd) ++log_wd;
     const int32_t B = Wd * 32;
+    const int32_t S = multi ? it->count * B : B;  // slots of one pass
     int rc;
     if ((rc = ws.dead.reserve((size_t)n * Wd * 4)) != GAPA_OK) return rc;
     if ((rc = ws.reach.reserve((size_t)n * Wd * 4)) != GAPA_OK) return rc;
@@ -538,17 +617,19 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         if ((rc = ws.ucount.reserve((size_t)B * n * 4)) != GAPA_OK) return rc;
         if ((rc = launch_fill_u32(ws.ucount.ptr, 0u, (int64_t)B * n, s)) != GAPA_OK) return rc;
     }
+    // pending pairs of slot (b, i) are nodes of instance b: at most B per node
     const int64_t max_pairs = (int64_t)B * std::max(g->n_noniso, 1);
     if ((rc = ws.pairs.reserve((size_t)max_pairs * 8)) != GAPA_OK) return rc;
     if ((rc = ws.worklist.reserve((size_t)std::max(g->n_noniso, 1) * 4)) != GAPA_OK) return rc;
-    if ((rc = ws.small.reserve((size_t)(2 * B + 64 + (size_t)kSweepGrid * B) * 4)) != GAPA_OK) return rc;
+    const size_t nparts = multi ? 0 : (size_t)kSweepGrid * B;
+    if ((rc = ws.small.reserve((size_t)(2 * (size_t)S + 64 + nparts) * 4)) != GAPA_OK) return rc;
     int32_t *root = ws.small.as<int32_t>();
-    int32_t *other = root + B;
-    int32_t *ctr = root + 2 * B;  // [0] worklist count, [1] pair count, [2..] changed flags
+    int32_t *other = root + S;
+    int32_t *ctr = root + 2 * S;  // [0] worklist count, [1] pair count, [2..] changed flags
     int32_t *wl_count = ctr, *pair_count = ctr + 1, *changed = ctr + 2;
-    int32_t *single_part = ctr + 64;  // [kSweepGrid][B] singleton counts per collect block
+    int32_t *single_part = ctr + 64;  // [kSweepGrid][B] singleton counts per collect block (one instance)
     ws.stats_ctr = ctr;
-    ws.stats_B = B;
+    ws.stats_B = S;
     uint32_t *dead = ws.dead.as<uint32_t>(), *reach = ws.reach.as<uint32_t>();
     int32_t *parent = ws.parent.as<int32_t>(), *ucount = ws.ucount.as<int32_t>();
     int64_t *pairs = ws.pairs.as<int64_t>();
@@ -556,23 +637,29 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
 
     const int32_t nb = (int32_t)g->band_off.size() - 1;
     const int32_t noniso = g->n_noniso;
-    for (int32_t c0 = 0; c0 < P; c0 += B) {
-        const int32_t Br = std::min(B, P - c0);
+    const int32_t chunks = multi ? 1 : (P + B - 1) / B;
+    for (int32_t c = 0; c < chunks; ++c) {
+        const int32_t c0 = c * B;
+        Insts I{};
+        if (multi) {
+            I = Insts{it->count, B, 0, 0, it->voff, it->live, it->moff, it->node_inst, it->tiles};
+        } else {
+            I = Insts{1, B, n, std::min(B, P - c0), nullptr, nullptr, nullptr, nullptr, nullptr};
+        }
         unsigned long long *fit = reinterpret_cast<unsigned long long *>(fitness + c0);
         int32_t *mc = mcn ? mcn + c0 : nullptr;
         const int32_t *al = alive + c0;
         TimedScope pass(timer, "fitness_pass", s, 1);
         {
             TimedScope ts(timer, "k_dead_transpose", s);
-            int32_t log_wd = 0;
-            while ((1 << log_wd) < Wd) ++log_wd;
-            hipLaunchKernelGGL(k_dead_transpose, dim3((W + kTileWords - 1) / kTileWords), dim3(kBlk), 0, s,
-                               masks + (int64_t)c0 * W, W, Br, log_wd, n, dead, reach);
+            const int32_t tiles = multi ? it->ntiles : (W + kTileWords - 1) / kTileWords;
+            hipLaunchKernelGGL(k_dead_transpose, dim3(tiles), dim3(kBlk), 0, s, masks + (int64_t)c0 * W, I, log_wd,
+                               dead, reach);
         }
         {
             TimedScope ts(timer, "k_seed", s);
-            const int32_t th = std::max(Br, 64);
-            hipLaunchKernelGGL(k_seed, dim3((th + 63) / 64), dim3(64), 0, s, dead, g->d_order, n, Wd, Br, root, reach,
+            const int32_t th = std::max(S, 64);
+            hipLaunchKernelGGL(k_seed, dim3((th + 63) / 64), dim3(64), 0, s, dead, g->d_order, I, Wd, root, reach,
                                parent, other, ctr, fit, mc);
         }
         {
@@ -599,29 +686,30 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         }
         {
             TimedScope ts(timer, "k_collect_pairs", s);
-            hipLaunchKernelGGL(k_collect_pairs, dim3(kSweepGrid), dim3(kBlk), 0, s, worklist, wl_count, Wd, n,
-                               g->d_row_ptr, g->d_colD, dead, reach, pairs, pair_count, parent, single_part);
+            hipLaunchKernelGGL(k_collect_pairs, dim3(kSweepGrid), dim3(kBlk), 0, s, worklist, wl_count, Wd, I,
+                               g->d_row_ptr, g->d_colD, dead, reach, pairs, pair_count, parent, single_part, other);
         }
         {
             TimedScope ts(timer, "k_pairs_hook", s);
-            hipLaunchKernelGGL(k_pairs_hook, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, n, Wd,
+            hipLaunchKernelGGL(k_pairs_hook, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, I, Wd,
                                g->d_row_ptr, g->d_col, dead, reach, root, parent);
         }
         {
             TimedScope ts(timer, "k_pairs_count", s);
-            hipLaunchKernelGGL(k_pairs_count, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, n, parent, ucount);
+            hipLaunchKernelGGL(k_pairs_count, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, ucount);
         }
         {
             TimedScope ts(timer, "k_pairs_reduce", s);
-            hipLaunchKernelGGL(k_pairs_reduce, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, n, parent, root,
+            hipLaunchKernelGGL(k_pairs_reduce, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, root,
                                ucount, other, fit, mc);
         }
         {
             TimedScope ts(timer, "k_root_final", s);
-            hipLaunchKernelGGL(k_single_sum, dim3((B + 63) / 64, (kSweepGrid + kSumRows - 1) / kSumRows), dim3(64), 0, s,
-                               single_part, wl_count, kSweepGrid, B, other);
-            hipLaunchKernelGGL(k_root_final, dim3((Br + 63) / 64), dim3(64), 0, s, root, parent, al, other,
-                               g->d_row_ptr, Br, n, ucount, fit, mc);
+            if (!multi)
+                hipLaunchKernelGGL(k_single_sum, dim3((B + 63) / 64, (kSweepGrid + kSumRows - 1) / kSumRows), dim3(64),
+                                   0, s, single_part, wl_count, kSweepGrid, B, other);
+            hipLaunchKernelGGL(k_root_final, dim3((S + 63) / 64), dim3(64), 0, s, root, I, parent, al, other,
+                               g->d_row_ptr, ucount, fit, mc);
         }
         GAPA_HIP(hipGetLastError());
     }

@@ -10,6 +10,12 @@
 // sequential by definition (rejection draws that depend on the current
 // membership, in ascending slot order) run on one lane over LDS only; their
 // first-attempt draws are computed by the whole block beforehand.
+//
+// A launch serves one GA or a batch of independent GAs (one per instance
+// graph): blockIdx.y selects the instance, whose sizes, seed and buffer
+// offsets come from a device table, so every instance follows exactly the
+// rules (and draws) of a GA run alone.  The generation number is read from
+// device memory, which lets a whole generation be captured once and replayed.
 #include <algorithm>
 #include <climits>
 
@@ -22,18 +28,56 @@ namespace {
 constexpr int kOpBlock = 256;
 constexpr int kRankTile = 64;
 
+// Launch arguments: buffer bases shared by all instances of the launch.
 struct OpArgs {
-    const int32_t *pop;     // [P][k] current population, rows ascending
-    const int64_t *fit;     // [P]   ordered by (PC, position)
-    const uint32_t *noniso; // [W]   bit v set: v has an edge
-    int32_t *children;      // [L][k] out: rows ascending
-    uint32_t *masks;        // [L][W] out: removed-node bit set of each child
-    int32_t *alive;         // [L]   out: surviving non-isolated nodes
-    int32_t *flag;          // [1]   attempts exhausted
-    uint64_t seed, t_pc, t_pm;
-    uint32_t gen;
-    int32_t P, k, n, W, KW, T, n_noniso;
+    const GaInst *inst;       // [instances]
+    const int32_t *pop;       // current population rows, ascending
+    const int64_t *fit;       // current fitness, ordered by (PC, position)
+    const uint32_t *noniso;   // non-isolated node bit sets
+    int32_t *children;        // out: child rows, ascending
+    uint32_t *masks;          // out: removed-node bit set of each child
+    int32_t *alive;           // out: surviving non-isolated nodes of each child
+    int32_t *flag;            // [1] attempts exhausted
+    const uint32_t *gen_ctr;  // [1] generations completed
 };
+
+// One instance's view, resolved by each block from the table.
+struct Op {
+    const int32_t *pop;     // [P][k]
+    const int64_t *fit;     // [P]
+    const uint32_t *noniso; // [W] bit v set: v has an edge
+    int32_t *children;      // [L][k]
+    uint32_t *masks;        // [L][W]
+    int32_t *alive;         // [L]
+    int32_t *flag;
+    uint64_t seed, t_pc, t_pm;
+    int32_t P, L, k, n, W, KW, T, n_noniso;
+};
+
+__device__ __forceinline__ Op resolve(const OpArgs &a)
+{
+    const GaInst &I = a.inst[blockIdx.y];
+    Op o;
+    o.pop = a.pop ? a.pop + I.pop_off : nullptr;
+    o.fit = a.fit ? a.fit + I.fit_off : nullptr;
+    o.noniso = a.noniso + I.noniso_off;
+    o.children = a.children + I.child_off;
+    o.masks = a.masks + I.mask_off;
+    o.alive = a.alive + I.slot_off;
+    o.flag = a.flag;
+    o.seed = I.seed;
+    o.t_pc = I.t_pc;
+    o.t_pm = I.t_pm;
+    o.P = I.P;
+    o.L = I.L;
+    o.k = I.k;
+    o.n = I.n;
+    o.W = I.W;
+    o.KW = I.KW;
+    o.T = I.T;
+    o.n_noniso = I.n_noniso;
+    return o;
+}
 
 // LDS of one operator block: membership bits over the nodes, the row by slot,
 // a list of slots, and three bit sets over the slots.
@@ -46,7 +90,7 @@ struct OpLds {
     uint32_t *mut;        // [KW]
 };
 
-__device__ __forceinline__ OpLds carve(uint32_t *smem, const OpArgs &a)
+__device__ __forceinline__ OpLds carve(uint32_t *smem, const Op &a)
 {
     OpLds l;
     l.U = smem;
@@ -106,7 +150,7 @@ __device__ int32_t wave_list_slots(const uint32_t *bits, int32_t k, int32_t *lis
 // earlier lane).  All lanes before the first rejected one are committed at
 // once; the rejected one is resolved alone with further attempts, exactly as
 // the sequential rule would; the next batch starts after it.
-__device__ void wave_draw_in_order(const OpLds &l, const OpArgs &a, const int32_t *list, int32_t count, bool swap,
+__device__ void wave_draw_in_order(const OpLds &l, const Op &a, const int32_t *list, int32_t count, bool swap,
                                    uint32_t ind, uint32_t gen, uint32_t stream)
 {
     const int lane = threadIdx.x & 63;
@@ -178,7 +222,7 @@ __device__ int32_t block_exclusive_scan(int32_t x, int32_t *total)
     return before + incl - x;
 }
 
-__device__ void clear_lds(const OpLds &l, const OpArgs &a)
+__device__ void clear_lds(const OpLds &l, const Op &a)
 {
     for (int32_t w = threadIdx.x; w < a.W; w += blockDim.x) l.U[w] = 0u;
     for (int32_t w = threadIdx.x; w < a.KW; w += blockDim.x) l.from_donor[w] = l.dup[w] = l.mut[w] = 0u;
@@ -189,7 +233,7 @@ __device__ void clear_lds(const OpLds &l, const OpArgs &a)
 // enumerated in order: each thread owns a contiguous run of words, a block
 // scan of their popcounts gives its output offset) and its count of
 // surviving non-isolated nodes.
-__device__ void emit(const OpLds &l, const OpArgs &a, int32_t idx)
+__device__ void emit(const OpLds &l, const Op &a, int32_t idx)
 {
     __syncthreads();
     uint32_t *m = a.masks + (int64_t)idx * a.W;
@@ -222,11 +266,13 @@ __device__ void emit(const OpLds &l, const OpArgs &a, int32_t idx)
 
 // Initial individual i (eq. 2): slot j takes the first INIT draw that is not
 // already in the row; the row is then sorted.
-__global__ __launch_bounds__(kOpBlock) void k_init(OpArgs a)
+__global__ __launch_bounds__(kOpBlock) void k_init(OpArgs args)
 {
     extern __shared__ uint32_t smem[];
-    const OpLds l = carve(smem, a);
+    const Op a = resolve(args);
     const int32_t i = blockIdx.x;
+    if (i >= a.P) return;
+    const OpLds l = carve(smem, a);
     clear_lds(l, a);
     __syncthreads();
     if (threadIdx.x < 64) wave_draw_in_order(l, a, nullptr, a.k, false, i, 0, kStreamInit);
@@ -245,18 +291,21 @@ __global__ __launch_bounds__(kOpBlock) void k_init(OpArgs a)
 //   eq. 9   each mutated slot, ascending, swaps its gene for a uniform
 //           non-member (MUTATE draws).
 //   sort    the row ascending.
-__global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs a)
+__global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs args)
 {
     extern __shared__ uint32_t smem[];
     __shared__ int32_t s_donor;
-    const OpLds l = carve(smem, a);
+    const Op a = resolve(args);
     const int32_t o = blockIdx.x;
+    if (o >= a.L) return;
+    const uint32_t gen = *args.gen_ctr + 1u;
+    const OpLds l = carve(smem, a);
 
     if (threadIdx.x == 0) {
         int32_t best = -1;
         Words4 w{0, 0, 0, 0};
         for (int32_t c = 0; c < a.T; ++c) {
-            if ((c & 3) == 0) w = draw(a.seed, (uint32_t)(c >> 2), o, a.gen, kStreamSelect, 0);
+            if ((c & 3) == 0) w = draw(a.seed, (uint32_t)(c >> 2), o, gen, kStreamSelect, 0);
             const uint32_t word = (c & 3) == 0 ? w.w0 : (c & 3) == 1 ? w.w1 : (c & 3) == 2 ? w.w2 : w.w3;
             const int32_t x = (int32_t)bounded(word, (uint32_t)a.P);
             if (best < 0 || a.fit[x] < a.fit[best] || (a.fit[x] == a.fit[best] && x < best)) best = x;
@@ -270,7 +319,7 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs a)
     const int32_t *donor = a.pop + (int64_t)s_donor * a.k;
     // crossover coins; values taken from the base row enter the membership set
     for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
-        const Words4 x = draw(a.seed, j, o, a.gen, kStreamXover, 0);
+        const Words4 x = draw(a.seed, j, o, gen, kStreamXover, 0);
         const bool take = (uint64_t)x.w0 < a.t_pc;
         const int32_t c = take ? donor[j] : base[j];
         l.row[j] = c;
@@ -305,137 +354,178 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs a)
     // repair, then mutation, each in ascending slot order (one wave)
     if (threadIdx.x < 64) {
         const int32_t nd = wave_list_slots(l.dup, a.k, l.list);
-        wave_draw_in_order(l, a, l.list, nd, false, o, a.gen, kStreamRepair);
+        wave_draw_in_order(l, a, l.list, nd, false, o, gen, kStreamRepair);
         const int32_t nm = wave_list_slots(l.mut, a.k, l.list);
-        wave_draw_in_order(l, a, l.list, nm, true, o, a.gen, kStreamMutate);
+        wave_draw_in_order(l, a, l.list, nm, true, o, gen, kStreamMutate);
     }
     emit(l, a, o);
 }
 
-// Elitism (eq. 10-11) as a merge by ranks.  Keys: parents (PC, tag r) for the
-// npar rows already ordered by (PC, tag), pooled offspring (PC, tag npar + o)
-// for o = pool[q] (q < npool; pool NULL: o = q).  A key's output position is
-// the number of keys smaller in (PC, tag) order.  k_rank_count adds, per
-// (key, tile of pooled offspring), the offspring below the key; k_rank_place
-// adds the parents (they are sorted: a binary search) and writes the first
-// `keep` positions.
-__global__ __launch_bounds__(kRankTile) void k_rank_count(const int64_t *__restrict__ f_par, int32_t npar,
-                                                          const int64_t *__restrict__ f_pool,
-                                                          const int32_t *__restrict__ pool, int32_t npool,
-                                                          int32_t *__restrict__ pos)
+// Elitism (eq. 10-11) as a merge by ranks, per instance (blockIdx.z or y).
+// Keys: parents (PC, tag r) for the npar rows already ordered by (PC, tag),
+// pooled offspring (PC, tag npar + o) for o = pool[q] (q < npool; pool NULL:
+// o = q).  At generation 0 there are no parents and the P initial
+// individuals are the pool.  A key's output position is the number of keys
+// smaller in (PC, tag) order.  k_rank_count adds, per (key, tile of pooled
+// offspring), the offspring below the key; k_rank_place adds the parents
+// (they are sorted: a binary search) and writes the first P positions.
+struct RankArgs {
+    const GaInst *inst;
+    const int64_t *f_par;   // current fitness (instance base fit_off)
+    const int64_t *f_pool;  // pooled offspring fitness (instance base slot_off)
+    const int32_t *pool;    // NULL, or [npool] offspring of each pooled entry (one instance)
+    int32_t npool;          // with pool
+    int32_t init;           // generation 0: no parents
+    int32_t *pos;           // [P + pool] (instance base rank_off)
+    int32_t *src;           // [P] source tag of each kept row (instance base fit_off)
+    int64_t *f_out;         // next fitness (instance base fit_off)
+};
+
+struct RankView {
+    const int64_t *f_par, *f_pool;
+    int32_t *pos;
+    int32_t npar, npool;
+};
+
+__device__ __forceinline__ RankView rank_view(const RankArgs &a, int32_t b)
+{
+    const GaInst &I = a.inst[b];
+    RankView v;
+    v.npar = a.init ? 0 : I.P;
+    v.npool = a.init ? I.P : (a.pool ? a.npool : I.L);
+    v.f_par = a.f_par + I.fit_off;
+    v.f_pool = a.f_pool + I.slot_off;
+    v.pos = a.pos + I.rank_off;
+    return v;
+}
+
+__global__ __launch_bounds__(kRankTile) void k_rank_count(RankArgs a)
 {
     __shared__ int64_t tf[kRankTile];
     __shared__ int32_t tt[kRankTile];
+    const RankView r = rank_view(a, blockIdx.z);
     // blockDim.x == kRankTile
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t q0 = blockIdx.y * kRankTile;
+    if (q0 >= r.npool) return;  // uniform over the block
     const int32_t q = q0 + threadIdx.x;
-    tf[threadIdx.x] = q < npool ? f_pool[q] : INT64_MAX;
-    tt[threadIdx.x] = q < npool ? (pool ? pool[q] : q) : INT_MAX;
+    tf[threadIdx.x] = q < r.npool ? r.f_pool[q] : INT64_MAX;
+    tt[threadIdx.x] = q < r.npool ? (a.pool ? a.pool[q] : q) : INT_MAX;
     __syncthreads();
-    if (t >= npar + npool) return;
-    const bool is_par = t < npar;
-    const int64_t f = is_par ? f_par[t] : f_pool[t - npar];
-    const int32_t tag = is_par ? -1 : (pool ? pool[t - npar] : t - npar);
-    const int32_t m = min(kRankTile, npool - q0);
+    if (t >= r.npar + r.npool) return;
+    const bool is_par = t < r.npar;
+    const int64_t f = is_par ? r.f_par[t] : r.f_pool[t - r.npar];
+    const int32_t tag = is_par ? -1 : (a.pool ? a.pool[t - r.npar] : t - r.npar);
+    const int32_t m = min(kRankTile, r.npool - q0);
     int32_t cnt = 0;
     for (int32_t i = 0; i < m; ++i) {
         const int64_t g = tf[i];
         // pooled offspring tags exceed every parent tag
         cnt += is_par ? (g < f) : (g < f || (g == f && tt[i] < tag));
     }
-    if (cnt) atomicAdd(pos + t, cnt);
+    if (cnt) atomicAdd(r.pos + t, cnt);
 }
 
-__global__ void k_rank_place(const int64_t *__restrict__ f_par, int32_t npar, const int64_t *__restrict__ f_pool,
-                             const int32_t *__restrict__ pool, int32_t npool, int32_t keep,
-                             const int32_t *__restrict__ pos, int32_t *__restrict__ src, int64_t *__restrict__ f_out)
+__global__ void k_rank_place(RankArgs a)
 {
+    const GaInst &I = a.inst[blockIdx.y];
+    const RankView r = rank_view(a, blockIdx.y);
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= npar + npool) return;
-    int32_t p = pos[t];
+    if (t >= r.npar + r.npool) return;
+    int32_t p = r.pos[t];
     int64_t f;
     int32_t tag;
-    if (t < npar) {
-        f = f_par[t];
+    if (t < r.npar) {
+        f = r.f_par[t];
         p += t;
         tag = t;
     } else {
-        f = f_pool[t - npar];
-        int32_t lo = 0, hi = npar;  // parents with PC <= f come first
+        f = r.f_pool[t - r.npar];
+        int32_t lo = 0, hi = r.npar;  // parents with PC <= f come first
         while (lo < hi) {
             const int32_t mid = (lo + hi) >> 1;
-            if (f_par[mid] <= f) lo = mid + 1;
+            if (r.f_par[mid] <= f) lo = mid + 1;
             else hi = mid;
         }
         p += lo;
-        tag = npar + (pool ? pool[t - npar] : t - npar);
+        tag = r.npar + (a.pool ? a.pool[t - r.npar] : t - r.npar);
     }
-    if (p < keep) {
-        src[p] = tag;
-        f_out[p] = f;
+    if (p < I.P) {
+        a.src[I.fit_off + p] = tag;
+        a.f_out[I.fit_off + p] = f;
     }
 }
 
-__global__ void k_gather_rows(const int32_t *__restrict__ src, int32_t npar, const int32_t *__restrict__ parents,
-                              const int32_t *__restrict__ children, int32_t k, int32_t *__restrict__ out)
+// Row r of the next population from its source tag; after generation 0 the
+// first block also advances the device generation counter (every reader of
+// it in this generation has finished: stream order).
+__global__ void k_gather_rows(const GaInst *__restrict__ inst, const int32_t *__restrict__ src, int32_t init,
+                              const int32_t *__restrict__ parents, const int32_t *__restrict__ children,
+                              int32_t *__restrict__ out, uint32_t *__restrict__ gen_ctr)
 {
+    const GaInst &I = inst[blockIdx.y];
     const int32_t r = blockIdx.x;
-    const int32_t tag = src[r];
-    const int32_t *s = tag < npar ? parents + (int64_t)tag * k : children + (int64_t)(tag - npar) * k;
-    int32_t *d = out + (int64_t)r * k;
+    if (!init && r == 0 && blockIdx.y == 0 && threadIdx.x == 0) gen_ctr[0] += 1u;
+    if (r >= I.P) return;
+    const int32_t npar = init ? 0 : I.P;
+    const int32_t tag = src[I.fit_off + r];
+    const int32_t k = I.k;
+    const int32_t *s = tag < npar ? parents + I.pop_off + (int64_t)tag * k
+                                  : children + I.child_off + (int64_t)(tag - npar) * k;
+    int32_t *d = out + I.pop_off + (int64_t)r * k;
     for (int32_t j = threadIdx.x; j < k; j += blockDim.x) d[j] = s[j];
 }
 
-OpArgs make_args(gapa_ga *ga, const int32_t *pop, const int64_t *fit, uint32_t gen)
+OpArgs make_args(gapa_ga *ga, const int32_t *pop, const int64_t *fit)
 {
-    const gapa_graph *g = ga->graph;
     OpArgs a;
+    a.inst = ga->inst.as<GaInst>();
     a.pop = pop;
     a.fit = fit;
-    a.noniso = g->d_noniso;
+    a.noniso = ga->noniso ? ga->noniso : ga->graph->d_noniso;
     a.children = ga->children.as<int32_t>();
     a.masks = ga->masks.as<uint32_t>();
     a.alive = ga->alive.as<int32_t>();
     a.flag = ga->flag.as<int32_t>();
-    a.seed = ga->params.seed;
-    a.t_pc = ga->t_pc;
-    a.t_pm = ga->t_pm;
-    a.gen = gen;
-    a.P = ga->params.pop;
-    a.k = ga->params.k;
-    a.n = g->n;
-    a.W = g->words;
-    a.KW = (a.k + 31) / 32;
-    a.T = ga->params.tournament;
-    a.n_noniso = g->n_noniso;
+    a.gen_ctr = ga->gen_ctr.as<uint32_t>();
     return a;
 }
 
 }  // namespace
 
-int ga_rank_and_gather(gapa_ga *ga, const int64_t *f_par, const int32_t *par_rows, int32_t npar,
-                       const int64_t *f_pool, const int32_t *pool, int32_t npool, hipStream_t s)
+int ga_rank_and_gather(gapa_ga *ga, bool init, const int64_t *f_pool, const int32_t *pool, int32_t npool,
+                       hipStream_t s)
 {
-    const int nxt = npar ? 1 - ga->cur : ga->cur;
-    const int32_t P = ga->params.pop, k = ga->params.k;
-    const int32_t total = npar + npool;
+    const int nxt = init ? ga->cur : 1 - ga->cur;
+    const int32_t count = ga->count;
     int32_t *pos = ga->rank.as<int32_t>();
     int rc;
-    if ((rc = launch_fill_u32(pos, 0u, total, s)) != GAPA_OK) return rc;
+    if ((rc = launch_fill_u32(pos, 0u, ga->rank_total, s)) != GAPA_OK) return rc;
+    RankArgs a;
+    a.inst = ga->inst.as<GaInst>();
+    a.f_par = ga->fit[ga->cur].as<int64_t>();
+    a.f_pool = f_pool;
+    a.pool = pool;
+    a.npool = npool;
+    a.init = init ? 1 : 0;
+    a.pos = pos;
+    a.src = ga->src.as<int32_t>();
+    a.f_out = ga->fit[nxt].as<int64_t>();
+    // launch extents: the largest instance
+    const int32_t max_pool = init ? ga->max_pop : (pool ? npool : ga->max_lambda);
+    const int32_t max_total = init ? ga->max_pop : (pool ? ga->max_pop + npool : ga->max_pop_lambda);
     TimedScope pass(&ga->timer, "elitism", s, 1);
     {
         TimedScope ts(&ga->timer, "elitism_rank", s);
-        const dim3 grid((total + kRankTile - 1) / kRankTile, (npool + kRankTile - 1) / kRankTile);
-        if (npool > 0)
-            hipLaunchKernelGGL(k_rank_count, grid, dim3(kRankTile), 0, s, f_par, npar, f_pool, pool, npool, pos);
-        hipLaunchKernelGGL(k_rank_place, dim3((total + 255) / 256), dim3(256), 0, s, f_par, npar, f_pool, pool, npool,
-                           P, pos, ga->src.as<int32_t>(), ga->fit[nxt].as<int64_t>());
+        const dim3 grid((max_total + kRankTile - 1) / kRankTile, (max_pool + kRankTile - 1) / kRankTile, count);
+        if (max_pool > 0) hipLaunchKernelGGL(k_rank_count, grid, dim3(kRankTile), 0, s, a);
+        hipLaunchKernelGGL(k_rank_place, dim3((max_total + 255) / 256, count), dim3(256), 0, s, a);
     }
     {
         TimedScope ts(&ga->timer, "gather_rows", s);
-        hipLaunchKernelGGL(k_gather_rows, dim3(P), dim3(256), 0, s, ga->src.as<int32_t>(), npar, par_rows,
-                           ga->children.as<int32_t>(), k, ga->pop[nxt].as<int32_t>());
+        hipLaunchKernelGGL(k_gather_rows, dim3(ga->max_pop, count), dim3(256), 0, s, ga->inst.as<GaInst>(),
+                           ga->src.as<int32_t>(), a.init, ga->pop[ga->cur].as<int32_t>(), ga->children.as<int32_t>(),
+                           ga->pop[nxt].as<int32_t>(), ga->gen_ctr.as<uint32_t>());
     }
     GAPA_HIP(hipGetLastError());
     ga->cur = nxt;
@@ -462,44 +552,47 @@ int ga_prepare_kernels(size_t lds)
 
 int ga_launch_init(gapa_ga *ga, hipStream_t s)
 {
-    OpArgs a = make_args(ga, nullptr, nullptr, 0);
+    OpArgs a = make_args(ga, nullptr, nullptr);
     TimedScope ts(&ga->timer, "ga_init", s, 1);
-    hipLaunchKernelGGL(k_init, dim3(ga->params.pop), dim3(kOpBlock), ga->op_lds_bytes, s, a);
+    hipLaunchKernelGGL(k_init, dim3(ga->max_pop, ga->count), dim3(kOpBlock), ga->op_lds_bytes, s, a);
     GAPA_HIP(hipGetLastError());
     return GAPA_OK;
 }
 
-int ga_launch_offspring(gapa_ga *ga, uint32_t gen, int32_t count, hipStream_t s)
+int ga_launch_offspring(gapa_ga *ga, hipStream_t s)
 {
-    OpArgs a = make_args(ga, ga->pop[ga->cur].as<int32_t>(), ga->fit[ga->cur].as<int64_t>(), gen);
+    OpArgs a = make_args(ga, ga->pop[ga->cur].as<int32_t>(), ga->fit[ga->cur].as<int64_t>());
     TimedScope ts(&ga->timer, "ga_offspring", s, 1);
-    hipLaunchKernelGGL(k_offspring, dim3(count), dim3(kOpBlock), ga->op_lds_bytes, s, a);
+    hipLaunchKernelGGL(k_offspring, dim3(ga->max_lambda, ga->count), dim3(kOpBlock), ga->op_lds_bytes, s, a);
     GAPA_HIP(hipGetLastError());
     return GAPA_OK;
+}
+
+static int ga_eval_children(gapa_ga *ga, bool init, hipStream_t s)
+{
+    if (ga->count > 1)
+        return eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(), 0,
+                          ga->child_fit.as<int64_t>(), nullptr, ga->ws, &ga->timer, s,
+                          init ? &ga->tab_init : &ga->tab_gen);
+    return eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(),
+                      init ? ga->params.pop : ga->lambda, ga->child_fit.as<int64_t>(), nullptr, ga->ws, &ga->timer,
+                      s);
 }
 
 int ga_init_population(gapa_ga *ga, hipStream_t s)
 {
-    const int32_t P = ga->params.pop;
-    int rc = ga_launch_init(ga, s);
-    if (rc != GAPA_OK) return rc;
-    rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(), P, ga->child_fit.as<int64_t>(),
-                    nullptr, ga->ws, &ga->timer, s);
-    if (rc != GAPA_OK) return rc;
-    return ga_rank_and_gather(ga, nullptr, nullptr, 0, ga->child_fit.as<int64_t>(), nullptr, P, s);
+    int rc = launch_fill_u32(ga->gen_ctr.ptr, 0u, 1, s);
+    if (rc == GAPA_OK) rc = ga_launch_init(ga, s);
+    if (rc == GAPA_OK) rc = ga_eval_children(ga, true, s);
+    if (rc == GAPA_OK) rc = ga_rank_and_gather(ga, true, ga->child_fit.as<int64_t>(), nullptr, 0, s);
+    return rc;
 }
 
 int ga_generation(gapa_ga *ga, hipStream_t s)
 {
-    const int32_t P = ga->params.pop, L = ga->lambda;
-    const uint32_t gen = (uint32_t)(ga->generation + 1);
-    int rc = ga_launch_offspring(ga, gen, L, s);
-    if (rc != GAPA_OK) return rc;
-    rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(), L, ga->child_fit.as<int64_t>(),
-                    nullptr, ga->ws, &ga->timer, s);
-    if (rc != GAPA_OK) return rc;
-    rc = ga_rank_and_gather(ga, ga->fit[ga->cur].as<int64_t>(), ga->pop[ga->cur].as<int32_t>(), P,
-                            ga->child_fit.as<int64_t>(), nullptr, L, s);
+    int rc = ga_launch_offspring(ga, s);
+    if (rc == GAPA_OK) rc = ga_eval_children(ga, false, s);
+    if (rc == GAPA_OK) rc = ga_rank_and_gather(ga, false, ga->child_fit.as<int64_t>(), nullptr, 0, s);
     if (rc != GAPA_OK) return rc;
     ga->generation += 1;
     return GAPA_OK;

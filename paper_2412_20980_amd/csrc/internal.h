@@ -122,14 +122,33 @@ struct gapa_graph {
 
 namespace gapa {
 
+// Several instances (disjoint node ranges of one graph, each with its own
+// individuals) evaluated in one bit-parallel fitness pass.  All arrays are on
+// the device.  Slot i of instance b is entry b * bseg + i of the alive,
+// fitness and mcn arrays; its removed-node bit set (local node ids, W_b =
+// ceil(n_b / 32) words) starts at word moff[b] + i * W_b of the mask array.
+struct InstTable {
+    int32_t count = 0;
+    int32_t bseg = 0;                    // slots per instance: 32 * Wd, Wd a power of two <= 32
+    const int32_t *voff = nullptr;       // [count + 1] first node of each instance
+    const int32_t *live = nullptr;       // [count] slots in use
+    const int64_t *moff = nullptr;       // [count]
+    const int32_t *node_inst = nullptr;  // [n] instance of each node
+    const int32_t *tiles = nullptr;      // [2 * ntiles] (instance, first node word) of each 8-word tile
+    int32_t ntiles = 0;
+};
+
 // Fitness of P individuals given as removed-node bit sets masks[P][W]
 // (device) with alive[P] = surviving non-isolated nodes of each.  Writes
 // fitness[P] (int64) and, if mcn != nullptr, mcn[P] (int32).  Runs the graph's
 // selected algorithm.
+// With an instance table of count > 1 (bit-parallel algorithm only), P is
+// ignored and all slots of all instances are evaluated in one pass.
 int eval_masks(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness, int32_t *mcn,
-               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it = nullptr);
 int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
-                    int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+                    int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s,
+                    const InstTable *it = nullptr);
 int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,
                          FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
 // Same from gene rows genes[P][k] (device node ids; a repeated id in a row is
@@ -152,15 +171,34 @@ int launch_mask_build(const int32_t *genes, int32_t P, int32_t k, int32_t n, int
 size_t ga_op_lds_bytes(int32_t n, int32_t k);
 int ga_prepare_kernels(size_t lds);
 
+// Device table entry of one GA instance: where its rows live in the shared
+// buffers, its sizes and its random-stream parameters.  A single GA is a
+// one-entry table with every offset 0.
+struct GaInst {
+    int64_t pop_off;    // first element of its rows in pop[*] (row stride k)
+    int64_t child_off;  // first element of its rows in children (row stride k)
+    int64_t mask_off;   // first word of its child masks (row stride W)
+    int32_t fit_off;    // first entry in fit[*] and src
+    int32_t slot_off;   // first entry in child_fit and alive
+    int32_t rank_off;   // first entry in rank
+    int32_t noniso_off; // first word of its non-isolated node bit set
+    uint64_t seed, t_pc, t_pm;
+    int32_t P, L, k, n, W, KW, T, n_noniso;
+};
+
 int ga_init_population(gapa_ga *ga, hipStream_t s);
+// One generation of every instance; the generation number is read on the
+// device, so the launches can be captured into a graph and replayed.
 int ga_generation(gapa_ga *ga, hipStream_t s);
 int ga_launch_init(gapa_ga *ga, hipStream_t s);
-int ga_launch_offspring(gapa_ga *ga, uint32_t gen, int32_t count, hipStream_t s);
-// Elitism over the npar current parents (f_par / par_rows; 0 at generation 0)
-// and npool evaluated offspring (f_pool[q] is the fitness of child pool[q], or
-// of child q when pool is NULL); writes the next population buffer.
-int ga_rank_and_gather(gapa_ga *ga, const int64_t *f_par, const int32_t *par_rows, int32_t npar,
-                       const int64_t *f_pool, const int32_t *pool, int32_t npool, hipStream_t s);
+int ga_launch_offspring(gapa_ga *ga, hipStream_t s);
+// Elitism of every instance over its current parents (none at generation 0,
+// `init`) and its evaluated offspring (f_pool[q] is the fitness of child
+// pool[q], or of child q when pool is NULL; a pool only with one instance);
+// writes the next population buffer and, after generation 0, advances the
+// device generation counter.
+int ga_rank_and_gather(gapa_ga *ga, bool init, const int64_t *f_pool, const int32_t *pool, int32_t npool,
+                       hipStream_t s);
 
 // Error reporting for HIP calls.
 int hip_fail(hipError_t e, const char *what);
@@ -173,24 +211,45 @@ int hip_fail(hipError_t e, const char *what);
 }  // namespace gapa
 
 struct gapa_ga {
-    gapa_graph *graph = nullptr;
-    gapa_params params{};
+    gapa_graph *graph = nullptr;  // for a batch: the disjoint union of the instance graphs
+    gapa_params params{};         // first instance's parameters
     int32_t lambda = 0;
     uint64_t t_pc = 0, t_pm = 0;  // Bernoulli thresholds floor(p * 2^32)
     int64_t generation = 0;
     int cur = 0;                  // which population buffer is current
-    gapa::DevBuf pop[2];          // int32 [P][k]
-    gapa::DevBuf fit[2];          // int64 [P]
-    gapa::DevBuf children;        // int32 [lambda][k]
-    gapa::DevBuf child_fit;       // int64 [lambda]
-    gapa::DevBuf masks;           // uint32 [max(P, lambda)][W] removed-node bit sets
-    gapa::DevBuf alive;           // int32 [max(P, lambda)] surviving non-isolated nodes
-    gapa::DevBuf src;             // int32 [P] elitism: source tag of each kept row
-    gapa::DevBuf rank;            // int32 [P + lambda] elitism: offspring below each key
+    int32_t count = 1;            // instances
+    std::vector<gapa::GaInst> hinst;
+    gapa::DevBuf inst;            // GaInst [count]
+    int32_t max_pop = 0, max_lambda = 0, max_pop_lambda = 0, rank_total = 0;
+    gapa::DevBuf pop[2];          // int32 rows of every instance
+    gapa::DevBuf fit[2];          // int64 [sum P]
+    gapa::DevBuf children;        // int32 rows
+    gapa::DevBuf child_fit;       // int64 slots
+    gapa::DevBuf masks;           // uint32 removed-node bit sets of the children
+    gapa::DevBuf alive;           // int32 slots: surviving non-isolated nodes
+    gapa::DevBuf src;             // int32 [sum P] elitism: source tag of each kept row
+    gapa::DevBuf rank;            // int32 [sum (P + lambda)] elitism: offspring below each key
     gapa::DevBuf flag;            // int32 [4] device error flags
+    gapa::DevBuf gen_ctr;         // uint32 [1] generations completed (read by the operator kernel)
+    uint32_t *noniso = nullptr;   // batch: per-instance non-isolated bit sets (else the graph's)
+    gapa::DevBuf noniso_buf;
+    // batch: instance tables of the fitness pass at generation 0 and later
+    gapa::InstTable tab_init, tab_gen;
+    gapa::DevBuf tab_voff, tab_live_init, tab_live_gen, tab_moff, tab_node_inst, tab_tiles;
     gapa::FitnessWorkspace ws;
     gapa::KernelTimer timer;
     hipStream_t last_stream = nullptr;
     size_t op_lds_bytes = 0;      // dynamic LDS of the operator kernels
     bool failed = false;
+    // graph replay of one generation (one per current-buffer parity)
+    bool use_graph = false;
+    bool warm = false;            // a generation has run eagerly: buffers are sized
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graphs[2] = {nullptr, nullptr};
+    hipGraphExec_t execs[2] = {nullptr, nullptr};
+};
+
+struct gapa_batch {
+    gapa_ga *ga = nullptr;
+    gapa_graph *super = nullptr;  // owned
 };

@@ -39,12 +39,15 @@ GAPA_DEVICE_PTRS = 1 << 0
 GAPA_TRUST_INPUT = 1 << 1
 GAPA_WANT_MCN = 1 << 2
 GAPA_UNIONFIND = 1 << 3
+GAPA_GRAPH_REPLAY = 1 << 4
 
 EXPORTED = (
     "gapa_graph_create", "gapa_graph_destroy", "gapa_eval_population",
     "gapa_ga_create", "gapa_generation_step", "gapa_best", "gapa_get_population", "gapa_ga_destroy",
     "gapa_graph_set_timing", "gapa_graph_kernel_times", "gapa_ga_set_timing", "gapa_ga_kernel_times",
     "gapa_graph_fitness_stats", "gapa_ga_fitness_stats", "gapa_last_error", "gapa_version",
+    "gapa_batch_create", "gapa_batch_step", "gapa_batch_best", "gapa_batch_get_population",
+    "gapa_batch_set_timing", "gapa_batch_kernel_times", "gapa_batch_destroy",
 )
 
 
@@ -85,9 +88,14 @@ def lib() -> C.CDLL:
     L.gapa_best.argtypes = [vp, vp, i64p, i64p]
     L.gapa_get_population.argtypes = [vp, vp, vp]
     L.gapa_ga_destroy.argtypes = [vp]
-    for f in (L.gapa_graph_set_timing, L.gapa_ga_set_timing):
+    L.gapa_batch_create.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(gapa_params), vp, C.POINTER(vp)]
+    L.gapa_batch_step.argtypes = [vp, C.c_int32, vp]
+    L.gapa_batch_best.argtypes = [vp, C.c_int32, vp, i64p, i64p]
+    L.gapa_batch_get_population.argtypes = [vp, C.c_int32, vp, vp]
+    L.gapa_batch_destroy.argtypes = [vp]
+    for f in (L.gapa_graph_set_timing, L.gapa_ga_set_timing, L.gapa_batch_set_timing):
         f.argtypes = [vp, C.c_int32]
-    for f in (L.gapa_graph_kernel_times, L.gapa_ga_kernel_times):
+    for f in (L.gapa_graph_kernel_times, L.gapa_ga_kernel_times, L.gapa_batch_kernel_times):
         f.argtypes = [vp, C.POINTER(gapa_kernel_time), C.c_int32, i32p]
     for f in (L.gapa_graph_fitness_stats, L.gapa_ga_fitness_stats):
         f.argtypes = [vp, i64p]
@@ -217,9 +225,13 @@ class Graph:
 
 # -------------------------------------------------------------------- GA ----
 
-def gapa_ga_create(graph_handle, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, stream=None):
-    p = gapa_params(k=k, pop=pop, tournament=tournament, offspring=offspring, seed=seed, pc=pc, pm=pm, flags=0,
-                    reserved=0)
+def make_params(k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, flags=0) -> gapa_params:
+    return gapa_params(k=k, pop=pop, tournament=tournament, offspring=offspring, seed=seed, pc=pc, pm=pm,
+                       flags=flags, reserved=0)
+
+
+def gapa_ga_create(graph_handle, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, stream=None, flags=0):
+    p = make_params(k, pop, seed, pc, pm, tournament, offspring, flags)
     h = C.c_void_p()
     _check(lib().gapa_ga_create(graph_handle, C.byref(p), _stream_ptr(stream), C.byref(h)))
     return h
@@ -249,12 +261,15 @@ def gapa_ga_destroy(h):
 
 
 class GA:
-    """The GA on one graph; generation 0 is drawn and evaluated at creation."""
+    """The GA on one graph; generation 0 is drawn and evaluated at creation.
+    replay=True records one generation as a HIP graph and replays it."""
 
-    def __init__(self, graph: Graph, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, stream=None):
+    def __init__(self, graph: Graph, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, stream=None,
+                 replay: bool = False):
         self.graph = graph
         self.k, self.pop = int(k), int(pop)
-        self.handle = gapa_ga_create(graph.handle, k, pop, seed, pc, pm, tournament, offspring, stream)
+        self.handle = gapa_ga_create(graph.handle, k, pop, seed, pc, pm, tournament, offspring, stream,
+                                     GAPA_GRAPH_REPLAY if replay else 0)
 
     def step(self, n: int = 1, stream=None):
         gapa_generation_step(self.handle, n, stream)
@@ -277,6 +292,86 @@ class GA:
     def close(self):
         if self.handle:
             gapa_ga_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------- batch ----
+
+def gapa_batch_create(graph_handles, params, stream=None):
+    """graph_handles: sequence of graph handles; params: sequence of
+    gapa_params (one per instance)."""
+    count = len(graph_handles)
+    hs = (C.c_void_p * count)(*[h.value if isinstance(h, C.c_void_p) else h for h in graph_handles])
+    ps = (gapa_params * count)(*params)
+    out = C.c_void_p()
+    _check(lib().gapa_batch_create(count, hs, ps, _stream_ptr(stream), C.byref(out)))
+    return out
+
+
+def gapa_batch_step(h, n_generations: int = 1, stream=None):
+    _check(lib().gapa_batch_step(h, n_generations, _stream_ptr(stream)))
+
+
+def gapa_batch_best(h, idx: int, k: int):
+    genes = np.zeros(k, dtype=np.int32)
+    f = C.c_int64(0)
+    g = C.c_int64(0)
+    _check(lib().gapa_batch_best(h, idx, genes.ctypes.data, C.byref(f), C.byref(g)))
+    return genes, int(f.value), int(g.value)
+
+
+def gapa_batch_get_population(h, idx: int, P: int, k: int):
+    genes = np.zeros((P, k), dtype=np.int32)
+    F = np.zeros(P, dtype=np.int64)
+    _check(lib().gapa_batch_get_population(h, idx, genes.ctypes.data, F.ctypes.data))
+    return genes, F
+
+
+def gapa_batch_destroy(h):
+    _check(lib().gapa_batch_destroy(h))
+
+
+class Batch:
+    """Independent GAs, one per (graph, parameters) pair, advanced together;
+    instance b evolves exactly as GA(graphs[b], **params[b]) would."""
+
+    def __init__(self, graphs, params, stream=None, replay: bool = True):
+        """graphs: sequence of Graph; params: sequence of dicts with keys k,
+        pop, seed and optionally pc, pm, tournament, offspring."""
+        self.graphs = list(graphs)
+        self.params = [dict(p) for p in params]
+        flags = GAPA_GRAPH_REPLAY if replay else 0
+        ps = [make_params(flags=flags, **p) for p in self.params]
+        self.handle = gapa_batch_create([g.handle for g in self.graphs], ps, stream)
+
+    def __len__(self):
+        return len(self.graphs)
+
+    def step(self, n: int = 1, stream=None):
+        gapa_batch_step(self.handle, n, stream)
+
+    def best(self, idx: int):
+        return gapa_batch_best(self.handle, idx, self.params[idx]["k"])
+
+    def population(self, idx: int):
+        p = self.params[idx]
+        return gapa_batch_get_population(self.handle, idx, p["pop"], p["k"])
+
+    def set_timing(self, level: int = 1):
+        _check(lib().gapa_batch_set_timing(self.handle, int(level)))
+
+    def kernel_times(self) -> dict:
+        return _kernel_times(lib().gapa_batch_kernel_times, self.handle)
+
+    def close(self):
+        if self.handle:
+            gapa_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

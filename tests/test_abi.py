@@ -90,3 +90,19 @@ def test_no_device_reported_after_validation():
         pytest.skip("a GPU is present")
     rc, h = _create(3, [0, 1, 3, 4], [1, 0, 2, 1])
     assert rc == gapa.GAPA_E_NO_DEVICE
+
+
+def test_batch_arguments_rejected_on_host(L):
+    from paper_2412_20980_amd import gapa
+    out = C.c_void_p()
+    hs = (C.c_void_p * 1)(None)
+    ps = (gapa.gapa_params * 1)(gapa.make_params(1, 1, 0))
+    assert L.gapa_batch_create(1, hs, ps, None, None) == gapa.GAPA_E_INVALID_ARG
+    assert L.gapa_batch_create(1, None, ps, None, C.byref(out)) == gapa.GAPA_E_INVALID_ARG
+    assert L.gapa_batch_create(0, hs, ps, None, C.byref(out)) == gapa.GAPA_E_INVALID_ARG
+    assert L.gapa_batch_create(5000, hs, ps, None, C.byref(out)) == gapa.GAPA_E_INVALID_ARG
+    assert L.gapa_batch_create(1, hs, ps, None, C.byref(out)) == gapa.GAPA_E_INVALID_ARG  # NULL graph
+    assert L.gapa_batch_step(None, 1, None) == gapa.GAPA_E_INVALID_ARG
+    assert L.gapa_batch_best(None, 0, None, None, None) == gapa.GAPA_E_INVALID_ARG
+    assert L.gapa_batch_get_population(None, 0, None, None) == gapa.GAPA_E_INVALID_ARG
+    assert L.gapa_batch_destroy(None) == 0
