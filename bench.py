@@ -1,14 +1,18 @@
 """Benchmark: GA generations of critical node detection on one MI355X.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-replay]
+  python bench.py --workload batched64    # 64 independent GAs advanced together
   python bench.py --copy-calibration      # plain 1 GiB copies, for counter scaling
 
 A step is one whole generation of the method on the device: tournament
 selection, crossover with repair, mutation, batched exact fitness of all
 offspring and elitism.  The default workload is the 200k-node Chung-Lu
 power-law graph (gamma 2.5, mean degree 10), budget k = 2000, population 1024,
-1024 offspring per generation.  Inputs are resident in HBM before timing
-starts.  Prints one JSON line.
+1024 offspring per generation, run for its 500 generations: the first 100 are
+warm-up, the other 400 are timed (the fitness cost changes as the population
+concentrates on hubs, so early generations alone would not represent the run).
+Generations are replayed from a recorded HIP graph unless --no-replay.
+Inputs are resident in HBM before timing starts.  Prints one JSON line.
 
 Roofline: the batched fitness of one chunk of individuals (up to 1024) is the
 measured unit ("fitness_pass": removed-node bit sets, then the fixed sequence
@@ -88,6 +92,55 @@ def cpu_baseline(w, budget_s: float = 12.0):
                       f"generations, {evals} BFS fitness evaluations with operators and elitism, {dt:.1f} s wall"}
 
 
+def run_batched(args, torch, gapa, inputs):
+    """The 64-instance workload: independent GAs on graphs of log-uniform size
+    in [1000, 50000] (BA m=3 and ER mean degree 8 alternating), k = n / 100,
+    P = 128, advanced together (one operator launch, one fitness pass over the
+    disjoint union, one elitism launch per generation, replayed as a HIP
+    graph)."""
+    ws = inputs.batched_instances()
+    print(f"# batched: {len(ws)} instances, sum n={sum(w.graph.n for w in ws)} "
+          f"sum m={sum(w.graph.m for w in ws)}", file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    graphs = [gapa.Graph.from_csr(w.graph, trust=True) for w in ws]
+    params = [dict(k=w.k, pop=w.pop, seed=w.seed, pc=w.pc, pm=w.pm, tournament=w.tournament) for w in ws]
+    bt = gapa.Batch(graphs, params, stream=stream, replay=not args.no_replay)
+    bt.step(args.warmup, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(args.steps, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # per-pass durations from the library's events (generations run eagerly
+    # while timing is on)
+    bt.set_timing(1)
+    bt.step(args.steps, stream=stream)
+    torch.cuda.synchronize()
+    passes = bt.kernel_times()
+    bt.set_timing(0)
+    lam = sum(w.offspring or w.pop for w in ws)
+    fit_ms = passes["fitness_pass"][1] / passes["fitness_pass"][0]
+    unit_bytes = sum((w.offspring or w.pop) * algorithmic_bytes_per_eval(w.graph.n, w.graph.nnz) for w in ws)
+    achieved = unit_bytes / (fit_ms * 1e-3) / 1e9
+    return {
+        "metric": METRIC,
+        "value": lam * args.steps / dt,
+        "unit": "fitness evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "batched64_p128", "instances": len(ws), "sum_n": sum(w.graph.n for w in ws),
+                   "sum_m": sum(w.graph.m for w in ws), "pop": 128, "k": "n/100", "replay": not args.no_replay,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "fitness_pass", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": fit_ms, "launches": passes["fitness_pass"][0],
+                     "algorithmic_bytes_per_launch": unit_bytes},
+        "operator_ms_per_step": {k: v[1] / v[0] for k, v in sorted(passes.items()) if k != "fitness_pass"},
+    }
+
+
 def copy_calibration():
     import torch
     n = 1 << 28  # 2^28 float32 = 1 GiB
@@ -103,12 +156,16 @@ def copy_calibration():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # defaults: the workload's whole run (500 generations at n = 200k, 200 for
+    # the batched instances) with the first fifth untimed
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="cl200k_k2000_p1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-replay", action="store_true", help="launch generations eagerly instead of replaying a "
+                    "recorded HIP graph")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build evaluates one GPU's share of the population "
@@ -124,6 +181,13 @@ def main():
 
     from paper_2412_20980_amd import gapa, inputs
 
+    if args.workload == "batched64":
+        args.warmup = 40 if args.warmup is None else args.warmup
+        args.steps = 160 if args.steps is None else args.steps
+        print(json.dumps(run_batched(args, torch, gapa, inputs)), flush=True)
+        return
+    args.warmup = 100 if args.warmup is None else args.warmup
+    args.steps = 400 if args.steps is None else args.steps
     w = inputs.workload(args.workload)
     g = w.graph
     lam = w.offspring or w.pop
@@ -131,7 +195,8 @@ def main():
 
     stream = torch.cuda.Stream()
     graph = gapa.Graph.from_csr(g, trust=True)
-    ga = gapa.GA(graph, w.k, w.pop, w.seed, w.pc, w.pm, w.tournament, w.offspring, stream=stream)
+    ga = gapa.GA(graph, w.k, w.pop, w.seed, w.pc, w.pm, w.tournament, w.offspring, stream=stream,
+                 replay=not args.no_replay)
     ga.step(args.warmup, stream=stream)
     torch.cuda.synchronize()
 
@@ -189,7 +254,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "graph": g.name, "n": g.n, "m": g.m, "k": w.k, "pop": w.pop,
                    "offspring": lam, "pc": w.pc, "pm": w.pm, "tournament": w.tournament,
-                   "parallelism": "single GPU"},
+                   "replay": not args.no_replay, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "fitness_pass", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["bytes_per_pass"] if traffic else None,

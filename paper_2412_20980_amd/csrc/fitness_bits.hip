@@ -233,22 +233,32 @@ __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restr
 }
 
 // Pull for one node by its lane group: OR the neighbours' reach rows (in
-// degree-descending order) until every pending bit is covered.  Returns true
-// if the node gained bits.
+// degree-descending order), four at a time, until every pending bit is
+// covered or max_scan neighbours have been read.  Returns true if the node
+// gained bits.  Whatever stays pending is picked up by a later sweep or, in
+// the end, by the union-find pass, so the cap only moves work.
+constexpr int kBandScan = 64;  // neighbours read per node in the ordered sweep
+
 __device__ __forceinline__ bool pull_node(int32_t v, int Wd, int w, uint64_t gmask,
                                           const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
-                                          const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach)
+                                          const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach,
+                                          int32_t max_scan)
 {
     const uint32_t mine = ld_relaxed_u(reach + (int64_t)v * Wd + w);
     const uint32_t pend = ~dead[(int64_t)v * Wd + w] & ~mine;
     if ((__ballot(pend != 0) & gmask) == 0) return false;
     uint32_t acc = 0;
-    const int32_t e0 = row_ptr[v], e1 = row_ptr[v + 1];
-    for (int32_t e = e0; e < e1; ++e) {
-        const int32_t u = colD[e];
-        acc |= ld_relaxed_u(reach + (int64_t)u * Wd + w);
+    const int32_t e0 = row_ptr[v];
+    const int32_t e1 = row_ptr[v + 1] - e0 > max_scan ? e0 + max_scan : row_ptr[v + 1];
+    int32_t e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        const int32_t u0 = colD[e], u1 = colD[e + 1], u2 = colD[e + 2], u3 = colD[e + 3];
+        acc |= ld_relaxed_u(reach + (int64_t)u0 * Wd + w) | ld_relaxed_u(reach + (int64_t)u1 * Wd + w) |
+               ld_relaxed_u(reach + (int64_t)u2 * Wd + w) | ld_relaxed_u(reach + (int64_t)u3 * Wd + w);
         if ((__ballot((acc & pend) != pend) & gmask) == 0) break;
     }
+    if ((__ballot((acc & pend) != pend) & gmask) != 0)
+        for (; e < e1; ++e) acc |= ld_relaxed_u(reach + (int64_t)colD[e] * Wd + w);
     const uint32_t gain = acc & pend;
     if (gain) __hip_atomic_store(reach + (int64_t)v * Wd + w, mine | gain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return (__ballot(gain != 0) & gmask) != 0;
@@ -273,7 +283,7 @@ __global__ void k_pull_band(const int32_t *__restrict__ band_v, int32_t b0, int3
         const bool valid = idx < count;
         const int32_t v = valid ? band_v[b0 + idx] : 0;
         if (__ballot(valid) == 0) continue;
-        if (valid) pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach);
+        if (valid) pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach, kBandScan);
     }
 }
 
@@ -364,7 +374,7 @@ __global__ void k_pull_worklist(const int32_t *__restrict__ worklist, const int3
         const bool valid = idx < count;
         const int32_t v = valid ? worklist[idx] : 0;
         if (__ballot(valid) == 0) continue;
-        if (valid) any_gain |= pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach);
+        if (valid) any_gain |= pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach, INT_MAX);
     }
     // one flag for the whole grid: set it with a plain store, and only if no
     // other wave has (same-address atomics from every wave would serialise)
