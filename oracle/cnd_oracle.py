@@ -59,6 +59,8 @@ def lib():
             L.oracle_ga_init.argtypes = [pp, C.c_int32, i32p, i32p, i32p, i64p, C.c_int32]
             L.oracle_ga_step.argtypes = [pp, C.c_int32, C.c_int32, i32p, i32p, i32p, i64p, i32p, C.c_int32, i32p, i64p, C.c_int32]
             L.oracle_max_threads.restype = C.c_int
+            L.oracle_uniform_sym.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_int32, C.c_double,
+                                             C.POINTER(C.c_double)]
             _lib = L
     return _lib
 
@@ -88,6 +90,14 @@ def philox(ctr, key) -> np.ndarray:
 def draw(seed, slot, ind, gen, stream, attempt=0) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     lib().oracle_draw(seed, slot, ind, gen, stream, attempt, _p(out, C.c_uint32))
+    return out
+
+
+def uniform_sym(seed: int, tensor: int, rows: int, cols: int, bound: float) -> np.ndarray:
+    """[rows, cols] float64: element (r, c) = bound * (2u - 1), u from the
+    first word of draw(seed, slot c, ind r, gen tensor, stream 5)."""
+    out = np.zeros((rows, cols), dtype=np.float64)
+    lib().oracle_uniform_sym(seed, tensor, rows, cols, bound, out.ctypes.data_as(C.POINTER(C.c_double)))
     return out
 
 

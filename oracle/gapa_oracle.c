@@ -99,6 +99,21 @@ void oracle_draw(uint64_t seed, uint32_t slot, uint32_t ind, uint32_t gen,
     draw(seed, slot, ind, gen, stream, attempt, out);
 }
 
+/* Learned-screening extension (not in the paper): initial weights.  Element
+ * (r, c) of parameter tensor t is bound * (2u - 1) with u = (w + 1/2) / 2^32,
+ * w the first word of the draw (slot c, individual r, generation t, stream
+ * SURR_INIT = 5): a uniform value in (-bound, bound), computed in double. */
+void oracle_uniform_sym(uint64_t seed, uint32_t tensor, int64_t rows, int32_t cols, double bound, double *out)
+{
+    for (int64_t r = 0; r < rows; ++r)
+        for (int32_t c = 0; c < cols; ++c) {
+            uint32_t w[4];
+            draw(seed, (uint32_t)c, (uint32_t)r, tensor, 5u, 0u, w);
+            const double u = ((double)w[0] + 0.5) * (1.0 / 4294967296.0);
+            out[r * cols + c] = bound * (2.0 * u - 1.0);
+        }
+}
+
 /* Integer in [0, m): the high word of w*m (multiply-shift, no rejection). */
 uint32_t oracle_bounded(uint32_t w, uint32_t m)
 {
