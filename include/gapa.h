@@ -157,6 +157,105 @@ GAPA_API int gapa_get_population(gapa_ga *ga, int32_t *genes_out, int64_t *fitne
 GAPA_API int gapa_ga_destroy(gapa_ga *ga);
 
 /* ---------------------------------------------------------------------------
+ * Learned screening surrogate (an extension; not in the paper).  The paper
+ * evaluates every offspring exactly (Section III-C).  With a surrogate
+ * attached, each generation still makes `offspring` children with the same
+ * operators, but a small network predicts their fitness and only the
+ * `screen` children with the lowest predictions are evaluated exactly and
+ * enter elitism; exact fitness stays the only value the population holds.
+ *
+ *   x(S) = sum over v in S of E[v]           E: n x 64 node embeddings
+ *   yhat = w3 . relu(W2 relu(W1 x + b1) + b2) + b3      (64 -> 256 -> 256 -> 1)
+ *
+ * FP32 master weights, bfloat16 copies for the products (matrix-core
+ * kernels, FP32 accumulation).  Trained online on (S, ln(1 + PC(S))) pairs of
+ * the exactly evaluated offspring, kept in a ring buffer: labels are
+ * standardised by the buffer's mean and standard deviation; mean squared
+ * error; Adam (Kingma and Ba 2015) with beta = (0.9, 0.999), eps = 1e-8;
+ * `train_steps` steps per generation on batches drawn with Philox stream 6
+ * (slot j, individual step, generation).  Initial weights from Philox stream
+ * 5: E uniform in +-0.05, W1 and W2 uniform in +-sqrt(6 / fan_in), w3 in
+ * +-sqrt(3 / fan_in), biases 0.
+ *
+ * Generations 1..warmup_gens evaluate every child (and train).  Later
+ * generations screen; the Spearman correlation between predictions and exact
+ * fitness over the evaluated children (at most 1024 of them, evenly spaced)
+ * is the judge: after `fallback_gens` consecutive screened generations with
+ * a correlation below min_rho, the next generation evaluates every child.
+ * ------------------------------------------------------------------------- */
+enum {
+    GAPA_SCREEN_RANDOM = 1u << 0 /* gapa_surrogate_params.flags: screen a uniformly
+                                    random subset instead (Philox stream 7); no
+                                    training -- the ablation baseline             */
+};
+
+typedef struct gapa_surrogate_params {
+    int32_t emb_dim;       /* 64 (the only supported value)                       */
+    int32_t hidden;        /* 256 (the only supported value)                      */
+    int32_t screen;        /* children evaluated exactly per screened generation,
+                              1 <= screen <= offspring                            */
+    int32_t batch;         /* training batch: 32, 64, 128, 256, 512 or 1024        */
+    int32_t train_steps;   /* Adam steps per generation, >= 0                      */
+    int32_t warmup_gens;   /* full generations before screening starts, >= 0       */
+    int32_t buffer;        /* ring buffer capacity in pairs, >= batch             */
+    int32_t fallback_gens; /* consecutive low-correlation generations that trigger
+                              one full generation; 0 never                        */
+    float lr;              /* Adam step size, > 0                                  */
+    float min_rho;         /* judge threshold                                     */
+    uint32_t flags;        /* 0 or GAPA_SCREEN_RANDOM                              */
+    int32_t reserved;      /* 0                                                   */
+} gapa_surrogate_params;
+
+/* Attaches a surrogate to a GA at generation 0 (one instance, offspring <=
+ * 8192, n * 64 embeddings and a buffer of `buffer` rows of k genes in device
+ * memory).  Later gapa_generation_step calls run screened generations
+ * (eagerly: GAPA_GRAPH_REPLAY does not apply). */
+GAPA_API int gapa_surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, void *stream);
+
+typedef struct gapa_surrogate_report {
+    int64_t generation;  /* generation the figures belong to                      */
+    int32_t evaluated;   /* children evaluated exactly in it                       */
+    int32_t screened;    /* 1 if it was screened, 0 if every child was evaluated  */
+    double spearman;     /* judge correlation (0 when no prediction was made)     */
+    double rel_err;      /* mean |expm1(prediction) - PC| / max(PC, 1)             */
+    double loss;         /* mean squared error of its last training step          */
+    int32_t fallbacks;   /* full generations forced by the judge so far            */
+    int32_t train_steps; /* Adam steps taken so far                               */
+} gapa_surrogate_report;
+
+/* Figures of the last generation (host pointer; waits for the GA's work). */
+GAPA_API int gapa_surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out);
+
+/* Children evaluated exactly in the last generation, ascending (host; waits):
+ * up to `cap` indices into pool_out, the number through *count. */
+GAPA_API int gapa_surrogate_last_pool(gapa_ga *ga, int32_t *pool_out, int32_t cap, int32_t *count);
+
+/* Predictions made in the last generation for all of its children, in child
+ * order (0 entries when that generation made none: warm-up, or random
+ * screening); host pointer, waits.  They precede that generation's training. */
+GAPA_API int gapa_surrogate_last_predictions(gapa_ga *ga, float *yhat_out, int32_t cap, int32_t *count);
+
+/* Predictions (standardised scale) of the current model for P gene rows:
+ * genes int32 [P][k] and yhat float [P], device pointers, enqueued on
+ * `stream`.  Genes must be node ids in [0, n) (not checked). */
+GAPA_API int gapa_surrogate_predict(gapa_ga *ga, const int32_t *genes, int32_t P, float *yhat, void *stream);
+
+/* One Adam step on an explicit batch: genes int32 [B][k] (rows of distinct
+ * node ids), target float [B] (standardised labels), device pointers, B a
+ * supported batch size.  With keep_grads the step's gradients are kept for
+ * gapa_surrogate_tensor(kind 1). */
+GAPA_API int gapa_surrogate_train_batch(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B,
+                                        int32_t keep_grads, void *stream);
+
+/* Copies a tensor between the model and host memory: which 0 E [n][64],
+ * 1 W1 [256][64], 2 b1 [256], 3 W2 [256][256], 4 b2 [256], 5 w3 [256], 6 b3 [1];
+ * kind 0 the FP32 weights, 1 the last kept gradient; set = 1 writes the
+ * weights (kind 0 only; the bfloat16 copies follow).  count must equal the
+ * tensor's size.  Waits for the GA's work. */
+GAPA_API int gapa_surrogate_tensor(gapa_ga *ga, int32_t which, int32_t kind, float *host, int64_t count,
+                                   int32_t set);
+
+/* ---------------------------------------------------------------------------
  * Batch of independent GAs (Section III-D runs several GA processes side by
  * side in its M and MNM modes; here many independent instances share each
  * device pass instead).

@@ -118,12 +118,12 @@ def loss_and_grads(p: dict, sets: np.ndarray, target: np.ndarray, bf16_ops: bool
     dz2 = np.outer(dy, r(p["w3"])) * (f["z2"] > 0)
     dz2b = r(dz2)
     g["W2"] = dz2b.T @ f["h1"]
-    g["b2"] = dz2.sum(axis=0)
+    g["b2"] = dz2b.sum(axis=0)
     dh1 = dz2b @ r(p["W2"])
     dz1 = dh1 * (f["z1"] > 0)
     dz1b = r(dz1)
     g["W1"] = dz1b.T @ f["x"]
-    g["b1"] = dz1.sum(axis=0)
+    g["b1"] = dz1b.sum(axis=0)
     dx = dz1b @ r(p["W1"])
     dE = np.zeros_like(p["E"])
     np.add.at(dE, np.asarray(sets, dtype=np.int64).ravel(), np.repeat(dx, sets.shape[1], axis=0))

@@ -700,6 +700,11 @@ int capture_generation(gapa_ga *ga, int c)
 int ga_run(gapa_ga *ga, int32_t n_generations, hipStream_t s)
 {
     for (int32_t i = 0; i < n_generations; ++i) {
+        if (ga->surr) {
+            const int rc = surrogate_generation(ga, s);
+            if (rc != GAPA_OK) return rc;
+            continue;
+        }
         if (!(ga->use_graph && ga->warm && ga->timer.level == 0)) {
             const int rc = ga_generation(ga, s);
             if (rc != GAPA_OK) return rc;
@@ -779,6 +784,8 @@ void ga_release(gapa_ga *ga)
 {
     (void)hipDeviceSynchronize();
     release_graphs(ga);
+    surrogate_release(ga->surr);
+    ga->surr = nullptr;
     if (ga->cap_stream) (void)hipStreamDestroy(ga->cap_stream);
     ga->cap_stream = nullptr;
     for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit, &ga->masks,
@@ -896,6 +903,114 @@ int gapa_ga_kernel_times(gapa_ga *ga, gapa_kernel_time *out, int32_t cap, int32_
 {
     if (!ga) return GAPA_E_INVALID_ARG;
     return ga_collect_times(ga, out, cap, count);
+}
+
+// --------------------------------------------------------------- surrogate ---
+
+static int surr_check(gapa_ga *ga)
+{
+    g_last_error.clear();
+    if (!ga) {
+        set_error("GA is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (ga->failed) {
+        set_error("GA handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    if (!ga->surr) {
+        set_error("no surrogate attached");
+        return GAPA_E_STATE;
+    }
+    return GAPA_OK;
+}
+
+int gapa_surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, void *stream)
+{
+    g_last_error.clear();
+    if (!ga || !sp) {
+        set_error("NULL argument");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (ga->failed) {
+        set_error("GA handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    DeviceGuard dg(ga->graph->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (s != ga->last_stream) {
+        hipError_t e = hipStreamSynchronize(ga->last_stream);
+        if (e != hipSuccess) return fail_handle(&ga->failed, hip_fail(e, "hipStreamSynchronize"));
+        ga->last_stream = s;
+    }
+    const int rc = surrogate_attach(ga, sp, s);
+    if (rc != GAPA_OK && ga->surr) {
+        (void)hipDeviceSynchronize();
+        surrogate_release(ga->surr);
+        ga->surr = nullptr;
+    }
+    return rc == GAPA_E_DEVICE ? fail_handle(&ga->failed, rc) : rc;
+}
+
+int gapa_surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out)
+{
+    int rc = surr_check(ga);
+    if (rc != GAPA_OK) return rc;
+    if (!out) return GAPA_E_INVALID_ARG;
+    DeviceGuard dg(ga->graph->device);
+    return fail_handle(&ga->failed, surrogate_stats(ga, out));
+}
+
+int gapa_surrogate_last_pool(gapa_ga *ga, int32_t *pool_out, int32_t cap, int32_t *count)
+{
+    int rc = surr_check(ga);
+    if (rc != GAPA_OK) return rc;
+    if (cap < 0) return GAPA_E_INVALID_ARG;
+    DeviceGuard dg(ga->graph->device);
+    return fail_handle(&ga->failed, surrogate_last_pool(ga, pool_out, cap, count));
+}
+
+int gapa_surrogate_last_predictions(gapa_ga *ga, float *yhat_out, int32_t cap, int32_t *count)
+{
+    int rc = surr_check(ga);
+    if (rc != GAPA_OK) return rc;
+    if (cap < 0) return GAPA_E_INVALID_ARG;
+    DeviceGuard dg(ga->graph->device);
+    return fail_handle(&ga->failed, surrogate_last_predictions(ga, yhat_out, cap, count));
+}
+
+int gapa_surrogate_predict(gapa_ga *ga, const int32_t *genes, int32_t P, float *yhat, void *stream)
+{
+    int rc = surr_check(ga);
+    if (rc != GAPA_OK) return rc;
+    if (P < 0 || (P > 0 && (!genes || !yhat))) {
+        set_error("invalid arguments");
+        return GAPA_E_INVALID_ARG;
+    }
+    DeviceGuard dg(ga->graph->device);
+    return fail_handle(&ga->failed, surrogate_predict(ga, genes, P, yhat, static_cast<hipStream_t>(stream)));
+}
+
+int gapa_surrogate_train_batch(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B, int32_t keep_grads,
+                               void *stream)
+{
+    int rc = surr_check(ga);
+    if (rc != GAPA_OK) return rc;
+    if (!genes || !target) {
+        set_error("invalid arguments");
+        return GAPA_E_INVALID_ARG;
+    }
+    DeviceGuard dg(ga->graph->device);
+    return fail_handle(&ga->failed,
+                       surrogate_train_batch(ga, genes, target, B, keep_grads != 0, static_cast<hipStream_t>(stream)));
+}
+
+int gapa_surrogate_tensor(gapa_ga *ga, int32_t which, int32_t kind, float *host, int64_t count, int32_t set)
+{
+    int rc = surr_check(ga);
+    if (rc != GAPA_OK) return rc;
+    DeviceGuard dg(ga->graph->device);
+    return fail_handle(&ga->failed, surrogate_tensor(ga, which, kind, host, count, set != 0));
 }
 
 // ------------------------------------------------------------------- batch ---

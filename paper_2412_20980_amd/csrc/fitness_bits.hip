@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restr
     const int32_t rows = min(32 * kTileWords, nb - j0 * 32);
     for (int32_t x = threadIdx.x; x < (rows << log_wd); x += blockDim.x) {
         dead[v0 * Wd + x] = tile[(x >> log_wd) * Wo + (x & (Wd - 1))];
-        reach[v0 * Wd + x] = 0u;
+        if (reach) reach[v0 * Wd + x] = 0u;
     }
 }
 
@@ -603,6 +603,18 @@ __global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, in
 }
 
 }  // namespace
+
+int launch_bits_transpose(const uint32_t *masks, int32_t P, int32_t W, int32_t n, uint32_t *rows, hipStream_t s)
+{
+    int32_t Wd = P / 32, log_wd = 0;
+    if (P % 32 != 0 || Wd < 1 || Wd > 32 || (Wd & (Wd - 1)) != 0) return GAPA_E_INVALID_ARG;
+    while ((1 << log_wd) < Wd) ++log_wd;
+    const Insts I{1, P, n, P, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipLaunchKernelGGL(k_dead_transpose, dim3((W + kTileWords - 1) / kTileWords), dim3(kBlk), 0, s, masks, I, log_wd,
+                       rows, nullptr);
+    GAPA_HIP(hipGetLastError());
+    return GAPA_OK;
+}
 
 int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
                     int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it)

@@ -156,6 +156,11 @@ int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_
 int eval_genes(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int64_t *fitness, int32_t *mcn,
                int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
 
+// Removed-node bit sets masks[P][W] of P = 32 Wd individuals (Wd a power of
+// two <= 32) to node-major rows rows[n][Wd]: bit i of row v is set when
+// individual i removes v.
+int launch_bits_transpose(const uint32_t *masks, int32_t P, int32_t W, int32_t n, uint32_t *rows, hipStream_t s);
+
 // Fills count 32-bit words at p with value (a kernel, not a memset node).
 int launch_fill_u32(void *p, uint32_t value, int64_t count, hipStream_t s);
 
@@ -199,6 +204,22 @@ int ga_launch_offspring(gapa_ga *ga, hipStream_t s);
 // device generation counter.
 int ga_rank_and_gather(gapa_ga *ga, bool init, const int64_t *f_pool, const int32_t *pool, int32_t npool,
                        hipStream_t s);
+
+// ------------------------------------------------------------ surrogate -----
+
+struct SurrogateState;
+// Allocates and initialises the learned screening model of a one-instance GA.
+int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s);
+void surrogate_release(SurrogateState *st);
+// One generation with screening (or a full one during warm-up / fallback).
+int surrogate_generation(gapa_ga *ga, hipStream_t s);
+int surrogate_predict(gapa_ga *ga, const int32_t *genes, int32_t P, float *yhat, hipStream_t s);
+int surrogate_train_batch(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B, bool keep_grads,
+                          hipStream_t s);
+int surrogate_tensor(gapa_ga *ga, int32_t which, int32_t kind, float *host, int64_t count, bool set);
+int surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out);
+int surrogate_last_pool(gapa_ga *ga, int32_t *pool, int32_t cap, int32_t *count);
+int surrogate_last_predictions(gapa_ga *ga, float *yhat, int32_t cap, int32_t *count);
 
 // Error reporting for HIP calls.
 int hip_fail(hipError_t e, const char *what);
@@ -247,6 +268,7 @@ struct gapa_ga {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graphs[2] = {nullptr, nullptr};
     hipGraphExec_t execs[2] = {nullptr, nullptr};
+    gapa::SurrogateState *surr = nullptr;  // learned screening, when attached
 };
 
 struct gapa_batch {

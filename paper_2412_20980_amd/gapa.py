@@ -40,6 +40,8 @@ GAPA_TRUST_INPUT = 1 << 1
 GAPA_WANT_MCN = 1 << 2
 GAPA_UNIONFIND = 1 << 3
 GAPA_GRAPH_REPLAY = 1 << 4
+GAPA_SCREEN_RANDOM = 1 << 0
+SURROGATE_TENSORS = ("E", "W1", "b1", "W2", "b2", "w3", "b3")
 
 EXPORTED = (
     "gapa_graph_create", "gapa_graph_destroy", "gapa_eval_population",
@@ -48,6 +50,8 @@ EXPORTED = (
     "gapa_graph_fitness_stats", "gapa_ga_fitness_stats", "gapa_last_error", "gapa_version",
     "gapa_batch_create", "gapa_batch_step", "gapa_batch_best", "gapa_batch_get_population",
     "gapa_batch_set_timing", "gapa_batch_kernel_times", "gapa_batch_destroy",
+    "gapa_surrogate_attach", "gapa_surrogate_stats", "gapa_surrogate_last_pool", "gapa_surrogate_predict",
+    "gapa_surrogate_train_batch", "gapa_surrogate_tensor", "gapa_surrogate_last_predictions",
 )
 
 
@@ -62,6 +66,21 @@ class gapa_params(C.Structure):
         ("k", C.c_int32), ("pop", C.c_int32), ("tournament", C.c_int32), ("offspring", C.c_int32),
         ("seed", C.c_uint64), ("pc", C.c_double), ("pm", C.c_double),
         ("flags", C.c_uint32), ("reserved", C.c_int32),
+    ]
+
+
+class gapa_surrogate_params(C.Structure):
+    _fields_ = [
+        ("emb_dim", C.c_int32), ("hidden", C.c_int32), ("screen", C.c_int32), ("batch", C.c_int32),
+        ("train_steps", C.c_int32), ("warmup_gens", C.c_int32), ("buffer", C.c_int32), ("fallback_gens", C.c_int32),
+        ("lr", C.c_float), ("min_rho", C.c_float), ("flags", C.c_uint32), ("reserved", C.c_int32),
+    ]
+
+
+class gapa_surrogate_report(C.Structure):
+    _fields_ = [
+        ("generation", C.c_int64), ("evaluated", C.c_int32), ("screened", C.c_int32), ("spearman", C.c_double),
+        ("rel_err", C.c_double), ("loss", C.c_double), ("fallbacks", C.c_int32), ("train_steps", C.c_int32),
     ]
 
 
@@ -93,6 +112,13 @@ def lib() -> C.CDLL:
     L.gapa_batch_best.argtypes = [vp, C.c_int32, vp, i64p, i64p]
     L.gapa_batch_get_population.argtypes = [vp, C.c_int32, vp, vp]
     L.gapa_batch_destroy.argtypes = [vp]
+    L.gapa_surrogate_attach.argtypes = [vp, C.POINTER(gapa_surrogate_params), vp]
+    L.gapa_surrogate_stats.argtypes = [vp, C.POINTER(gapa_surrogate_report)]
+    L.gapa_surrogate_last_pool.argtypes = [vp, vp, C.c_int32, i32p]
+    L.gapa_surrogate_predict.argtypes = [vp, vp, C.c_int32, vp, vp]
+    L.gapa_surrogate_last_predictions.argtypes = [vp, vp, C.c_int32, i32p]
+    L.gapa_surrogate_train_batch.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp]
+    L.gapa_surrogate_tensor.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int64, C.c_int32]
     for f in (L.gapa_graph_set_timing, L.gapa_ga_set_timing, L.gapa_batch_set_timing):
         f.argtypes = [vp, C.c_int32]
     for f in (L.gapa_graph_kernel_times, L.gapa_ga_kernel_times, L.gapa_batch_kernel_times):
@@ -288,6 +314,63 @@ class GA:
 
     def fitness_stats(self) -> dict:
         return _fitness_stats(lib().gapa_ga_fitness_stats, self.handle)
+
+    # --- learned screening surrogate ---
+    def attach_surrogate(self, screen: int, batch: int = 1024, train_steps: int = 4, warmup_gens: int = 10,
+                         buffer: int = 65536, fallback_gens: int = 3, lr: float = 1e-3, min_rho: float = 0.3,
+                         random_screen: bool = False, stream=None):
+        sp = gapa_surrogate_params(emb_dim=64, hidden=256, screen=screen, batch=batch, train_steps=train_steps,
+                                   warmup_gens=warmup_gens, buffer=buffer, fallback_gens=fallback_gens, lr=lr,
+                                   min_rho=min_rho, flags=GAPA_SCREEN_RANDOM if random_screen else 0, reserved=0)
+        _check(lib().gapa_surrogate_attach(self.handle, C.byref(sp), _stream_ptr(stream)))
+
+    def surrogate_stats(self) -> dict:
+        r = gapa_surrogate_report()
+        _check(lib().gapa_surrogate_stats(self.handle, C.byref(r)))
+        return {f: getattr(r, f) for f, _ in r._fields_}
+
+    def last_pool(self) -> np.ndarray:
+        cnt = C.c_int32(0)
+        _check(lib().gapa_surrogate_last_pool(self.handle, None, 0, C.byref(cnt)))
+        out = np.zeros(cnt.value, dtype=np.int32)
+        if cnt.value:
+            _check(lib().gapa_surrogate_last_pool(self.handle, out.ctypes.data, cnt.value, C.byref(cnt)))
+        return out
+
+    def last_predictions(self) -> np.ndarray:
+        cnt = C.c_int32(0)
+        _check(lib().gapa_surrogate_last_predictions(self.handle, None, 0, C.byref(cnt)))
+        out = np.zeros(cnt.value, dtype=np.float32)
+        if cnt.value:
+            _check(lib().gapa_surrogate_last_predictions(self.handle, out.ctypes.data, cnt.value, C.byref(cnt)))
+        return out
+
+    def predict(self, genes, stream=None):
+        """genes: torch int32 CUDA tensor [P, k]; returns float32 predictions."""
+        assert _is_dev_tensor(genes) and genes.dtype == torch.int32 and genes.is_contiguous()
+        y = torch.empty(genes.shape[0], dtype=torch.float32, device=genes.device)
+        _check(lib().gapa_surrogate_predict(self.handle, genes.data_ptr(), genes.shape[0], y.data_ptr(),
+                                            _stream_ptr(stream)))
+        return y
+
+    def train_batch(self, genes, target, keep_grads: bool = True, stream=None):
+        assert _is_dev_tensor(genes) and _is_dev_tensor(target)
+        _check(lib().gapa_surrogate_train_batch(self.handle, genes.data_ptr(), target.data_ptr(), genes.shape[0],
+                                                int(keep_grads), _stream_ptr(stream)))
+
+    def surrogate_tensor(self, name: str, grad: bool = False, n: int | None = None) -> np.ndarray:
+        which = SURROGATE_TENSORS.index(name)
+        n = self.graph.n if n is None else n
+        shape = {"E": (n, 64), "W1": (256, 64), "b1": (256,), "W2": (256, 256), "b2": (256,), "w3": (256,),
+                 "b3": (1,)}[name]
+        out = np.zeros(shape, dtype=np.float32)
+        _check(lib().gapa_surrogate_tensor(self.handle, which, int(grad), out.ctypes.data, out.size, 0))
+        return out
+
+    def set_surrogate_tensor(self, name: str, value):
+        which = SURROGATE_TENSORS.index(name)
+        arr = np.ascontiguousarray(value, dtype=np.float32)
+        _check(lib().gapa_surrogate_tensor(self.handle, which, 0, arr.ctypes.data, arr.size, 1))
 
     def close(self):
         if self.handle:

@@ -1,0 +1,211 @@
+"""Learned screening surrogate on the GPU, through the C ABI, against the
+surrogate oracle.
+
+Integer work is exact: initial weights (Philox, float32) bit for bit;
+screening decisions equal the oracle's selection applied to the device's own
+float32 predictions; the GA trajectory equals the oracle's replay given the
+device's screened indices, generation by generation.  Floating-point work is
+compared at tolerances: the forward pass and the gradients against the
+oracle computing with the same bfloat16 operand roundings in float64 (the
+remaining differences are float32 accumulation order and the rare bfloat16
+rounding that flips because of it), one Adam step against the oracle's
+formula on the device's gradients.  A last test shows what the trained
+network gains over random screening at the same exact-evaluation budget."""
+import numpy as np
+import pytest
+
+from oracle import cnd_oracle as O
+from oracle import surrogate_oracle as S
+from paper_2412_20980_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2412_20980_amd import gapa
+    return gapa
+
+
+def make_ga(gp, g, k=20, pop=32, seed=7, lam=128, **surr):
+    graph = gp.Graph.from_csr(g)
+    ga = gp.GA(graph, k, pop, seed, 0.7, 0.05, 2, lam)
+    opts = dict(screen=32, batch=64, train_steps=2, warmup_gens=2, buffer=4096, fallback_gens=3)
+    opts.update(surr)
+    ga.attach_surrogate(**opts)
+    return graph, ga
+
+
+def weights(ga, n):
+    return {name: ga.surrogate_tensor(name, n=n).astype(np.float64) for name in S.TENSORS}
+
+
+def test_initial_weights_bit_exact(gp):
+    g = inputs.barabasi_albert(700, 3, seed=1)
+    _, ga = make_ga(gp, g, seed=(1 << 33) + 5)
+    ref = S.init_params((1 << 33) + 5, g.n)
+    got = weights(ga, g.n)
+    for name in S.TENSORS:
+        assert np.array_equal(got[name], ref[name]), name
+
+
+def random_weights(rng, n):
+    # float32 values with the scale of a trained model, biases non-zero
+    return {"E": rng.normal(0, 0.05, (n, 64)), "W1": rng.normal(0, 0.2, (256, 64)), "b1": rng.normal(0, 0.1, 256),
+            "W2": rng.normal(0, 0.08, (256, 256)), "b2": rng.normal(0, 0.1, 256), "w3": rng.normal(0, 0.1, 256),
+            "b3": rng.normal(0, 0.5, 1)}
+
+
+def set_weights(ga, p):
+    for name in S.TENSORS:
+        ga.set_surrogate_tensor(name, p[name])
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+
+
+@pytest.mark.parametrize("P", [1, 63, 200])
+def test_forward_matches_oracle(gp, P):
+    import torch
+    g = inputs.barabasi_albert(900, 3, seed=2)
+    _, ga = make_ga(gp, g)
+    p = set_weights(ga, random_weights(np.random.default_rng(P), g.n))
+    sets = inputs.random_population(g.n, 20, P, seed=P)
+    y = ga.predict(torch.from_numpy(sets).cuda()).cpu().numpy().astype(np.float64)
+    ref_b = S.forward(p, sets, bf16_ops=True)["yhat"]
+    ref = S.forward(p, sets)["yhat"]
+    scale = 1.0 + np.max(np.abs(ref_b))
+    assert np.max(np.abs(y - ref_b)) <= 2e-3 * scale
+    assert np.max(np.abs(y - ref)) <= 3e-2 * scale
+
+
+def test_gradients_match_oracle(gp):
+    import torch
+    g = inputs.barabasi_albert(900, 3, seed=3)
+    _, ga = make_ga(gp, g, batch=64)
+    p = set_weights(ga, random_weights(np.random.default_rng(5), g.n))
+    sets = inputs.random_population(g.n, 20, 64, seed=9)
+    target = np.random.default_rng(6).normal(size=64).astype(np.float32)
+    ga.train_batch(torch.from_numpy(sets).cuda(), torch.from_numpy(target).cuda(), keep_grads=True)
+    _, ref, _ = S.loss_and_grads(p, sets, target.astype(np.float64), bf16_ops=True)
+    for name in S.TENSORS:
+        got = ga.surrogate_tensor(name, grad=True, n=g.n).astype(np.float64)
+        nr = np.linalg.norm(ref[name])
+        assert np.linalg.norm(got - ref[name]) <= 5e-3 * nr + 1e-9, name
+    # rows of E outside every set get no gradient
+    used = np.zeros(g.n, bool)
+    used[sets.ravel()] = True
+    assert not ga.surrogate_tensor("E", grad=True, n=g.n)[~used].any()
+
+
+def test_adam_step_matches_formula(gp):
+    import torch
+    g = inputs.barabasi_albert(600, 3, seed=4)
+    _, ga = make_ga(gp, g, batch=32)
+    p = set_weights(ga, random_weights(np.random.default_rng(8), g.n))
+    sets = inputs.random_population(g.n, 15, 32, seed=3)
+    target = np.linspace(-1, 1, 32).astype(np.float32)
+    ga.train_batch(torch.from_numpy(sets).cuda(), torch.from_numpy(target).cuda(), keep_grads=True)
+    grads = {name: ga.surrogate_tensor(name, grad=True, n=g.n).astype(np.float64) for name in S.TENSORS}
+    q = {k: v.copy() for k, v in p.items()}
+    S.Adam(q, lr=1e-3).step(q, grads)
+    got = weights(ga, g.n)
+    for name in S.TENSORS:
+        assert np.max(np.abs(got[name] - q[name])) <= 2e-6, name
+
+
+def run_replayed(gp, g, gens, **kw):
+    """Device GA with a surrogate next to the oracle replaying its screening
+    decisions; checks the screening and the state every generation."""
+    lam, k, pop, seed = kw.pop("lam", 128), kw.pop("k", 20), kw.pop("pop", 32), kw.pop("seed", 7)
+    _, ga = make_ga(gp, g, k=k, pop=pop, seed=seed, lam=lam, **kw)
+    opts = dict(screen=32, batch=64, train_steps=2, warmup_gens=2, buffer=4096)
+    opts.update({k2: v for k2, v in kw.items() if k2 in opts})
+    sga = S.SurrogateGA(g, k, pop, seed, lam, batch=opts["batch"], steps=opts["train_steps"],
+                        warmup=opts["warmup_gens"], buffer=opts["buffer"], bf16_ops=True)
+    screened = 0
+    for gen in range(1, gens + 1):
+        ga.step(1)
+        st = ga.surrogate_stats()
+        pool = ga.last_pool()
+        assert st["generation"] == gen and st["evaluated"] == len(pool)
+        if st["screened"]:
+            screened += 1
+            yhat = ga.last_predictions()
+            assert len(yhat) == lam
+            # the selection is exact given the device's float32 predictions
+            assert np.array_equal(pool, S.screen(yhat.astype(np.float64), opts["screen"]))
+        else:
+            assert np.array_equal(pool, np.arange(lam))
+        sga.step(pool)
+        pop_d, F_d = ga.population()
+        assert np.array_equal(F_d, sga.ga.F), f"fitness differs at generation {gen}"
+        assert np.array_equal(pop_d, sga.ga.pop), f"population differs at generation {gen}"
+    return ga, sga, screened
+
+
+def test_screened_trajectory_replays_exactly(gp):
+    g = inputs.barabasi_albert(1500, 3, seed=5)
+    ga, sga, screened = run_replayed(gp, g, 8)
+    assert screened == 6
+    st = ga.surrogate_stats()
+    assert st["train_steps"] == 16
+    # the device model and the oracle's float64 replay of its training stay close
+    got, ref = weights(ga, g.n), sga.params
+    for name in ("W1", "W2", "w3"):
+        assert np.linalg.norm(got[name] - ref[name]) <= 2e-2 * np.linalg.norm(ref[name]), name
+
+
+def test_fallback_to_full_generations(gp):
+    """An unreachable correlation threshold forces a full generation after
+    every screened one."""
+    g = inputs.erdos_renyi(1200, 4.0, seed=6)
+    ga, _, screened = run_replayed(gp, g, 7, min_rho=2.0, fallback_gens=1, warmup_gens=1)
+    st = ga.surrogate_stats()
+    assert screened == 3 and st["fallbacks"] == 3
+
+
+def test_attach_rejects_bad_parameters(gp, ba200):
+    graph = gp.Graph.from_csr(ba200)
+    ga = gp.GA(graph, 10, 16, 1, offspring=64)
+    for bad in (dict(screen=0), dict(screen=65), dict(batch=48), dict(batch=2048), dict(buffer=16), dict(lr=0.0)):
+        opts = dict(screen=16, batch=32, buffer=256)
+        opts.update(bad)
+        with pytest.raises(gp.GapaError) as e:
+            ga.attach_surrogate(**opts)
+        assert e.value.code == gp.GAPA_E_INVALID_ARG, bad
+    ga.step(1)
+    with pytest.raises(gp.GapaError):
+        ga.attach_surrogate(screen=16, batch=32, buffer=256)  # not at generation 0
+    ga2 = gp.GA(graph, 10, 16, 1, offspring=64)
+    with pytest.raises(gp.GapaError) as e:
+        ga2.surrogate_stats()
+    assert e.value.code == gp.GAPA_E_STATE
+
+
+def best_after(gp, g, gens, seed, random_screen):
+    graph = gp.Graph.from_csr(g, trust=True)
+    ga = gp.GA(graph, 100, 128, seed, 0.7, 0.05, 2, 1024)
+    ga.attach_surrogate(screen=128, batch=256, train_steps=4, warmup_gens=5, buffer=16384, fallback_gens=0,
+                        random_screen=random_screen)
+    ga.step(gens)
+    rho = ga.surrogate_stats()["spearman"]
+    return ga.best()[1], rho
+
+
+def test_trained_screening_beats_random_screening(gp):
+    """Same seeds, same operators, the same number of exact evaluations per
+    generation (128 of 1024 children): screening by the trained network must
+    reach a lower pairwise connectivity than screening at random, and its
+    predictions must rank the evaluated children (positive correlation)."""
+    g = inputs.chung_lu(20000, 2.5, 10.0, 100_000, seed=7)
+    wins, rhos = 0, []
+    for seed in (1, 2, 3):
+        print(f"surrogate vs random, seed {seed}", flush=True)
+        f_s, rho = best_after(gp, g, 40, seed, False)
+        f_r, _ = best_after(gp, g, 40, seed, True)
+        print(f"  best PC surrogate {f_s} random {f_r} rho {rho:.3f}", flush=True)
+        wins += f_s < f_r
+        rhos.append(rho)
+    assert wins >= 2
+    assert np.mean(rhos) > 0.3
