@@ -170,7 +170,7 @@ GAPA_API int gapa_ga_destroy(gapa_ga *ga);
  * FP32 master weights, bfloat16 copies for the products (matrix-core
  * kernels, FP32 accumulation).  Trained online on (S, ln(1 + PC(S))) pairs of
  * the exactly evaluated offspring, kept in a ring buffer: labels are
- * standardised by the buffer's mean and standard deviation; mean squared
+ * standardised by the buffer's mean and spread sqrt(variance + 1e-12); mean squared
  * error; Adam (Kingma and Ba 2015) with beta = (0.9, 0.999), eps = 1e-8;
  * `train_steps` steps per generation on batches drawn with Philox stream 6
  * (slot j, individual step, generation).  Initial weights from Philox stream
@@ -178,9 +178,11 @@ GAPA_API int gapa_ga_destroy(gapa_ga *ga);
  * +-sqrt(3 / fan_in), biases 0.
  *
  * Generations 1..warmup_gens evaluate every child (and train).  Later
- * generations screen; the Spearman correlation between predictions and exact
- * fitness over the evaluated children (at most 1024 of them, evenly spaced)
- * is the judge: after `fallback_gens` consecutive screened generations with
+ * generations screen; a screened generation also evaluates min(32, offspring
+ * - screen) of the other children, drawn uniformly with Philox stream 7, for
+ * the judge only (they join the training buffer, not elitism).  The judge is
+ * the Spearman correlation between predictions and exact fitness over the
+ * evaluated children (at most 1024 of them, evenly spaced): after `fallback_gens` consecutive screened generations with
  * a correlation below min_rho, the next generation evaluates every child.
  * ------------------------------------------------------------------------- */
 enum {
@@ -215,7 +217,9 @@ GAPA_API int gapa_surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp,
 typedef struct gapa_surrogate_report {
     int64_t generation;  /* generation the figures belong to                      */
     int32_t evaluated;   /* children evaluated exactly in it                       */
+    int32_t pooled;      /* of which entered elitism                              */
     int32_t screened;    /* 1 if it was screened, 0 if every child was evaluated  */
+    int32_t reserved;
     double spearman;     /* judge correlation (0 when no prediction was made)     */
     double rel_err;      /* mean |expm1(prediction) - PC| / max(PC, 1)             */
     double loss;         /* mean squared error of its last training step          */
@@ -226,8 +230,9 @@ typedef struct gapa_surrogate_report {
 /* Figures of the last generation (host pointer; waits for the GA's work). */
 GAPA_API int gapa_surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out);
 
-/* Children evaluated exactly in the last generation, ascending (host; waits):
- * up to `cap` indices into pool_out, the number through *count. */
+/* Children evaluated exactly in the last generation (host; waits): the pooled
+ * ones ascending, then the judge's extra sample ascending; up to `cap`
+ * indices into pool_out, the number through *count. */
 GAPA_API int gapa_surrogate_last_pool(gapa_ga *ga, int32_t *pool_out, int32_t cap, int32_t *count);
 
 /* Predictions made in the last generation for all of its children, in child
@@ -317,6 +322,34 @@ GAPA_API int gapa_batch_kernel_times(gapa_batch *b, gapa_kernel_time *out, int32
  * something.  All zero before the first evaluation. */
 GAPA_API int gapa_graph_fitness_stats(gapa_graph *g, int64_t out[4]);
 GAPA_API int gapa_ga_fitness_stats(gapa_ga *ga, int64_t out[4]);
+
+/* Launch shapes of the bit-parallel fitness pass.  They change speed only:
+ * results never depend on them.
+ *   sweep_grid   blocks of the worklist, pair and union-find kernels, 1..65535
+ *   band_scan    neighbours a node reads in the ordered sweep, >= 1
+ *   sweeps       follow-up sweeps over the nodes still pending, 0..32
+ *   band_blocks  block cap of one band launch, 1..65535
+ * Defaults 4096, 64, 4, 8192.  A change also applies to GAs and batches on
+ * the graph (recorded generations are re-recorded). */
+typedef struct gapa_tuning {
+    int32_t sweep_grid;
+    int32_t band_scan;
+    int32_t sweeps;
+    int32_t band_blocks;
+} gapa_tuning;
+
+GAPA_API int gapa_graph_get_tuning(gapa_graph *g, gapa_tuning *out);
+GAPA_API int gapa_graph_set_tuning(gapa_graph *g, const gapa_tuning *t);
+
+/* Autotuner: times `reps` >= 1 fitness passes over the children the GA (or
+ * batch) currently holds for each launch shape of a fixed candidate grid
+ * (sweep_grid 2048/4096/8192, band_scan 32/64/128, sweeps 3/4/6, band_blocks
+ * 4096/16384), keeps the fastest on the evaluating graph and returns it
+ * through best_out (may be NULL).  Work is enqueued on `stream` and waited
+ * for.  It overwrites only scratch fitness values; the GA state is
+ * untouched. */
+GAPA_API int gapa_ga_autotune(gapa_ga *ga, int32_t reps, void *stream, gapa_tuning *best_out);
+GAPA_API int gapa_batch_autotune(gapa_batch *b, int32_t reps, void *stream, gapa_tuning *best_out);
 
 /* Message of the last failed call on this thread ("" if none). */
 GAPA_API const char *gapa_last_error(void);

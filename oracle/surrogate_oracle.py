@@ -161,12 +161,17 @@ def label(F) -> np.ndarray:
     return np.log1p(np.asarray(F, dtype=np.float64))
 
 
+SPREAD_FLOOR = 1e-6
+
+
 def standardise(labels: np.ndarray):
-    """Mean and (population) standard deviation of the buffered labels; a
-    zero spread gives 1."""
+    """Mean and spread of the buffered labels: sqrt(variance + 1e-12), the
+    population variance floored so that a buffer of (nearly) equal labels
+    gives targets near zero instead of amplified rounding noise (1e-6 in
+    ln(1 + PC) is far below the differences that rank individuals)."""
     mu = float(np.mean(labels))
-    sd = float(np.sqrt(np.mean((labels - mu) ** 2)))
-    return mu, (sd if sd > 0.0 else 1.0)
+    var = float(np.mean((labels - mu) ** 2))
+    return mu, math.sqrt(var + SPREAD_FLOOR ** 2)
 
 
 def screen(yhat: np.ndarray, m: int) -> np.ndarray:
@@ -252,7 +257,10 @@ class SurrogateGA:
             self.losses.append(loss)
         return mu, sd
 
-    def step(self, pool=None):
+    def step(self, pool=None, extra=None):
+        """One generation.  pool: the children that enter elitism (all during
+        warm-up or when None); extra: children evaluated for the judge only
+        (they join the buffer after the pool)."""
         gen = self.ga.generation + 1
         p = self.ga.params
         if gen <= self.warmup or pool is None:
@@ -260,5 +268,17 @@ class SurrogateGA:
         pool = np.asarray(pool, dtype=np.int32)
         kids, kf = self.ga.step(pool_idx=pool, keep_children=True)
         self.append(kids[pool], kf[pool])
+        if extra is not None and len(extra):
+            extra = np.asarray(extra, dtype=np.int64)
+            self.append(kids[extra], O.eval_population(self.ga.graph, kids[extra]))
         self.train(gen)
         return kids, kf, pool
+
+
+def judge_extra(seed: int, gen: int, lam: int, pool, count: int) -> np.ndarray:
+    """The judge's unbiased sample of a screened generation: the `count`
+    children outside the pool with the smallest (first word of draw(seed, o,
+    1, gen, stream 7), o), ascending."""
+    chosen = set(int(x) for x in pool)
+    keys = [(int(O.draw(seed, o, 1, gen, 7)[0]), o) for o in range(lam) if o not in chosen]
+    return np.sort(np.array([o for _, o in sorted(keys)[:count]], dtype=np.int64))

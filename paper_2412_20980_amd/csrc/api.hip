@@ -2,6 +2,7 @@
 // device buffers, streams, error reporting and kernel timing around the
 // fitness and genetic-operator kernels.
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -699,6 +700,12 @@ int capture_generation(gapa_ga *ga, int c)
 
 int ga_run(gapa_ga *ga, int32_t n_generations, hipStream_t s)
 {
+    if (ga->captured_version != ga->graph->tune_version) {
+        // launch shapes changed: record again, after one eager generation
+        release_graphs(ga);
+        ga->warm = false;
+        ga->captured_version = ga->graph->tune_version;
+    }
     for (int32_t i = 0; i < n_generations; ++i) {
         if (ga->surr) {
             const int rc = surrogate_generation(ga, s);
@@ -903,6 +910,106 @@ int gapa_ga_kernel_times(gapa_ga *ga, gapa_kernel_time *out, int32_t cap, int32_
 {
     if (!ga) return GAPA_E_INVALID_ARG;
     return ga_collect_times(ga, out, cap, count);
+}
+
+// ------------------------------------------------------------------ tuning ---
+
+static bool tuning_ok(const gapa_tuning *t)
+{
+    return t && t->sweep_grid >= 1 && t->sweep_grid <= 65535 && t->band_scan >= 1 && t->sweeps >= 0 &&
+           t->sweeps <= 32 && t->band_blocks >= 1 && t->band_blocks <= 65535;
+}
+
+int gapa_graph_get_tuning(gapa_graph *g, gapa_tuning *out)
+{
+    if (!g || !out) return GAPA_E_INVALID_ARG;
+    out->sweep_grid = g->tune.sweep_grid;
+    out->band_scan = g->tune.band_scan;
+    out->sweeps = g->tune.sweeps;
+    out->band_blocks = g->tune.band_blocks;
+    return GAPA_OK;
+}
+
+int gapa_graph_set_tuning(gapa_graph *g, const gapa_tuning *t)
+{
+    g_last_error.clear();
+    if (!g || !tuning_ok(t)) {
+        set_error("invalid tuning (sweep_grid and band_blocks 1..65535, band_scan >= 1, sweeps 0..32)");
+        return GAPA_E_INVALID_ARG;
+    }
+    DeviceGuard dg(g->device);
+    (void)hipDeviceSynchronize();  // passes in flight keep the shapes they were launched with
+    g->tune.sweep_grid = t->sweep_grid;
+    g->tune.band_scan = t->band_scan;
+    g->tune.sweeps = t->sweeps;
+    g->tune.band_blocks = t->band_blocks;
+    g->tune_version += 1;
+    return GAPA_OK;
+}
+
+int gapa_ga_autotune(gapa_ga *ga, int32_t reps, void *stream, gapa_tuning *best_out)
+{
+    g_last_error.clear();
+    if (!ga || reps < 1) {
+        set_error("invalid arguments");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (ga->failed) {
+        set_error("GA handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    DeviceGuard dg(ga->graph->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    gapa_graph *g = ga->graph;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail_handle(&ga->failed, hip_fail(e, "hipDeviceSynchronize"));
+    const bool init = ga->generation == 0;
+    const Tuning saved = g->tune;
+    Tuning best = saved;
+    double best_t = 1e300;
+    const int32_t grids[3] = {2048, 4096, 8192}, scans[3] = {32, 64, 128}, sweeps[3] = {3, 4, 6};
+    const int32_t bands[2] = {4096, 16384};
+    int rc = GAPA_OK;
+    for (int32_t gi : grids)
+        for (int32_t sc : scans)
+            for (int32_t sw : sweeps)
+                for (int32_t bb : bands) {
+                    g->tune = Tuning{gi, sc, sw, bb};
+                    // one untimed pass sizes the buffers for this shape
+                    rc = ga_eval_children(ga, init, s);
+                    if (rc == GAPA_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = hip_fail(e, "sync");
+                    if (rc != GAPA_OK) {
+                        g->tune = saved;
+                        return fail_handle(&ga->failed, rc);
+                    }
+                    const auto t0 = std::chrono::steady_clock::now();
+                    for (int32_t r = 0; r < reps && rc == GAPA_OK; ++r) rc = ga_eval_children(ga, init, s);
+                    if (rc == GAPA_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = hip_fail(e, "sync");
+                    if (rc != GAPA_OK) {
+                        g->tune = saved;
+                        return fail_handle(&ga->failed, rc);
+                    }
+                    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                    if (t < best_t) {
+                        best_t = t;
+                        best = g->tune;
+                    }
+                }
+    g->tune = best;
+    g->tune_version += 1;
+    if (best_out) {
+        best_out->sweep_grid = best.sweep_grid;
+        best_out->band_scan = best.band_scan;
+        best_out->sweeps = best.sweeps;
+        best_out->band_blocks = best.band_blocks;
+    }
+    return GAPA_OK;
+}
+
+int gapa_batch_autotune(gapa_batch *b, int32_t reps, void *stream, gapa_tuning *best_out)
+{
+    if (!b) return GAPA_E_INVALID_ARG;
+    return gapa_ga_autotune(b->ga, reps, stream, best_out);
 }
 
 // --------------------------------------------------------------- surrogate ---

@@ -32,8 +32,6 @@ namespace gapa {
 namespace {
 
 constexpr int kBlk = 256;
-constexpr int kSweepGrid = 4096;  // blocks of the grid-stride worklist kernels
-constexpr int kSweeps = 4;        // follow-up sweeps over the pending nodes
 
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p)
 {
@@ -237,7 +235,6 @@ __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restr
 // covered or max_scan neighbours have been read.  Returns true if the node
 // gained bits.  Whatever stays pending is picked up by a later sweep or, in
 // the end, by the union-find pass, so the cap only moves work.
-constexpr int kBandScan = 64;  // neighbours read per node in the ordered sweep
 
 __device__ __forceinline__ bool pull_node(int32_t v, int Wd, int w, uint64_t gmask,
                                           const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
@@ -267,7 +264,7 @@ __device__ __forceinline__ bool pull_node(int32_t v, int Wd, int w, uint64_t gma
 // One band of the ordered sweep: nodes band_v[b0, b1).
 __global__ void k_pull_band(const int32_t *__restrict__ band_v, int32_t b0, int32_t b1, int32_t Wd,
                             const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
-                            const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach)
+                            const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach, int32_t max_scan)
 {
     const int lane = threadIdx.x & 63;
     const int w = lane & (Wd - 1);
@@ -283,7 +280,7 @@ __global__ void k_pull_band(const int32_t *__restrict__ band_v, int32_t b0, int3
         const bool valid = idx < count;
         const int32_t v = valid ? band_v[b0 + idx] : 0;
         if (__ballot(valid) == 0) continue;
-        if (valid) pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach, kBandScan);
+        if (valid) pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach, max_scan);
     }
 }
 
@@ -643,13 +640,15 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
     const int64_t max_pairs = (int64_t)B * std::max(g->n_noniso, 1);
     if ((rc = ws.pairs.reserve((size_t)max_pairs * 8)) != GAPA_OK) return rc;
     if ((rc = ws.worklist.reserve((size_t)std::max(g->n_noniso, 1) * 4)) != GAPA_OK) return rc;
-    const size_t nparts = multi ? 0 : (size_t)kSweepGrid * B;
+    const Tuning &tu = g->tune;
+    const int32_t grid = tu.sweep_grid;
+    const size_t nparts = multi ? 0 : (size_t)grid * B;
     if ((rc = ws.small.reserve((size_t)(2 * (size_t)S + 64 + nparts) * 4)) != GAPA_OK) return rc;
     int32_t *root = ws.small.as<int32_t>();
     int32_t *other = root + S;
     int32_t *ctr = root + 2 * S;  // [0] worklist count, [1] pair count, [2..] changed flags
     int32_t *wl_count = ctr, *pair_count = ctr + 1, *changed = ctr + 2;
-    int32_t *single_part = ctr + 64;  // [kSweepGrid][B] singleton counts per collect block (one instance)
+    int32_t *single_part = ctr + 64;  // [grid][B] singleton counts per collect block (one instance)
     ws.stats_ctr = ctr;
     ws.stats_B = S;
     uint32_t *dead = ws.dead.as<uint32_t>(), *reach = ws.reach.as<uint32_t>();
@@ -690,9 +689,9 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
                 const int32_t b0 = g->band_off[b], b1 = g->band_off[b + 1];
                 if (b1 <= b0) continue;
                 const int64_t threads = (int64_t)(b1 - b0) * Wd;
-                const int blocks = (int)std::min<int64_t>((threads + kBlk - 1) / kBlk, 8192);
+                const int blocks = (int)std::min<int64_t>((threads + kBlk - 1) / kBlk, tu.band_blocks);
                 hipLaunchKernelGGL(k_pull_band, dim3(blocks), dim3(kBlk), 0, s, g->d_band_v, b0, b1, Wd,
-                                   g->d_row_ptr, g->d_colD, dead, reach);
+                                   g->d_row_ptr, g->d_colD, dead, reach, tu.band_scan);
             }
         }
         if (noniso > 0) {
@@ -702,34 +701,34 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         }
         {
             TimedScope ts(timer, "k_pull_worklist", s);
-            for (int32_t sw = 1; sw <= kSweeps; ++sw)
-                hipLaunchKernelGGL(k_pull_worklist, dim3(kSweepGrid), dim3(kBlk), 0, s, worklist, wl_count, Wd,
+            for (int32_t sw = 1; sw <= tu.sweeps; ++sw)
+                hipLaunchKernelGGL(k_pull_worklist, dim3(grid), dim3(kBlk), 0, s, worklist, wl_count, Wd,
                                    g->d_row_ptr, g->d_colD, dead, reach, changed, sw);
         }
         {
             TimedScope ts(timer, "k_collect_pairs", s);
-            hipLaunchKernelGGL(k_collect_pairs, dim3(kSweepGrid), dim3(kBlk), 0, s, worklist, wl_count, Wd, I,
+            hipLaunchKernelGGL(k_collect_pairs, dim3(grid), dim3(kBlk), 0, s, worklist, wl_count, Wd, I,
                                g->d_row_ptr, g->d_colD, dead, reach, pairs, pair_count, parent, single_part, other);
         }
         {
             TimedScope ts(timer, "k_pairs_hook", s);
-            hipLaunchKernelGGL(k_pairs_hook, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, I, Wd,
+            hipLaunchKernelGGL(k_pairs_hook, dim3(grid), dim3(kBlk), 0, s, pairs, pair_count, I, Wd,
                                g->d_row_ptr, g->d_col, dead, reach, root, parent);
         }
         {
             TimedScope ts(timer, "k_pairs_count", s);
-            hipLaunchKernelGGL(k_pairs_count, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, ucount);
+            hipLaunchKernelGGL(k_pairs_count, dim3(grid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, ucount);
         }
         {
             TimedScope ts(timer, "k_pairs_reduce", s);
-            hipLaunchKernelGGL(k_pairs_reduce, dim3(kSweepGrid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, root,
+            hipLaunchKernelGGL(k_pairs_reduce, dim3(grid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, root,
                                ucount, other, fit, mc);
         }
         {
             TimedScope ts(timer, "k_root_final", s);
             if (!multi)
-                hipLaunchKernelGGL(k_single_sum, dim3((B + 63) / 64, (kSweepGrid + kSumRows - 1) / kSumRows), dim3(64),
-                                   0, s, single_part, wl_count, kSweepGrid, B, other);
+                hipLaunchKernelGGL(k_single_sum, dim3((B + 63) / 64, (grid + kSumRows - 1) / kSumRows), dim3(64), 0,
+                                   s, single_part, wl_count, grid, B, other);
             hipLaunchKernelGGL(k_root_final, dim3((S + 63) / 64), dim3(64), 0, s, root, I, parent, al, other,
                                g->d_row_ptr, ucount, fit, mc);
         }

@@ -568,7 +568,7 @@ int ga_launch_offspring(gapa_ga *ga, hipStream_t s)
     return GAPA_OK;
 }
 
-static int ga_eval_children(gapa_ga *ga, bool init, hipStream_t s)
+int ga_eval_children(gapa_ga *ga, bool init, hipStream_t s)
 {
     if (ga->count > 1)
         return eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(), 0,

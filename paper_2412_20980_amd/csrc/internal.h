@@ -98,6 +98,15 @@ struct FitnessWorkspace {
     DevBuf flag;     // int32 [4]     device error flags
 };
 
+// Launch shapes of the bit-parallel fitness pass (results do not depend on
+// them; only speed does).
+struct Tuning {
+    int32_t sweep_grid = 4096;   // blocks of the worklist, pair and union-find kernels
+    int32_t band_scan = 64;      // neighbours read per node in the ordered sweep
+    int32_t sweeps = 4;          // follow-up sweeps over the pending nodes
+    int32_t band_blocks = 8192;  // block cap of one band launch
+};
+
 }  // namespace gapa
 
 struct gapa_graph {
@@ -115,6 +124,8 @@ struct gapa_graph {
     std::vector<int32_t> band_off;  // host: band b is d_band_v[band_off[b], band_off[b+1])
     int32_t n_noniso = 0;       // nodes with at least one edge
     int32_t algorithm = 0;      // 0: bit-parallel sweeps, 1: edge-parallel union-find
+    gapa::Tuning tune;
+    int32_t tune_version = 0;   // bumped by every tuning change (recorded graphs are re-recorded)
     gapa::FitnessWorkspace ws;
     gapa::KernelTimer timer;
     bool failed = false;
@@ -204,6 +215,9 @@ int ga_launch_offspring(gapa_ga *ga, hipStream_t s);
 // device generation counter.
 int ga_rank_and_gather(gapa_ga *ga, bool init, const int64_t *f_pool, const int32_t *pool, int32_t npool,
                        hipStream_t s);
+// Exact fitness of the children currently held (the initial population at
+// generation 0) into child_fit.
+int ga_eval_children(gapa_ga *ga, bool init, hipStream_t s);
 
 // ------------------------------------------------------------ surrogate -----
 
@@ -265,6 +279,7 @@ struct gapa_ga {
     // graph replay of one generation (one per current-buffer parity)
     bool use_graph = false;
     bool warm = false;            // a generation has run eagerly: buffers are sized
+    int32_t captured_version = -1;  // graph tuning the recorded generations were made with
     hipStream_t cap_stream = nullptr;
     hipGraph_t graphs[2] = {nullptr, nullptr};
     hipGraphExec_t execs[2] = {nullptr, nullptr};

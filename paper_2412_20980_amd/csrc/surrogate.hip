@@ -31,6 +31,7 @@ constexpr int kH = 256;
 constexpr int kMlpRows = 64;  // samples per MLP block, 16 per wave
 constexpr uint32_t kStreamSurrInit = 5, kStreamSurrSample = 6, kStreamSurrRandom = 7;
 constexpr int kJudgeMax = 1024;
+constexpr int kJudgeExtra = 32;  // unscreened children evaluated for the judge in a screened generation
 constexpr int kMaxLambda = 8192;
 
 // flat layout of the MLP parameters after E (weights, gradients, partials)
@@ -513,34 +514,14 @@ __device__ __forceinline__ uint64_t pred_key(float y, uint32_t idx)
     return ((uint64_t)u << 32) | idx;
 }
 
-// The m children with the smallest keys (prediction, index) or, when yhat is
-// NULL, the smallest (first word of draw(seed, o, 0, gen, stream 7), index):
-// a bitonic sort of lambda keys in LDS, then the chosen indices in ascending
-// order.  One block of 1024 threads; lambda <= 8192.
-size_t screen_lds(int32_t lambda)
+__device__ __forceinline__ uint64_t random_key(uint64_t seed, uint32_t gen, uint32_t ind, uint32_t i)
 {
-    size_t L = 1;
-    while ((int32_t)L < lambda) L <<= 1;
-    return L * 8 + (size_t)kMaxLambda / 32 * 4;
+    return ((uint64_t)draw(seed, i, ind, gen, kStreamSurrRandom, 0).w0 << 32) | i;
 }
 
-__global__ __launch_bounds__(1024) void k_screen(const float *__restrict__ yhat, int32_t lambda, int32_t m,
-                                                 uint64_t seed, uint32_t gen, int32_t *__restrict__ pool)
+// Bitonic sort of key[0, L) ascending (L a power of two); whole block.
+__device__ void block_sort(uint64_t *key, int32_t L)
 {
-    extern __shared__ __align__(16) uint64_t key[];  // [L], then chosen bits
-    __shared__ int32_t s_wave[16];
-    int32_t L = 1;
-    while (L < lambda) L <<= 1;
-    uint32_t *chosen = reinterpret_cast<uint32_t *>(key + L);
-    for (int32_t i = threadIdx.x; i < L; i += blockDim.x) {
-        uint64_t kk = ~0ull;
-        if (i < lambda)
-            kk = yhat ? pred_key(yhat[i], i)
-                      : (((uint64_t)draw(seed, (uint32_t)i, 0, gen, kStreamSurrRandom, 0).w0 << 32) | (uint32_t)i);
-        key[i] = kk;
-    }
-    for (int32_t i = threadIdx.x; i < kMaxLambda / 32; i += blockDim.x) chosen[i] = 0u;
-    __syncthreads();
     for (int32_t size = 2; size <= L; size <<= 1)
         for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
             for (int32_t i = threadIdx.x; i < L; i += blockDim.x) {
@@ -556,17 +537,18 @@ __global__ __launch_bounds__(1024) void k_screen(const float *__restrict__ yhat,
             }
             __syncthreads();
         }
-    for (int32_t i = threadIdx.x; i < m; i += blockDim.x) {
-        const uint32_t idx = (uint32_t)key[i];
-        atomicOr(&chosen[idx >> 5], 1u << (idx & 31));
-    }
-    __syncthreads();
-    // compaction in index order: thread t owns words [t * per, ...)
+}
+
+// Indices whose bit is set in bits[0, ceil(lambda / 32)), ascending, to
+// out[]; whole block (blockDim.x <= 1024).
+__device__ void block_compact(const uint32_t *bits, int32_t lambda, int32_t *out)
+{
+    __shared__ int32_t s_wave[16];
     const int32_t words = (lambda + 31) / 32;
     const int32_t per = (words + blockDim.x - 1) / blockDim.x;
     const int32_t w0 = min(words, (int32_t)threadIdx.x * per), w1 = min(words, w0 + per);
     int32_t cnt = 0;
-    for (int32_t w = w0; w < w1; ++w) cnt += __popc(chosen[w]);
+    for (int32_t w = w0; w < w1; ++w) cnt += __popc(bits[w]);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int32_t incl = cnt;
     for (int off = 1; off < 64; off <<= 1) {
@@ -578,7 +560,54 @@ __global__ __launch_bounds__(1024) void k_screen(const float *__restrict__ yhat,
     int32_t off = incl - cnt;
     for (int q = 0; q < wv; ++q) off += s_wave[q];
     for (int32_t w = w0; w < w1; ++w)
-        for (uint32_t x = chosen[w]; x; x &= x - 1) pool[off++] = w * 32 + __ffs(x) - 1;
+        for (uint32_t x = bits[w]; x; x &= x - 1) out[off++] = w * 32 + __ffs(x) - 1;
+    __syncthreads();
+}
+
+// Screening.  pool[0, m): the m children with the smallest (prediction,
+// index) or, when yhat is NULL, the smallest (first word of
+// draw(seed, o, 0, gen, stream 7), o); ascending.  pool[m, m + extra): the
+// judge's unbiased sample, the `extra` other children with the smallest
+// (first word of draw(seed, o, 1, gen, stream 7), o); ascending.  One block
+// of 1024 threads, keys in LDS, lambda <= 8192.
+size_t screen_lds(int32_t lambda)
+{
+    size_t L = 1;
+    while ((int32_t)L < lambda) L <<= 1;
+    return L * 8 + (size_t)kMaxLambda / 32 * 4 * 2;
+}
+
+__global__ __launch_bounds__(1024) void k_screen(const float *__restrict__ yhat, int32_t lambda, int32_t m,
+                                                 int32_t extra, uint64_t seed, uint32_t gen,
+                                                 int32_t *__restrict__ pool)
+{
+    extern __shared__ __align__(16) uint64_t key[];  // [L], then two bit sets
+    int32_t L = 1;
+    while (L < lambda) L <<= 1;
+    uint32_t *chosen = reinterpret_cast<uint32_t *>(key + L);
+    uint32_t *judged = chosen + kMaxLambda / 32;
+    for (int32_t i = threadIdx.x; i < L; i += blockDim.x)
+        key[i] = i < lambda ? (yhat ? pred_key(yhat[i], i) : random_key(seed, gen, 0, i)) : ~0ull;
+    for (int32_t i = threadIdx.x; i < kMaxLambda / 32; i += blockDim.x) chosen[i] = judged[i] = 0u;
+    __syncthreads();
+    block_sort(key, L);
+    for (int32_t i = threadIdx.x; i < m; i += blockDim.x) {
+        const uint32_t idx = (uint32_t)key[i];
+        atomicOr(&chosen[idx >> 5], 1u << (idx & 31));
+    }
+    __syncthreads();
+    block_compact(chosen, lambda, pool);
+    if (extra <= 0) return;
+    for (int32_t i = threadIdx.x; i < L; i += blockDim.x)
+        key[i] = (i < lambda && !((chosen[i >> 5] >> (i & 31)) & 1u)) ? random_key(seed, gen, 1, i) : ~0ull;
+    __syncthreads();
+    block_sort(key, L);
+    for (int32_t i = threadIdx.x; i < extra; i += blockDim.x) {
+        const uint32_t idx = (uint32_t)key[i];
+        atomicOr(&judged[idx >> 5], 1u << (idx & 31));
+    }
+    __syncthreads();
+    block_compact(judged, lambda, pool + m);
 }
 
 __global__ void k_iota(int32_t *__restrict__ out, int32_t count)
@@ -611,7 +640,10 @@ __global__ void k_append(const int32_t *__restrict__ children, int32_t k, const 
     if (threadIdx.x == 0) buf_y[slot] = log1p((double)F[q]);
 }
 
-// Mean and standard deviation of the buffered labels (one block, fixed order).
+// Mean and spread of the buffered labels (one block, fixed order): the
+// spread is sqrt(variance + floor^2), so that a buffer of (nearly) equal
+// labels gives targets near zero rather than amplified rounding noise.
+constexpr double kSpreadFloor = 1e-6;
 __global__ __launch_bounds__(1024) void k_label_stats(const double *__restrict__ y, int32_t count,
                                                       double *__restrict__ out)
 {
@@ -635,9 +667,8 @@ __global__ __launch_bounds__(1024) void k_label_stats(const double *__restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double sd = sqrt(s[0] / count);
         out[0] = mu;
-        out[1] = sd > 0.0 ? sd : 1.0;
+        out[1] = sqrt(s[0] / count + kSpreadFloor * kSpreadFloor);
     }
 }
 
@@ -730,7 +761,7 @@ struct SurrogateState {
     bool force_full = false;
     bool stats_pending = false;
     int64_t last_gen = 0;
-    int32_t last_evaluated = 0;
+    int32_t last_evaluated = 0, last_pooled = 0;
     bool last_screened = false, last_predicted = false;
     DevBuf theta, m, v, partial, keep_mlp, keep_E;      // float
     DevBuf Eb, W1b, W2b, w3b, W1bT, W2bT;               // bf16
@@ -930,8 +961,8 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->buf_genes, (size_t)sp->buffer * st->k * 4);
     res(st->buf_y, (size_t)sp->buffer * 8);
     res(st->pool, (size_t)L * 4);
-    res(st->cmasks, (size_t)sp->screen * st->W * 4);
-    res(st->calive, (size_t)sp->screen * 4);
+    res(st->cmasks, (size_t)(sp->screen + kJudgeExtra) * st->W * 4);
+    res(st->calive, (size_t)(sp->screen + kJudgeExtra) * 4);
     res(st->dstats, 64);
     if (rc != GAPA_OK) return rc;
     GAPA_HIP(hipHostMalloc(reinterpret_cast<void **>(&st->hstats), 64, hipHostMallocDefault));
@@ -987,7 +1018,8 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
     float *yhat = st.yhat.as<float>();
     if (predict && (rc = predict_rows(st, ga->children.as<int32_t>(), nullptr, L, yhat, s)) != GAPA_OK) return rc;
     int64_t *F = ga->child_fit.as<int64_t>();
-    int32_t npool = L;
+    int32_t npool = L;     // children that enter elitism
+    int32_t neval = L;     // children evaluated exactly (the pool, then the judge's extra sample)
     const int32_t *pool = nullptr;
     if (full) {
         if ((rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(), L, F, nullptr, ga->ws,
@@ -996,23 +1028,25 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         if ((rc = ga_rank_and_gather(ga, false, F, nullptr, 0, s)) != GAPA_OK) return rc;
     } else {
         npool = st.sp.screen;
+        const int32_t extra = predict ? std::min(kJudgeExtra, L - npool) : 0;
+        neval = npool + extra;
         pool = st.pool.as<int32_t>();
-        hipLaunchKernelGGL(k_screen, dim3(1), dim3(1024), screen_lds(L), s, random ? nullptr : yhat, L, npool,
+        hipLaunchKernelGGL(k_screen, dim3(1), dim3(1024), screen_lds(L), s, random ? nullptr : yhat, L, npool, extra,
                            st.seed, gen, st.pool.as<int32_t>());
-        hipLaunchKernelGGL(k_gather_pool, dim3(npool), dim3(256), 0, s, pool, ga->masks.as<uint32_t>(), st.W,
+        hipLaunchKernelGGL(k_gather_pool, dim3(neval), dim3(256), 0, s, pool, ga->masks.as<uint32_t>(), st.W,
                            ga->alive.as<int32_t>(), st.cmasks.as<uint32_t>(), st.calive.as<int32_t>());
         GAPA_HIP(hipGetLastError());
-        if ((rc = eval_masks(ga->graph, st.cmasks.as<uint32_t>(), st.calive.as<int32_t>(), npool, F, nullptr, ga->ws,
+        if ((rc = eval_masks(ga->graph, st.cmasks.as<uint32_t>(), st.calive.as<int32_t>(), neval, F, nullptr, ga->ws,
                              &ga->timer, s)) != GAPA_OK)
             return rc;
         if ((rc = ga_rank_and_gather(ga, false, F, pool, npool, s)) != GAPA_OK) return rc;
     }
     double *ds = st.dstats.as<double>();
-    if (predict) hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, npool, ds, ds + 2);
+    if (predict) hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, neval, ds, ds + 2);
     if (!random) {
-        hipLaunchKernelGGL(k_append, dim3(npool), dim3(256), 0, s, ga->children.as<int32_t>(), st.k, pool, F,
+        hipLaunchKernelGGL(k_append, dim3(neval), dim3(256), 0, s, ga->children.as<int32_t>(), st.k, pool, F,
                            st.appended, st.sp.buffer, st.buf_genes.as<int32_t>(), st.buf_y.as<double>());
-        st.appended += npool;
+        st.appended += neval;
         const int32_t count = (int32_t)std::min<int64_t>(st.appended, st.sp.buffer);
         hipLaunchKernelGGL(k_label_stats, dim3(1), dim3(1024), 0, s, st.buf_y.as<double>(), count, ds);
         for (int32_t t = 0; t < st.sp.train_steps; ++t) {
@@ -1029,7 +1063,8 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
     GAPA_HIP(hipEventRecord(st.ready, s));
     st.stats_pending = true;
     st.last_gen = gen;
-    st.last_evaluated = npool;
+    st.last_evaluated = neval;
+    st.last_pooled = npool;
     st.last_screened = !full;
     st.last_predicted = predict;
     if (full) {
@@ -1100,6 +1135,7 @@ int surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out)
     if (st.stats_pending) GAPA_HIP(hipEventSynchronize(st.ready));
     out->generation = st.last_gen;
     out->evaluated = st.last_evaluated;
+    out->pooled = st.last_pooled;
     out->screened = st.last_screened ? 1 : 0;
     out->spearman = st.last_predicted ? st.hstats[2] : 0.0;
     out->rel_err = st.last_predicted ? st.hstats[3] : 0.0;

@@ -52,6 +52,7 @@ EXPORTED = (
     "gapa_batch_set_timing", "gapa_batch_kernel_times", "gapa_batch_destroy",
     "gapa_surrogate_attach", "gapa_surrogate_stats", "gapa_surrogate_last_pool", "gapa_surrogate_predict",
     "gapa_surrogate_train_batch", "gapa_surrogate_tensor", "gapa_surrogate_last_predictions",
+    "gapa_graph_get_tuning", "gapa_graph_set_tuning", "gapa_ga_autotune", "gapa_batch_autotune",
 )
 
 
@@ -79,9 +80,15 @@ class gapa_surrogate_params(C.Structure):
 
 class gapa_surrogate_report(C.Structure):
     _fields_ = [
-        ("generation", C.c_int64), ("evaluated", C.c_int32), ("screened", C.c_int32), ("spearman", C.c_double),
+        ("generation", C.c_int64), ("evaluated", C.c_int32), ("pooled", C.c_int32), ("screened", C.c_int32),
+        ("reserved", C.c_int32), ("spearman", C.c_double),
         ("rel_err", C.c_double), ("loss", C.c_double), ("fallbacks", C.c_int32), ("train_steps", C.c_int32),
     ]
+
+
+class gapa_tuning(C.Structure):
+    _fields_ = [("sweep_grid", C.c_int32), ("band_scan", C.c_int32), ("sweeps", C.c_int32),
+                ("band_blocks", C.c_int32)]
 
 
 class gapa_kernel_time(C.Structure):
@@ -112,6 +119,10 @@ def lib() -> C.CDLL:
     L.gapa_batch_best.argtypes = [vp, C.c_int32, vp, i64p, i64p]
     L.gapa_batch_get_population.argtypes = [vp, C.c_int32, vp, vp]
     L.gapa_batch_destroy.argtypes = [vp]
+    L.gapa_graph_get_tuning.argtypes = [vp, C.POINTER(gapa_tuning)]
+    L.gapa_graph_set_tuning.argtypes = [vp, C.POINTER(gapa_tuning)]
+    L.gapa_ga_autotune.argtypes = [vp, C.c_int32, vp, C.POINTER(gapa_tuning)]
+    L.gapa_batch_autotune.argtypes = [vp, C.c_int32, vp, C.POINTER(gapa_tuning)]
     L.gapa_surrogate_attach.argtypes = [vp, C.POINTER(gapa_surrogate_params), vp]
     L.gapa_surrogate_stats.argtypes = [vp, C.POINTER(gapa_surrogate_report)]
     L.gapa_surrogate_last_pool.argtypes = [vp, vp, C.c_int32, i32p]
@@ -237,6 +248,15 @@ class Graph:
     def fitness_stats(self) -> dict:
         return _fitness_stats(lib().gapa_graph_fitness_stats, self.handle)
 
+    def get_tuning(self) -> dict:
+        t = gapa_tuning()
+        _check(lib().gapa_graph_get_tuning(self.handle, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in t._fields_}
+
+    def set_tuning(self, sweep_grid=4096, band_scan=64, sweeps=4, band_blocks=8192):
+        t = gapa_tuning(sweep_grid=sweep_grid, band_scan=band_scan, sweeps=sweeps, band_blocks=band_blocks)
+        _check(lib().gapa_graph_set_tuning(self.handle, C.byref(t)))
+
     def close(self):
         if self.handle:
             gapa_graph_destroy(self.handle)
@@ -315,6 +335,11 @@ class GA:
     def fitness_stats(self) -> dict:
         return _fitness_stats(lib().gapa_ga_fitness_stats, self.handle)
 
+    def autotune(self, reps: int = 3, stream=None) -> dict:
+        t = gapa_tuning()
+        _check(lib().gapa_ga_autotune(self.handle, reps, _stream_ptr(stream), C.byref(t)))
+        return {f: getattr(t, f) for f, _ in t._fields_}
+
     # --- learned screening surrogate ---
     def attach_surrogate(self, screen: int, batch: int = 1024, train_steps: int = 4, warmup_gens: int = 10,
                          buffer: int = 65536, fallback_gens: int = 3, lr: float = 1e-3, min_rho: float = 0.3,
@@ -348,6 +373,8 @@ class GA:
     def predict(self, genes, stream=None):
         """genes: torch int32 CUDA tensor [P, k]; returns float32 predictions."""
         assert _is_dev_tensor(genes) and genes.dtype == torch.int32 and genes.is_contiguous()
+        if genes.dim() != 2 or genes.shape[1] != self.k:
+            raise ValueError(f"genes must be [P, {self.k}] (the GA's budget), got {tuple(genes.shape)}")
         y = torch.empty(genes.shape[0], dtype=torch.float32, device=genes.device)
         _check(lib().gapa_surrogate_predict(self.handle, genes.data_ptr(), genes.shape[0], y.data_ptr(),
                                             _stream_ptr(stream)))
@@ -355,6 +382,10 @@ class GA:
 
     def train_batch(self, genes, target, keep_grads: bool = True, stream=None):
         assert _is_dev_tensor(genes) and _is_dev_tensor(target)
+        if genes.dtype != torch.int32 or not genes.is_contiguous() or genes.dim() != 2 or genes.shape[1] != self.k:
+            raise ValueError(f"genes must be a contiguous int32 [B, {self.k}] tensor (the GA's budget)")
+        if target.dtype != torch.float32 or not target.is_contiguous() or target.numel() != genes.shape[0]:
+            raise ValueError("target must be a contiguous float32 tensor with one entry per row")
         _check(lib().gapa_surrogate_train_batch(self.handle, genes.data_ptr(), target.data_ptr(), genes.shape[0],
                                                 int(keep_grads), _stream_ptr(stream)))
 
@@ -448,6 +479,11 @@ class Batch:
 
     def set_timing(self, level: int = 1):
         _check(lib().gapa_batch_set_timing(self.handle, int(level)))
+
+    def autotune(self, reps: int = 3, stream=None) -> dict:
+        t = gapa_tuning()
+        _check(lib().gapa_batch_autotune(self.handle, reps, _stream_ptr(stream), C.byref(t)))
+        return {f: getattr(t, f) for f, _ in t._fields_}
 
     def kernel_times(self) -> dict:
         return _kernel_times(lib().gapa_batch_kernel_times, self.handle)

@@ -196,3 +196,51 @@ def test_batched_instances_match_golden(gp):
     for b, r in enumerate(ref):
         _, f, _ = bt.best(b)
         assert f == r["best"][gens]
+
+
+@pytest.fixture(scope="module")
+def cl200k_small_pop():
+    g = inputs.chung_lu_200k()
+    genes = inputs.hub_biased_population(g, 2000, 200, seed=3)
+    return g, genes, O.eval_population(g, genes)
+
+
+@pytest.mark.parametrize("tune", [dict(sweep_grid=16, band_scan=1, sweeps=0, band_blocks=16),
+                                  dict(sweep_grid=65535, band_scan=1 << 20, sweeps=32, band_blocks=65535),
+                                  dict(sweep_grid=300, band_scan=5, sweeps=1, band_blocks=77)])
+def test_launch_shapes_never_change_results(gp, cl200k_small_pop, tune):
+    g, genes, ref = cl200k_small_pop
+    print(f"tuning {tune}", flush=True)
+    graph = gp.Graph.from_csr(g, trust=True)
+    graph.set_tuning(**tune)
+    assert graph.get_tuning() == tune
+    assert np.array_equal(graph.eval(genes), ref)
+
+
+def test_autotuned_batch_and_retuned_replay_keep_trajectories(gp):
+    csrs, params = uneven_instances()
+    graphs = [gp.Graph.from_csr(g) for g in csrs]
+    bt = gp.Batch(graphs, params, replay=True)
+    ogas = [oracle_for(g, p) for g, p in zip(csrs, params)]
+    for gen in range(1, 7):
+        bt.step(1)
+        for o in ogas:
+            o.step()
+        if gen == 2:
+            best = bt.autotune(reps=1)
+            print(f"autotuned {best}", flush=True)
+        for b, o in enumerate(ogas):
+            pop, F = bt.population(b)
+            assert np.array_equal(F, o.F) and np.array_equal(pop, o.pop), (b, gen)
+    # a replayed single GA whose graph is retuned mid-run
+    g = inputs.erdos_renyi(900, 3.0, seed=51)
+    graph = gp.Graph.from_csr(g)
+    ga = gp.GA(graph, 30, 48, 5, 0.7, 0.1, 2, 100, replay=True)
+    oga = O.OracleGA(g, 30, 48, 5, 0.7, 0.1, 2, 100)
+    for gen in range(1, 7):
+        if gen == 4:
+            graph.set_tuning(sweep_grid=128, band_scan=8, sweeps=1, band_blocks=64)
+        ga.step(1)
+        oga.step()
+        pop, F = ga.population()
+        assert np.array_equal(F, oga.F) and np.array_equal(pop, oga.pop), gen

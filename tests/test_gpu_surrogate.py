@@ -101,7 +101,7 @@ def test_gradients_match_oracle(gp):
 def test_adam_step_matches_formula(gp):
     import torch
     g = inputs.barabasi_albert(600, 3, seed=4)
-    _, ga = make_ga(gp, g, batch=32)
+    _, ga = make_ga(gp, g, k=15, batch=32)
     p = set_weights(ga, random_weights(np.random.default_rng(8), g.n))
     sets = inputs.random_population(g.n, 15, 32, seed=3)
     target = np.linspace(-1, 1, 32).astype(np.float32)
@@ -127,17 +127,21 @@ def run_replayed(gp, g, gens, **kw):
     for gen in range(1, gens + 1):
         ga.step(1)
         st = ga.surrogate_stats()
-        pool = ga.last_pool()
-        assert st["generation"] == gen and st["evaluated"] == len(pool)
+        evaluated = ga.last_pool()
+        assert st["generation"] == gen and st["evaluated"] == len(evaluated)
+        pool, extra = evaluated[:st["pooled"]], evaluated[st["pooled"]:]
         if st["screened"]:
             screened += 1
             yhat = ga.last_predictions()
             assert len(yhat) == lam
             # the selection is exact given the device's float32 predictions
             assert np.array_equal(pool, S.screen(yhat.astype(np.float64), opts["screen"]))
+            # the judge's unbiased extra sample
+            assert len(extra) == min(32, lam - opts["screen"])
+            assert np.array_equal(extra, S.judge_extra(seed, gen, lam, pool, len(extra)))
         else:
-            assert np.array_equal(pool, np.arange(lam))
-        sga.step(pool)
+            assert np.array_equal(pool, np.arange(lam)) and len(extra) == 0
+        sga.step(pool, extra)
         pop_d, F_d = ga.population()
         assert np.array_equal(F_d, sga.ga.F), f"fitness differs at generation {gen}"
         assert np.array_equal(pop_d, sga.ga.pop), f"population differs at generation {gen}"
@@ -145,15 +149,26 @@ def run_replayed(gp, g, gens, **kw):
 
 
 def test_screened_trajectory_replays_exactly(gp):
-    g = inputs.barabasi_albert(1500, 3, seed=5)
-    ga, sga, screened = run_replayed(gp, g, 8)
+    # a tree (BA with one edge per node): removals split it, so labels vary
+    g = inputs.barabasi_albert(1500, 1, seed=5)
+    ga, sga, screened = run_replayed(gp, g, 8, fallback_gens=0)
     assert screened == 6
     st = ga.surrogate_stats()
     assert st["train_steps"] == 16
-    # the device model and the oracle's float64 replay of its training stay close
+    # The device model and the oracle's float64 replay of its training stay
+    # close.  Adam scales every coordinate's step to about lr whatever the
+    # gradient's size, so coordinates whose gradient is near zero can step in
+    # opposite directions on the two sides: weights drift apart by a few
+    # percent over 16 steps, while the predictions they make stay aligned.
+    import torch
     got, ref = weights(ga, g.n), sga.params
     for name in ("W1", "W2", "w3"):
-        assert np.linalg.norm(got[name] - ref[name]) <= 2e-2 * np.linalg.norm(ref[name]), name
+        assert np.linalg.norm(got[name] - ref[name]) <= 0.06 * np.linalg.norm(ref[name]), name
+    sets = inputs.random_population(g.n, 20, 256, seed=11)
+    y_dev = ga.predict(torch.from_numpy(sets).cuda()).cpu().numpy().astype(np.float64)
+    y_ref = S.forward(ref, sets, bf16_ops=True)["yhat"]
+    assert np.corrcoef(y_dev, y_ref)[0, 1] > 0.98
+    assert np.linalg.norm(y_dev - y_ref) <= 0.1 * np.linalg.norm(y_ref - y_ref.mean()) + 1e-3 * len(sets)
 
 
 def test_fallback_to_full_generations(gp):
@@ -163,6 +178,17 @@ def test_fallback_to_full_generations(gp):
     ga, _, screened = run_replayed(gp, g, 7, min_rho=2.0, fallback_gens=1, warmup_gens=1)
     st = ga.surrogate_stats()
     assert screened == 3 and st["fallbacks"] == 3
+
+
+def test_binding_rejects_rows_of_the_wrong_width(gp):
+    import torch
+    g = inputs.barabasi_albert(300, 2, seed=9)
+    _, ga = make_ga(gp, g, k=15, batch=32)
+    with pytest.raises(ValueError):
+        ga.predict(torch.zeros((4, 14), dtype=torch.int32, device="cuda"))
+    with pytest.raises(ValueError):
+        ga.train_batch(torch.zeros((32, 16), dtype=torch.int32, device="cuda"),
+                       torch.zeros(32, dtype=torch.float32, device="cuda"))
 
 
 def test_attach_rejects_bad_parameters(gp, ba200):
