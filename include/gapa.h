@@ -171,7 +171,8 @@ GAPA_API int gapa_ga_destroy(gapa_ga *ga);
  * kernels, FP32 accumulation).  Trained online on (S, ln(1 + PC(S))) pairs of
  * the exactly evaluated offspring, kept in a ring buffer: labels are
  * standardised by the buffer's mean and spread sqrt(variance + 1e-12); mean squared
- * error; Adam (Kingma and Ba 2015) with beta = (0.9, 0.999), eps = 1e-8;
+ * error; Adam (Kingma and Ba 2015) with beta = (0.9, 0.999), eps = 1e-8, lazy
+ * on E (rows of nodes absent from the batch keep weights and moments);
  * `train_steps` steps per generation on batches drawn with Philox stream 6
  * (slot j, individual step, generation).  Initial weights from Philox stream
  * 5: E uniform in +-0.05, W1 and W2 uniform in +-sqrt(6 / fan_in), w3 in

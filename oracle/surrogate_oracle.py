@@ -16,10 +16,10 @@ Model, for a removed-node set S (an individual) over node embeddings E [n, D]:
     z2 = W2 h1 + b2, h2 = relu(z2)                             (H)
     yhat = w3 . h2 + b3
 
-trained on y = ln(1 + PC(S)) standardised by the mean and standard deviation
-of the labels held in the replay buffer, with the mean squared error and Adam
+trained on y = ln(1 + PC(S)) standardised by the mean and spread of the
+labels held in the replay buffer, with the mean squared error and Adam
 (Kingma and Ba, ICLR 2015, Algorithm 1: bias-corrected first and second
-moment estimates).  Everything here is float64.  With ``bf16=True`` the
+moment estimates; lazy on the embedding table, whose gradient is sparse).  Everything here is float64.  With ``bf16=True`` the
 forward and backward passes round the operands of every product to bfloat16
 (through float32, round to nearest even) exactly where the device kernels
 do, so that the device can be compared tightly; without it they are the
@@ -124,7 +124,7 @@ def loss_and_grads(p: dict, sets: np.ndarray, target: np.ndarray, bf16_ops: bool
     dz1b = r(dz1)
     g["W1"] = dz1b.T @ f["x"]
     g["b1"] = dz1b.sum(axis=0)
-    dx = dz1b @ r(p["W1"])
+    dx = r(dz1b @ r(p["W1"]))
     dE = np.zeros_like(p["E"])
     np.add.at(dE, np.asarray(sets, dtype=np.int64).ravel(), np.repeat(dx, sets.shape[1], axis=0))
     g["E"] = dE
@@ -134,9 +134,13 @@ def loss_and_grads(p: dict, sets: np.ndarray, target: np.ndarray, bf16_ops: bool
 # --- Adam ---------------------------------------------------------------------
 
 class Adam:
-    """Kingma and Ba (2015), Algorithm 1, applied to every tensor densely:
+    """Kingma and Ba (2015), Algorithm 1:
     m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
-    theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)."""
+    theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+    dense for every tensor except the embedding table when `rows` is given:
+    there it is lazy, as for sparse gradients (torch.optim.SparseAdam): only
+    the listed rows (the nodes present in the batch) update their moments and
+    weights, with the global step count t."""
 
     def __init__(self, params: dict, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self.lr, self.b1, self.b2, self.eps = lr, beta1, beta2, eps
@@ -144,14 +148,26 @@ class Adam:
         self.v = {k: np.zeros_like(v) for k, v in params.items()}
         self.t = 0
 
-    def step(self, params: dict, grads: dict):
+    def _update(self, params, grads, k, sel):
+        m, v, g = self.m[k], self.v[k], grads[k]
+        m[sel] = self.b1 * m[sel] + (1.0 - self.b1) * g[sel]
+        v[sel] = self.b2 * v[sel] + (1.0 - self.b2) * g[sel] ** 2
+        params[k][sel] = params[k][sel] - self.lr * (m[sel] / self.c1) / (np.sqrt(v[sel] / self.c2) + self.eps)
+
+    def step(self, params: dict, grads: dict, rows=None):
         self.t += 1
-        c1 = 1.0 - self.b1 ** self.t
-        c2 = 1.0 - self.b2 ** self.t
+        self.c1 = 1.0 - self.b1 ** self.t
+        self.c2 = 1.0 - self.b2 ** self.t
         for k in params:
-            self.m[k] = self.b1 * self.m[k] + (1.0 - self.b1) * grads[k]
-            self.v[k] = self.b2 * self.v[k] + (1.0 - self.b2) * grads[k] ** 2
-            params[k] = params[k] - self.lr * (self.m[k] / c1) / (np.sqrt(self.v[k] / c2) + self.eps)
+            if k == "E" and rows is not None:
+                self._update(params, grads, k, np.asarray(rows, dtype=np.int64))
+            else:
+                self._update(params, grads, k, slice(None))
+
+
+def batch_rows(sets) -> np.ndarray:
+    """Nodes present in a batch of sets (the rows of E a lazy step touches)."""
+    return np.unique(np.asarray(sets, dtype=np.int64))
 
 
 # --- labels, screening, judge statistics -----------------------------------------
@@ -252,8 +268,9 @@ class SurrogateGA:
         mu, sd = standardise(self.buf_y[:count])
         for t in range(self.steps):
             idx = sample_batch(self.seed, gen, t, self.batch, count)
-            loss, g, _ = loss_and_grads(self.params, self.buf_sets[idx], (self.buf_y[idx] - mu) / sd, self.bf16_ops)
-            self.opt.step(self.params, g)
+            sets = self.buf_sets[idx]
+            loss, g, _ = loss_and_grads(self.params, sets, (self.buf_y[idx] - mu) / sd, self.bf16_ops)
+            self.opt.step(self.params, g, rows=batch_rows(sets))
             self.losses.append(loss)
         return mu, sd
 

@@ -39,6 +39,7 @@ struct OpArgs {
     int32_t *alive;           // out: surviving non-isolated nodes of each child
     int32_t *flag;            // [1] attempts exhausted
     const uint32_t *gen_ctr;  // [1] generations completed
+    int32_t rows_only;        // emit only the rows (no bit sets, no alive counts)
 };
 
 // One instance's view, resolved by each block from the table.
@@ -52,6 +53,7 @@ struct Op {
     int32_t *flag;
     uint64_t seed, t_pc, t_pm;
     int32_t P, L, k, n, W, KW, T, n_noniso;
+    int32_t rows_only;
 };
 
 __device__ __forceinline__ Op resolve(const OpArgs &a)
@@ -76,6 +78,7 @@ __device__ __forceinline__ Op resolve(const OpArgs &a)
     o.KW = I.KW;
     o.T = I.T;
     o.n_noniso = I.n_noniso;
+    o.rows_only = a.rows_only;
     return o;
 }
 
@@ -238,11 +241,12 @@ __device__ void emit(const OpLds &l, const Op &a, int32_t idx)
     __syncthreads();
     uint32_t *m = a.masks + (int64_t)idx * a.W;
     int32_t gone = 0;
-    for (int32_t w = threadIdx.x; w < a.W; w += blockDim.x) {
-        const uint32_t x = l.U[w];
-        m[w] = x;
-        gone += __popc(x & a.noniso[w]);
-    }
+    if (!a.rows_only)
+        for (int32_t w = threadIdx.x; w < a.W; w += blockDim.x) {
+            const uint32_t x = l.U[w];
+            m[w] = x;
+            gone += __popc(x & a.noniso[w]);
+        }
     const int32_t per = (a.W + blockDim.x - 1) / blockDim.x;
     const int32_t w0 = min(a.W, (int32_t)threadIdx.x * per), w1 = min(a.W, w0 + per);
     int32_t cnt = 0;
@@ -259,7 +263,7 @@ __device__ void emit(const OpLds &l, const Op &a, int32_t idx)
     int32_t *dst = a.children + (int64_t)idx * a.k;
     for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) dst[j] = l.list[j];
     if (threadIdx.x == 0) {
-        a.alive[idx] = a.n_noniso - gone_total;
+        if (!a.rows_only) a.alive[idx] = a.n_noniso - gone_total;
         if (total != a.k) atomicOr(a.flag, 1);
     }
 }
@@ -488,6 +492,7 @@ OpArgs make_args(gapa_ga *ga, const int32_t *pop, const int64_t *fit)
     a.alive = ga->alive.as<int32_t>();
     a.flag = ga->flag.as<int32_t>();
     a.gen_ctr = ga->gen_ctr.as<uint32_t>();
+    a.rows_only = 0;
     return a;
 }
 
@@ -559,9 +564,10 @@ int ga_launch_init(gapa_ga *ga, hipStream_t s)
     return GAPA_OK;
 }
 
-int ga_launch_offspring(gapa_ga *ga, hipStream_t s)
+int ga_launch_offspring(gapa_ga *ga, hipStream_t s, bool rows_only)
 {
     OpArgs a = make_args(ga, ga->pop[ga->cur].as<int32_t>(), ga->fit[ga->cur].as<int64_t>());
+    a.rows_only = rows_only ? 1 : 0;
     TimedScope ts(&ga->timer, "ga_offspring", s, 1);
     hipLaunchKernelGGL(k_offspring, dim3(ga->max_lambda, ga->count), dim3(kOpBlock), ga->op_lds_bytes, s, a);
     GAPA_HIP(hipGetLastError());

@@ -207,7 +207,9 @@ int ga_init_population(gapa_ga *ga, hipStream_t s);
 // device, so the launches can be captured into a graph and replayed.
 int ga_generation(gapa_ga *ga, hipStream_t s);
 int ga_launch_init(gapa_ga *ga, hipStream_t s);
-int ga_launch_offspring(gapa_ga *ga, hipStream_t s);
+// rows_only: the children's rows only; their bit sets and alive counts are
+// left for the caller to build (for the few it evaluates).
+int ga_launch_offspring(gapa_ga *ga, hipStream_t s, bool rows_only = false);
 // Elitism of every instance over its current parents (none at generation 0,
 // `init`) and its evaluated offspring (f_pool[q] is the fitness of child
 // pool[q], or of child q when pool is NULL; a pool only with one instance);

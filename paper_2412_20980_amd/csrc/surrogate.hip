@@ -214,7 +214,7 @@ struct MlpArgs {
     const float *target; // [N] standardised labels
     float dscale;        // 2 / B
     float *lossv;        // [N] squared errors
-    float *dx;           // [N][64] gradient of x(S)
+    uint16_t *dxT;       // [64][N] gradient of x(S), bf16, dimension-major
     float *partial;      // [blocks][kMlpParams] per-block parameter gradients
 };
 
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs a)
         const int32_t row = row0 + wr0 + 4 * lg + r;
         if (row < a.N)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) a.dx[(int64_t)row * kD + t * 16 + lr] = ax[t][r];
+            for (int t = 0; t < 4; ++t) a.dxT[(int64_t)(t * 16 + lr) * a.N + row] = f2bf(ax[t][r]);
     }
 
     // parameter gradients of the block's 64 samples
@@ -471,36 +471,110 @@ __global__ void k_adam_mlp(float *__restrict__ theta, float *__restrict__ m, flo
     mlp_copy(cp, j, th);
 }
 
-// Embeddings: one wave per node, lane d = dimension.  The gradient of E[v]
-// is the sum of dx over the batch samples whose set holds v (bits of the
-// node-major row, samples ascending); then Adam and the bf16 copy.
-__global__ __launch_bounds__(256) void k_adam_E(const uint32_t *__restrict__ bits, int32_t Wb,
-                                                const float *__restrict__ dx, float *__restrict__ E,
-                                                float *__restrict__ m, float *__restrict__ v,
-                                                uint16_t *__restrict__ Eb, float *__restrict__ keep, int64_t n,
-                                                AdamArgs o)
+// Embeddings.  dE = M^T dx, M the batch's sample x node membership matrix:
+// for the hub nodes that sit in most sets of a converged population this is
+// a dense contraction over the batch, so it runs on the matrix cores.  The B
+// operand (dx of the whole batch, bf16, dimension-major) is staged once per
+// block in LDS, rows padded by 8 elements so that the 16 rows a k-step reads
+// fall in different banks; each wave then walks tiles of 16 nodes: the A
+// operand is the tile's membership bits (node-major rows, one 32-bit word
+// per 32 samples) expanded to bf16 0/1, K = the batch; k-steps whose word is
+// zero for the whole tile are skipped.  Rows of nodes in some sample get
+// their gradient and touched[v] = 1; the others touched[v] = 0 (Adam is lazy
+// on E: those rows keep weights and moments).
+__global__ __launch_bounds__(1024) void k_grad_E(const uint32_t *__restrict__ bits, int32_t Wb,
+                                                const uint16_t *__restrict__ dxT, int32_t B, float *__restrict__ gE,
+                                                uint8_t *__restrict__ touched, int64_t n)
 {
-    const int64_t node = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (node >= n) return;
-    const uint32_t mine = lane < Wb ? bits[node * Wb + lane] : 0u;
-    float g = 0.f;
-    for (int w = 0; w < Wb; ++w) {
-        uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)mine, w);
-        while (x) {
-            const int s = w * 32 + __ffs(x) - 1;
-            x &= x - 1;
-            g += dx[(int64_t)s * kD + lane];
+    extern __shared__ __align__(16) uint16_t sB[];
+    const int32_t SB = B + 8;
+    for (int32_t c = threadIdx.x; c < kD * (B / 8); c += blockDim.x) {
+        const int32_t d = c / (B / 8), e = (c % (B / 8)) * 8;
+        *reinterpret_cast<uint4 *>(sB + d * SB + e) = *reinterpret_cast<const uint4 *>(dxT + (int64_t)d * B + e);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int64_t tiles = (n + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * nw + wv; tile < tiles; tile += (int64_t)gridDim.x * nw) {
+        const int64_t v0 = tile * 16;
+        const int64_t row = v0 + lr;
+        // lane (lr, lg) holds words 8 lg .. 8 lg + 7 of node v0 + lr
+        uint32_t w8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int ks = 8 * lg + u;
+            w8[u] = (row < n && ks < Wb) ? bits[row * Wb + ks] : 0u;
+        }
+        uint32_t rowany = 0u;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rowany |= w8[u];
+        rowany |= (uint32_t)__shfl_xor((int)rowany, 16, 64);
+        rowany |= (uint32_t)__shfl_xor((int)rowany, 32, 64);
+        if (lg == 0 && row < n) touched[row] = rowany != 0u;
+        if (__ballot(rowany != 0u) == 0) continue;
+        f32x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 32; ++ks) {
+            // word ks of this lane's row sits in lane lr + 16 (ks / 8), slot ks % 8
+            const uint32_t word = ks < Wb ? (uint32_t)__shfl((int)w8[ks & 7], lr + 16 * (ks >> 3), 64) : 0u;
+            if (__ballot(word != 0u) == 0) continue;
+            const uint32_t byte = (word >> (8 * lg)) & 0xFFu;
+            uint4 q;
+            q.x = ((byte & 1u) ? 0x3F80u : 0u) | ((byte & 2u) ? 0x3F800000u : 0u);
+            q.y = ((byte & 4u) ? 0x3F80u : 0u) | ((byte & 8u) ? 0x3F800000u : 0u);
+            q.z = ((byte & 16u) ? 0x3F80u : 0u) | ((byte & 32u) ? 0x3F800000u : 0u);
+            q.w = ((byte & 64u) ? 0x3F80u : 0u) | ((byte & 128u) ? 0x3F800000u : 0u);
+            const bf16x8 A = __builtin_bit_cast(bf16x8, q);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = mfma(A, ld8(sB + (t * 16 + lr) * SB + ks * 32 + lg * 8), acc[t]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t node = v0 + 4 * lg + r;
+            if (node < n)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) gE[node * kD + t * 16 + lr] = acc[t][r];
         }
     }
-    const int64_t i = node * kD + lane;
-    if (keep) keep[i] = g;
-    float th = E[i], mm = m[i], vv = v[i];
-    adam(th, mm, vv, g, o);
-    E[i] = th;
-    m[i] = mm;
-    v[i] = vv;
-    Eb[i] = f2bf(th);
+}
+
+size_t grad_E_lds(int32_t B)
+{
+    return (size_t)kD * (B + 8) * 2;
+}
+
+// Lazy Adam on E, four weights per thread: rows with touched[v] = 0 are
+// left alone; the others step with the global step count.
+__global__ void k_adam_E(const float *__restrict__ gE, const uint8_t *__restrict__ touched, float *__restrict__ E,
+                         float *__restrict__ m, float *__restrict__ v, uint16_t *__restrict__ Eb,
+                         float *__restrict__ keep, int64_t n, AdamArgs o)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // float4 index
+    if (q >= n * (kD / 4)) return;
+    const int64_t node = q / (kD / 4);
+    if (!touched[node]) {
+        if (keep) reinterpret_cast<float4 *>(keep)[q] = float4{0.f, 0.f, 0.f, 0.f};
+        return;
+    }
+    const float4 g = reinterpret_cast<const float4 *>(gE)[q];
+    float4 th = reinterpret_cast<float4 *>(E)[q];
+    float4 mm = reinterpret_cast<float4 *>(m)[q];
+    float4 vv = reinterpret_cast<float4 *>(v)[q];
+    adam(th.x, mm.x, vv.x, g.x, o);
+    adam(th.y, mm.y, vv.y, g.y, o);
+    adam(th.z, mm.z, vv.z, g.z, o);
+    adam(th.w, mm.w, vv.w, g.w, o);
+    reinterpret_cast<float4 *>(E)[q] = th;
+    reinterpret_cast<float4 *>(m)[q] = mm;
+    reinterpret_cast<float4 *>(v)[q] = vv;
+    uint2 h;
+    h.x = f2bf(th.x) | ((uint32_t)f2bf(th.y) << 16);
+    h.y = f2bf(th.z) | ((uint32_t)f2bf(th.w) << 16);
+    reinterpret_cast<uint2 *>(Eb)[q] = h;
+    if (keep) reinterpret_cast<float4 *>(keep)[q] = g;
 }
 
 // --------------------------------------------------------- GA-side steps ----
@@ -616,15 +690,13 @@ __global__ void k_iota(int32_t *__restrict__ out, int32_t count)
     if (i < count) out[i] = i;
 }
 
-// Copies the removed-node bit sets and alive counts of the pooled children.
-__global__ void k_gather_pool(const int32_t *__restrict__ pool, const uint32_t *__restrict__ masks, int32_t W,
-                              const int32_t *__restrict__ alive, uint32_t *__restrict__ cmasks,
-                              int32_t *__restrict__ calive)
+// Copies the rows of the selected children (pool entries q) to crows[q].
+__global__ void k_gather_pool_rows(const int32_t *__restrict__ pool, const int32_t *__restrict__ children, int32_t k,
+                                   int32_t *__restrict__ crows)
 {
     const int32_t q = blockIdx.x;
     const int32_t o = pool[q];
-    for (int32_t w = threadIdx.x; w < W; w += blockDim.x) cmasks[(int64_t)q * W + w] = masks[(int64_t)o * W + w];
-    if (threadIdx.x == 0) calive[q] = alive[o];
+    for (int32_t j = threadIdx.x; j < k; j += blockDim.x) crows[(int64_t)q * k + j] = children[(int64_t)o * k + j];
 }
 
 // Ring buffer: entry (base + q) mod cap takes child pool[q] (q when pool is
@@ -765,10 +837,11 @@ struct SurrogateState {
     bool last_screened = false, last_predicted = false;
     DevBuf theta, m, v, partial, keep_mlp, keep_E;      // float
     DevBuf Eb, W1b, W2b, w3b, W1bT, W2bT;               // bf16
-    DevBuf xb, yhat, ytrain, dx, target, lossv;         // per sample (yhat: the generation's predictions)
+    DevBuf xb, yhat, ytrain, dxT, target, lossv;        // per sample (yhat: the generation's predictions)
     DevBuf bgenes, bmasks, balive, bflag, brows;        // training batch
+    DevBuf gE, touched;                                 // embedding gradient, rows present in the batch
     DevBuf buf_genes, buf_y;                            // ring buffer
-    DevBuf pool, cmasks, calive;                        // screened children
+    DevBuf pool, crows, cmasks, calive;                 // screened children
     DevBuf dstats;                                      // double [8]: mu, sd, rho, rel_err, loss
     double *hstats = nullptr;                           // pinned copy of dstats
     hipEvent_t ready = nullptr;
@@ -849,7 +922,7 @@ int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B
     a.target = target;
     a.dscale = 2.0f / B;
     a.lossv = st.lossv.as<float>();
-    a.dx = st.dx.as<float>();
+    a.dxT = st.dxT.as<uint16_t>();
     a.partial = st.partial.as<float>();
     const int32_t nblk = (B + kMlpRows - 1) / kMlpRows;
     hipLaunchKernelGGL(k_mlp<true>, dim3(nblk), dim3(256), kMlpLds, s, a);
@@ -867,9 +940,14 @@ int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B
     if ((rc = launch_bits_transpose(st.bmasks.as<uint32_t>(), B, g->words, g->n, st.brows.as<uint32_t>(), s)) !=
         GAPA_OK)
         return rc;
-    const int64_t threads = (int64_t)st.n * 64;
-    hipLaunchKernelGGL(k_adam_E, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, st.brows.as<uint32_t>(),
-                       Wb, st.dx.as<float>(), st.theta.as<float>(), st.m.as<float>(), st.v.as<float>(),
+    const int64_t tiles = ((int64_t)st.n + 15) / 16;
+    // one 16-wave block per compute unit shares one staged copy of dx
+    const unsigned eblocks = (unsigned)std::min<int64_t>((tiles + 15) / 16, 256);
+    hipLaunchKernelGGL(k_grad_E, dim3(eblocks), dim3(1024), grad_E_lds(B), s, st.brows.as<uint32_t>(), Wb,
+                       st.dxT.as<uint16_t>(), B, st.gE.as<float>(), st.touched.as<uint8_t>(), (int64_t)st.n);
+    const int64_t quads = (int64_t)st.n * (kD / 4);
+    hipLaunchKernelGGL(k_adam_E, dim3((unsigned)((quads + 255) / 256)), dim3(256), 0, s, st.gE.as<float>(),
+                       st.touched.as<uint8_t>(), st.theta.as<float>(), st.m.as<float>(), st.v.as<float>(),
                        st.Eb.as<uint16_t>(), keep ? st.keep_E.as<float>() : nullptr, (int64_t)st.n, o);
     GAPA_HIP(hipGetLastError());
     st.have_keep = keep;
@@ -950,7 +1028,7 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->xb, (size_t)rows * kD * 2);
     res(st->yhat, (size_t)rows * 4);
     res(st->ytrain, (size_t)B * 4);
-    res(st->dx, (size_t)B * kD * 4);
+    res(st->dxT, (size_t)B * kD * 2);
     res(st->target, (size_t)B * 4);
     res(st->lossv, (size_t)B * 4);
     res(st->bgenes, (size_t)B * st->k * 4);
@@ -958,9 +1036,12 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->balive, (size_t)B * 4);
     res(st->bflag, 16);
     res(st->brows, (size_t)st->n * (B / 32) * 4);
+    res(st->gE, (size_t)nE * 4);
+    res(st->touched, (size_t)st->n);
     res(st->buf_genes, (size_t)sp->buffer * st->k * 4);
     res(st->buf_y, (size_t)sp->buffer * 8);
     res(st->pool, (size_t)L * 4);
+    res(st->crows, (size_t)(sp->screen + kJudgeExtra) * st->k * 4);
     res(st->cmasks, (size_t)(sp->screen + kJudgeExtra) * st->W * 4);
     res(st->calive, (size_t)(sp->screen + kJudgeExtra) * 4);
     res(st->dstats, 64);
@@ -974,6 +1055,8 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMlpLds));
     GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_screen), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)screen_lds(kMaxLambda)));
+    GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_grad_E), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)grad_E_lds(1024)));
     const unsigned blocks = (unsigned)((P + 255) / 256);
     hipLaunchKernelGGL(k_surr_init, dim3(blocks), dim3(256), 0, s, st->theta.as<float>(), (int64_t)st->n, st->seed,
                        0.05, std::sqrt(6.0 / kD), std::sqrt(6.0 / kH), std::sqrt(3.0 / kH));
@@ -991,9 +1074,10 @@ void surrogate_release(SurrogateState *st)
 {
     if (!st) return;
     for (DevBuf *b : {&st->theta, &st->m, &st->v, &st->partial, &st->keep_mlp, &st->keep_E, &st->Eb, &st->W1b,
-                      &st->W2b, &st->w3b, &st->W1bT, &st->W2bT, &st->xb, &st->yhat, &st->ytrain, &st->dx, &st->target,
-                      &st->lossv, &st->bgenes, &st->bmasks, &st->balive, &st->bflag, &st->brows, &st->buf_genes,
-                      &st->buf_y, &st->pool, &st->cmasks, &st->calive, &st->dstats})
+                      &st->W2b, &st->w3b, &st->W1bT, &st->W2bT, &st->xb, &st->yhat, &st->ytrain, &st->dxT, &st->target,
+                      &st->lossv, &st->bgenes, &st->bmasks, &st->balive, &st->bflag, &st->brows, &st->gE, &st->touched,
+                      &st->buf_genes,
+                      &st->buf_y, &st->pool, &st->crows, &st->cmasks, &st->calive, &st->dstats})
         b->release();
     if (st->hstats) (void)hipHostFree(st->hstats);
     if (st->ready) (void)hipEventDestroy(st->ready);
@@ -1013,7 +1097,8 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         st.force_full = false;
     }
     const int32_t L = st.lambda;
-    if ((rc = ga_launch_offspring(ga, s)) != GAPA_OK) return rc;
+    // a screened generation builds bit sets only for the children it evaluates
+    if ((rc = ga_launch_offspring(ga, s, !full)) != GAPA_OK) return rc;
     const bool predict = !random && (int64_t)gen > st.sp.warmup_gens;
     float *yhat = st.yhat.as<float>();
     if (predict && (rc = predict_rows(st, ga->children.as<int32_t>(), nullptr, L, yhat, s)) != GAPA_OK) return rc;
@@ -1033,9 +1118,14 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         pool = st.pool.as<int32_t>();
         hipLaunchKernelGGL(k_screen, dim3(1), dim3(1024), screen_lds(L), s, random ? nullptr : yhat, L, npool, extra,
                            st.seed, gen, st.pool.as<int32_t>());
-        hipLaunchKernelGGL(k_gather_pool, dim3(neval), dim3(256), 0, s, pool, ga->masks.as<uint32_t>(), st.W,
-                           ga->alive.as<int32_t>(), st.cmasks.as<uint32_t>(), st.calive.as<int32_t>());
+        hipLaunchKernelGGL(k_gather_pool_rows, dim3(neval), dim3(256), 0, s, pool, ga->children.as<int32_t>(), st.k,
+                           st.crows.as<int32_t>());
         GAPA_HIP(hipGetLastError());
+        gapa_graph *g = ga->graph;
+        if ((rc = launch_mask_build(st.crows.as<int32_t>(), neval, st.k, g->n, g->words, g->d_noniso, g->n_noniso,
+                                    st.cmasks.as<uint32_t>(), st.calive.as<int32_t>(), st.bflag.as<int32_t>(), s)) !=
+            GAPA_OK)
+            return rc;
         if ((rc = eval_masks(ga->graph, st.cmasks.as<uint32_t>(), st.calive.as<int32_t>(), neval, F, nullptr, ga->ws,
                              &ga->timer, s)) != GAPA_OK)
             return rc;

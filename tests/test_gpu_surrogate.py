@@ -108,7 +108,7 @@ def test_adam_step_matches_formula(gp):
     ga.train_batch(torch.from_numpy(sets).cuda(), torch.from_numpy(target).cuda(), keep_grads=True)
     grads = {name: ga.surrogate_tensor(name, grad=True, n=g.n).astype(np.float64) for name in S.TENSORS}
     q = {k: v.copy() for k, v in p.items()}
-    S.Adam(q, lr=1e-3).step(q, grads)
+    S.Adam(q, lr=1e-3).step(q, grads, rows=S.batch_rows(sets))
     got = weights(ga, g.n)
     for name in S.TENSORS:
         assert np.max(np.abs(got[name] - q[name])) <= 2e-6, name

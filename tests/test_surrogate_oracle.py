@@ -169,6 +169,33 @@ def test_adam_matches_torch():
         assert np.allclose(q[k], tp[k].detach().numpy(), rtol=1e-12, atol=1e-15), k
 
 
+def test_lazy_adam_on_embeddings_matches_torch_sparse_adam():
+    """Rows outside the batch keep weights and moments; the others follow
+    torch.optim.SparseAdam (the lazy variant for sparse gradients)."""
+    rng = np.random.default_rng(13)
+    p = tiny_params(rng, n=12, D=3, H=4)
+    q = {k: v.copy() for k, v in p.items()}
+    opt = S.Adam(q, lr=1e-3)
+    E = torch.tensor(p["E"], dtype=torch.float64, requires_grad=True)
+    topt = torch.optim.SparseAdam([E], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    seen = set()
+    for step in range(4):
+        sets = rng.integers(0, 12, size=(3, 2))
+        rows = S.batch_rows(sets)
+        seen.update(rows.tolist())
+        g = {k: rng.normal(size=v.shape) for k, v in p.items()}
+        g["E"][np.setdiff1d(np.arange(12), rows)] = 0.0
+        opt.step(q, g, rows=rows)
+        E.grad = torch.sparse_coo_tensor(torch.tensor(rows)[None, :], torch.tensor(g["E"][rows]), (12, 3))
+        topt.step()
+    # SparseAdam adds eps to sqrt(v) before the bias correction (eps scaled
+    # by sqrt(1 - b2^t)): ~1e-10 here; a wrong row set would differ by ~1e-3
+    assert np.allclose(q["E"], E.detach().numpy(), rtol=0, atol=1e-8)
+    never = np.setdiff1d(np.arange(12), sorted(seen))
+    assert never.size > 0 and np.array_equal(q["E"][never], p["E"][never])
+    assert np.all(opt.m["E"][never] == 0) and np.all(opt.v["E"][never] == 0)
+
+
 def test_screen_brute_force_with_ties():
     rng = np.random.default_rng(9)
     yhat = rng.integers(0, 20, size=300).astype(np.float64)  # many ties
