@@ -107,6 +107,10 @@ def run_batched(args, torch, gapa, inputs):
     bt = gapa.Batch(graphs, params, stream=stream, replay=not args.no_replay)
     bt.step(args.warmup, stream=stream)
     torch.cuda.synchronize()
+    tuning = None if args.no_autotune else bt.autotune(reps=3, stream=stream)
+    bt.step(2, stream=stream)
+    torch.cuda.synchronize()
+    args.warmup += 2
     t0 = time.perf_counter()
     bt.step(args.steps, stream=stream)
     torch.cuda.synchronize()
@@ -132,6 +136,7 @@ def run_batched(args, torch, gapa, inputs):
         "dtype": "int64", "data": "synthetic",
         "config": {"workload": "batched64_p128", "instances": len(ws), "sum_n": sum(w.graph.n for w in ws),
                    "sum_m": sum(w.graph.m for w in ws), "pop": 128, "k": "n/100", "replay": not args.no_replay,
+                   "tuning": tuning,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "fitness_pass", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -139,6 +144,73 @@ def run_batched(args, torch, gapa, inputs):
                      "algorithmic_bytes_per_launch": unit_bytes},
         "operator_ms_per_step": {k: v[1] / v[0] for k, v in sorted(passes.items()) if k != "fitness_pass"},
     }
+
+
+def time_to_target(torch, gapa, inputs, seeds=(0,), cap_factor=2.0):
+    """Wall time until the best pairwise connectivity reaches the plain GA's
+    generation-500 value on the 200k-node workload: the plain GA (1024
+    offspring, all evaluated), the surrogate-screened GA (4096 offspring, the
+    512 with the lowest predictions evaluated, network trained online) and
+    the random-screening ablation (4096 offspring, 512 chosen at random).
+    Clocks start before GA creation (initial population included) and
+    include training; every run checks its best after each generation."""
+    base = inputs.workload("cl200k_k2000_p1024")
+    sw = inputs.workload("cl200k_k2000_p1024_screen4096")
+    graph = gapa.Graph.from_csr(base.graph, trust=True)
+    stream = torch.cuda.Stream()
+
+    def run(kind, seed, target=None, gens=None, cap_s=None):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "plain":
+            ga = gapa.GA(graph, base.k, base.pop, seed, base.pc, base.pm, base.tournament, base.offspring,
+                         stream=stream, replay=True)
+        else:
+            ga = gapa.GA(graph, sw.k, sw.pop, seed, sw.pc, sw.pm, sw.tournament, sw.offspring, stream=stream)
+            ga.attach_surrogate(screen=sw.exact_top, batch=1024, train_steps=4, warmup_gens=10, buffer=65536,
+                                fallback_gens=3, random_screen=(kind == "random"), stream=stream)
+        g, best, hit = 0, None, None
+        while True:
+            ga.step(1, stream=stream)
+            g += 1
+            best = ga.best()[1]
+            el = time.perf_counter() - t0
+            if target is not None and hit is None and best <= target:
+                hit = (el, g)
+                if gens is None:
+                    break
+            if gens is not None and g >= gens:
+                break
+            if cap_s is not None and el > cap_s:
+                break
+        stats = ga.surrogate_stats() if kind != "plain" else None
+        ga.close()
+        return {"best": int(best), "gens": g, "wall_s": time.perf_counter() - t0, "hit": hit, "stats": stats}
+
+    out = []
+    for seed in seeds:
+        print(f"# time-to-target seed {seed}: plain", file=sys.stderr, flush=True)
+        plain = run("plain", seed, gens=base.generations)
+        target = plain["best"]
+        plain_hit = run("plain", seed, target=target, gens=None)
+        cap = cap_factor * plain["wall_s"]
+        print(f"# target {target}, plain {plain['wall_s']:.3f} s; surrogate", file=sys.stderr, flush=True)
+        surr = run("surrogate", seed, target=target, cap_s=cap)
+        print("# random screening", file=sys.stderr, flush=True)
+        rnd = run("random", seed, target=target, cap_s=cap)
+        rec = {"seed": seed, "target_pc": target, "plain_500_gens_s": plain["wall_s"],
+               "plain_s": plain_hit["hit"][0], "plain_gens": plain_hit["hit"][1]}
+        for name, r in (("surrogate", surr), ("random", rnd)):
+            rec[name + "_s"] = r["hit"][0] if r["hit"] else None
+            rec[name + "_gens"] = r["hit"][1] if r["hit"] else None
+            rec[name + "_best_at_stop"] = r["best"]
+            rec[name + "_gens_run"] = r["gens"]
+        st = surr["stats"]
+        rec["surrogate_last_spearman"] = st["spearman"]
+        rec["surrogate_fallbacks"] = st["fallbacks"]
+        rec["speedup_vs_plain"] = (rec["plain_s"] / rec["surrogate_s"]) if rec["surrogate_s"] else None
+        out.append(rec)
+    return {"cap": f"{cap_factor} x plain 500-generation wall time", "runs": out}
 
 
 def copy_calibration():
@@ -166,6 +238,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-replay", action="store_true", help="launch generations eagerly instead of replaying a "
                     "recorded HIP graph")
+    ap.add_argument("--no-time-to-target", action="store_true", help="skip the surrogate time-to-target runs")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes of the fitness pass")
+    ap.add_argument("--ttt-seeds", default="0", help="comma-separated seeds of the time-to-target runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build evaluates one GPU's share of the population "
@@ -199,6 +274,11 @@ def main():
                  replay=not args.no_replay)
     ga.step(args.warmup, stream=stream)
     torch.cuda.synchronize()
+    # launch shapes of the fitness pass, chosen on the warmed-up population
+    tuning = graph.get_tuning() if args.no_autotune else ga.autotune(reps=3, stream=stream)
+    ga.step(2, stream=stream)  # one eager generation re-records the replayed one with the new shapes
+    torch.cuda.synchronize()
+    args.warmup += 2
 
     # timed region: exactly K generations
     t0 = time.perf_counter()
@@ -254,7 +334,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "graph": g.name, "n": g.n, "m": g.m, "k": w.k, "pop": w.pop,
                    "offspring": lam, "pc": w.pc, "pm": w.pm, "tournament": w.tournament,
-                   "replay": not args.no_replay, "parallelism": "single GPU"},
+                   "replay": not args.no_replay, "tuning": tuning, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "fitness_pass", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["bytes_per_pass"] if traffic else None,
@@ -267,6 +347,8 @@ def main():
         "best_pc": best_f,
         "generation": gen_count,
     }
+    if not args.no_time_to_target:
+        out["time_to_target"] = time_to_target(torch, gapa, inputs, [int(x) for x in args.ttt_seeds.split(",")])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)

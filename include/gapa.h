@@ -330,7 +330,7 @@ GAPA_API int gapa_ga_fitness_stats(gapa_ga *ga, int64_t out[4]);
  *   band_scan    neighbours a node reads in the ordered sweep, >= 1
  *   sweeps       follow-up sweeps over the nodes still pending, 0..32
  *   band_blocks  block cap of one band launch, 1..65535
- * Defaults 4096, 64, 4, 8192.  A change also applies to GAs and batches on
+ * Defaults 4096, 32, 3, 8192.  A change also applies to GAs and batches on
  * the graph (recorded generations are re-recorded). */
 typedef struct gapa_tuning {
     int32_t sweep_grid;
@@ -344,7 +344,7 @@ GAPA_API int gapa_graph_set_tuning(gapa_graph *g, const gapa_tuning *t);
 
 /* Autotuner: times `reps` >= 1 fitness passes over the children the GA (or
  * batch) currently holds for each launch shape of a fixed candidate grid
- * (sweep_grid 2048/4096/8192, band_scan 32/64/128, sweeps 3/4/6, band_blocks
+ * (sweep_grid 2048/4096/8192, band_scan 16/32/64, sweeps 2/3/4, band_blocks
  * 4096/16384), keeps the fastest on the evaluating graph and returns it
  * through best_out (may be NULL).  Work is enqueued on `stream` and waited
  * for.  It overwrites only scratch fitness values; the GA state is

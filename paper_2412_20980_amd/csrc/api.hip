@@ -967,7 +967,7 @@ int gapa_ga_autotune(gapa_ga *ga, int32_t reps, void *stream, gapa_tuning *best_
     const Tuning saved = g->tune;
     Tuning best = saved;
     double best_t = 1e300;
-    const int32_t grids[3] = {2048, 4096, 8192}, scans[3] = {32, 64, 128}, sweeps[3] = {3, 4, 6};
+    const int32_t grids[3] = {2048, 4096, 8192}, scans[3] = {16, 32, 64}, sweeps[3] = {2, 3, 4};
     const int32_t bands[2] = {4096, 16384};
     int rc = GAPA_OK;
     for (int32_t gi : grids)

@@ -306,43 +306,51 @@ __device__ __forceinline__ int32_t block_reserve(int32_t mine, int32_t *counter,
     return *s_base;
 }
 
-constexpr int kCompactRange = 64;   // input items per compaction block
+constexpr int kCompactRange = 64;   // input items per compaction step
+constexpr int kPendSteps = 8;       // steps per block in k_collect_pending
 
 // Nodes still pending after the ordered sweep -> worklist.  A block owns
-// kCompactRange nodes; every thread issues the loads of all its (node, word)
-// entries before testing any of them.
+// kPendSteps * kCompactRange nodes, taken kCompactRange at a time; in each
+// step every thread issues the loads of all its (node, word) entries before
+// testing any of them.  Found nodes gather in LDS, and the block reserves its
+// room in the worklist with a single global atomic (atomics on one address
+// serialise: fewer, larger blocks keep them off the critical path).
 __global__ __launch_bounds__(kBlk) void k_collect_pending(const int32_t *__restrict__ band_v, int32_t count,
                                                           int32_t Wd, const uint32_t *__restrict__ dead,
                                                           const uint32_t *__restrict__ reach,
                                                           int32_t *__restrict__ worklist, int32_t *__restrict__ wl_count)
 {
     __shared__ int32_t s_tot, s_base, s_off;
-    __shared__ int32_t s_list[kCompactRange];
+    __shared__ int32_t s_list[kPendSteps * kCompactRange];
     const int w = threadIdx.x & (Wd - 1);
     const uint64_t gmask = group_mask(Wd);
     const int32_t gpb = blockDim.x / Wd;
-    const int32_t r0 = blockIdx.x * kCompactRange, r1 = min(count, r0 + kCompactRange);
     if (threadIdx.x == 0) s_off = 0;
-    // iterations: kCompactRange / gpb = kCompactRange * Wd / kBlk <= kIter
-    constexpr int kIter = kCompactRange * 32 / kBlk;
-    uint32_t pend[kIter];
-    int32_t vv[kIter];
-    const int32_t iters = (kCompactRange + gpb - 1) / gpb;
-#pragma unroll
-    for (int it = 0; it < kIter; ++it) {
-        const int32_t idx = r0 + it * gpb + (int32_t)(threadIdx.x / Wd);
-        vv[it] = (it < iters && idx < r1) ? band_v[idx] : -1;
-    }
-#pragma unroll
-    for (int it = 0; it < kIter; ++it) {
-        const int32_t v = vv[it];
-        pend[it] = v >= 0 ? (~dead[(int64_t)v * Wd + w] & ~reach[(int64_t)v * Wd + w]) : 0u;
-    }
     __syncthreads();
+    // iterations per step: kCompactRange / gpb = kCompactRange * Wd / kBlk <= kIter
+    constexpr int kIter = kCompactRange * 32 / kBlk;
+    const int32_t iters = (kCompactRange + gpb - 1) / gpb;
+    for (int step = 0; step < kPendSteps; ++step) {
+        const int32_t r0 = (blockIdx.x * kPendSteps + step) * kCompactRange;
+        if (r0 >= count) break;  // uniform over the block
+        const int32_t r1 = min(count, r0 + kCompactRange);
+        uint32_t pend[kIter];
+        int32_t vv[kIter];
 #pragma unroll
-    for (int it = 0; it < kIter; ++it) {
-        const bool any = (__ballot(pend[it] != 0) & gmask) != 0;
-        if (vv[it] >= 0 && any && w == 0) s_list[atomicAdd(&s_off, 1)] = vv[it];
+        for (int it = 0; it < kIter; ++it) {
+            const int32_t idx = r0 + it * gpb + (int32_t)(threadIdx.x / Wd);
+            vv[it] = (it < iters && idx < r1) ? band_v[idx] : -1;
+        }
+#pragma unroll
+        for (int it = 0; it < kIter; ++it) {
+            const int32_t v = vv[it];
+            pend[it] = v >= 0 ? (~dead[(int64_t)v * Wd + w] & ~reach[(int64_t)v * Wd + w]) : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < kIter; ++it) {
+            const bool any = (__ballot(pend[it] != 0) & gmask) != 0;
+            if (vv[it] >= 0 && any && w == 0) s_list[atomicAdd(&s_off, 1)] = vv[it];
+        }
     }
     __syncthreads();
     const int32_t found = s_off;
@@ -385,8 +393,9 @@ __global__ void k_pull_worklist(const int32_t *__restrict__ worklist, const int3
 // several instances directly into other[i]).
 // The rest go to the pair list for the union-find (parent[i][v] = v).
 // Padding individuals remove every node, so their bits are never pending.
-// Each block owns kCompactRange worklist entries: one pass counts, one global
-// atomic reserves, a second pass writes.
+// A block takes kPairRange worklist entries at a time: one pass splits every
+// (node, word) entry and keeps the result in registers, one global atomic
+// reserves room, a second pass writes the pairs.
 __device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t gmask,
                                               const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
                                               const uint32_t *__restrict__ dead, const uint32_t *__restrict__ reach,
@@ -404,6 +413,8 @@ __device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t
     multi = pend & nb;
 }
 
+constexpr int kPairRange = 64;  // worklist entries per reservation in k_collect_pairs
+
 __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restrict__ worklist,
                                                         const int32_t *__restrict__ wl_count, int32_t Wd, const Insts I,
                                                         const int32_t *__restrict__ row_ptr,
@@ -419,23 +430,37 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restric
     const uint64_t gmask = group_mask(Wd);
     const int32_t gpb = blockDim.x / Wd;
     // singleton counts: per-block LDS counters written as a partial row when
-    // all slots fit (one instance), else global atomics per slot
+    // all slots fit (one instance, at most 1024 slots), else global atomics
     const int32_t B = I.count * I.bseg;
     const bool lds_singles = I.count == 1;
     const int32_t count = *wl_count;
-    if ((int64_t)blockIdx.x * kCompactRange >= count) return;  // no range: no partial row (see k_single_sum)
-    for (int32_t t = threadIdx.x; t < B; t += blockDim.x) s_single[t] = 0;
+    if ((int64_t)blockIdx.x * kPairRange >= count) return;  // no range: no partial row (see k_single_sum)
+    if (lds_singles)
+        for (int32_t t = threadIdx.x; t < B; t += blockDim.x) s_single[t] = 0;
     __syncthreads();
-    for (int32_t r0 = blockIdx.x * kCompactRange; r0 < count; r0 += gridDim.x * kCompactRange) {
-        const int32_t r1 = min(count, r0 + kCompactRange);
+    // entries per thread and range: kPairRange / gpb <= kIter (Wd <= 32)
+    constexpr int kIter = kPairRange * 32 / kBlk;
+    const int32_t iters = (kPairRange + gpb - 1) / gpb;
+    for (int32_t r0 = blockIdx.x * kPairRange; r0 < count; r0 += gridDim.x * kPairRange) {
+        const int32_t r1 = min(count, r0 + kPairRange);
+        // one split per (node, word), kept for the write pass
+        uint32_t multi[kIter];
+        int32_t vv[kIter];
         int32_t mine = 0;
-        for (int32_t idx0 = r0; idx0 < r1; idx0 += gpb) {
-            const int32_t idx = idx0 + (int32_t)(threadIdx.x / Wd);
-            const bool valid = idx < r1;
+#pragma unroll
+        for (int it = 0; it < kIter; ++it) {
+            const int32_t idx = r0 + it * gpb + (int32_t)(threadIdx.x / Wd);
+            const bool valid = it < iters && idx < r1;
             const int32_t v = valid ? worklist[idx] : 0;
-            uint32_t single, multi;
-            pending_split(v, Wd, w, gmask, row_ptr, colD, dead, reach, valid, single, multi);
-            mine += __popc(multi);
+            vv[it] = v;
+            uint32_t single, mul;
+            if (it < iters) {  // uniform over the block
+                pending_split(v, Wd, w, gmask, row_ptr, colD, dead, reach, valid, single, mul);
+            } else {
+                single = mul = 0u;
+            }
+            multi[it] = mul;
+            mine += __popc(mul);
             const int32_t gbase = inst_of_node(I, v) * I.bseg + w * 32;
             for (; single; single &= single - 1) {
                 if (lds_singles) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
@@ -443,18 +468,16 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restric
             }
         }
         const int32_t base = block_reserve(mine, pair_count, &s_tot, &s_base, &s_off);
-        for (int32_t idx0 = r0; idx0 < r1; idx0 += gpb) {
-            const int32_t idx = idx0 + (int32_t)(threadIdx.x / Wd);
-            const bool valid = idx < r1;
-            const int32_t v = valid ? worklist[idx] : 0;
-            uint32_t single, multi;
-            pending_split(v, Wd, w, gmask, row_ptr, colD, dead, reach, valid, single, multi);
-            if (!multi) continue;
-            int32_t q = base + atomicAdd(&s_off, __popc(multi));
+#pragma unroll
+        for (int it = 0; it < kIter; ++it) {
+            uint32_t mul = multi[it];
+            if (!mul) continue;
+            const int32_t v = vv[it];
+            int32_t q = base + atomicAdd(&s_off, __popc(mul));
             const int32_t b = inst_of_node(I, v);
             const int32_t vl = v - i_voff(I, b);
-            for (; multi; multi &= multi - 1) {
-                const int32_t gi = b * I.bseg + w * 32 + __ffs(multi) - 1;
+            for (; mul; mul &= mul - 1) {
+                const int32_t gi = b * I.bseg + w * 32 + __ffs(mul) - 1;
                 pairs[q++] = ((int64_t)gi << 32) | (uint32_t)v;
                 parent[uf_block(I, gi) + vl] = vl;
             }
@@ -574,7 +597,7 @@ __global__ void k_single_sum(const int32_t *__restrict__ single_part, const int3
                              int32_t nparts, int32_t B, int32_t *__restrict__ other)
 {
     const int32_t i = blockIdx.x * 64 + threadIdx.x;
-    const int32_t used = min(nparts, (*wl_count + kCompactRange - 1) / kCompactRange);
+    const int32_t used = min(nparts, (*wl_count + kPairRange - 1) / kPairRange);
     const int32_t b0 = blockIdx.y * kSumRows;
     if (i >= B || b0 >= used) return;
     const int32_t b1 = min(used, b0 + kSumRows);
@@ -696,7 +719,8 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         }
         if (noniso > 0) {
             TimedScope ts(timer, "k_collect_pending", s);
-            hipLaunchKernelGGL(k_collect_pending, dim3((unsigned)((noniso + kCompactRange - 1) / kCompactRange)),
+            const int32_t per_block = kPendSteps * kCompactRange;
+            hipLaunchKernelGGL(k_collect_pending, dim3((unsigned)((noniso + per_block - 1) / per_block)),
                                dim3(kBlk), 0, s, g->d_band_v, noniso, Wd, dead, reach, worklist, wl_count);
         }
         {

@@ -102,8 +102,8 @@ struct FitnessWorkspace {
 // them; only speed does).
 struct Tuning {
     int32_t sweep_grid = 4096;   // blocks of the worklist, pair and union-find kernels
-    int32_t band_scan = 64;      // neighbours read per node in the ordered sweep
-    int32_t sweeps = 4;          // follow-up sweeps over the pending nodes
+    int32_t band_scan = 32;      // neighbours read per node in the ordered sweep
+    int32_t sweeps = 3;          // follow-up sweeps over the pending nodes
     int32_t band_blocks = 8192;  // block cap of one band launch
 };
 

@@ -253,7 +253,7 @@ class Graph:
         _check(lib().gapa_graph_get_tuning(self.handle, C.byref(t)))
         return {f: getattr(t, f) for f, _ in t._fields_}
 
-    def set_tuning(self, sweep_grid=4096, band_scan=64, sweeps=4, band_blocks=8192):
+    def set_tuning(self, sweep_grid=4096, band_scan=32, sweeps=3, band_blocks=8192):
         t = gapa_tuning(sweep_grid=sweep_grid, band_scan=band_scan, sweeps=sweeps, band_blocks=band_blocks)
         _check(lib().gapa_graph_set_tuning(self.handle, C.byref(t)))
 
