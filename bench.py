@@ -2,6 +2,7 @@
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-replay]
   python bench.py --workload batched64    # 64 independent GAs advanced together
+  python bench.py --workload surrogate    # screened generations (4096 offspring, 512 evaluated)
   python bench.py --copy-calibration      # plain 1 GiB copies, for counter scaling
 
 A step is one whole generation of the method on the device: tournament
@@ -213,6 +214,35 @@ def time_to_target(torch, gapa, inputs, seeds=(0,), cap_factor=2.0):
     return {"cap": f"{cap_factor} x plain 500-generation wall time", "runs": out}
 
 
+def run_surrogate(args, torch, gapa, inputs):
+    """Screened generations on the 200k-node workload: 4096 offspring, the 512
+    with the lowest predictions (plus 32 random others for the judge)
+    evaluated exactly, 4 Adam steps per generation; warm-up generations
+    (full evaluation) are not timed."""
+    w = inputs.workload("cl200k_k2000_p1024_screen4096")
+    graph = gapa.Graph.from_csr(w.graph, trust=True)
+    stream = torch.cuda.Stream()
+    ga = gapa.GA(graph, w.k, w.pop, w.seed, w.pc, w.pm, w.tournament, w.offspring, stream=stream)
+    ga.attach_surrogate(screen=w.exact_top, batch=1024, train_steps=4, warmup_gens=10, buffer=65536, fallback_gens=0,
+                        stream=stream)
+    ga.step(args.warmup, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ga.step(args.steps, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ga.surrogate_stats()
+    return {
+        "metric": METRIC, "value": w.offspring * args.steps / dt, "unit": "offspring screened/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+int64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "offspring": w.offspring, "screened": w.exact_top, "judge_extra": 32,
+                   "train_steps": 4, "batch": 1024, "parallelism": "single GPU"},
+        "surrogate": st,
+    }
+
+
 def copy_calibration():
     import torch
     n = 1 << 28  # 2^28 float32 = 1 GiB
@@ -256,6 +286,11 @@ def main():
 
     from paper_2412_20980_amd import gapa, inputs
 
+    if args.workload == "surrogate":
+        args.warmup = 20 if args.warmup is None else args.warmup
+        args.steps = 20 if args.steps is None else args.steps
+        print(json.dumps(run_surrogate(args, torch, gapa, inputs)), flush=True)
+        return
     if args.workload == "batched64":
         args.warmup = 40 if args.warmup is None else args.warmup
         args.steps = 160 if args.steps is None else args.steps
