@@ -51,9 +51,14 @@ def algorithmic_bytes_per_eval(n: int, nnz: int) -> int:
     return 4 * (n + 1) + 4 * nnz + 4 * math.ceil(n / 32) + 8 * n + 8
 
 
+FITNESS_SOURCES = ("fitness_bits.hip", "fitness.hip", "device_common.h")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources of the fitness-pass kernels (the ones the traffic
+    counters were taken on)."""
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2412_20980_amd", "csrc", "*"))):
+    for path in [os.path.join(ROOT, "paper_2412_20980_amd", "csrc", f) for f in FITNESS_SOURCES]:
         with open(path, "rb") as f:
             h.update(os.path.basename(path).encode())
             h.update(f.read())

@@ -83,11 +83,13 @@ __device__ __forceinline__ Op resolve(const OpArgs &a)
 }
 
 // LDS of one operator block: membership bits over the nodes, the row by slot,
-// a list of slots, and three bit sets over the slots.
+// a list of slots (16-bit: the LDS limit keeps k far below 65536), and three
+// bit sets over the slots.  Kept small so that four blocks fit a compute unit
+// at n = 200k, k = 2000.
 struct OpLds {
     uint32_t *U;          // [W]
     int32_t *row;         // [k]
-    int32_t *list;        // [k]
+    uint16_t *list;       // [k, rounded up to even]
     uint32_t *from_donor; // [KW]
     uint32_t *dup;        // [KW]
     uint32_t *mut;        // [KW]
@@ -98,8 +100,8 @@ __device__ __forceinline__ OpLds carve(uint32_t *smem, const Op &a)
     OpLds l;
     l.U = smem;
     l.row = reinterpret_cast<int32_t *>(smem + a.W);
-    l.list = l.row + a.k;
-    l.from_donor = reinterpret_cast<uint32_t *>(l.list + a.k);
+    l.list = reinterpret_cast<uint16_t *>(l.row + a.k);
+    l.from_donor = reinterpret_cast<uint32_t *>(l.list + ((a.k + 1) & ~1));
     l.dup = l.from_donor + a.KW;
     l.mut = l.dup + a.KW;
     return l;
@@ -130,7 +132,7 @@ __device__ int32_t first_non_member(const uint32_t *U, uint32_t u, uint32_t t0, 
 
 // Slots whose bit is set in bits[0 .. ceil(k/32)), ascending, into list[];
 // returns how many.  Run by one whole wave.
-__device__ int32_t wave_list_slots(const uint32_t *bits, int32_t k, int32_t *list)
+__device__ int32_t wave_list_slots(const uint32_t *bits, int32_t k, uint16_t *list)
 {
     const int lane = threadIdx.x & 63;
     int32_t count = 0;
@@ -138,7 +140,7 @@ __device__ int32_t wave_list_slots(const uint32_t *bits, int32_t k, int32_t *lis
         const int32_t j = j0 + lane;
         const bool on = j < k && ((bits[j >> 5] >> (j & 31)) & 1u);
         const uint64_t mask = __ballot(on);
-        if (on) list[count + __popcll(mask & ((1ull << lane) - 1ull))] = j;
+        if (on) list[count + __popcll(mask & ((1ull << lane) - 1ull))] = (uint16_t)j;
         count += __popcll(mask);
     }
     return count;
@@ -153,7 +155,7 @@ __device__ int32_t wave_list_slots(const uint32_t *bits, int32_t k, int32_t *lis
 // earlier lane).  All lanes before the first rejected one are committed at
 // once; the rejected one is resolved alone with further attempts, exactly as
 // the sequential rule would; the next batch starts after it.
-__device__ void wave_draw_in_order(const OpLds &l, const Op &a, const int32_t *list, int32_t count, bool swap,
+__device__ void wave_draw_in_order(const OpLds &l, const Op &a, const uint16_t *list, int32_t count, bool swap,
                                    uint32_t ind, uint32_t gen, uint32_t stream)
 {
     const int lane = threadIdx.x & 63;
@@ -254,14 +256,14 @@ __device__ void emit(const OpLds &l, const Op &a, int32_t idx)
     int32_t total = 0, gone_total = 0;
     (void)block_exclusive_scan(gone, &gone_total);
     int32_t off = block_exclusive_scan(cnt, &total);
-    // the sorted row is staged in LDS (the slot list is free by now) and
-    // written out coalesced
+    // the sorted row is staged in LDS (the row by slot is no longer needed)
+    // and written out coalesced
     for (int32_t w = w0; w < w1; ++w)
         for (uint32_t bits = l.U[w]; bits; bits &= bits - 1)
-            if (off < a.k) l.list[off++] = w * 32 + __ffs(bits) - 1;
+            if (off < a.k) l.row[off++] = w * 32 + __ffs(bits) - 1;
     __syncthreads();
     int32_t *dst = a.children + (int64_t)idx * a.k;
-    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) dst[j] = l.list[j];
+    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) dst[j] = l.row[j];
     if (threadIdx.x == 0) {
         if (!a.rows_only) a.alive[idx] = a.n_noniso - gone_total;
         if (total != a.k) atomicOr(a.flag, 1);
@@ -541,7 +543,7 @@ size_t ga_op_lds_bytes(int32_t n, int32_t k)
 {
     const size_t W = ((size_t)n + 31) / 32;
     const size_t KW = ((size_t)k + 31) / 32;
-    return 4 * (W + 2 * (size_t)k + 3 * KW);
+    return 4 * (W + (size_t)k + 3 * KW) + 2 * (((size_t)k + 1) & ~(size_t)1);
 }
 
 int ga_prepare_kernels(size_t lds)
