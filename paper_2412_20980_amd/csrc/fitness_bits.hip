@@ -404,10 +404,18 @@ __device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t
     const uint32_t pend = valid ? (~dead[(int64_t)v * Wd + w] & ~reach[(int64_t)v * Wd + w]) : 0u;
     uint32_t nb = 0;
     if ((__ballot(pend != 0) & gmask) != 0) {
-        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-            nb |= ~dead[(int64_t)colD[e] * Wd + w];
+        // four neighbours per step; stopping once every pending bit has a
+        // surviving neighbour (or at the end of the list) gives the same split
+        int32_t e = row_ptr[v];
+        const int32_t e1 = row_ptr[v + 1];
+        for (; e + 4 <= e1; e += 4) {
+            const int32_t u0 = colD[e], u1 = colD[e + 1], u2 = colD[e + 2], u3 = colD[e + 3];
+            nb |= ~dead[(int64_t)u0 * Wd + w] | ~dead[(int64_t)u1 * Wd + w] | ~dead[(int64_t)u2 * Wd + w] |
+                  ~dead[(int64_t)u3 * Wd + w];
             if ((__ballot((nb & pend) != pend) & gmask) == 0) break;
         }
+        if ((__ballot((nb & pend) != pend) & gmask) != 0)
+            for (; e < e1; ++e) nb |= ~dead[(int64_t)colD[e] * Wd + w];
     }
     single = pend & ~nb;
     multi = pend & nb;
