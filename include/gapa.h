@@ -145,6 +145,15 @@ GAPA_API int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, g
  * and offspring.  Enqueues only; no host synchronisation. */
 GAPA_API int gapa_generation_step(gapa_ga *ga, int32_t n_generations, void *stream);
 
+/* With GAPA_GRAPH_REPLAY: records n_generations (1..4096) generations, from
+ * the current state's buffer parity, as one HIP graph, without running them;
+ * a later gapa_generation_step of exactly n_generations from the same parity
+ * is then one graph launch.  Needs one generation run since creation or the
+ * last tuning change (buffers sized); GAPA_E_STATE otherwise, or with a
+ * surrogate attached.  Results are those of running the generations
+ * eagerly. */
+GAPA_API int gapa_ga_record(gapa_ga *ga, int32_t n_generations);
+
 /* Best individual after the last enqueued generation (eq. 1's arg max): its k
  * genes ascending (genes_out, k int32, may be NULL), PC (may be NULL) and the
  * generation count (may be NULL).  Host pointers; waits for the GA's work. */
@@ -285,6 +294,7 @@ GAPA_API int gapa_surrogate_tensor(gapa_ga *ga, int32_t which, int32_t kind, flo
 GAPA_API int gapa_batch_create(int32_t count, gapa_graph *const *graphs, const gapa_params *params, void *stream,
                                gapa_batch **out);
 GAPA_API int gapa_batch_step(gapa_batch *b, int32_t n_generations, void *stream);
+GAPA_API int gapa_batch_record(gapa_batch *b, int32_t n_generations);
 GAPA_API int gapa_batch_best(gapa_batch *b, int32_t idx, int32_t *genes_out, int64_t *fitness_out,
                              int64_t *generation_out);
 GAPA_API int gapa_batch_get_population(gapa_batch *b, int32_t idx, int32_t *genes_out, int64_t *fitness_out);

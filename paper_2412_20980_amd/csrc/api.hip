@@ -663,22 +663,29 @@ template <class T> int upload(DevBuf &buf, const std::vector<T> &v)
 
 void release_graphs(gapa_ga *ga)
 {
-    for (int c = 0; c < 2; ++c) {
-        if (ga->execs[c]) (void)hipGraphExecDestroy(ga->execs[c]);
-        if (ga->graphs[c]) (void)hipGraphDestroy(ga->graphs[c]);
-        ga->execs[c] = nullptr;
-        ga->graphs[c] = nullptr;
+    for (auto &r : ga->replays) {
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        if (r.graph) (void)hipGraphDestroy(r.graph);
     }
+    ga->replays.clear();
 }
 
-// Records one generation starting from population buffer c as a HIP graph.
-// The host-side counters are restored afterwards: nothing ran.
-int capture_generation(gapa_ga *ga, int c)
+gapa_ga::Replay *find_replay(gapa_ga *ga, int parity, int32_t gens)
+{
+    for (auto &r : ga->replays)
+        if (r.parity == parity && r.gens == gens) return &r;
+    return nullptr;
+}
+
+// Records `gens` generations starting from population buffer c as one HIP
+// graph.  The host-side counters are restored afterwards: nothing ran.
+int capture_generations(gapa_ga *ga, int c, int32_t gens)
 {
     if (!ga->cap_stream) GAPA_HIP(hipStreamCreateWithFlags(&ga->cap_stream, hipStreamNonBlocking));
     const int64_t gen = ga->generation;
     GAPA_HIP(hipStreamBeginCapture(ga->cap_stream, hipStreamCaptureModeRelaxed));
-    const int rc = ga_generation(ga, ga->cap_stream);
+    int rc = GAPA_OK;
+    for (int32_t i = 0; i < gens && rc == GAPA_OK; ++i) rc = ga_generation(ga, ga->cap_stream);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(ga->cap_stream, &graph);
     ga->cur = c;
@@ -693,12 +700,20 @@ int capture_generation(gapa_ga *ga, int c)
         (void)hipGraphDestroy(graph);
         return hip_fail(e2, "hipGraphInstantiate");
     }
-    ga->graphs[c] = graph;
-    ga->execs[c] = exec;
+    if (ga->replays.size() >= 8) {  // keep the one-generation recordings, drop the oldest longer one
+        for (size_t i = 0; i < ga->replays.size(); ++i)
+            if (ga->replays[i].gens > 1) {
+                (void)hipGraphExecDestroy(ga->replays[i].exec);
+                (void)hipGraphDestroy(ga->replays[i].graph);
+                ga->replays.erase(ga->replays.begin() + i);
+                break;
+            }
+    }
+    ga->replays.push_back(gapa_ga::Replay{c, gens, graph, exec});
     return GAPA_OK;
 }
 
-int ga_run(gapa_ga *ga, int32_t n_generations, hipStream_t s)
+void check_tuning_version(gapa_ga *ga)
 {
     if (ga->captured_version != ga->graph->tune_version) {
         // launch shapes changed: record again, after one eager generation
@@ -706,28 +721,59 @@ int ga_run(gapa_ga *ga, int32_t n_generations, hipStream_t s)
         ga->warm = false;
         ga->captured_version = ga->graph->tune_version;
     }
-    for (int32_t i = 0; i < n_generations; ++i) {
+}
+
+int ga_run(gapa_ga *ga, int32_t n_generations, hipStream_t s)
+{
+    check_tuning_version(ga);
+    for (int32_t i = 0; i < n_generations;) {
         if (ga->surr) {
             const int rc = surrogate_generation(ga, s);
             if (rc != GAPA_OK) return rc;
+            ++i;
             continue;
         }
         if (!(ga->use_graph && ga->warm && ga->timer.level == 0)) {
             const int rc = ga_generation(ga, s);
             if (rc != GAPA_OK) return rc;
             ga->warm = true;  // every buffer of a generation has its final size
+            ++i;
             continue;
         }
         const int c = ga->cur;
-        if (!ga->execs[c]) {
-            const int rc = capture_generation(ga, c);
-            if (rc != GAPA_OK) return rc;
+        // a recording of all remaining generations (made by gapa_ga_record), else one generation
+        gapa_ga::Replay *r = find_replay(ga, c, n_generations - i);
+        if (!r) {
+            r = find_replay(ga, c, 1);
+            if (!r) {
+                const int rc = capture_generations(ga, c, 1);
+                if (rc != GAPA_OK) return rc;
+                r = find_replay(ga, c, 1);
+            }
         }
-        GAPA_HIP(hipGraphLaunch(ga->execs[c], s));
-        ga->cur = 1 - c;
-        ga->generation += 1;
+        const int32_t gens = r->gens;
+        GAPA_HIP(hipGraphLaunch(r->exec, s));
+        ga->cur = (gens & 1) ? 1 - c : c;
+        ga->generation += gens;
+        i += gens;
     }
     return GAPA_OK;
+}
+
+int ga_record(gapa_ga *ga, int32_t n_generations)
+{
+    check_tuning_version(ga);
+    if (!ga->use_graph || ga->surr || !ga->warm) {
+        set_error("recording needs GAPA_GRAPH_REPLAY, no surrogate, and one generation run since the last "
+                  "tuning change");
+        return GAPA_E_STATE;
+    }
+    if (n_generations < 1 || n_generations > 4096) {
+        set_error("n_generations must be in [1, 4096]");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (find_replay(ga, ga->cur, n_generations)) return GAPA_OK;
+    return capture_generations(ga, ga->cur, n_generations);
 }
 
 int ga_step_checked(gapa_ga *ga, int32_t n_generations, hipStream_t s)
@@ -863,6 +909,22 @@ int gapa_generation_step(gapa_ga *ga, int32_t n_generations, void *stream)
         return GAPA_E_INVALID_ARG;
     }
     return ga_step_checked(ga, n_generations, static_cast<hipStream_t>(stream));
+}
+
+int gapa_ga_record(gapa_ga *ga, int32_t n_generations)
+{
+    g_last_error.clear();
+    if (!ga) {
+        set_error("GA is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (ga->failed) {
+        set_error("GA handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    DeviceGuard dg(ga->graph->device);
+    const int rc = ga_record(ga, n_generations);
+    return rc == GAPA_E_DEVICE ? fail_handle(&ga->failed, rc) : rc;
 }
 
 int gapa_best(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out, int64_t *generation_out)
@@ -1266,6 +1328,12 @@ int gapa_batch_step(gapa_batch *b, int32_t n_generations, void *stream)
         return GAPA_E_INVALID_ARG;
     }
     return ga_step_checked(b->ga, n_generations, static_cast<hipStream_t>(stream));
+}
+
+int gapa_batch_record(gapa_batch *b, int32_t n_generations)
+{
+    if (!b) return GAPA_E_INVALID_ARG;
+    return gapa_ga_record(b->ga, n_generations);
 }
 
 int gapa_batch_best(gapa_batch *b, int32_t idx, int32_t *genes_out, int64_t *fitness_out, int64_t *generation_out)

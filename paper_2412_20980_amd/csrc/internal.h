@@ -283,8 +283,13 @@ struct gapa_ga {
     bool warm = false;            // a generation has run eagerly: buffers are sized
     int32_t captured_version = -1;  // graph tuning the recorded generations were made with
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graphs[2] = {nullptr, nullptr};
-    hipGraphExec_t execs[2] = {nullptr, nullptr};
+    struct Replay {
+        int parity;        // current population buffer the recording starts from
+        int32_t gens;      // generations it runs
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<Replay> replays;
     gapa::SurrogateState *surr = nullptr;  // learned screening, when attached
 };
 

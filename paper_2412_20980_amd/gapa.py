@@ -53,6 +53,7 @@ EXPORTED = (
     "gapa_surrogate_attach", "gapa_surrogate_stats", "gapa_surrogate_last_pool", "gapa_surrogate_predict",
     "gapa_surrogate_train_batch", "gapa_surrogate_tensor", "gapa_surrogate_last_predictions",
     "gapa_graph_get_tuning", "gapa_graph_set_tuning", "gapa_ga_autotune", "gapa_batch_autotune",
+    "gapa_ga_record", "gapa_batch_record",
 )
 
 
@@ -119,6 +120,8 @@ def lib() -> C.CDLL:
     L.gapa_batch_best.argtypes = [vp, C.c_int32, vp, i64p, i64p]
     L.gapa_batch_get_population.argtypes = [vp, C.c_int32, vp, vp]
     L.gapa_batch_destroy.argtypes = [vp]
+    L.gapa_ga_record.argtypes = [vp, C.c_int32]
+    L.gapa_batch_record.argtypes = [vp, C.c_int32]
     L.gapa_graph_get_tuning.argtypes = [vp, C.POINTER(gapa_tuning)]
     L.gapa_graph_set_tuning.argtypes = [vp, C.POINTER(gapa_tuning)]
     L.gapa_ga_autotune.argtypes = [vp, C.c_int32, vp, C.POINTER(gapa_tuning)]
@@ -335,6 +338,11 @@ class GA:
     def fitness_stats(self) -> dict:
         return _fitness_stats(lib().gapa_ga_fitness_stats, self.handle)
 
+    def record(self, n: int):
+        """Record n generations as one HIP graph (replay mode); a later step(n)
+        from the same buffer parity is one launch."""
+        _check(lib().gapa_ga_record(self.handle, n))
+
     def autotune(self, reps: int = 3, stream=None) -> dict:
         t = gapa_tuning()
         _check(lib().gapa_ga_autotune(self.handle, reps, _stream_ptr(stream), C.byref(t)))
@@ -479,6 +487,9 @@ class Batch:
 
     def set_timing(self, level: int = 1):
         _check(lib().gapa_batch_set_timing(self.handle, int(level)))
+
+    def record(self, n: int):
+        _check(lib().gapa_batch_record(self.handle, n))
 
     def autotune(self, reps: int = 3, stream=None) -> dict:
         t = gapa_tuning()

@@ -244,3 +244,45 @@ def test_autotuned_batch_and_retuned_replay_keep_trajectories(gp):
         oga.step()
         pop, F = ga.population()
         assert np.array_equal(F, oga.F) and np.array_equal(pop, oga.pop), gen
+
+
+def test_multi_generation_recordings_match_oracle(gp):
+    """Several generations recorded as one HIP graph: a step call of that
+    many generations from the same buffer parity is one launch, and the
+    trajectory stays the oracle's (an odd count ends on the other parity,
+    where the next call falls back to one-generation replays)."""
+    g = inputs.erdos_renyi(800, 3.0, seed=43)
+    graph = gp.Graph.from_csr(g)
+    ga = gp.GA(graph, 40, 64, 43, 0.7, 0.1, 2, 1500, replay=True)
+    oga = O.OracleGA(g, 40, 64, 43, 0.7, 0.1, 2, 1500)
+    with pytest.raises(gp.GapaError) as e:
+        ga.record(4)  # nothing run yet: buffers not sized
+    assert e.value.code == gp.GAPA_E_STATE
+    ga.step(1)
+    oga.step()
+    with pytest.raises(gp.GapaError) as e:
+        ga.record(0)
+    assert e.value.code == gp.GAPA_E_INVALID_ARG
+    ga.record(4)
+    ga.record(5)
+    for n in (4, 4, 5, 5, 3):
+        print(f"step({n})", flush=True)
+        ga.step(n)
+        for _ in range(n):
+            oga.step()
+        pop, F = ga.population()
+        assert np.array_equal(F, oga.F) and np.array_equal(pop, oga.pop), n
+        graph.eval(pop[:2])  # eager work between launches
+    csrs, params = uneven_instances()
+    bt = gp.Batch([gp.Graph.from_csr(c) for c in csrs], params, replay=True)
+    ogas = [oracle_for(c, p) for c, p in zip(csrs, params)]
+    bt.step(1)
+    bt.record(6)
+    for _ in range(2):
+        bt.step(6)
+    for o in ogas:
+        for _ in range(13):
+            o.step()
+    for b, o in enumerate(ogas):
+        pop, F = bt.population(b)
+        assert np.array_equal(F, o.F) and np.array_equal(pop, o.pop), b
