@@ -176,7 +176,7 @@ def time_to_target(torch, gapa, inputs, seeds=(0,), cap_factor=2.0):
                          stream=stream, replay=True)
         else:
             ga = gapa.GA(graph, sw.k, sw.pop, seed, sw.pc, sw.pm, sw.tournament, sw.offspring, stream=stream)
-            ga.attach_surrogate(screen=sw.exact_top, batch=1024, train_steps=4, warmup_gens=10, buffer=65536,
+            ga.attach_surrogate(screen=sw.exact_top, batch=1024, train_steps=2, warmup_gens=10, buffer=65536,
                                 fallback_gens=3, random_screen=(kind == "random"), stream=stream)
         g, best, hit = 0, None, None
         while True:
@@ -225,13 +225,13 @@ def time_to_target(torch, gapa, inputs, seeds=(0,), cap_factor=2.0):
 def run_surrogate(args, torch, gapa, inputs):
     """Screened generations on the 200k-node workload: 4096 offspring, the 512
     with the lowest predictions (plus 32 random others for the judge)
-    evaluated exactly, 4 Adam steps per generation; warm-up generations
+    evaluated exactly, 2 Adam steps per generation; warm-up generations
     (full evaluation) are not timed."""
     w = inputs.workload("cl200k_k2000_p1024_screen4096")
     graph = gapa.Graph.from_csr(w.graph, trust=True)
     stream = torch.cuda.Stream()
     ga = gapa.GA(graph, w.k, w.pop, w.seed, w.pc, w.pm, w.tournament, w.offspring, stream=stream)
-    ga.attach_surrogate(screen=w.exact_top, batch=1024, train_steps=4, warmup_gens=10, buffer=65536, fallback_gens=0,
+    ga.attach_surrogate(screen=w.exact_top, batch=1024, train_steps=2, warmup_gens=10, buffer=65536, fallback_gens=0,
                         stream=stream)
     ga.step(args.warmup, stream=stream)
     torch.cuda.synchronize()

@@ -92,6 +92,9 @@ enum {
  * ------------------------------------------------------------------------- */
 GAPA_API int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                       uint32_t flags, gapa_graph **out);
+/* Releases the caller's handle.  GAs and batches created on the graph hold
+ * their own references: its device memory is freed once the last of them is
+ * destroyed too, so handles may be destroyed in any order.  NULL is OK. */
 GAPA_API int gapa_graph_destroy(gapa_graph *g);
 
 /* ---------------------------------------------------------------------------

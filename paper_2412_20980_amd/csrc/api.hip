@@ -403,6 +403,28 @@ int graph_build(int dev, int32_t n, int64_t nnz, const int32_t *row_ptr, const i
     return GAPA_OK;
 }
 
+void graph_retain(gapa_graph *g)
+{
+    g->refs.fetch_add(1);
+}
+
+// Drops one reference; the last one frees the graph.
+void graph_release(gapa_graph *g)
+{
+    if (g->refs.fetch_sub(1) != 1) return;
+    {
+        DeviceGuard dg(g->device);
+        (void)hipDeviceSynchronize();
+        if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
+        if (g->d_col) (void)hipFree(g->d_col);
+        for (int32_t *p : {g->d_src, g->d_colD, g->d_order, g->d_band_v})
+            if (p) (void)hipFree(p);
+        if (g->d_noniso) (void)hipFree(g->d_noniso);
+        release_workspace(g->ws);
+    }
+    delete g;
+}
+
 }  // namespace
 }  // namespace gapa
 
@@ -442,18 +464,7 @@ int gapa_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int3
 
 int gapa_graph_destroy(gapa_graph *g)
 {
-    if (!g) return GAPA_OK;
-    {
-        DeviceGuard dg(g->device);
-        (void)hipDeviceSynchronize();
-        if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
-        if (g->d_col) (void)hipFree(g->d_col);
-        for (int32_t *p : {g->d_src, g->d_colD, g->d_order, g->d_band_v})
-            if (p) (void)hipFree(p);
-        if (g->d_noniso) (void)hipFree(g->d_noniso);
-        release_workspace(g->ws);
-    }
-    delete g;
+    if (g) graph_release(g);
     return GAPA_OK;
 }
 
@@ -887,6 +898,7 @@ int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **
         return GAPA_E_OOM;
     }
     ga->graph = g;
+    graph_retain(g);
     auto fail = [&](int code) {
         gapa_ga_destroy(ga);
         return code;
@@ -952,11 +964,13 @@ int gapa_get_population(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out)
 int gapa_ga_destroy(gapa_ga *ga)
 {
     if (!ga) return GAPA_OK;
+    gapa_graph *g = ga->graph;
     {
-        DeviceGuard dg(ga->graph->device);
+        DeviceGuard dg(g->device);
         ga_release(ga);
     }
     delete ga;
+    graph_release(g);
     return GAPA_OK;
 }
 
@@ -1244,6 +1258,7 @@ int gapa_batch_create(int32_t count, gapa_graph *const *graphs, const gapa_param
     int rc;
     if (count == 1) {
         ga->graph = graphs[0];
+        graph_retain(ga->graph);
     } else {
         // the disjoint union of the instance graphs: instance b's node v is
         // node voff[b] + v
@@ -1268,6 +1283,7 @@ int gapa_batch_create(int32_t count, gapa_graph *const *graphs, const gapa_param
         if ((rc = graph_build(graphs[0]->device, N, M, rp.data(), ci.data(), voff, 0, &bt->super)) != GAPA_OK)
             return fail(rc);
         ga->graph = bt->super;
+        graph_retain(ga->graph);
     }
     if ((rc = ga_allocate(ga, count, params, ns.data(), nonisos.data(), count > 1 ? bseg : 0)) != GAPA_OK)
         return fail(rc);
@@ -1290,7 +1306,7 @@ int gapa_batch_create(int32_t count, gapa_graph *const *graphs, const gapa_param
             live_gen[b] = I.L;
             moff[b] = I.mask_off;
             for (int32_t v = voff[b]; v < voff[b + 1]; ++v) node_inst[v] = b;
-            for (int32_t j0 = 0; j0 < I.W; j0 += 8) {
+            for (int32_t j0 = 0; j0 < I.W; j0 += kTransposeWords) {
                 tiles.push_back(b);
                 tiles.push_back(j0);
             }
@@ -1374,11 +1390,13 @@ int gapa_batch_destroy(gapa_batch *b)
 {
     if (!b) return GAPA_OK;
     if (b->ga) {
-        if (b->ga->graph) {
-            DeviceGuard dg(b->ga->graph->device);
+        gapa_graph *g = b->ga->graph;
+        if (g) {
+            DeviceGuard dg(g->device);
             ga_release(b->ga);
         }
         delete b->ga;
+        if (g) graph_release(g);
     }
     gapa_graph_destroy(b->super);
     delete b;

@@ -67,4 +67,14 @@ __device__ __forceinline__ bool test_bit(const uint32_t *bits, uint32_t i)
     return (bits[i >> 5] >> (i & 31)) & 1u;
 }
 
+// Workgroups go to the chip's eight XCDs in turn (workgroup b to XCD b mod 8),
+// each XCD with its own L2.  This maps workgroup b of nblk to a tile so that
+// every XCD takes one contiguous range of tiles: neighbouring tiles that share
+// cache lines are then read through the same L2.  A bijection on [0, nblk).
+__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t nblk)
+{
+    const int32_t q = nblk >> 3, r = nblk & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 }  // namespace gapa

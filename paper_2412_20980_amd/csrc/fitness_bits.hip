@@ -108,7 +108,7 @@ __device__ __forceinline__ int64_t uf_block(const Insts &I, int32_t gi)
 // ballots, and writes the tile's dead rows, which are one contiguous range of
 // the node-major array.  The same range of reach rows is cleared.
 // Individuals past B_real are padding and remove every node.
-constexpr int kTileWords = 8;
+constexpr int kTileWords = kTransposeWords;
 
 // 32 x 32 bit-matrix transpose across the 32 lanes of a half-wave: lane r
 // holds row r (bit c = entry (r, c)); afterwards lane c holds column c (bit r =
@@ -132,8 +132,10 @@ __global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restr
                                                          uint32_t *__restrict__ reach)
 {
     // this tile: instance b, its node words [j0, j0 + kTileWords)
-    const int32_t b = I.count == 1 ? 0 : I.tiles[2 * blockIdx.x];
-    const int32_t j0 = I.count == 1 ? blockIdx.x * kTileWords : I.tiles[2 * blockIdx.x + 1];
+    // tiles side by side read the same 128-byte lines of each mask row
+    const int32_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const int32_t b = I.count == 1 ? 0 : I.tiles[2 * t];
+    const int32_t j0 = I.count == 1 ? t * kTileWords : I.tiles[2 * t + 1];
     const int32_t vb = i_voff(I, b);
     const int32_t nb = i_voff(I, b + 1) - vb;
     const int32_t W = (nb + 31) / 32;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <map>
 #include <string>
 #include <vector>
@@ -110,6 +111,7 @@ struct Tuning {
 }  // namespace gapa
 
 struct gapa_graph {
+    std::atomic<int32_t> refs{1};  // the caller's handle, plus one per GA or batch using the graph
     int device = 0;
     int32_t n = 0;
     int64_t nnz = 0;
@@ -132,6 +134,10 @@ struct gapa_graph {
 };
 
 namespace gapa {
+
+// Node words per tile of the dead-row transpose (32 nodes each); the tile
+// lists of instance tables step by it.
+constexpr int kTransposeWords = 4;
 
 // Several instances (disjoint node ranges of one graph, each with its own
 // individuals) evaluated in one bit-parallel fitness pass.  All arrays are on

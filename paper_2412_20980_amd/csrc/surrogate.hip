@@ -28,13 +28,14 @@ namespace {
 
 constexpr int kD = 64;
 constexpr int kH = 256;
-constexpr int kMlpRows = 64;  // samples per MLP block, 16 per wave
+constexpr int kMlpRows = 16;  // samples per MLP block (one matrix-core row tile)
+constexpr int kMlpWaves = 8;  // waves per MLP block, each with 32 hidden units (two column tiles)
 constexpr uint32_t kStreamSurrInit = 5, kStreamSurrSample = 6, kStreamSurrRandom = 7;
 constexpr int kJudgeMax = 1024;
 constexpr int kJudgeExtra = 32;  // unscreened children evaluated for the judge in a screened generation
 constexpr int kMaxLambda = 8192;
 
-// flat layout of the MLP parameters after E (weights, gradients, partials)
+// flat layout of the MLP parameters after E (weights, gradients)
 constexpr int kOffW1 = 0;
 constexpr int kOffB1 = kOffW1 + kH * kD;
 constexpr int kOffW2 = kOffB1 + kH;
@@ -43,9 +44,8 @@ constexpr int kOffW3 = kOffB2 + kH;
 constexpr int kOffB3 = kOffW3 + kH;
 constexpr int kMlpParams = kOffB3 + 1;
 
-// LDS of the MLP kernel (bf16 elements): X [64][72], H1, DZ2, DZ1 [64][264]
+// LDS row strides of the MLP kernel (bf16 elements): X [16][72], H1, DZ2 [16][264]
 constexpr int kSX = 72, kSH = 264;
-constexpr size_t kMlpLds = 2 * ((size_t)kMlpRows * kSX + 3 * (size_t)kMlpRows * kSH) + 4 * (4 * kH + 4);
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -210,219 +210,187 @@ struct MlpArgs {
     const float *b1, *b2, *b3;
     float *yhat;         // [N]
     int32_t N;
-    // training
-    const float *target; // [N] standardised labels
+    // training (N = B, a multiple of 16)
+    const float *target; // [B] standardised labels
     float dscale;        // 2 / B
-    float *lossv;        // [N] squared errors
-    uint16_t *dxT;       // [64][N] gradient of x(S), bf16, dimension-major
-    float *partial;      // [blocks][kMlpParams] per-block parameter gradients
+    float *lossv;        // [B] squared errors
+    float *dy;           // [B] d loss / d yhat
+    // feature-major bf16 activations and gradients for the weight gradients:
+    // xT [64][B], h1T, h2T, dz1T, dz2T [256][B]; dxT [64][B] for dE
+    uint16_t *xT, *h1T, *h2T, *dz1T, *dz2T, *dxT;
 };
 
-// Forward for 64 samples per block, 16 per wave (rows r0 + i).  MFMA tiles
-// are 16 x 16 with K = 32: lane l holds A[l % 16][8 (l / 16) .. + 7],
+// Stores the four rows 4 lg .. 4 lg + 3 of one C-tile column as one 8-byte
+// write into a feature-major [features][N] array.
+__device__ __forceinline__ void store_col4(uint16_t *T, int32_t N, int32_t feat, int32_t row, uint16_t h0, uint16_t h1,
+                                           uint16_t h2, uint16_t h3)
+{
+    uint2 q;
+    q.x = h0 | ((uint32_t)h1 << 16);
+    q.y = h2 | ((uint32_t)h3 << 16);
+    *reinterpret_cast<uint2 *>(T + (int64_t)feat * N + row) = q;
+}
+
+// Forward for 16 samples per block (rows row0 .. row0 + 15); wave wv owns
+// hidden units 32 wv .. 32 wv + 31 (two 16-wide column tiles) of each layer.
+// MFMA tiles are 16 x 16 with K = 32: lane l holds A[l % 16][8 (l / 16) .. + 7],
 // B[8 (l / 16) .. + 7][l % 16] and C[4 (l / 16) + r][l % 16], r = 0..3.
 // With kTrain the block also runs the backward pass of its samples:
-// dyhat = 2 (yhat - t) / B; dz2 = dyhat w3 [z2 > 0]; dh1 = dz2 W2;
-// dz1 = dh1 [z1 > 0]; dx = dz1 W1; and its share of every parameter
-// gradient (dW2 = dz2^T h1, dW1 = dz1^T x, biases, w3), written as one
-// partial row per block and summed in block order later.
+// dyhat = 2 (yhat - t) / B; dz2 = dyhat w3 [h2 > 0]; dh1 = dz2 W2;
+// dz1 = dh1 [h1 > 0]; dx = dz1 W1, and writes the bf16 activations and
+// gradients the weight-gradient kernel contracts over the batch.
 template <bool kTrain>
-__global__ __launch_bounds__(256) void k_mlp(MlpArgs a)
+__global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpArgs a)
 {
-    extern __shared__ __align__(16) uint16_t lds[];
-    uint16_t *sX = lds;
-    uint16_t *sH1 = sX + kMlpRows * kSX;
-    uint16_t *sDZ2 = sH1 + kMlpRows * kSH;
-    uint16_t *sDZ1 = sDZ2 + kMlpRows * kSH;
-    float *sW3 = reinterpret_cast<float *>(sDZ1 + kMlpRows * kSH);  // [4][256] wave shares of dw3
-    float *sB3 = sW3 + 4 * kH;                                      // [4]
+    __shared__ __align__(16) uint16_t sX[kMlpRows * kSX];
+    __shared__ __align__(16) uint16_t sH1[kMlpRows * kSH];   // h1, then dz1 in place
+    __shared__ __align__(16) uint16_t sDZ2[kMlpRows * kSH];
+    __shared__ float sY[kMlpWaves][kMlpRows];
+    __shared__ float sDy[kMlpRows];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
     const int32_t row0 = blockIdx.x * kMlpRows;
-    const int wr0 = wv * 16;
+    const int c0 = wv * 32;
 
-    for (int t = threadIdx.x; t < kMlpRows * 8; t += blockDim.x) {
-        const int r = t >> 3, c8 = (t & 7) * 8;
+    if (threadIdx.x < kMlpRows * 8) {
+        const int r = threadIdx.x >> 3, c8 = (threadIdx.x & 7) * 8;
         uint4 v = {0u, 0u, 0u, 0u};
         if (row0 + r < a.N) v = *reinterpret_cast<const uint4 *>(a.xb + (int64_t)(row0 + r) * kD + c8);
         *reinterpret_cast<uint4 *>(sX + r * kSX + c8) = v;
     }
     __syncthreads();
+    if (kTrain)
+        for (int q = threadIdx.x; q < kD * (kMlpRows / 4); q += blockDim.x) {
+            const int d = q >> 2, r = (q & 3) * 4;
+            store_col4(a.xT, a.N, d, row0 + r, sX[r * kSX + d], sX[(r + 1) * kSX + d], sX[(r + 2) * kSX + d],
+                       sX[(r + 3) * kSX + d]);
+        }
 
-    f32x4 acc[16];
-    // layer 1: z1 = x W1^T + b1
+    // layer 1: z1 = x W1^T + b1, h1 = relu(z1) in bf16
+    f32x4 acc[2];
+    float h1v[2][4];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 2; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < kD / 32; ++ks) {
-        const bf16x8 A = ld8(sX + (wr0 + lr) * kSX + ks * 32 + lg * 8);
+        const bf16x8 A = ld8(sX + lr * kSX + ks * 32 + lg * 8);
 #pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = mfma(A, ld8(a.W1b + (t * 16 + lr) * kD + ks * 32 + lg * 8), acc[t]);
+        for (int t = 0; t < 2; ++t) acc[t] = mfma(A, ld8(a.W1b + (c0 + t * 16 + lr) * kD + ks * 32 + lg * 8), acc[t]);
     }
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const float b = a.b1[t * 16 + lr];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sH1[(wr0 + 4 * lg + r) * kSH + t * 16 + lr] = f2bf(fmaxf(acc[t][r] + b, 0.f));
-    }
-    __syncthreads();
-    // layer 2: z2 = h1 W2^T + b2
-#pragma unroll
-    for (int t = 0; t < 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < kH / 32; ++ks) {
-        const bf16x8 A = ld8(sH1 + (wr0 + lr) * kSH + ks * 32 + lg * 8);
-#pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = mfma(A, ld8(a.W2b + (t * 16 + lr) * kH + ks * 32 + lg * 8), acc[t]);
-    }
-    // h2 (as its bf16 value) and yhat = w3 . h2 + b3
-    float p[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const float b = a.b2[t * 16 + lr];
-        const float w = bf2f(a.w3b[t * 16 + lr]);
+    for (int t = 0; t < 2; ++t) {
+        const int c = c0 + t * 16 + lr;
+        const float b = a.b1[c];
+        uint16_t h[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float h = bf2f(f2bf(fmaxf(acc[t][r] + b, 0.f)));
-            acc[t][r] = h;
-            p[r] += h * w;
+            h[r] = f2bf(fmaxf(acc[t][r] + b, 0.f));
+            h1v[t][r] = bf2f(h[r]);
+            sH1[(4 * lg + r) * kSH + c] = h[r];
         }
+        if (kTrain) store_col4(a.h1T, a.N, c, row0 + 4 * lg, h[0], h[1], h[2], h[3]);
+    }
+    __syncthreads();
+
+    // layer 2: z2 = h1 W2^T + b2, h2 = relu(z2) in bf16; yhat = w3 . h2 + b3
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kH / 32; ++ks) {
+        const bf16x8 A = ld8(sH1 + lr * kSH + ks * 32 + lg * 8);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[t] = mfma(A, ld8(a.W2b + (c0 + t * 16 + lr) * kH + ks * 32 + lg * 8), acc[t]);
+    }
+    float p[4] = {0.f, 0.f, 0.f, 0.f};
+    float w3v[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int c = c0 + t * 16 + lr;
+        const float b = a.b2[c];
+        w3v[t] = bf2f(a.w3b[c]);
+        uint16_t h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            h[r] = f2bf(fmaxf(acc[t][r] + b, 0.f));
+            acc[t][r] = bf2f(h[r]);
+            p[r] += acc[t][r] * w3v[t];
+        }
+        if (kTrain) store_col4(a.h2T, a.N, c, row0 + 4 * lg, h[0], h[1], h[2], h[3]);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int off = 1; off < 16; off <<= 1) p[r] += __shfl_xor(p[r], off, 64);
-    const float b3 = a.b3[0];
-    float dy[4];
+    if (lr == 0)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int32_t row = row0 + wr0 + 4 * lg + r;
-        const float y = p[r] + b3;
-        dy[r] = 0.f;
+        for (int r = 0; r < 4; ++r) sY[wv][4 * lg + r] = p[r];
+    __syncthreads();
+    if (threadIdx.x < kMlpRows) {
+        const int r = threadIdx.x;
+        const int32_t row = row0 + r;
+        float y = 0.f;
+#pragma unroll
+        for (int w = 0; w < kMlpWaves; ++w) y += sY[w][r];
+        y += a.b3[0];
+        float d = 0.f;
         if (row < a.N) {
-            if (lr == 0) a.yhat[row] = y;
+            a.yhat[row] = y;
             if (kTrain) {
                 const float e = y - a.target[row];
-                dy[r] = e * a.dscale;
-                if (lr == 0) a.lossv[row] = e * e;
+                d = e * a.dscale;
+                a.lossv[row] = e * e;
+                a.dy[row] = d;
             }
         }
+        sDy[r] = d;
     }
     if (!kTrain) return;
-
-    // dz2, and this wave's share of dw3 (cols t*16 + lr) and db3
-    float q3[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const float w = bf2f(a.w3b[t * 16 + lr]);
-        q3[t] = 0.f;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float h = acc[t][r];
-            q3[t] += dy[r] * h;
-            sDZ2[(wr0 + 4 * lg + r) * kSH + t * 16 + lr] = f2bf(h > 0.f ? dy[r] * w : 0.f);
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        q3[t] += __shfl_xor(q3[t], 16, 64);
-        q3[t] += __shfl_xor(q3[t], 32, 64);
-    }
-    if (lg == 0)
-#pragma unroll
-        for (int t = 0; t < 16; ++t) sW3[wv * kH + t * 16 + lr] = q3[t];
-    float sd = ((dy[0] + dy[1]) + dy[2]) + dy[3];
-    sd += __shfl_xor(sd, 16, 64);
-    sd += __shfl_xor(sd, 32, 64);
-    if (lane == 0) sB3[wv] = sd;
     __syncthreads();
 
-    // dh1 = dz2 W2, dz1 = dh1 [h1 > 0]
+    // dz2 = dyhat w3 [h2 > 0]
 #pragma unroll
-    for (int t = 0; t < 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < kH / 32; ++ks) {
-        const bf16x8 A = ld8(sDZ2 + (wr0 + lr) * kSH + ks * 32 + lg * 8);
-#pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = mfma(A, ld8(a.W2bT + (t * 16 + lr) * kH + ks * 32 + lg * 8), acc[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < 16; ++t)
+    for (int t = 0; t < 2; ++t) {
+        const int c = c0 + t * 16 + lr;
+        uint16_t h[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int idx = (wr0 + 4 * lg + r) * kSH + t * 16 + lr;
-            sDZ1[idx] = f2bf(bf2f(sH1[idx]) > 0.f ? acc[t][r] : 0.f);
+            h[r] = f2bf(acc[t][r] > 0.f ? sDy[4 * lg + r] * w3v[t] : 0.f);
+            sDZ2[(4 * lg + r) * kSH + c] = h[r];
         }
+        store_col4(a.dz2T, a.N, c, row0 + 4 * lg, h[0], h[1], h[2], h[3]);
+    }
     __syncthreads();
 
-    // dx = dz1 W1
-    f32x4 ax[4];
+    // dh1 = dz2 W2, dz1 = dh1 [h1 > 0] (into sH1: each element by its owner)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) ax[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 2; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
     for (int ks = 0; ks < kH / 32; ++ks) {
-        const bf16x8 A = ld8(sDZ1 + (wr0 + lr) * kSH + ks * 32 + lg * 8);
+        const bf16x8 A = ld8(sDZ2 + lr * kSH + ks * 32 + lg * 8);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) ax[t] = mfma(A, ld8(a.W1bT + (t * 16 + lr) * kH + ks * 32 + lg * 8), ax[t]);
+        for (int t = 0; t < 2; ++t)
+            acc[t] = mfma(A, ld8(a.W2bT + (c0 + t * 16 + lr) * kH + ks * 32 + lg * 8), acc[t]);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int32_t row = row0 + wr0 + 4 * lg + r;
-        if (row < a.N)
+    for (int t = 0; t < 2; ++t) {
+        const int c = c0 + t * 16 + lr;
+        uint16_t h[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) a.dxT[(int64_t)(t * 16 + lr) * a.N + row] = f2bf(ax[t][r]);
+        for (int r = 0; r < 4; ++r) {
+            h[r] = f2bf(h1v[t][r] > 0.f ? acc[t][r] : 0.f);
+            sH1[(4 * lg + r) * kSH + c] = h[r];
+        }
+        store_col4(a.dz1T, a.N, c, row0 + 4 * lg, h[0], h[1], h[2], h[3]);
     }
+    __syncthreads();
 
-    // parameter gradients of the block's 64 samples
-    float *P = a.partial + (int64_t)blockIdx.x * kMlpParams;
-    // dW2[j][i] = sum_s dz2[s][j] h1[s][i]: wave wv takes j tiles 4wv..4wv+3
-    {
-        bf16x8 A[4][2];
+    // dx = dz1 W1: waves 0..3, one 16-wide tile of the 64 dimensions each
+    if (wv < kD / 16) {
+        f32x4 ax = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) A[u][ks] = gather8(sDZ2 + (ks * 32 + lg * 8) * kSH + (4 * wv + u) * 16 + lr, kSH);
-        for (int it = 0; it < 16; ++it) {
-            const bf16x8 B0 = gather8(sH1 + (lg * 8) * kSH + it * 16 + lr, kSH);
-            const bf16x8 B1 = gather8(sH1 + (32 + lg * 8) * kSH + it * 16 + lr, kSH);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                f32x4 c = mfma(A[u][0], B0, f32x4{0.f, 0.f, 0.f, 0.f});
-                c = mfma(A[u][1], B1, c);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) P[kOffW2 + ((4 * wv + u) * 16 + 4 * lg + r) * kH + it * 16 + lr] = c[r];
-            }
-        }
-    }
-    // dW1[j][d] = sum_s dz1[s][j] x[s][d]
-    {
-        bf16x8 A[4][2];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) A[u][ks] = gather8(sDZ1 + (ks * 32 + lg * 8) * kSH + (4 * wv + u) * 16 + lr, kSH);
-#pragma unroll
-        for (int dt = 0; dt < 4; ++dt) {
-            const bf16x8 B0 = gather8(sX + (lg * 8) * kSX + dt * 16 + lr, kSX);
-            const bf16x8 B1 = gather8(sX + (32 + lg * 8) * kSX + dt * 16 + lr, kSX);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                f32x4 c = mfma(A[u][0], B0, f32x4{0.f, 0.f, 0.f, 0.f});
-                c = mfma(A[u][1], B1, c);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) P[kOffW1 + ((4 * wv + u) * 16 + 4 * lg + r) * kD + dt * 16 + lr] = c[r];
-            }
-        }
-    }
-    // biases and w3, one thread per hidden unit, samples in order
-    {
-        const int j = threadIdx.x;
-        float s1 = 0.f, s2 = 0.f;
-        for (int s = 0; s < kMlpRows; ++s) {
-            s1 += bf2f(sDZ1[s * kSH + j]);
-            s2 += bf2f(sDZ2[s * kSH + j]);
-        }
-        P[kOffB1 + j] = s1;
-        P[kOffB2 + j] = s2;
-        P[kOffW3 + j] = ((sW3[j] + sW3[kH + j]) + sW3[2 * kH + j]) + sW3[3 * kH + j];
-        if (j == 0) P[kOffB3] = ((sB3[0] + sB3[1]) + sB3[2]) + sB3[3];
+        for (int ks = 0; ks < kH / 32; ++ks)
+            ax = mfma(ld8(sH1 + lr * kSH + ks * 32 + lg * 8), ld8(a.W1bT + (wv * 16 + lr) * kH + ks * 32 + lg * 8), ax);
+        store_col4(a.dxT, a.N, wv * 16 + lr, row0 + 4 * lg, f2bf(ax[0]), f2bf(ax[1]), f2bf(ax[2]), f2bf(ax[3]));
     }
 }
 
@@ -440,35 +408,87 @@ __device__ __forceinline__ float adam(float &theta, float &m, float &v, float g,
     return theta;
 }
 
-// MLP parameters: gradient = partial rows summed in block order; Adam; the
-// bfloat16 copies.  Block 0 also averages the per-sample squared errors.
-__global__ void k_adam_mlp(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
-                           const float *__restrict__ partial, int32_t nblk, float *__restrict__ keep, AdamArgs o,
-                           Bf16Copies cp, const float *__restrict__ lossv, int32_t B, double *__restrict__ loss_out)
+struct WgradArgs {
+    const uint16_t *xT, *h1T, *h2T, *dz1T, *dz2T;  // feature-major [features][B] bf16
+    const float *dy, *lossv;                       // [B]
+    int32_t B;
+    float *theta, *m, *v;                          // MLP parameters (flat layout), moments
+    float *keep;                                   // NULL, or the gradient of every parameter
+    Bf16Copies cp;
+    AdamArgs o;
+    double *loss_out;                              // mean squared error of the batch
+};
+
+__device__ __forceinline__ void adam_param(const WgradArgs &a, int32_t j, float g)
 {
-    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0) {
-        __shared__ double s_l[256];
-        double acc = 0.0;
-        for (int32_t s = threadIdx.x; s < B; s += blockDim.x) acc += (double)lossv[s];
-        s_l[threadIdx.x] = acc;
-        __syncthreads();
-        for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-            if ((int)threadIdx.x < off) s_l[threadIdx.x] += s_l[threadIdx.x + off];
-            __syncthreads();
+    if (a.keep) a.keep[j] = g;
+    float th = a.theta[j], mm = a.m[j], vv = a.v[j];
+    adam(th, mm, vv, g, a.o);
+    a.theta[j] = th;
+    a.m[j] = mm;
+    a.v[j] = vv;
+    mlp_copy(a.cp, j, th);
+}
+
+// MLP parameter gradients over the batch, then Adam and the bfloat16 copies;
+// one wave per task.  Tasks 0..255: 16 x 16 tiles of dW2 = dz2^T h1;
+// 256..319: tiles of dW1 = dz1^T x (K = the batch, on the matrix cores);
+// 320..331: 64 entries each of db1 = sum dz1, db2 = sum dz2 and
+// dw3 = sum dyhat h2 (samples in order); 332: db3 = sum dyhat and the loss.
+constexpr int kWgradTasks = 333;
+__global__ __launch_bounds__(64) void k_mlp_wgrad(WgradArgs a)
+{
+    const int32_t task = blockIdx.x;
+    const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+    const int32_t B = a.B;
+    if (task < 320) {
+        const bool w2 = task < 256;
+        const int32_t J = w2 ? task >> 4 : (task - 256) >> 2;  // output rows (hidden unit j)
+        const int32_t I = w2 ? task & 15 : (task - 256) & 3;    // output columns
+        const uint16_t *At = (w2 ? a.dz2T : a.dz1T) + (int64_t)(J * 16 + lr) * B + lg * 8;
+        const uint16_t *Bt = (w2 ? a.h1T : a.xT) + (int64_t)(I * 16 + lr) * B + lg * 8;
+        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int32_t ks = 0; ks < B; ks += 32) acc = mfma(ld8(At + ks), ld8(Bt + ks), acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int32_t j = J * 16 + 4 * lg + r, i = I * 16 + lr;
+            adam_param(a, w2 ? kOffW2 + j * kH + i : kOffW1 + j * kD + i, acc[r]);
         }
-        if (threadIdx.x == 0) *loss_out = s_l[0] / B;
+        return;
     }
-    if (j >= kMlpParams) return;
+    if (task < 332) {
+        const int32_t kind = (task - 320) >> 2;  // 0 b1, 1 b2, 2 w3
+        const int32_t j = ((task - 320) & 3) * 64 + lane;
+        const uint16_t *row = (kind == 0 ? a.dz1T : kind == 1 ? a.dz2T : a.h2T) + (int64_t)j * B;
+        float g = 0.f;
+        for (int32_t s0 = 0; s0 < B; s0 += 8) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(row + s0);
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float x = bf2f((uint16_t)(w[e >> 1] >> (16 * (e & 1))));
+                g += kind == 2 ? a.dy[s0 + e] * x : x;
+            }
+        }
+        adam_param(a, kind == 0 ? kOffB1 + j : kind == 1 ? kOffB2 + j : kOffW3 + j, g);
+        return;
+    }
+    // db3 and the loss: lane l takes samples l, l + 64, ...; lanes combined in a fixed tree
     float g = 0.f;
-    for (int32_t b = 0; b < nblk; ++b) g += partial[(int64_t)b * kMlpParams + j];
-    if (keep) keep[j] = g;
-    float th = theta[j], mm = m[j], vv = v[j];
-    adam(th, mm, vv, g, o);
-    theta[j] = th;
-    m[j] = mm;
-    v[j] = vv;
-    mlp_copy(cp, j, th);
+    double l2 = 0.0;
+    for (int32_t s0 = lane; s0 < B; s0 += 64) {
+        g += a.dy[s0];
+        l2 += (double)a.lossv[s0];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        g += __shfl_xor(g, off, 64);
+        l2 += __shfl_xor(l2, off, 64);
+    }
+    if (lane == 0) {
+        adam_param(a, kOffB3, g);
+        *a.loss_out = l2 / B;
+    }
 }
 
 // Embeddings.  dE = M^T dx, M the batch's sample x node membership matrix:
@@ -479,12 +499,14 @@ __global__ void k_adam_mlp(float *__restrict__ theta, float *__restrict__ m, flo
 // fall in different banks; each wave then walks tiles of 16 nodes: the A
 // operand is the tile's membership bits (node-major rows, one 32-bit word
 // per 32 samples) expanded to bf16 0/1, K = the batch; k-steps whose word is
-// zero for the whole tile are skipped.  Rows of nodes in some sample get
-// their gradient and touched[v] = 1; the others touched[v] = 0 (Adam is lazy
-// on E: those rows keep weights and moments).
-__global__ __launch_bounds__(1024) void k_grad_E(const uint32_t *__restrict__ bits, int32_t Wb,
-                                                const uint16_t *__restrict__ dxT, int32_t B, float *__restrict__ gE,
-                                                uint8_t *__restrict__ touched, int64_t n)
+// zero for the whole tile are skipped.  Adam is lazy on E: a node in some
+// sample steps with the global step count, straight from the accumulators;
+// the others keep weights and moments.
+__global__ __launch_bounds__(1024) void k_grad_adam_E(const uint32_t *__restrict__ bits, int32_t Wb,
+                                                     const uint16_t *__restrict__ dxT, int32_t B,
+                                                     float *__restrict__ E, float *__restrict__ m,
+                                                     float *__restrict__ v, uint16_t *__restrict__ Eb,
+                                                     float *__restrict__ keep, int64_t n, AdamArgs o)
 {
     extern __shared__ __align__(16) uint16_t sB[];
     const int32_t SB = B + 8;
@@ -511,8 +533,12 @@ __global__ __launch_bounds__(1024) void k_grad_E(const uint32_t *__restrict__ bi
         for (int u = 0; u < 8; ++u) rowany |= w8[u];
         rowany |= (uint32_t)__shfl_xor((int)rowany, 16, 64);
         rowany |= (uint32_t)__shfl_xor((int)rowany, 32, 64);
-        if (lg == 0 && row < n) touched[row] = rowany != 0u;
-        if (__ballot(rowany != 0u) == 0) continue;
+        if (__ballot(rowany != 0u) == 0) {
+            if (keep)
+                for (int q = lane; q < 16 * kD; q += 64)
+                    if (v0 + q / kD < n) keep[v0 * kD + q] = 0.f;
+            continue;
+        }
         f32x4 acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -531,12 +557,26 @@ __global__ __launch_bounds__(1024) void k_grad_E(const uint32_t *__restrict__ bi
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[t] = mfma(A, ld8(sB + (t * 16 + lr) * SB + ks * 32 + lg * 8), acc[t]);
         }
+        // lane (lr, lg) holds dE[v0 + 4 lg + r][16 t + lr]; node v0 + i's
+        // membership flag sits in lane i
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t node = v0 + 4 * lg + r;
-            if (node < n)
+            const bool touched = __shfl((int)rowany, 4 * lg + r, 64) != 0;
+            if (node >= n) continue;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) gE[node * kD + t * 16 + lr] = acc[t][r];
+            for (int t = 0; t < 4; ++t) {
+                const int64_t idx = node * kD + t * 16 + lr;
+                const float g = acc[t][r];
+                if (keep) keep[idx] = touched ? g : 0.f;
+                if (!touched) continue;
+                float th = E[idx], mm = m[idx], vv = v[idx];
+                adam(th, mm, vv, g, o);
+                E[idx] = th;
+                m[idx] = mm;
+                v[idx] = vv;
+                Eb[idx] = f2bf(th);
+            }
         }
     }
 }
@@ -546,93 +586,127 @@ size_t grad_E_lds(int32_t B)
     return (size_t)kD * (B + 8) * 2;
 }
 
-// Lazy Adam on E, four weights per thread: rows with touched[v] = 0 are
-// left alone; the others step with the global step count.
-__global__ void k_adam_E(const float *__restrict__ gE, const uint8_t *__restrict__ touched, float *__restrict__ E,
-                         float *__restrict__ m, float *__restrict__ v, uint16_t *__restrict__ Eb,
-                         float *__restrict__ keep, int64_t n, AdamArgs o)
-{
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // float4 index
-    if (q >= n * (kD / 4)) return;
-    const int64_t node = q / (kD / 4);
-    if (!touched[node]) {
-        if (keep) reinterpret_cast<float4 *>(keep)[q] = float4{0.f, 0.f, 0.f, 0.f};
-        return;
-    }
-    const float4 g = reinterpret_cast<const float4 *>(gE)[q];
-    float4 th = reinterpret_cast<float4 *>(E)[q];
-    float4 mm = reinterpret_cast<float4 *>(m)[q];
-    float4 vv = reinterpret_cast<float4 *>(v)[q];
-    adam(th.x, mm.x, vv.x, g.x, o);
-    adam(th.y, mm.y, vv.y, g.y, o);
-    adam(th.z, mm.z, vv.z, g.z, o);
-    adam(th.w, mm.w, vv.w, g.w, o);
-    reinterpret_cast<float4 *>(E)[q] = th;
-    reinterpret_cast<float4 *>(m)[q] = mm;
-    reinterpret_cast<float4 *>(v)[q] = vv;
-    uint2 h;
-    h.x = f2bf(th.x) | ((uint32_t)f2bf(th.y) << 16);
-    h.y = f2bf(th.z) | ((uint32_t)f2bf(th.w) << 16);
-    reinterpret_cast<uint2 *>(Eb)[q] = h;
-    if (keep) reinterpret_cast<float4 *>(keep)[q] = g;
-}
-
 // --------------------------------------------------------- GA-side steps ----
 
-// Orderable key of a prediction (NaN last); ties broken by index.
-__device__ __forceinline__ uint64_t pred_key(float y, uint32_t idx)
+// Orderable 32-bit key of a prediction (NaN last); ties are broken by index.
+__device__ __forceinline__ uint32_t pred_key(float y)
 {
     uint32_t u = __float_as_uint(y);
     if (y != y) u = 0x7FFFFFFFu;
-    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-    return ((uint64_t)u << 32) | idx;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__device__ __forceinline__ uint64_t random_key(uint64_t seed, uint32_t gen, uint32_t ind, uint32_t i)
+__device__ __forceinline__ uint32_t random_key(uint64_t seed, uint32_t gen, uint32_t ind, uint32_t i)
 {
-    return ((uint64_t)draw(seed, i, ind, gen, kStreamSurrRandom, 0).w0 << 32) | i;
+    return draw(seed, i, ind, gen, kStreamSurrRandom, 0).w0;
 }
 
-// Bitonic sort of key[0, L) ascending (L a power of two); whole block.
-__device__ void block_sort(uint64_t *key, int32_t L)
+__device__ __forceinline__ bool bit_of(const uint32_t *bits, int32_t i)
 {
-    for (int32_t size = 2; size <= L; size <<= 1)
-        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int32_t i = threadIdx.x; i < L; i += blockDim.x) {
-                const int32_t p = i ^ stride;
-                if (p > i) {
-                    const bool up = (i & size) == 0;
-                    const uint64_t x = key[i], y = key[p];
-                    if ((x > y) == up) {
-                        key[i] = y;
-                        key[p] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    return (bits[i >> 5] >> (i & 31)) & 1u;
 }
 
-// Indices whose bit is set in bits[0, ceil(lambda / 32)), ascending, to
-// out[]; whole block (blockDim.x <= 1024).
-__device__ void block_compact(const uint32_t *bits, int32_t lambda, int32_t *out)
+// Exclusive prefix sum over the block (blockDim.x a multiple of 64, <= 1024);
+// also returns the block total.  Every thread must call it.
+__device__ int32_t block_scan(int32_t x, int32_t *total)
 {
     __shared__ int32_t s_wave[16];
-    const int32_t words = (lambda + 31) / 32;
-    const int32_t per = (words + blockDim.x - 1) / blockDim.x;
-    const int32_t w0 = min(words, (int32_t)threadIdx.x * per), w1 = min(words, w0 + per);
-    int32_t cnt = 0;
-    for (int32_t w = w0; w < w1; ++w) cnt += __popc(bits[w]);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int32_t incl = cnt;
+    int32_t incl = x;
+#pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const int32_t y = __shfl_up(incl, off, 64);
         if (lane >= off) incl += y;
     }
     if (lane == 63) s_wave[wv] = incl;
     __syncthreads();
-    int32_t off = incl - cnt;
-    for (int q = 0; q < wv; ++q) off += s_wave[q];
+    int32_t before = 0, sum = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+        if (q < wv) before += s_wave[q];
+        sum += s_wave[q];
+    }
+    __syncthreads();
+    *total = sum;
+    return before + incl - x;
+}
+
+// Sets in sel (a bit set over [0, L), cleared by the caller) the `want`
+// entries with the smallest (key[i], i) among those not in excl (NULL: none
+// excluded); want must not exceed the entries left.  Radix selection on the
+// key, eight bits a pass: each pass counts the candidates' next digit and
+// keeps the digit that holds the want-th smallest; the keys equal to the
+// final value are then taken in index order.  Whole block.
+__device__ void block_select(const uint32_t *key, const uint32_t *excl, int32_t L, int32_t want, uint32_t *sel)
+{
+    __shared__ int32_t hist[256];
+    __shared__ uint32_t s_val;
+    __shared__ int32_t s_need;
+    if (want <= 0) return;
+    uint32_t val = 0;  // digits fixed so far
+    int32_t need = want;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int32_t i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        const uint32_t hi_mask = shift == 24 ? 0u : ~0u << (shift + 8);
+        for (int32_t i = threadIdx.x; i < L; i += blockDim.x)
+            if (!(excl && bit_of(excl, i)) && (key[i] & hi_mask) == (val & hi_mask))
+                atomicAdd(&hist[(key[i] >> shift) & 255u], 1);
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            // lane l holds digits 4l .. 4l + 3
+            const int l = threadIdx.x;
+            const int32_t c0 = hist[4 * l], c1 = hist[4 * l + 1], c2 = hist[4 * l + 2], c3 = hist[4 * l + 3];
+            int32_t incl = c0 + c1 + c2 + c3;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int32_t y = __shfl_up(incl, off, 64);
+                if (l >= off) incl += y;
+            }
+            int32_t before = incl - (c0 + c1 + c2 + c3);
+            // the digit whose cumulative count first reaches need
+            const int32_t cs[4] = {c0, c1, c2, c3};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (before < need && before + cs[e] >= need) {
+                    s_val = val | ((uint32_t)(4 * l + e) << shift);
+                    s_need = need - before;
+                }
+                before += cs[e];
+            }
+        }
+        __syncthreads();
+        val = s_val;
+        need = s_need;
+        __syncthreads();
+    }
+    // keys below val are taken; of the keys equal to val, the first `need`
+    // in index order.  Thread t owns the index range [t per, (t + 1) per).
+    const int32_t per = (L + blockDim.x - 1) / blockDim.x;
+    const int32_t i0 = min(L, (int32_t)threadIdx.x * per), i1 = min(L, i0 + per);
+    int32_t eq = 0;
+    for (int32_t i = i0; i < i1; ++i) eq += !(excl && bit_of(excl, i)) && key[i] == val;
+    int32_t total = 0;
+    int32_t rank = block_scan(eq, &total);
+    for (int32_t i = i0; i < i1; ++i) {
+        if (excl && bit_of(excl, i)) continue;
+        bool take = key[i] < val;
+        if (key[i] == val) take = rank++ < need;
+        if (take) atomicOr(&sel[i >> 5], 1u << (i & 31));
+    }
+    __syncthreads();
+}
+
+// Indices whose bit is set in bits[0, ceil(lambda / 32)), ascending, to
+// out[]; whole block (blockDim.x <= 1024).
+__device__ void block_compact(const uint32_t *bits, int32_t lambda, int32_t *out)
+{
+    const int32_t words = (lambda + 31) / 32;
+    const int32_t per = (words + blockDim.x - 1) / blockDim.x;
+    const int32_t w0 = min(words, (int32_t)threadIdx.x * per), w1 = min(words, w0 + per);
+    int32_t cnt = 0;
+    for (int32_t w = w0; w < w1; ++w) cnt += __popc(bits[w]);
+    int32_t total = 0;
+    int32_t off = block_scan(cnt, &total);
     for (int32_t w = w0; w < w1; ++w)
         for (uint32_t x = bits[w]; x; x &= x - 1) out[off++] = w * 32 + __ffs(x) - 1;
     __syncthreads();
@@ -644,43 +718,22 @@ __device__ void block_compact(const uint32_t *bits, int32_t lambda, int32_t *out
 // judge's unbiased sample, the `extra` other children with the smallest
 // (first word of draw(seed, o, 1, gen, stream 7), o); ascending.  One block
 // of 1024 threads, keys in LDS, lambda <= 8192.
-size_t screen_lds(int32_t lambda)
-{
-    size_t L = 1;
-    while ((int32_t)L < lambda) L <<= 1;
-    return L * 8 + (size_t)kMaxLambda / 32 * 4 * 2;
-}
-
 __global__ __launch_bounds__(1024) void k_screen(const float *__restrict__ yhat, int32_t lambda, int32_t m,
                                                  int32_t extra, uint64_t seed, uint32_t gen,
                                                  int32_t *__restrict__ pool)
 {
-    extern __shared__ __align__(16) uint64_t key[];  // [L], then two bit sets
-    int32_t L = 1;
-    while (L < lambda) L <<= 1;
-    uint32_t *chosen = reinterpret_cast<uint32_t *>(key + L);
-    uint32_t *judged = chosen + kMaxLambda / 32;
-    for (int32_t i = threadIdx.x; i < L; i += blockDim.x)
-        key[i] = i < lambda ? (yhat ? pred_key(yhat[i], i) : random_key(seed, gen, 0, i)) : ~0ull;
+    __shared__ uint32_t key[kMaxLambda];
+    __shared__ uint32_t chosen[kMaxLambda / 32], judged[kMaxLambda / 32];
+    for (int32_t i = threadIdx.x; i < lambda; i += blockDim.x)
+        key[i] = yhat ? pred_key(yhat[i]) : random_key(seed, gen, 0, i);
     for (int32_t i = threadIdx.x; i < kMaxLambda / 32; i += blockDim.x) chosen[i] = judged[i] = 0u;
     __syncthreads();
-    block_sort(key, L);
-    for (int32_t i = threadIdx.x; i < m; i += blockDim.x) {
-        const uint32_t idx = (uint32_t)key[i];
-        atomicOr(&chosen[idx >> 5], 1u << (idx & 31));
-    }
-    __syncthreads();
+    block_select(key, nullptr, lambda, m, chosen);
     block_compact(chosen, lambda, pool);
     if (extra <= 0) return;
-    for (int32_t i = threadIdx.x; i < L; i += blockDim.x)
-        key[i] = (i < lambda && !((chosen[i >> 5] >> (i & 31)) & 1u)) ? random_key(seed, gen, 1, i) : ~0ull;
+    for (int32_t i = threadIdx.x; i < lambda; i += blockDim.x) key[i] = random_key(seed, gen, 1, i);
     __syncthreads();
-    block_sort(key, L);
-    for (int32_t i = threadIdx.x; i < extra; i += blockDim.x) {
-        const uint32_t idx = (uint32_t)key[i];
-        atomicOr(&judged[idx >> 5], 1u << (idx & 31));
-    }
-    __syncthreads();
+    block_select(key, chosen, lambda, extra, judged);
     block_compact(judged, lambda, pool + m);
 }
 
@@ -835,11 +888,11 @@ struct SurrogateState {
     int64_t last_gen = 0;
     int32_t last_evaluated = 0, last_pooled = 0;
     bool last_screened = false, last_predicted = false;
-    DevBuf theta, m, v, partial, keep_mlp, keep_E;      // float
+    DevBuf theta, m, v, keep_mlp, keep_E;               // float
     DevBuf Eb, W1b, W2b, w3b, W1bT, W2bT;               // bf16
-    DevBuf xb, yhat, ytrain, dxT, target, lossv;        // per sample (yhat: the generation's predictions)
+    DevBuf xb, yhat, ytrain, target, lossv, dy;         // per sample (yhat: the generation's predictions)
+    DevBuf xT, h1T, h2T, dz1T, dz2T, dxT;               // feature-major training activations, bf16
     DevBuf bgenes, bmasks, balive, bflag, brows;        // training batch
-    DevBuf gE, touched;                                 // embedding gradient, rows present in the batch
     DevBuf buf_genes, buf_y;                            // ring buffer
     DevBuf pool, crows, cmasks, calive;                 // screened children
     DevBuf dstats;                                      // double [8]: mu, sd, rho, rel_err, loss
@@ -890,7 +943,7 @@ int predict_rows(SurrogateState &st, const int32_t *genes, const int32_t *rows, 
     hipLaunchKernelGGL(k_embed, dim3(N), dim3(256), 0, s, genes, rows, st.k, st.Eb.as<uint16_t>(),
                        st.xb.as<uint16_t>());
     MlpArgs a = mlp_args(st, st.xb.as<uint16_t>(), yhat, N);
-    hipLaunchKernelGGL(k_mlp<false>, dim3((N + kMlpRows - 1) / kMlpRows), dim3(256), kMlpLds, s, a);
+    hipLaunchKernelGGL(k_mlp<false>, dim3((N + kMlpRows - 1) / kMlpRows), dim3(64 * kMlpWaves), 0, s, a);
     GAPA_HIP(hipGetLastError());
     return GAPA_OK;
 }
@@ -922,15 +975,32 @@ int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B
     a.target = target;
     a.dscale = 2.0f / B;
     a.lossv = st.lossv.as<float>();
+    a.dy = st.dy.as<float>();
+    a.xT = st.xT.as<uint16_t>();
+    a.h1T = st.h1T.as<uint16_t>();
+    a.h2T = st.h2T.as<uint16_t>();
+    a.dz1T = st.dz1T.as<uint16_t>();
+    a.dz2T = st.dz2T.as<uint16_t>();
     a.dxT = st.dxT.as<uint16_t>();
-    a.partial = st.partial.as<float>();
-    const int32_t nblk = (B + kMlpRows - 1) / kMlpRows;
-    hipLaunchKernelGGL(k_mlp<true>, dim3(nblk), dim3(256), kMlpLds, s, a);
-    float *th = mlp_theta(st);
+    hipLaunchKernelGGL(k_mlp<true>, dim3(B / kMlpRows), dim3(64 * kMlpWaves), 0, s, a);
     const int64_t nE = (int64_t)st.n * kD;
-    hipLaunchKernelGGL(k_adam_mlp, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, th, st.m.as<float>() + nE,
-                       st.v.as<float>() + nE, st.partial.as<float>(), nblk, keep ? st.keep_mlp.as<float>() : nullptr,
-                       o, copies(st), st.lossv.as<float>(), B, st.dstats.as<double>() + 4);
+    WgradArgs w{};
+    w.xT = a.xT;
+    w.h1T = a.h1T;
+    w.h2T = a.h2T;
+    w.dz1T = a.dz1T;
+    w.dz2T = a.dz2T;
+    w.dy = a.dy;
+    w.lossv = a.lossv;
+    w.B = B;
+    w.theta = mlp_theta(st);
+    w.m = st.m.as<float>() + nE;
+    w.v = st.v.as<float>() + nE;
+    w.keep = keep ? st.keep_mlp.as<float>() : nullptr;
+    w.cp = copies(st);
+    w.o = o;
+    w.loss_out = st.dstats.as<double>() + 4;
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(kWgradTasks), dim3(64), 0, s, w);
     // membership bits of the batch, node-major: removed-node bit sets of the
     // rows, transposed
     int rc = launch_mask_build(genes, B, st.k, g->n, g->words, g->d_noniso, g->n_noniso, st.bmasks.as<uint32_t>(),
@@ -943,11 +1013,8 @@ int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B
     const int64_t tiles = ((int64_t)st.n + 15) / 16;
     // one 16-wave block per compute unit shares one staged copy of dx
     const unsigned eblocks = (unsigned)std::min<int64_t>((tiles + 15) / 16, 256);
-    hipLaunchKernelGGL(k_grad_E, dim3(eblocks), dim3(1024), grad_E_lds(B), s, st.brows.as<uint32_t>(), Wb,
-                       st.dxT.as<uint16_t>(), B, st.gE.as<float>(), st.touched.as<uint8_t>(), (int64_t)st.n);
-    const int64_t quads = (int64_t)st.n * (kD / 4);
-    hipLaunchKernelGGL(k_adam_E, dim3((unsigned)((quads + 255) / 256)), dim3(256), 0, s, st.gE.as<float>(),
-                       st.touched.as<uint8_t>(), st.theta.as<float>(), st.m.as<float>(), st.v.as<float>(),
+    hipLaunchKernelGGL(k_grad_adam_E, dim3(eblocks), dim3(1024), grad_E_lds(B), s, st.brows.as<uint32_t>(), Wb,
+                       st.dxT.as<uint16_t>(), B, st.theta.as<float>(), st.m.as<float>(), st.v.as<float>(),
                        st.Eb.as<uint16_t>(), keep ? st.keep_E.as<float>() : nullptr, (int64_t)st.n, o);
     GAPA_HIP(hipGetLastError());
     st.have_keep = keep;
@@ -1008,7 +1075,6 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     const int64_t P = nE + kMlpParams;
     const int32_t B = sp->batch;
     const int32_t rows = std::max(L, B);
-    const int32_t nblk = (B + kMlpRows - 1) / kMlpRows;
     int rc = GAPA_OK;
     auto res = [&](DevBuf &b, size_t bytes) {
         if (rc == GAPA_OK) rc = b.reserve(bytes);
@@ -1016,7 +1082,6 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->theta, P * 4);
     res(st->m, P * 4);
     res(st->v, P * 4);
-    res(st->partial, (size_t)nblk * kMlpParams * 4);
     res(st->keep_mlp, (size_t)kMlpParams * 4);
     res(st->keep_E, (size_t)nE * 4);
     res(st->Eb, (size_t)nE * 2);
@@ -1028,6 +1093,12 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->xb, (size_t)rows * kD * 2);
     res(st->yhat, (size_t)rows * 4);
     res(st->ytrain, (size_t)B * 4);
+    res(st->dy, (size_t)B * 4);
+    res(st->xT, (size_t)B * kD * 2);
+    res(st->h1T, (size_t)B * kH * 2);
+    res(st->h2T, (size_t)B * kH * 2);
+    res(st->dz1T, (size_t)B * kH * 2);
+    res(st->dz2T, (size_t)B * kH * 2);
     res(st->dxT, (size_t)B * kD * 2);
     res(st->target, (size_t)B * 4);
     res(st->lossv, (size_t)B * 4);
@@ -1036,8 +1107,6 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->balive, (size_t)B * 4);
     res(st->bflag, 16);
     res(st->brows, (size_t)st->n * (B / 32) * 4);
-    res(st->gE, (size_t)nE * 4);
-    res(st->touched, (size_t)st->n);
     res(st->buf_genes, (size_t)sp->buffer * st->k * 4);
     res(st->buf_y, (size_t)sp->buffer * 8);
     res(st->pool, (size_t)L * 4);
@@ -1049,13 +1118,7 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     GAPA_HIP(hipHostMalloc(reinterpret_cast<void **>(&st->hstats), 64, hipHostMallocDefault));
     std::memset(st->hstats, 0, 64);
     GAPA_HIP(hipEventCreateWithFlags(&st->ready, hipEventDisableTiming));
-    GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp<false>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMlpLds));
-    GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp<true>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMlpLds));
-    GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_screen), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)screen_lds(kMaxLambda)));
-    GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_grad_E), hipFuncAttributeMaxDynamicSharedMemorySize,
+    GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_grad_adam_E), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)grad_E_lds(1024)));
     const unsigned blocks = (unsigned)((P + 255) / 256);
     hipLaunchKernelGGL(k_surr_init, dim3(blocks), dim3(256), 0, s, st->theta.as<float>(), (int64_t)st->n, st->seed,
@@ -1073,11 +1136,11 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
 void surrogate_release(SurrogateState *st)
 {
     if (!st) return;
-    for (DevBuf *b : {&st->theta, &st->m, &st->v, &st->partial, &st->keep_mlp, &st->keep_E, &st->Eb, &st->W1b,
-                      &st->W2b, &st->w3b, &st->W1bT, &st->W2bT, &st->xb, &st->yhat, &st->ytrain, &st->dxT, &st->target,
-                      &st->lossv, &st->bgenes, &st->bmasks, &st->balive, &st->bflag, &st->brows, &st->gE, &st->touched,
-                      &st->buf_genes,
-                      &st->buf_y, &st->pool, &st->crows, &st->cmasks, &st->calive, &st->dstats})
+    for (DevBuf *b : {&st->theta, &st->m, &st->v, &st->keep_mlp, &st->keep_E, &st->Eb, &st->W1b, &st->W2b, &st->w3b,
+                      &st->W1bT, &st->W2bT, &st->xb, &st->yhat, &st->ytrain, &st->target, &st->lossv, &st->dy,
+                      &st->xT, &st->h1T, &st->h2T, &st->dz1T, &st->dz2T, &st->dxT, &st->bgenes, &st->bmasks,
+                      &st->balive, &st->bflag, &st->brows, &st->buf_genes, &st->buf_y, &st->pool, &st->crows,
+                      &st->cmasks, &st->calive, &st->dstats})
         b->release();
     if (st->hstats) (void)hipHostFree(st->hstats);
     if (st->ready) (void)hipEventDestroy(st->ready);
@@ -1116,7 +1179,7 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         const int32_t extra = predict ? std::min(kJudgeExtra, L - npool) : 0;
         neval = npool + extra;
         pool = st.pool.as<int32_t>();
-        hipLaunchKernelGGL(k_screen, dim3(1), dim3(1024), screen_lds(L), s, random ? nullptr : yhat, L, npool, extra,
+        hipLaunchKernelGGL(k_screen, dim3(1), dim3(1024), 0, s, random ? nullptr : yhat, L, npool, extra,
                            st.seed, gen, st.pool.as<int32_t>());
         hipLaunchKernelGGL(k_gather_pool_rows, dim3(neval), dim3(256), 0, s, pool, ga->children.as<int32_t>(), st.k,
                            st.crows.as<int32_t>());

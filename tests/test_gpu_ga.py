@@ -158,3 +158,30 @@ def test_side_stream_and_timing(gp, ba10k):
     assert np.array_equal(pop, oga.pop) and np.array_equal(F, oga.F)
     t = ga.kernel_times()
     assert "ga_offspring" in t and t["ga_offspring"][0] == 3
+
+
+def test_handles_destroyed_in_any_order(gp, ba200):
+    """A graph released before the GA and the batch built on it stays alive
+    until they are destroyed: they keep running, and afterwards the device
+    shows no error (a freed graph would be read at their destruction)."""
+    graph = gp.Graph.from_csr(ba200)
+    ga = gp.GA(graph, 10, 16, 1)
+    bt = gp.Batch([graph], [dict(k=10, pop=16, seed=1)])
+    graph.close()
+    ga.step(3)
+    bt.step(3)
+    pop_g, F_g = ga.population()
+    pop_b, F_b = bt.population(0)
+    assert np.array_equal(pop_g, pop_b) and np.array_equal(F_g, F_b)
+    oga = O.OracleGA(ba200, 10, 16, 1, 0.7, 0.05, 2)
+    for _ in range(3):
+        oga.step()
+    assert np.array_equal(F_g, oga.F) and np.array_equal(pop_g, oga.pop)
+    ga.close()
+    bt.close()
+    # a later GA runs cleanly (no error left behind by the releases)
+    g2 = gp.Graph.from_csr(ba200)
+    ga2 = gp.GA(g2, 10, 16, 2)
+    ga2.step(2)
+    ga2.close()
+    g2.close()
