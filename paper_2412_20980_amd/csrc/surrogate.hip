@@ -146,6 +146,22 @@ __global__ void k_bf16_copies(const float *__restrict__ theta, int64_t n, Bf16Co
     else mlp_copy(o, (int32_t)(i - nE), theta[i]);
 }
 
+// Copies the weights the forward pass reads (bf16 E, W1, W2, w3 and the FP32
+// biases) into the prediction snapshot, 16 bytes a thread.
+struct SnapArgs {
+    const uint4 *src[5];
+    uint4 *dst[5];
+    int64_t len[5];  // in 16-byte units
+};
+
+__global__ void k_snapshot(SnapArgs a)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int t = 0; t < 5; ++t)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.len[t]; i += stride)
+            a.dst[t][i] = a.src[t][i];
+}
+
 // ------------------------------------------------------------- embedding ----
 
 // x(S) of each row, rounded to bf16: one 256-thread block per row.  Lane
@@ -432,10 +448,12 @@ __device__ __forceinline__ void adam_param(const WgradArgs &a, int32_t j, float 
 
 // MLP parameter gradients over the batch, then Adam and the bfloat16 copies;
 // one wave per task.  Tasks 0..255: 16 x 16 tiles of dW2 = dz2^T h1;
-// 256..319: tiles of dW1 = dz1^T x (K = the batch, on the matrix cores);
-// 320..331: 64 entries each of db1 = sum dz1, db2 = sum dz2 and
-// dw3 = sum dyhat h2 (samples in order); 332: db3 = sum dyhat and the loss.
-constexpr int kWgradTasks = 333;
+// 256..319: tiles of dW1 = dz1^T x (K = the batch, on the matrix cores, eight
+// k-steps loaded at a time); then db1 = sum dz1,
+// db2 = sum dz2 and dw3 = sum dyhat h2, one entry per task (each lane adds a
+// run of samples in order, lanes combined in a fixed tree); the last task:
+// db3 = sum dyhat and the loss.
+constexpr int kWgradTasks = 320 + 3 * kH + 1;
 __global__ __launch_bounds__(64) void k_mlp_wgrad(WgradArgs a)
 {
     const int32_t task = blockIdx.x;
@@ -448,7 +466,18 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad(WgradArgs a)
         const uint16_t *At = (w2 ? a.dz2T : a.dz1T) + (int64_t)(J * 16 + lr) * B + lg * 8;
         const uint16_t *Bt = (w2 ? a.h1T : a.xT) + (int64_t)(I * 16 + lr) * B + lg * 8;
         f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int32_t ks = 0; ks < B; ks += 32) acc = mfma(ld8(At + ks), ld8(Bt + ks), acc);
+        constexpr int U = 8;
+        for (int32_t ks0 = 0; ks0 < B; ks0 += 32 * U) {
+            bf16x8 av[U], bv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t ks = ks0 + 32 * u;
+                av[u] = ks < B ? ld8(At + ks) : bf16x8{};
+                bv[u] = ks < B ? ld8(Bt + ks) : bf16x8{};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc = mfma(av[u], bv[u], acc);
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int32_t j = J * 16 + 4 * lg + r, i = I * 16 + lr;
@@ -456,21 +485,36 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad(WgradArgs a)
         }
         return;
     }
-    if (task < 332) {
-        const int32_t kind = (task - 320) >> 2;  // 0 b1, 1 b2, 2 w3
-        const int32_t j = ((task - 320) & 3) * 64 + lane;
+    if (task < 320 + 3 * kH) {
+        const int32_t kind = (task - 320) / kH;  // 0 b1, 1 b2, 2 w3
+        const int32_t j = (task - 320) % kH;
         const uint16_t *row = (kind == 0 ? a.dz1T : kind == 1 ? a.dz2T : a.h2T) + (int64_t)j * B;
+        // lane l adds samples [l per, (l + 1) per) in order, per = B / 64 (B >= 64)
+        // or one sample (B = 32)
+        const int32_t per = B >= 64 ? B >> 6 : 1;
+        const int32_t s0 = lane * per;
         float g = 0.f;
-        for (int32_t s0 = 0; s0 < B; s0 += 8) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(row + s0);
-            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        if (s0 < B) {
+            if ((per & 7) == 0) {
+                for (int32_t e0 = 0; e0 < per; e0 += 8) {
+                    const uint4 q = *reinterpret_cast<const uint4 *>(row + s0 + e0);
+                    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float x = bf2f((uint16_t)(w[e >> 1] >> (16 * (e & 1))));
-                g += kind == 2 ? a.dy[s0 + e] * x : x;
+                    for (int e = 0; e < 8; ++e) {
+                        const float x = bf2f((uint16_t)(w[e >> 1] >> (16 * (e & 1))));
+                        g += kind == 2 ? a.dy[s0 + e0 + e] * x : x;
+                    }
+                }
+            } else {
+                for (int32_t e = 0; e < per; ++e) {
+                    const float x = bf2f(row[s0 + e]);
+                    g += kind == 2 ? a.dy[s0 + e] * x : x;
+                }
             }
         }
-        adam_param(a, kind == 0 ? kOffB1 + j : kind == 1 ? kOffB2 + j : kOffW3 + j, g);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) g += __shfl_xor(g, off, 64);
+        if (lane == 0) adam_param(a, kind == 0 ? kOffB1 + j : kind == 1 ? kOffB2 + j : kOffW3 + j, g);
         return;
     }
     // db3 and the loss: lane l takes samples l, l + 64, ...; lanes combined in a fixed tree
@@ -890,14 +934,24 @@ struct SurrogateState {
     bool last_screened = false, last_predicted = false;
     DevBuf theta, m, v, keep_mlp, keep_E;               // float
     DevBuf Eb, W1b, W2b, w3b, W1bT, W2bT;               // bf16
-    DevBuf xb, yhat, ytrain, target, lossv, dy;         // per sample (yhat: the generation's predictions)
+    DevBuf xb, yhat;                                    // predictions: x(S) and yhat of the generation
+    DevBuf snap;                                        // prediction snapshot: Eb, W1b, W2b, w3b, biases
+    DevBuf xtrain, ytrain, target, lossv, dy;           // training batch, per sample
     DevBuf xT, h1T, h2T, dz1T, dz2T, dxT;               // feature-major training activations, bf16
-    DevBuf bgenes, bmasks, balive, bflag, brows;        // training batch
+    DevBuf bgenes, bmasks, balive, bflag, tflag, brows; // training batch
     DevBuf buf_genes, buf_y;                            // ring buffer
     DevBuf pool, crows, cmasks, calive;                 // screened children
     DevBuf dstats;                                      // double [8]: mu, sd, rho, rel_err, loss
+    DevBuf dloss;                                       // double: loss of the last training step
     double *hstats = nullptr;                           // pinned copy of dstats
     hipEvent_t ready = nullptr;
+    // Generation g's training runs on its own stream beside generation g + 1;
+    // the predictions of generation g read a snapshot of the weights trained
+    // through generation g - 2.
+    hipStream_t ts = nullptr;
+    hipEvent_t ev_pred = nullptr;   // main stream: the generation's predictions are made
+    hipEvent_t ev_snap = nullptr;   // training stream: training done and snapshot taken
+    hipEvent_t ev_data = nullptr;   // main stream: the generation's labels are in the buffer
     bool have_keep = false;
 };
 
@@ -919,7 +973,27 @@ float *mlp_theta(SurrogateState &st)
     return st.theta.as<float>() + (int64_t)st.n * kD;
 }
 
-MlpArgs mlp_args(SurrogateState &st, const uint16_t *xb, float *yhat, int32_t N)
+// The prediction snapshot: bf16 E [n][64], W1 [256][64], W2 [256][256],
+// w3 [256] and the FP32 biases b1, b2 (b3 after them), each part 256-byte
+// aligned.
+struct SnapLayout {
+    size_t eb, w1, w2, w3, bias, bytes;
+};
+
+SnapLayout snap_layout(int64_t n)
+{
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    SnapLayout l{};
+    l.eb = 0;
+    l.w1 = up((size_t)n * kD * 2);
+    l.w2 = l.w1 + up((size_t)kH * kD * 2);
+    l.w3 = l.w2 + up((size_t)kH * kH * 2);
+    l.bias = l.w3 + up((size_t)kH * 2);
+    l.bytes = l.bias + up((size_t)(2 * kH + 4) * 4);
+    return l;
+}
+
+MlpArgs mlp_args(SurrogateState &st, const uint16_t *xb, float *yhat, int32_t N, bool snapshot = false)
 {
     MlpArgs a{};
     const float *th = mlp_theta(st);
@@ -932,17 +1006,58 @@ MlpArgs mlp_args(SurrogateState &st, const uint16_t *xb, float *yhat, int32_t N)
     a.b1 = th + kOffB1;
     a.b2 = th + kOffB2;
     a.b3 = th + kOffB3;
+    if (snapshot) {
+        const SnapLayout l = snap_layout(st.n);
+        char *b = static_cast<char *>(st.snap.ptr);
+        a.W1b = reinterpret_cast<const uint16_t *>(b + l.w1);
+        a.W2b = reinterpret_cast<const uint16_t *>(b + l.w2);
+        a.w3b = reinterpret_cast<const uint16_t *>(b + l.w3);
+        a.b1 = reinterpret_cast<const float *>(b + l.bias);
+        a.b2 = a.b1 + kH;
+        a.b3 = a.b1 + 2 * kH;
+        a.W1bT = a.W2bT = nullptr;  // forward only
+    }
     a.yhat = yhat;
     a.N = N;
     return a;
 }
 
-int predict_rows(SurrogateState &st, const int32_t *genes, const int32_t *rows, int32_t N, float *yhat, hipStream_t s)
+// Copies the live weights into the prediction snapshot (stream s).
+int take_snapshot(SurrogateState &st, hipStream_t s)
+{
+    const SnapLayout l = snap_layout(st.n);
+    char *b = static_cast<char *>(st.snap.ptr);
+    const float *th = mlp_theta(st);
+    SnapArgs a{};
+    const void *src[5] = {st.Eb.ptr, st.W1b.ptr, st.W2b.ptr, st.w3b.ptr, th + kOffB1};
+    const size_t off[5] = {l.eb, l.w1, l.w2, l.w3, l.bias};
+    const size_t bytes[5] = {(size_t)st.n * kD * 2, (size_t)kH * kD * 2, (size_t)kH * kH * 2, (size_t)kH * 2,
+                             (size_t)kH * 4};
+    for (int t = 0; t < 5; ++t) {
+        a.src[t] = static_cast<const uint4 *>(src[t]);
+        a.dst[t] = reinterpret_cast<uint4 *>(b + off[t]);
+        a.len[t] = (int64_t)(bytes[t] / 16);
+    }
+    hipLaunchKernelGGL(k_snapshot, dim3(1024), dim3(256), 0, s, a);
+    GAPA_HIP(hipGetLastError());
+    // b2 and b3 are not next to b1 in the parameter layout
+    float *bias = reinterpret_cast<float *>(b + l.bias);
+    GAPA_HIP(hipMemcpyAsync(bias + kH, th + kOffB2, kH * 4, hipMemcpyDeviceToDevice, s));
+    GAPA_HIP(hipMemcpyAsync(bias + 2 * kH, th + kOffB3, 4, hipMemcpyDeviceToDevice, s));
+    return GAPA_OK;
+}
+
+// Predictions for N rows of genes (rows[] selects rows when not NULL), from
+// the live weights or from the snapshot.
+int predict_rows(SurrogateState &st, const int32_t *genes, const int32_t *rows, int32_t N, float *yhat, hipStream_t s,
+                 bool snapshot = false)
 {
     if (N <= 0) return GAPA_OK;
-    hipLaunchKernelGGL(k_embed, dim3(N), dim3(256), 0, s, genes, rows, st.k, st.Eb.as<uint16_t>(),
-                       st.xb.as<uint16_t>());
-    MlpArgs a = mlp_args(st, st.xb.as<uint16_t>(), yhat, N);
+    const uint16_t *Eb = snapshot ? reinterpret_cast<const uint16_t *>(static_cast<char *>(st.snap.ptr) +
+                                                                       snap_layout(st.n).eb)
+                                  : st.Eb.as<uint16_t>();
+    hipLaunchKernelGGL(k_embed, dim3(N), dim3(256), 0, s, genes, rows, st.k, Eb, st.xb.as<uint16_t>());
+    MlpArgs a = mlp_args(st, st.xb.as<uint16_t>(), yhat, N, snapshot);
     hipLaunchKernelGGL(k_mlp<false>, dim3((N + kMlpRows - 1) / kMlpRows), dim3(64 * kMlpWaves), 0, s, a);
     GAPA_HIP(hipGetLastError());
     return GAPA_OK;
@@ -970,8 +1085,8 @@ int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B
     st.steps += 1;
     const AdamArgs o = adam_args(st);
     hipLaunchKernelGGL(k_embed, dim3(B), dim3(256), 0, s, genes, nullptr, st.k, st.Eb.as<uint16_t>(),
-                       st.xb.as<uint16_t>());
-    MlpArgs a = mlp_args(st, st.xb.as<uint16_t>(), st.ytrain.as<float>(), B);
+                       st.xtrain.as<uint16_t>());
+    MlpArgs a = mlp_args(st, st.xtrain.as<uint16_t>(), st.ytrain.as<float>(), B);
     a.target = target;
     a.dscale = 2.0f / B;
     a.lossv = st.lossv.as<float>();
@@ -999,12 +1114,12 @@ int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B
     w.keep = keep ? st.keep_mlp.as<float>() : nullptr;
     w.cp = copies(st);
     w.o = o;
-    w.loss_out = st.dstats.as<double>() + 4;
+    w.loss_out = st.dloss.as<double>();
     hipLaunchKernelGGL(k_mlp_wgrad, dim3(kWgradTasks), dim3(64), 0, s, w);
     // membership bits of the batch, node-major: removed-node bit sets of the
     // rows, transposed
     int rc = launch_mask_build(genes, B, st.k, g->n, g->words, g->d_noniso, g->n_noniso, st.bmasks.as<uint32_t>(),
-                               st.balive.as<int32_t>(), st.bflag.as<int32_t>(), s);
+                               st.balive.as<int32_t>(), st.tflag.as<int32_t>(), s);
     if (rc != GAPA_OK) return rc;
     const int32_t Wb = B / 32;
     if ((rc = launch_bits_transpose(st.bmasks.as<uint32_t>(), B, g->words, g->n, st.brows.as<uint32_t>(), s)) !=
@@ -1092,6 +1207,8 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->w3b, kH * 2);
     res(st->xb, (size_t)rows * kD * 2);
     res(st->yhat, (size_t)rows * 4);
+    res(st->snap, snap_layout(st->n).bytes);
+    res(st->xtrain, (size_t)B * kD * 2);
     res(st->ytrain, (size_t)B * 4);
     res(st->dy, (size_t)B * 4);
     res(st->xT, (size_t)B * kD * 2);
@@ -1106,6 +1223,7 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->bmasks, (size_t)B * st->W * 4);
     res(st->balive, (size_t)B * 4);
     res(st->bflag, 16);
+    res(st->tflag, 16);
     res(st->brows, (size_t)st->n * (B / 32) * 4);
     res(st->buf_genes, (size_t)sp->buffer * st->k * 4);
     res(st->buf_y, (size_t)sp->buffer * 8);
@@ -1114,10 +1232,15 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->cmasks, (size_t)(sp->screen + kJudgeExtra) * st->W * 4);
     res(st->calive, (size_t)(sp->screen + kJudgeExtra) * 4);
     res(st->dstats, 64);
+    res(st->dloss, 8);
     if (rc != GAPA_OK) return rc;
     GAPA_HIP(hipHostMalloc(reinterpret_cast<void **>(&st->hstats), 64, hipHostMallocDefault));
     std::memset(st->hstats, 0, 64);
     GAPA_HIP(hipEventCreateWithFlags(&st->ready, hipEventDisableTiming));
+    GAPA_HIP(hipEventCreateWithFlags(&st->ev_pred, hipEventDisableTiming));
+    GAPA_HIP(hipEventCreateWithFlags(&st->ev_snap, hipEventDisableTiming));
+    GAPA_HIP(hipEventCreateWithFlags(&st->ev_data, hipEventDisableTiming));
+    GAPA_HIP(hipStreamCreateWithFlags(&st->ts, hipStreamNonBlocking));
     GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_grad_adam_E), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)grad_E_lds(1024)));
     const unsigned blocks = (unsigned)((P + 255) / 256);
@@ -1130,6 +1253,12 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     if ((rc = launch_fill_u32(st->v.ptr, 0u, P, s)) != GAPA_OK) return rc;
     if ((rc = launch_fill_u32(st->dstats.ptr, 0u, 16, s)) != GAPA_OK) return rc;
     if ((rc = launch_fill_u32(st->bflag.ptr, 0u, 4, s)) != GAPA_OK) return rc;
+    if ((rc = launch_fill_u32(st->tflag.ptr, 0u, 4, s)) != GAPA_OK) return rc;
+    if ((rc = launch_fill_u32(st->dloss.ptr, 0u, 2, s)) != GAPA_OK) return rc;
+    // the snapshot starts as the initial weights; training waits for set-up
+    if ((rc = take_snapshot(*st, s)) != GAPA_OK) return rc;
+    GAPA_HIP(hipEventRecord(st->ev_data, s));
+    GAPA_HIP(hipStreamWaitEvent(st->ts, st->ev_data, 0));
     return GAPA_OK;
 }
 
@@ -1137,13 +1266,17 @@ void surrogate_release(SurrogateState *st)
 {
     if (!st) return;
     for (DevBuf *b : {&st->theta, &st->m, &st->v, &st->keep_mlp, &st->keep_E, &st->Eb, &st->W1b, &st->W2b, &st->w3b,
-                      &st->W1bT, &st->W2bT, &st->xb, &st->yhat, &st->ytrain, &st->target, &st->lossv, &st->dy,
+                      &st->W1bT, &st->W2bT, &st->xb, &st->yhat, &st->snap, &st->xtrain, &st->ytrain,
+                      &st->target, &st->lossv, &st->dy, &st->tflag, &st->dloss,
                       &st->xT, &st->h1T, &st->h2T, &st->dz1T, &st->dz2T, &st->dxT, &st->bgenes, &st->bmasks,
                       &st->balive, &st->bflag, &st->brows, &st->buf_genes, &st->buf_y, &st->pool, &st->crows,
                       &st->cmasks, &st->calive, &st->dstats})
         b->release();
     if (st->hstats) (void)hipHostFree(st->hstats);
-    if (st->ready) (void)hipEventDestroy(st->ready);
+    if (st->ts) (void)hipStreamSynchronize(st->ts);
+    for (hipEvent_t e : {st->ready, st->ev_pred, st->ev_snap, st->ev_data})
+        if (e) (void)hipEventDestroy(e);
+    if (st->ts) (void)hipStreamDestroy(st->ts);
     delete st;
 }
 
@@ -1164,7 +1297,18 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
     if ((rc = ga_launch_offspring(ga, s, !full)) != GAPA_OK) return rc;
     const bool predict = !random && (int64_t)gen > st.sp.warmup_gens;
     float *yhat = st.yhat.as<float>();
-    if (predict && (rc = predict_rows(st, ga->children.as<int32_t>(), nullptr, L, yhat, s)) != GAPA_OK) return rc;
+    if (!random) {
+        // the snapshot holds the weights trained through generation gen - 2
+        GAPA_HIP(hipStreamWaitEvent(s, st.ev_snap, 0));
+        if (predict &&
+            (rc = predict_rows(st, ga->children.as<int32_t>(), nullptr, L, yhat, s, true)) != GAPA_OK)
+            return rc;
+        // once they are made, it takes the weights trained through gen - 1
+        GAPA_HIP(hipEventRecord(st.ev_pred, s));
+        GAPA_HIP(hipStreamWaitEvent(st.ts, st.ev_pred, 0));
+        if ((rc = take_snapshot(st, st.ts)) != GAPA_OK) return rc;
+        GAPA_HIP(hipEventRecord(st.ev_snap, st.ts));
+    }
     int64_t *F = ga->child_fit.as<int64_t>();
     int32_t npool = L;     // children that enter elitism
     int32_t neval = L;     // children evaluated exactly (the pool, then the judge's extra sample)
@@ -1197,16 +1341,23 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
     double *ds = st.dstats.as<double>();
     if (predict) hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, neval, ds, ds + 2);
     if (!random) {
+        // generation gen - 1's training is done with the buffer (and its loss is final)
+        GAPA_HIP(hipStreamWaitEvent(s, st.ev_snap, 0));
+        GAPA_HIP(hipMemcpyAsync(ds + 4, st.dloss.ptr, 8, hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(k_append, dim3(neval), dim3(256), 0, s, ga->children.as<int32_t>(), st.k, pool, F,
                            st.appended, st.sp.buffer, st.buf_genes.as<int32_t>(), st.buf_y.as<double>());
         st.appended += neval;
         const int32_t count = (int32_t)std::min<int64_t>(st.appended, st.sp.buffer);
         hipLaunchKernelGGL(k_label_stats, dim3(1), dim3(1024), 0, s, st.buf_y.as<double>(), count, ds);
+        GAPA_HIP(hipGetLastError());
+        // this generation's training, on the training stream
+        GAPA_HIP(hipEventRecord(st.ev_data, s));
+        GAPA_HIP(hipStreamWaitEvent(st.ts, st.ev_data, 0));
         for (int32_t t = 0; t < st.sp.train_steps; ++t) {
-            hipLaunchKernelGGL(k_sample, dim3(st.sp.batch), dim3(256), 0, s, st.seed, gen, (uint32_t)t, count,
+            hipLaunchKernelGGL(k_sample, dim3(st.sp.batch), dim3(256), 0, st.ts, st.seed, gen, (uint32_t)t, count,
                                st.buf_genes.as<int32_t>(), st.buf_y.as<double>(), ds, st.k,
                                st.bgenes.as<int32_t>(), st.target.as<float>());
-            if ((rc = train_step(ga, st.bgenes.as<int32_t>(), st.target.as<float>(), st.sp.batch, false, s)) !=
+            if ((rc = train_step(ga, st.bgenes.as<int32_t>(), st.target.as<float>(), st.sp.batch, false, st.ts)) !=
                 GAPA_OK)
                 return rc;
         }
@@ -1232,6 +1383,7 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
 int surrogate_predict(gapa_ga *ga, const int32_t *genes, int32_t P, float *yhat, hipStream_t s)
 {
     SurrogateState &st = *ga->surr;
+    GAPA_HIP(hipStreamSynchronize(st.ts));  // the live weights, after all enqueued training
     const int32_t chunk = std::max(st.lambda, st.sp.batch);  // rows of the x buffer
     for (int32_t c0 = 0; c0 < P; c0 += chunk) {
         const int32_t cnt = std::min(P - c0, chunk);
@@ -1249,6 +1401,7 @@ int surrogate_train_batch(gapa_ga *ga, const int32_t *genes, const float *target
         set_error("batch size %d differs from the surrogate's (%d)", B, st.sp.batch);
         return GAPA_E_INVALID_ARG;
     }
+    GAPA_HIP(hipStreamSynchronize(st.ts));
     return train_step(ga, genes, target, B, keep_grads, s);
 }
 
