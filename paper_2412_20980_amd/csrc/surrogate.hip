@@ -148,18 +148,26 @@ __global__ void k_bf16_copies(const float *__restrict__ theta, int64_t n, Bf16Co
 
 // Copies the weights the forward pass reads (bf16 E, W1, W2, w3 and the FP32
 // biases) into the prediction snapshot, 16 bytes a thread.
+constexpr int kSnapParts = 8;
 struct SnapArgs {
-    const uint4 *src[5];
-    uint4 *dst[5];
-    int64_t len[5];  // in 16-byte units
+    const uint32_t *src[kSnapParts];
+    uint32_t *dst[kSnapParts];
+    int64_t len[kSnapParts];  // in 4-byte words; parts of a multiple of 4 words are 16-byte aligned
 };
 
 __global__ void k_snapshot(SnapArgs a)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int t = 0; t < 5; ++t)
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.len[t]; i += stride)
-            a.dst[t][i] = a.src[t][i];
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int t = 0; t < kSnapParts; ++t) {
+        if (a.len[t] % 4 == 0) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.src[t]);
+            uint4 *dst = reinterpret_cast<uint4 *>(a.dst[t]);
+            for (int64_t i = t0; i < a.len[t] / 4; i += stride) dst[i] = src[i];
+        } else {
+            for (int64_t i = t0; i < a.len[t]; i += stride) a.dst[t][i] = a.src[t][i];
+        }
+    }
 }
 
 // ------------------------------------------------------------- embedding ----
@@ -234,6 +242,9 @@ struct MlpArgs {
     // feature-major bf16 activations and gradients for the weight gradients:
     // xT [64][B], h1T, h2T, dz1T, dz2T [256][B]; dxT [64][B] for dE
     uint16_t *xT, *h1T, *h2T, *dz1T, *dz2T, *dxT;
+    // prediction: the label mean and spread of the weights used, copied for the judge
+    const double *musd_src;
+    double *musd_dst;
 };
 
 // Stores the four rows 4 lg .. 4 lg + 3 of one C-tile column as one 8-byte
@@ -268,6 +279,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpArgs a)
     const int32_t row0 = blockIdx.x * kMlpRows;
     const int c0 = wv * 32;
 
+    if (!kTrain && a.musd_dst && blockIdx.x == 0 && threadIdx.x < 2) a.musd_dst[threadIdx.x] = a.musd_src[threadIdx.x];
     if (threadIdx.x < kMlpRows * 8) {
         const int r = threadIdx.x >> 3, c8 = (threadIdx.x & 7) * 8;
         uint4 v = {0u, 0u, 0u, 0u};
@@ -798,46 +810,48 @@ __global__ void k_gather_pool_rows(const int32_t *__restrict__ pool, const int32
 
 // Ring buffer: entry (base + q) mod cap takes child pool[q] (q when pool is
 // NULL) and the label ln(1 + F[q]).
+// Block 0 also copies the loss of the last finished training step.
 __global__ void k_append(const int32_t *__restrict__ children, int32_t k, const int32_t *__restrict__ pool,
                          const int64_t *__restrict__ F, int64_t base, int32_t cap, int32_t *__restrict__ buf_genes,
-                         double *__restrict__ buf_y)
+                         double *__restrict__ buf_y, const double *__restrict__ loss, double *__restrict__ loss_out)
 {
     const int32_t q = blockIdx.x;
     const int32_t o = pool ? pool[q] : q;
     const int64_t slot = (base + q) % cap;
     for (int32_t j = threadIdx.x; j < k; j += blockDim.x) buf_genes[slot * k + j] = children[(int64_t)o * k + j];
     if (threadIdx.x == 0) buf_y[slot] = log1p((double)F[q]);
+    if (q == 0 && threadIdx.x == 0) *loss_out = *loss;
 }
 
 // Mean and spread of the buffered labels (one block, fixed order): the
 // spread is sqrt(variance + floor^2), so that a buffer of (nearly) equal
 // labels gives targets near zero rather than amplified rounding noise.
 constexpr double kSpreadFloor = 1e-6;
+__device__ double block_sum_d(double a, double *s_w)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = a;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_w[w];
+    __syncthreads();
+    return t;
+}
+
 __global__ __launch_bounds__(1024) void k_label_stats(const double *__restrict__ y, int32_t count,
                                                       double *__restrict__ out)
 {
-    __shared__ double s[1024];
+    __shared__ double s_w[16];
     double a = 0.0;
     for (int32_t i = threadIdx.x; i < count; i += blockDim.x) a += y[i];
-    s[threadIdx.x] = a;
-    __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-        __syncthreads();
-    }
-    const double mu = s[0] / count;
-    __syncthreads();
+    const double mu = block_sum_d(a, s_w) / count;
     a = 0.0;
     for (int32_t i = threadIdx.x; i < count; i += blockDim.x) a += (y[i] - mu) * (y[i] - mu);
-    s[threadIdx.x] = a;
-    __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-        __syncthreads();
-    }
+    const double var = block_sum_d(a, s_w) / count;
     if (threadIdx.x == 0) {
         out[0] = mu;
-        out[1] = sqrt(s[0] / count + kSpreadFloor * kSpreadFloor);
+        out[1] = sqrt(var + kSpreadFloor * kSpreadFloor);
     }
 }
 
@@ -869,7 +883,7 @@ __global__ __launch_bounds__(1024) void k_judge(const float *__restrict__ yhat, 
 {
     __shared__ float s_y[kJudgeMax];
     __shared__ int64_t s_f[kJudgeMax];
-    __shared__ double s_a[1024], s_b[1024], s_c[1024], s_e[1024];
+    __shared__ double s_w[4][16];
     const int32_t J = min(m, kJudgeMax);
     const int32_t i = threadIdx.x;
     if (i < J) {
@@ -894,24 +908,24 @@ __global__ __launch_bounds__(1024) void k_judge(const float *__restrict__ yhat, 
         const double pred = expm1((double)s_y[i] * mu_sd[1] + mu_sd[0]);
         rel = fabs(pred - f) / fmax(f, 1.0);
     }
-    s_a[i] = ra * rb;
-    s_b[i] = ra * ra;
-    s_c[i] = rb * rb;
-    s_e[i] = rel;
+    // sums: a fixed tree inside each wave, then the waves in order
+    double q[4] = {ra * rb, ra * ra, rb * rb, rel};
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) q[t] += __shfl_xor(q[t], off, 64);
+    if ((i & 63) == 0)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) s_w[t][i >> 6] = q[t];
     __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-        if (i < off) {
-            s_a[i] += s_a[i + off];
-            s_b[i] += s_b[i + off];
-            s_c[i] += s_c[i + off];
-            s_e[i] += s_e[i + off];
-        }
-        __syncthreads();
-    }
     if (i == 0) {
-        const double den = sqrt(s_b[0] * s_c[0]);
-        out[0] = den > 0.0 ? s_a[0] / den : 0.0;
-        out[1] = s_e[0] / J;
+        double sum[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) sum[t] += s_w[t][w];
+        const double den = sqrt(sum[1] * sum[2]);
+        out[0] = den > 0.0 ? sum[0] / den : 0.0;
+        out[1] = sum[3] / J;
     }
 }
 
@@ -941,9 +955,11 @@ struct SurrogateState {
     DevBuf bgenes, bmasks, balive, bflag, tflag, brows; // training batch
     DevBuf buf_genes, buf_y;                            // ring buffer
     DevBuf pool, crows, cmasks, calive;                 // screened children
-    DevBuf dstats;                                      // double [8]: mu, sd, rho, rel_err, loss
+    DevBuf dstats;                                      // double [2]: label mean and spread of the predictions
     DevBuf dloss;                                       // double: loss of the last training step
-    double *hstats = nullptr;                           // pinned copy of dstats
+    DevBuf tstats;                                      // double [2]: label mean and spread the training uses
+    double *hstats = nullptr;                           // pinned, mapped: [2] rho, [3] rel_err, [4] loss
+    double *hstats_dev = nullptr;                       // its device address (the judge and k_append write it)
     hipEvent_t ready = nullptr;
     // Generation g's training runs on its own stream beside generation g + 1;
     // the predictions of generation g read a snapshot of the weights trained
@@ -977,7 +993,7 @@ float *mlp_theta(SurrogateState &st)
 // w3 [256] and the FP32 biases b1, b2 (b3 after them), each part 256-byte
 // aligned.
 struct SnapLayout {
-    size_t eb, w1, w2, w3, bias, bytes;
+    size_t eb, w1, w2, w3, bias, musd, bytes;
 };
 
 SnapLayout snap_layout(int64_t n)
@@ -989,7 +1005,8 @@ SnapLayout snap_layout(int64_t n)
     l.w2 = l.w1 + up((size_t)kH * kD * 2);
     l.w3 = l.w2 + up((size_t)kH * kH * 2);
     l.bias = l.w3 + up((size_t)kH * 2);
-    l.bytes = l.bias + up((size_t)(2 * kH + 4) * 4);
+    l.musd = l.bias + up((size_t)(2 * kH + 4) * 4);
+    l.bytes = l.musd + 256;
     return l;
 }
 
@@ -1029,21 +1046,21 @@ int take_snapshot(SurrogateState &st, hipStream_t s)
     char *b = static_cast<char *>(st.snap.ptr);
     const float *th = mlp_theta(st);
     SnapArgs a{};
-    const void *src[5] = {st.Eb.ptr, st.W1b.ptr, st.W2b.ptr, st.w3b.ptr, th + kOffB1};
-    const size_t off[5] = {l.eb, l.w1, l.w2, l.w3, l.bias};
-    const size_t bytes[5] = {(size_t)st.n * kD * 2, (size_t)kH * kD * 2, (size_t)kH * kH * 2, (size_t)kH * 2,
-                             (size_t)kH * 4};
-    for (int t = 0; t < 5; ++t) {
-        a.src[t] = static_cast<const uint4 *>(src[t]);
-        a.dst[t] = reinterpret_cast<uint4 *>(b + off[t]);
-        a.len[t] = (int64_t)(bytes[t] / 16);
+    // bf16 E, W1, W2, w3; the FP32 biases b1, b2, b3 (b2 and b3 are not next
+    // to b1 in the parameter layout); the label standardisation the
+    // snapshot's predictions are in
+    const void *src[kSnapParts] = {st.Eb.ptr, st.W1b.ptr, st.W2b.ptr, st.w3b.ptr, th + kOffB1, th + kOffB2,
+                                   th + kOffB3, st.tstats.ptr};
+    const size_t off[kSnapParts] = {l.eb, l.w1, l.w2, l.w3, l.bias, l.bias + kH * 4, l.bias + 2 * kH * 4, l.musd};
+    const size_t bytes[kSnapParts] = {(size_t)st.n * kD * 2, (size_t)kH * kD * 2, (size_t)kH * kH * 2,
+                                      (size_t)kH * 2, (size_t)kH * 4, (size_t)kH * 4, 4, 16};
+    for (int t = 0; t < kSnapParts; ++t) {
+        a.src[t] = static_cast<const uint32_t *>(src[t]);
+        a.dst[t] = reinterpret_cast<uint32_t *>(b + off[t]);
+        a.len[t] = (int64_t)(bytes[t] / 4);
     }
     hipLaunchKernelGGL(k_snapshot, dim3(1024), dim3(256), 0, s, a);
     GAPA_HIP(hipGetLastError());
-    // b2 and b3 are not next to b1 in the parameter layout
-    float *bias = reinterpret_cast<float *>(b + l.bias);
-    GAPA_HIP(hipMemcpyAsync(bias + kH, th + kOffB2, kH * 4, hipMemcpyDeviceToDevice, s));
-    GAPA_HIP(hipMemcpyAsync(bias + 2 * kH, th + kOffB3, 4, hipMemcpyDeviceToDevice, s));
     return GAPA_OK;
 }
 
@@ -1058,6 +1075,10 @@ int predict_rows(SurrogateState &st, const int32_t *genes, const int32_t *rows, 
                                   : st.Eb.as<uint16_t>();
     hipLaunchKernelGGL(k_embed, dim3(N), dim3(256), 0, s, genes, rows, st.k, Eb, st.xb.as<uint16_t>());
     MlpArgs a = mlp_args(st, st.xb.as<uint16_t>(), yhat, N, snapshot);
+    if (snapshot) {
+        a.musd_src = reinterpret_cast<const double *>(static_cast<char *>(st.snap.ptr) + snap_layout(st.n).musd);
+        a.musd_dst = st.dstats.as<double>();
+    }
     hipLaunchKernelGGL(k_mlp<false>, dim3((N + kMlpRows - 1) / kMlpRows), dim3(64 * kMlpWaves), 0, s, a);
     GAPA_HIP(hipGetLastError());
     return GAPA_OK;
@@ -1233,9 +1254,11 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->calive, (size_t)(sp->screen + kJudgeExtra) * 4);
     res(st->dstats, 64);
     res(st->dloss, 8);
+    res(st->tstats, 16);
     if (rc != GAPA_OK) return rc;
-    GAPA_HIP(hipHostMalloc(reinterpret_cast<void **>(&st->hstats), 64, hipHostMallocDefault));
+    GAPA_HIP(hipHostMalloc(reinterpret_cast<void **>(&st->hstats), 64, hipHostMallocMapped | hipHostMallocCoherent));
     std::memset(st->hstats, 0, 64);
+    GAPA_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&st->hstats_dev), st->hstats, 0));
     GAPA_HIP(hipEventCreateWithFlags(&st->ready, hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_pred, hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_snap, hipEventDisableTiming));
@@ -1255,6 +1278,11 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     if ((rc = launch_fill_u32(st->bflag.ptr, 0u, 4, s)) != GAPA_OK) return rc;
     if ((rc = launch_fill_u32(st->tflag.ptr, 0u, 4, s)) != GAPA_OK) return rc;
     if ((rc = launch_fill_u32(st->dloss.ptr, 0u, 2, s)) != GAPA_OK) return rc;
+    {
+        static const double musd0[2] = {0.0, 1.0};  // before any training: unstandardised
+        GAPA_HIP(hipMemcpyAsync(st->tstats.ptr, musd0, 16, hipMemcpyHostToDevice, s));
+        GAPA_HIP(hipStreamSynchronize(s));
+    }
     // the snapshot starts as the initial weights; training waits for set-up
     if ((rc = take_snapshot(*st, s)) != GAPA_OK) return rc;
     GAPA_HIP(hipEventRecord(st->ev_data, s));
@@ -1267,7 +1295,7 @@ void surrogate_release(SurrogateState *st)
     if (!st) return;
     for (DevBuf *b : {&st->theta, &st->m, &st->v, &st->keep_mlp, &st->keep_E, &st->Eb, &st->W1b, &st->W2b, &st->w3b,
                       &st->W1bT, &st->W2bT, &st->xb, &st->yhat, &st->snap, &st->xtrain, &st->ytrain,
-                      &st->target, &st->lossv, &st->dy, &st->tflag, &st->dloss,
+                      &st->target, &st->lossv, &st->dy, &st->tflag, &st->dloss, &st->tstats,
                       &st->xT, &st->h1T, &st->h2T, &st->dz1T, &st->dz2T, &st->dxT, &st->bgenes, &st->bmasks,
                       &st->balive, &st->bflag, &st->brows, &st->buf_genes, &st->buf_y, &st->pool, &st->crows,
                       &st->cmasks, &st->calive, &st->dstats})
@@ -1300,9 +1328,10 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
     if (!random) {
         // the snapshot holds the weights trained through generation gen - 2
         GAPA_HIP(hipStreamWaitEvent(s, st.ev_snap, 0));
-        if (predict &&
-            (rc = predict_rows(st, ga->children.as<int32_t>(), nullptr, L, yhat, s, true)) != GAPA_OK)
-            return rc;
+        if (predict) {
+            // (the prediction kernel also copies their label standardisation for the judge)
+            if ((rc = predict_rows(st, ga->children.as<int32_t>(), nullptr, L, yhat, s, true)) != GAPA_OK) return rc;
+        }
         // once they are made, it takes the weights trained through gen - 1
         GAPA_HIP(hipEventRecord(st.ev_pred, s));
         GAPA_HIP(hipStreamWaitEvent(st.ts, st.ev_pred, 0));
@@ -1339,23 +1368,24 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         if ((rc = ga_rank_and_gather(ga, false, F, pool, npool, s)) != GAPA_OK) return rc;
     }
     double *ds = st.dstats.as<double>();
-    if (predict) hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, neval, ds, ds + 2);
+    if (predict) hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, neval, ds, st.hstats_dev + 2);
     if (!random) {
         // generation gen - 1's training is done with the buffer (and its loss is final)
         GAPA_HIP(hipStreamWaitEvent(s, st.ev_snap, 0));
-        GAPA_HIP(hipMemcpyAsync(ds + 4, st.dloss.ptr, 8, hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(k_append, dim3(neval), dim3(256), 0, s, ga->children.as<int32_t>(), st.k, pool, F,
-                           st.appended, st.sp.buffer, st.buf_genes.as<int32_t>(), st.buf_y.as<double>());
+                           st.appended, st.sp.buffer, st.buf_genes.as<int32_t>(), st.buf_y.as<double>(),
+                           st.dloss.as<double>(), st.hstats_dev + 4);
         st.appended += neval;
         const int32_t count = (int32_t)std::min<int64_t>(st.appended, st.sp.buffer);
-        hipLaunchKernelGGL(k_label_stats, dim3(1), dim3(1024), 0, s, st.buf_y.as<double>(), count, ds);
         GAPA_HIP(hipGetLastError());
-        // this generation's training, on the training stream
+        // this generation's training, on the training stream: label statistics, then the steps
         GAPA_HIP(hipEventRecord(st.ev_data, s));
         GAPA_HIP(hipStreamWaitEvent(st.ts, st.ev_data, 0));
+        hipLaunchKernelGGL(k_label_stats, dim3(1), dim3(1024), 0, st.ts, st.buf_y.as<double>(), count,
+                           st.tstats.as<double>());
         for (int32_t t = 0; t < st.sp.train_steps; ++t) {
             hipLaunchKernelGGL(k_sample, dim3(st.sp.batch), dim3(256), 0, st.ts, st.seed, gen, (uint32_t)t, count,
-                               st.buf_genes.as<int32_t>(), st.buf_y.as<double>(), ds, st.k,
+                               st.buf_genes.as<int32_t>(), st.buf_y.as<double>(), st.tstats.as<double>(), st.k,
                                st.bgenes.as<int32_t>(), st.target.as<float>());
             if ((rc = train_step(ga, st.bgenes.as<int32_t>(), st.target.as<float>(), st.sp.batch, false, st.ts)) !=
                 GAPA_OK)
@@ -1363,7 +1393,6 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         }
     }
     GAPA_HIP(hipGetLastError());
-    GAPA_HIP(hipMemcpyAsync(st.hstats, ds, 64, hipMemcpyDeviceToHost, s));
     GAPA_HIP(hipEventRecord(st.ready, s));
     st.stats_pending = true;
     st.last_gen = gen;
