@@ -136,6 +136,44 @@ def eval_population(graph, genes: np.ndarray, nthreads: int | None = None, want_
     return (F, M) if want_mcn else F
 
 
+# --- the paper's dense reachability fitness (SixDST) ---------------------------
+
+def sixdst(graph, genes, hops: int) -> tuple[int, int]:
+    """The dense reachability fitness of Sec. III-D (eq. 13-17) for one
+    removal set: A_S is the adjacency matrix with every edge of a removed
+    node deleted (eq. 13), M = Normalizer((A_S + I)^hops) with the power
+    taken as `hops` successive products, each normalised (entries > 0 become
+    1; normalising in between leaves the support of the power unchanged).
+    Row i of M marks the nodes within `hops` hops of i, itself included; a
+    removed node's row is its own unit entry.  Returns
+    ((sum(M) - n) / 2, the largest row sum over surviving nodes (0 when
+    none survive)).  With hops at least the diameter of every component of
+    G[V minus S] the pair is (PC, MCN) exactly (eq. 16-17); the paper's
+    choice hops = 6 (eq. 15) is the truncation.  int64 dense products: for
+    small graphs only."""
+    n = graph.n
+    S = np.unique(np.asarray(genes, dtype=np.int64).ravel())
+    if S.size and (S.min() < 0 or S.max() >= n):
+        raise ValueError("gene out of range")
+    if hops < 1:
+        raise ValueError("hops must be at least 1")
+    A = np.zeros((n, n), dtype=np.int64)
+    for v in range(n):
+        A[v, graph.col_idx[graph.row_ptr[v]:graph.row_ptr[v + 1]]] = 1
+    A[S, :] = 0
+    A[:, S] = 0
+    step = A + np.eye(n, dtype=np.int64)
+    M = step.copy()
+    for _ in range(hops - 1):
+        M = ((M @ step) > 0).astype(np.int64)
+    alive = np.ones(n, dtype=bool)
+    alive[S] = False
+    rows = M.sum(axis=1)
+    total = int(M.sum())
+    mcn = int(rows[alive].max()) if alive.any() else 0
+    return (total - n) // 2, mcn
+
+
 # --- genetic algorithm --------------------------------------------------------
 
 def make_params(n, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0) -> OracleParams:
