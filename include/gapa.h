@@ -113,6 +113,28 @@ GAPA_API int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P
                          int64_t *fitness, int32_t *mcn, uint32_t flags, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * The paper's dense reachability fitness (Section III-D, eq. 13-17, the
+ * "SixDST" function), on the matrix cores.
+ *
+ * For each row S of genes: M = Normalizer((A_S + I)^hops), A_S the
+ * adjacency matrix with every edge of a removed node deleted (eq. 13), the
+ * power by repeated squaring with every product normalised (entries > 0
+ * become 1); row v of M marks the nodes within `hops` hops of v.
+ * pc:  int64 [P] out, (sum of M - n) / 2: the pairs of surviving nodes within
+ *      `hops` hops of each other.
+ * mcn: int32 [P] out, the largest row sum over surviving nodes (0 if none).
+ * With hops >= the diameter of every component these are PC and MCN of
+ * gapa_eval_population exactly; the paper uses hops = 6 (eq. 15).
+ * Dense n x n int8 matrices (three per individual in flight, within a 2 GiB
+ * workspace): n <= GAPA_SIXDST_MAX_N, hops >= 1, else GAPA_E_INVALID_ARG.
+ * Genes, flags (GAPA_DEVICE_PTRS, GAPA_TRUST_INPUT), stream and errors as for
+ * gapa_eval_population; results are exact integers.
+ * ------------------------------------------------------------------------- */
+#define GAPA_SIXDST_MAX_N 8192
+GAPA_API int gapa_sixdst_eval(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int32_t hops,
+                              int64_t *pc, int32_t *mcn, uint32_t flags, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Genetic algorithm (Section III-B, Fig. 1 single-GPU "S" mode).
  *
  * k          budget: genes per individual (1 <= k <= n / 2)

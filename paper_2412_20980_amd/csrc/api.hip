@@ -316,7 +316,7 @@ void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, const std:
 void release_workspace(FitnessWorkspace &w)
 {
     for (DevBuf *b : {&w.parent, &w.count, &w.dead, &w.reach, &w.ucount, &w.pairs, &w.worklist, &w.small, &w.masks,
-                      &w.alive, &w.genes, &w.fitness, &w.mcn, &w.flag})
+                      &w.alive, &w.genes, &w.fitness, &w.mcn, &w.flag, &w.six_mats, &w.six_tot})
         b->release();
     w.stats_ctr = nullptr;
 }
@@ -530,6 +530,88 @@ int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t
         e = hipMemcpyAsync(mcn, d_mcn, (size_t)P * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_handle(&g->failed, hip_fail(e, "eval_population copy-back"));
+    if (hflag[0]) {
+        set_error("a gene is not a node id in [0, %d)", g->n);
+        return GAPA_E_BAD_GENE;
+    }
+    return GAPA_OK;
+}
+
+int gapa_sixdst_eval(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int32_t hops, int64_t *pc,
+                     int32_t *mcn, uint32_t flags, void *stream)
+{
+    g_last_error.clear();
+    if (!g) {
+        set_error("graph is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (g->failed) {
+        set_error("graph handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    if (g->n > GAPA_SIXDST_MAX_N || hops < 1) {
+        set_error("dense reachability needs n <= %d (n = %d) and hops >= 1 (hops = %d)", GAPA_SIXDST_MAX_N, g->n,
+                  hops);
+        return GAPA_E_INVALID_ARG;
+    }
+    if (P < 0 || k < 0 || k > g->n || (P > 0 && ((k > 0 && !genes) || !pc || !mcn))) {
+        set_error("invalid population arguments (P=%d, k=%d)", P, k);
+        return GAPA_E_INVALID_ARG;
+    }
+    if (P == 0) return GAPA_OK;
+    const bool dev_ptrs = flags & GAPA_DEVICE_PTRS;
+    const bool trust = flags & GAPA_TRUST_INPUT;
+    if (!dev_ptrs && !trust) {
+        for (int64_t i = 0; i < (int64_t)P * k; ++i) {
+            if (genes[i] < 0 || genes[i] >= g->n) {
+                set_error("gene %d (row %lld) is not a node id in [0, %d)", genes[i], (long long)(i / std::max(k, 1)),
+                          g->n);
+                return GAPA_E_BAD_GENE;
+            }
+        }
+    }
+    DeviceGuard dg(g->device);
+    if (!dg.ok) {
+        set_error("cannot select device %d", g->device);
+        return GAPA_E_DEVICE;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FitnessWorkspace &w = g->ws;
+    // individuals in flight: three dense matrices each, within a 2 GiB workspace
+    const size_t per = sixdst_bytes_per_individual(g->n);
+    const int32_t chunk = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)P, ((size_t)2 << 30) / per));
+    int rc;
+    if ((rc = w.flag.reserve(16)) != GAPA_OK || (rc = w.masks.reserve((size_t)P * g->words * 4)) != GAPA_OK ||
+        (rc = w.alive.reserve((size_t)P * 4)) != GAPA_OK || (rc = w.six_mats.reserve((size_t)chunk * per)) != GAPA_OK ||
+        (rc = w.six_tot.reserve((size_t)chunk * 8)) != GAPA_OK)
+        return rc;
+    const int32_t *d_genes = genes;
+    int64_t *d_pc = pc;
+    int32_t *d_mcn = mcn;
+    if (!dev_ptrs) {
+        if ((rc = w.genes.reserve((size_t)std::max<int64_t>((int64_t)P * k, 1) * 4)) != GAPA_OK ||
+            (rc = w.fitness.reserve((size_t)P * 8)) != GAPA_OK || (rc = w.mcn.reserve((size_t)P * 4)) != GAPA_OK)
+            return rc;
+        if (k > 0)
+            GAPA_HIP(hipMemcpyAsync(w.genes.ptr, genes, (size_t)P * k * 4, hipMemcpyHostToDevice, s));
+        d_genes = w.genes.as<int32_t>();
+        d_pc = w.fitness.as<int64_t>();
+        d_mcn = w.mcn.as<int32_t>();
+    }
+    if ((rc = launch_fill_u32(w.flag.ptr, 0u, 4, s)) != GAPA_OK) return fail_handle(&g->failed, rc);
+    if ((rc = launch_mask_build(d_genes, P, k, g->n, g->words, g->d_noniso, g->n_noniso, w.masks.as<uint32_t>(),
+                                w.alive.as<int32_t>(), w.flag.as<int32_t>(), s)) != GAPA_OK)
+        return fail_handle(&g->failed, rc);
+    if ((rc = sixdst_eval_masks(g, w.masks.as<uint32_t>(), P, hops, chunk, w.six_mats.as<uint8_t>(),
+                                w.six_tot.as<unsigned long long>(), d_pc, d_mcn, s)) != GAPA_OK)
+        return fail_handle(&g->failed, rc);
+    if (dev_ptrs && trust) return GAPA_OK;
+    int32_t hflag[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(hflag, w.flag.ptr, 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && !dev_ptrs) e = hipMemcpyAsync(pc, d_pc, (size_t)P * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && !dev_ptrs) e = hipMemcpyAsync(mcn, d_mcn, (size_t)P * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_handle(&g->failed, hip_fail(e, "sixdst_eval copy-back"));
     if (hflag[0]) {
         set_error("a gene is not a node id in [0, %d)", g->n);
         return GAPA_E_BAD_GENE;

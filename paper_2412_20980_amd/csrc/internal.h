@@ -97,6 +97,8 @@ struct FitnessWorkspace {
     DevBuf fitness;  // int64 [P]
     DevBuf mcn;      // int32 [P]
     DevBuf flag;     // int32 [4]     device error flags
+    DevBuf six_mats; // int8 [3][chunk][n_pad][n_pad] dense reachability matrices
+    DevBuf six_tot;  // uint64 [chunk] their entry sums
 };
 
 // Launch shapes of the bit-parallel fitness pass (results do not depend on
@@ -180,6 +182,9 @@ int launch_bits_transpose(const uint32_t *masks, int32_t P, int32_t W, int32_t n
 
 // Fills count 32-bit words at p with value (a kernel, not a memset node).
 int launch_fill_u32(void *p, uint32_t value, int64_t count, hipStream_t s);
+size_t sixdst_bytes_per_individual(int32_t n);
+int sixdst_eval_masks(gapa_graph *g, const uint32_t *masks, int32_t P, int32_t hops, int32_t chunk, uint8_t *mats,
+                      unsigned long long *tot, int64_t *pc, int32_t *mcn, hipStream_t s);
 
 // genes[P][k] (device) -> masks[P][W] and alive[P]; out-of-range genes
 // raise flag[0].

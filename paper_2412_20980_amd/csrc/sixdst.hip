@@ -1,0 +1,192 @@
+// The paper's dense reachability fitness (Sec. III-D, eq. 13-17) on the
+// matrix cores.  For each removal set S:
+//
+//   M1 = A_S + I     A_S: the adjacency with every edge of a removed node
+//                    deleted (eq. 13), an n_pad x n_pad 0/1 int8 matrix
+//                    (n_pad = n rounded up to 64; padding rows and columns
+//                    are zero)
+//   M  = Normalizer(M1^hops)   by binary exponentiation, the products
+//                    (A+I)(A+I)^2(A+I)^4... of the paper, each normalised
+//                    (entries > 0 become 1)
+//   pc = (sum M - n) / 2,  mcn = the largest row sum over surviving nodes
+//
+// With hops at least the diameter of every component this is (PC, MCN)
+// exactly; the paper's hops = 6 (eq. 15) truncates.  Every matrix is a
+// power of one symmetric matrix, so every product is symmetric and column j
+// of the right operand is its row j: both operands of the int8 products
+// (v_mfma_i32_16x16x64_i8) are read as rows.  Integer arithmetic throughout:
+// the result is exact.
+#include <algorithm>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace gapa {
+namespace {
+
+constexpr int kTile = 64;    // output tile of a block; also the k-step of one product
+constexpr int kLd = 80;      // LDS row stride in bytes (16 rows of a k-step fall in distinct banks)
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bool removed(const uint32_t *mask, int32_t v)
+{
+    return (mask[v >> 5] >> (v & 31)) & 1u;
+}
+
+// Row i of M1 for individual z (block (i, z)).
+__global__ __launch_bounds__(256) void k_six_build(const uint32_t *__restrict__ masks, int32_t W,
+                                                   const int32_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col, int32_t n, int32_t np,
+                                                   uint8_t *__restrict__ M)
+{
+    const int32_t i = blockIdx.x, z = blockIdx.y;
+    uint8_t *row = M + ((int64_t)z * np + i) * np;
+    const uint32_t *mask = masks + (int64_t)z * W;
+    for (int32_t c = threadIdx.x; c < np / 16; c += blockDim.x) reinterpret_cast<uint4 *>(row)[c] = uint4{0, 0, 0, 0};
+    __syncthreads();
+    if (i >= n) return;
+    if (threadIdx.x == 0) row[i] = 1;
+    if (removed(mask, i)) return;
+    for (int32_t e = row_ptr[i] + threadIdx.x; e < row_ptr[i + 1]; e += blockDim.x) {
+        const int32_t j = col[e];
+        if (!removed(mask, j)) row[j] = 1;
+    }
+}
+
+// C = Normalizer(A B) for individual blockIdx.z, A and B symmetric.  The
+// block computes the 64 x 64 tile at rows 64 blockIdx.y, columns
+// 64 blockIdx.x; wave w takes rows 16 w .. 16 w + 15 of it and the four
+// 16-wide column tiles.  Per k-step of 64 bytes the 64 A rows and the 64 B
+// rows (B columns) of the step are staged in LDS, double-buffered: the next
+// step's global loads are in flight during the products.  MFMA operands:
+// lane l holds bytes 16 (l / 16) .. + 15 of the step for row / column l % 16
+// (the same byte order on both sides); C[4 (l / 16) + r][l % 16].
+__global__ __launch_bounds__(256) void k_six_gemm(const uint8_t *__restrict__ A, const uint8_t *__restrict__ B,
+                                                  uint8_t *__restrict__ C, int32_t np)
+{
+    __shared__ __align__(16) uint8_t sA[2][kTile * kLd];
+    __shared__ __align__(16) uint8_t sB[2][kTile * kLd];
+    const int64_t base = (int64_t)blockIdx.z * np * np;
+    const int32_t i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, lr = lane & 15, lg = lane >> 4;
+    // loader: thread t moves bytes 16 (t % 4) .. + 15 of row t / 4 of both tiles
+    const int lrow = t >> 2, lcol = (t & 3) * 16;
+    const uint8_t *ga = A + base + (int64_t)(i0 + lrow) * np + lcol;
+    const uint8_t *gb = B + base + (int64_t)(j0 + lrow) * np + lcol;
+    uint4 ra = *reinterpret_cast<const uint4 *>(ga);
+    uint4 rb = *reinterpret_cast<const uint4 *>(gb);
+    i32x4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = i32x4{0, 0, 0, 0};
+    const int32_t steps = np / kTile;
+    for (int32_t s = 0; s < steps; ++s) {
+        const int buf = s & 1;
+        *reinterpret_cast<uint4 *>(&sA[buf][lrow * kLd + lcol]) = ra;
+        *reinterpret_cast<uint4 *>(&sB[buf][lrow * kLd + lcol]) = rb;
+        __syncthreads();
+        if (s + 1 < steps) {
+            ra = *reinterpret_cast<const uint4 *>(ga + (int64_t)(s + 1) * kTile);
+            rb = *reinterpret_cast<const uint4 *>(gb + (int64_t)(s + 1) * kTile);
+        }
+        const i32x4 a = *reinterpret_cast<const i32x4 *>(&sA[buf][(wv * 16 + lr) * kLd + lg * 16]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const i32x4 b = *reinterpret_cast<const i32x4 *>(&sB[buf][(q * 16 + lr) * kLd + lg * 16]);
+            acc[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[q], 0, 0, 0);
+        }
+    }
+    // normalised tile through LDS, then written as 16-byte row pieces
+    __syncthreads();
+    uint8_t *tile = sA[0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tile[(wv * 16 + 4 * lg + r) * kLd + q * 16 + lr] = acc[q][r] > 0 ? 1 : 0;
+    __syncthreads();
+    *reinterpret_cast<uint4 *>(C + base + (int64_t)(i0 + lrow) * np + j0 + lcol) =
+        *reinterpret_cast<const uint4 *>(&tile[lrow * kLd + lcol]);
+}
+
+// Row sums of M (block (i, z), one wave): the sum of all entries and the
+// largest surviving row, by integer atomics (order-free).
+__global__ __launch_bounds__(64) void k_six_rows(const uint8_t *__restrict__ M, const uint32_t *__restrict__ masks,
+                                                 int32_t W, int32_t n, int32_t np,
+                                                 unsigned long long *__restrict__ total, int32_t *__restrict__ mcn)
+{
+    const int32_t i = blockIdx.x, z = blockIdx.y;
+    const uint4 *row = reinterpret_cast<const uint4 *>(M + ((int64_t)z * np + i) * np);
+    uint32_t sum = 0;
+    for (int32_t c = threadIdx.x; c < np / 16; c += 64) {
+        const uint4 q = row[c];
+        // entries are 0 or 1: the byte sum of a word is its popcount
+        sum += __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if (threadIdx.x == 0) {
+        atomicAdd(total + z, (unsigned long long)sum);
+        if (!removed(masks + (int64_t)z * W, i)) atomicMax(mcn + z, (int32_t)sum);
+    }
+}
+
+__global__ void k_six_final(const unsigned long long *__restrict__ total, int32_t count, int32_t n,
+                            int64_t *__restrict__ pc)
+{
+    const int32_t z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z < count) pc[z] = ((int64_t)total[z] - n) / 2;
+}
+
+}  // namespace
+
+size_t sixdst_bytes_per_individual(int32_t n)
+{
+    const size_t np = ((size_t)n + kTile - 1) / kTile * kTile;
+    return 3 * np * np;
+}
+
+// pc[P], mcn[P] (device) of the P removal sets given as bit sets masks[P][W]
+// (device); mats holds three np x np matrices for each of `chunk`
+// individuals, tot `chunk` counters.
+int sixdst_eval_masks(gapa_graph *g, const uint32_t *masks, int32_t P, int32_t hops, int32_t chunk, uint8_t *mats,
+                      unsigned long long *tot, int64_t *pc, int32_t *mcn, hipStream_t s)
+{
+    const int32_t n = g->n, W = g->words;
+    const int32_t np = (n + kTile - 1) / kTile * kTile;
+    const int64_t mat = (int64_t)np * np;
+    for (int32_t z0 = 0; z0 < P; z0 += chunk) {
+        const int32_t cnt = std::min(chunk, P - z0);
+        const uint32_t *mk = masks + (int64_t)z0 * W;
+        uint8_t *buf[3] = {mats, mats + (int64_t)cnt * mat, mats + 2 * (int64_t)cnt * mat};
+        hipLaunchKernelGGL(k_six_build, dim3(np, cnt), dim3(256), 0, s, mk, W, g->d_row_ptr, g->d_col, n, np, buf[0]);
+        // binary exponentiation: b holds M1^(2^j), r the product of the powers taken so far
+        int b = 0, r = -1;
+        const dim3 grid(np / kTile, np / kTile, cnt);
+        for (int32_t h = hops;;) {
+            if (h & 1) {
+                if (r < 0) {
+                    r = b;
+                } else {
+                    const int f = 3 - r - b;  // the free buffer
+                    hipLaunchKernelGGL(k_six_gemm, grid, dim3(256), 0, s, buf[r], buf[b], buf[f], np);
+                    r = f;
+                }
+            }
+            h >>= 1;
+            if (h == 0) break;
+            int f = 0;
+            while (f == r || f == b) ++f;
+            hipLaunchKernelGGL(k_six_gemm, grid, dim3(256), 0, s, buf[b], buf[b], buf[f], np);
+            b = f;
+        }
+        GAPA_HIP(hipGetLastError());
+        int rc = launch_fill_u32(tot, 0u, 2 * (int64_t)cnt, s);
+        if (rc == GAPA_OK) rc = launch_fill_u32(reinterpret_cast<uint32_t *>(mcn + z0), 0u, cnt, s);
+        if (rc != GAPA_OK) return rc;
+        hipLaunchKernelGGL(k_six_rows, dim3(n, cnt), dim3(64), 0, s, buf[r], mk, W, n, np, tot, mcn + z0);
+        hipLaunchKernelGGL(k_six_final, dim3((cnt + 255) / 256), dim3(256), 0, s, tot, cnt, n, pc + z0);
+        GAPA_HIP(hipGetLastError());
+    }
+    return GAPA_OK;
+}
+
+}  // namespace gapa

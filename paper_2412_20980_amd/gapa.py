@@ -53,7 +53,7 @@ EXPORTED = (
     "gapa_surrogate_attach", "gapa_surrogate_stats", "gapa_surrogate_last_pool", "gapa_surrogate_predict",
     "gapa_surrogate_train_batch", "gapa_surrogate_tensor", "gapa_surrogate_last_predictions",
     "gapa_graph_get_tuning", "gapa_graph_set_tuning", "gapa_ga_autotune", "gapa_batch_autotune",
-    "gapa_ga_record", "gapa_batch_record",
+    "gapa_ga_record", "gapa_batch_record", "gapa_sixdst_eval",
 )
 
 
@@ -121,6 +121,7 @@ def lib() -> C.CDLL:
     L.gapa_batch_get_population.argtypes = [vp, C.c_int32, vp, vp]
     L.gapa_batch_destroy.argtypes = [vp]
     L.gapa_ga_record.argtypes = [vp, C.c_int32]
+    L.gapa_sixdst_eval.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, C.c_uint32, vp]
     L.gapa_batch_record.argtypes = [vp, C.c_int32]
     L.gapa_graph_get_tuning.argtypes = [vp, C.POINTER(gapa_tuning)]
     L.gapa_graph_set_tuning.argtypes = [vp, C.POINTER(gapa_tuning)]
@@ -212,6 +213,29 @@ def gapa_eval_population(h, genes, fitness=None, mcn=None, flags: int = 0, strea
     return (fitness, mcn) if flags & GAPA_WANT_MCN else fitness
 
 
+def gapa_sixdst_eval(h, genes, hops: int, pc=None, mcn=None, flags: int = 0, stream=None):
+    """Dense reachability fitness (pc, mcn) of each row of genes: numpy
+    [P, k] int32 (host) or a torch int32 CUDA tensor (device; pc and mcn are
+    then torch CUDA tensors too)."""
+    if _is_dev_tensor(genes):
+        assert genes.dtype == torch.int32 and genes.is_contiguous() and genes.dim() == 2
+        P, k = genes.shape
+        pc = torch.empty(P, dtype=torch.int64, device=genes.device) if pc is None else pc
+        mcn = torch.empty(P, dtype=torch.int32, device=genes.device) if mcn is None else mcn
+        _check(lib().gapa_sixdst_eval(h, genes.data_ptr(), P, k, hops, pc.data_ptr(), mcn.data_ptr(),
+                                      flags | GAPA_DEVICE_PTRS, _stream_ptr(stream)))
+    else:
+        G = np.ascontiguousarray(genes, dtype=np.int32)
+        if G.ndim == 1:
+            G = G[None, :]
+        P, k = G.shape
+        pc = np.zeros(P, dtype=np.int64) if pc is None else pc
+        mcn = np.zeros(P, dtype=np.int32) if mcn is None else mcn
+        _check(lib().gapa_sixdst_eval(h, G.ctypes.data, P, k, hops, pc.ctypes.data, mcn.ctypes.data,
+                                      flags & ~GAPA_DEVICE_PTRS, _stream_ptr(stream)))
+    return pc, mcn
+
+
 def _fitness_stats(fn, h) -> dict:
     out = (C.c_int64 * 4)()
     _check(fn(h, out))
@@ -241,6 +265,10 @@ class Graph:
     def eval(self, genes, want_mcn: bool = False, trust: bool = False, stream=None):
         flags = (GAPA_WANT_MCN if want_mcn else 0) | (GAPA_TRUST_INPUT if trust else 0)
         return gapa_eval_population(self.handle, genes, flags=flags, stream=stream)
+
+    def sixdst(self, genes, hops: int = 6, trust: bool = False, stream=None):
+        """(pc, mcn) of the dense reachability fitness with `hops` hops."""
+        return gapa_sixdst_eval(self.handle, genes, hops, flags=GAPA_TRUST_INPUT if trust else 0, stream=stream)
 
     def set_timing(self, on: bool = True):
         _check(lib().gapa_graph_set_timing(self.handle, int(on)))
