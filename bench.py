@@ -3,6 +3,7 @@
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-replay]
   python bench.py --workload batched64    # 64 independent GAs advanced together
   python bench.py --workload surrogate    # screened generations (4096 offspring, 512 evaluated)
+  python bench.py --workload sixdst       # the paper's dense reachability fitness on the matrix cores
   python bench.py --copy-calibration      # plain 1 GiB copies, for counter scaling
 
 A step is one whole generation of the method on the device: tournament
@@ -246,8 +247,50 @@ def run_surrogate(args, torch, gapa, inputs):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+int64",
         "data": "synthetic",
         "config": {"workload": w.name, "offspring": w.offspring, "screened": w.exact_top, "judge_extra": 32,
-                   "train_steps": 4, "batch": 1024, "parallelism": "single GPU"},
+                   "train_steps": 2, "batch": 1024, "parallelism": "single GPU"},
         "surrogate": st,
+    }
+
+
+def run_sixdst(args, torch, gapa, inputs):
+    """The paper's dense reachability fitness (Sec. III-D, hops = 6) of 1024
+    removal sets of 20 nodes on a 2000-node BA graph (m = 2): three int8
+    matrix products of 2048 x 2048 per individual on the matrix cores.
+    Timed with HIP events on the launch stream around K population
+    evaluations (device-resident genes and results)."""
+    n, k, P, hops = 2000, 20, 1024, 6
+    g = inputs.barabasi_albert(n, 2, seed=11)
+    graph = gapa.Graph.from_csr(g, trust=True)
+    genes = torch.from_numpy(inputs.random_population(n, k, P, seed=12)).cuda()
+    pc = torch.empty(P, dtype=torch.int64, device="cuda")
+    mcn = torch.empty(P, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    flags = gapa.GAPA_TRUST_INPUT
+    for _ in range(args.warmup):
+        gapa.gapa_sixdst_eval(graph.handle, genes, hops, pc=pc, mcn=mcn, flags=flags, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        gapa.gapa_sixdst_eval(graph.handle, genes, hops, pc=pc, mcn=mcn, flags=flags, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    dt = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    np_ = (n + 63) // 64 * 64
+    products = 3  # hops 6: (A+I)^2, (A+I)^4, their product
+    ops = 2.0 * np_ ** 3 * products * P
+    achieved = ops / (ms * 1e-3) / 1e12
+    return {
+        "metric": METRIC, "value": P * args.steps / dt, "unit": "individuals evaluated/s (dense reachability)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+        "config": {"workload": f"sixdst_ba{n}_k{k}_p{P}_hops{hops}", "n": n, "k": k, "pop": P, "hops": hops,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "kernel": "dense reachability pass (int8 products)", "achieved": achieved,
+                     "peak": 5000.0, "unit": "TOP/s (int8)", "frac": achieved / 5000.0, "traffic": None,
+                     "avg_launch_ms": ms, "ops_per_launch": ops},
     }
 
 
@@ -298,6 +341,11 @@ def main():
         args.warmup = 20 if args.warmup is None else args.warmup
         args.steps = 20 if args.steps is None else args.steps
         print(json.dumps(run_surrogate(args, torch, gapa, inputs)), flush=True)
+        return
+    if args.workload == "sixdst":
+        args.warmup = 2 if args.warmup is None else args.warmup
+        args.steps = 5 if args.steps is None else args.steps
+        print(json.dumps(run_sixdst(args, torch, gapa, inputs)), flush=True)
         return
     if args.workload == "batched64":
         args.warmup = 40 if args.warmup is None else args.warmup

@@ -53,9 +53,10 @@ __global__ __launch_bounds__(256) void k_six_build(const uint32_t *__restrict__ 
     }
 }
 
-// C = Normalizer(A B) for individual blockIdx.z, A and B symmetric.  The
-// block computes the 64 x 64 tile at rows 64 blockIdx.y, columns
-// 64 blockIdx.x; wave w takes rows 16 w .. 16 w + 15 of it and the four
+// C = Normalizer(A B) for individual blockIdx.y, A and B symmetric powers of
+// one matrix, so C is symmetric: block t computes the 64 x 64 tile (bi, bj),
+// bi <= bj, the t-th of the upper triangle, and writes it and its mirror
+// image.  Wave w takes rows 16 w .. 16 w + 15 of the tile and the four
 // 16-wide column tiles.  Per k-step of 64 bytes the 64 A rows and the 64 B
 // rows (B columns) of the step are staged in LDS, double-buffered: the next
 // step's global loads are in flight during the products.  MFMA operands:
@@ -66,8 +67,14 @@ __global__ __launch_bounds__(256) void k_six_gemm(const uint8_t *__restrict__ A,
 {
     __shared__ __align__(16) uint8_t sA[2][kTile * kLd];
     __shared__ __align__(16) uint8_t sB[2][kTile * kLd];
-    const int64_t base = (int64_t)blockIdx.z * np * np;
-    const int32_t i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.y * np * np;
+    // t = bj (bj + 1) / 2 + bi
+    const int32_t t_lin = blockIdx.x;
+    int32_t bj = (int32_t)((sqrtf(8.f * (float)t_lin + 1.f) - 1.f) * 0.5f);
+    while ((bj + 1) * (bj + 2) / 2 <= t_lin) ++bj;
+    while (bj * (bj + 1) / 2 > t_lin) --bj;
+    const int32_t bi = t_lin - bj * (bj + 1) / 2;
+    const int32_t i0 = bi * kTile, j0 = bj * kTile;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, lr = lane & 15, lg = lane >> 4;
     // loader: thread t moves bytes 16 (t % 4) .. + 15 of row t / 4 of both tiles
     const int lrow = t >> 2, lcol = (t & 3) * 16;
@@ -105,27 +112,57 @@ __global__ __launch_bounds__(256) void k_six_gemm(const uint8_t *__restrict__ A,
     __syncthreads();
     *reinterpret_cast<uint4 *>(C + base + (int64_t)(i0 + lrow) * np + j0 + lcol) =
         *reinterpret_cast<const uint4 *>(&tile[lrow * kLd + lcol]);
+    if (bi != bj) {
+        // the mirror tile: row lrow of it is column lrow of this one
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            w[q] = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w[q] |= (uint32_t)tile[(lcol + 4 * q + e) * kLd + lrow] << (8 * e);
+        }
+        *reinterpret_cast<uint4 *>(C + base + (int64_t)(j0 + lrow) * np + i0 + lcol) = uint4{w[0], w[1], w[2], w[3]};
+    }
 }
 
-// Row sums of M (block (i, z), one wave): the sum of all entries and the
-// largest surviving row, by integer atomics (order-free).
-__global__ __launch_bounds__(64) void k_six_rows(const uint8_t *__restrict__ M, const uint32_t *__restrict__ masks,
-                                                 int32_t W, int32_t n, int32_t np,
-                                                 unsigned long long *__restrict__ total, int32_t *__restrict__ mcn)
+// Row sums of M: block (g, z) takes rows 32 g .. 32 g + 31 of individual z,
+// one wave per row at a time; the block adds its rows' total and largest
+// surviving row into the individual's counters (integer atomics, order-free).
+constexpr int kRowsPerBlock = 32;
+__global__ __launch_bounds__(256) void k_six_rows(const uint8_t *__restrict__ M, const uint32_t *__restrict__ masks,
+                                                  int32_t W, int32_t n, int32_t np,
+                                                  unsigned long long *__restrict__ total, int32_t *__restrict__ mcn)
 {
-    const int32_t i = blockIdx.x, z = blockIdx.y;
-    const uint4 *row = reinterpret_cast<const uint4 *>(M + ((int64_t)z * np + i) * np);
-    uint32_t sum = 0;
-    for (int32_t c = threadIdx.x; c < np / 16; c += 64) {
-        const uint4 q = row[c];
-        // entries are 0 or 1: the byte sum of a word is its popcount
-        sum += __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
-    }
+    __shared__ uint32_t s_sum[4], s_max[4];
+    const int32_t z = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t *mask = masks + (int64_t)z * W;
+    uint32_t bsum = 0, bmax = 0;
+    for (int32_t r = wv; r < kRowsPerBlock; r += 4) {
+        const int32_t i = blockIdx.x * kRowsPerBlock + r;
+        if (i >= n) break;
+        const uint4 *row = reinterpret_cast<const uint4 *>(M + ((int64_t)z * np + i) * np);
+        uint32_t sum = 0;
+        for (int32_t c = lane; c < np / 16; c += 64) {
+            const uint4 q = row[c];
+            // entries are 0 or 1: the byte sum of a word is its popcount
+            sum += __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
+        }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+        bsum += sum;
+        if (!removed(mask, i)) bmax = max(bmax, sum);
+    }
+    if (lane == 0) {
+        s_sum[wv] = bsum;
+        s_max[wv] = bmax;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        atomicAdd(total + z, (unsigned long long)sum);
-        if (!removed(masks + (int64_t)z * W, i)) atomicMax(mcn + z, (int32_t)sum);
+        const uint32_t t = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+        const uint32_t m = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+        if (t) atomicAdd(total + z, (unsigned long long)t);
+        if (m) atomicMax(mcn + z, (int32_t)m);
     }
 }
 
@@ -160,7 +197,8 @@ int sixdst_eval_masks(gapa_graph *g, const uint32_t *masks, int32_t P, int32_t h
         hipLaunchKernelGGL(k_six_build, dim3(np, cnt), dim3(256), 0, s, mk, W, g->d_row_ptr, g->d_col, n, np, buf[0]);
         // binary exponentiation: b holds M1^(2^j), r the product of the powers taken so far
         int b = 0, r = -1;
-        const dim3 grid(np / kTile, np / kTile, cnt);
+        const int32_t nt = np / kTile;
+        const dim3 grid(nt * (nt + 1) / 2, cnt);
         for (int32_t h = hops;;) {
             if (h & 1) {
                 if (r < 0) {
@@ -182,7 +220,8 @@ int sixdst_eval_masks(gapa_graph *g, const uint32_t *masks, int32_t P, int32_t h
         int rc = launch_fill_u32(tot, 0u, 2 * (int64_t)cnt, s);
         if (rc == GAPA_OK) rc = launch_fill_u32(reinterpret_cast<uint32_t *>(mcn + z0), 0u, cnt, s);
         if (rc != GAPA_OK) return rc;
-        hipLaunchKernelGGL(k_six_rows, dim3(n, cnt), dim3(64), 0, s, buf[r], mk, W, n, np, tot, mcn + z0);
+        hipLaunchKernelGGL(k_six_rows, dim3((n + kRowsPerBlock - 1) / kRowsPerBlock, cnt), dim3(256), 0, s, buf[r],
+                           mk, W, n, np, tot, mcn + z0);
         hipLaunchKernelGGL(k_six_final, dim3((cnt + 255) / 256), dim3(256), 0, s, tot, cnt, n, pc + z0);
         GAPA_HIP(hipGetLastError());
     }
