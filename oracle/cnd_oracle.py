@@ -24,7 +24,7 @@ _lock = threading.Lock()
 class OracleParams(C.Structure):
     _fields_ = [
         ("n", C.c_int32), ("k", C.c_int32), ("pop", C.c_int32), ("offspring", C.c_int32),
-        ("tournament", C.c_int32), ("pad", C.c_int32),
+        ("tournament", C.c_int32), ("objective", C.c_int32),
         ("seed", C.c_uint64), ("t_pc", C.c_uint64), ("t_pm", C.c_uint64),
     ]
 
@@ -176,19 +176,24 @@ def sixdst(graph, genes, hops: int) -> tuple[int, int]:
 
 # --- genetic algorithm --------------------------------------------------------
 
-def make_params(n, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0) -> OracleParams:
-    return OracleParams(n=n, k=k, pop=pop, offspring=offspring or pop, tournament=tournament, pad=0,
-                        seed=seed, t_pc=threshold(pc), t_pm=threshold(pm))
+OBJECTIVES = {"pc": 0, "mcn": 1}
+
+
+def make_params(n, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, objective="pc") -> OracleParams:
+    return OracleParams(n=n, k=k, pop=pop, offspring=offspring or pop, tournament=tournament,
+                        objective=OBJECTIVES[objective], seed=seed, t_pc=threshold(pc), t_pm=threshold(pm))
 
 
 class OracleGA:
     """The GA run on the host: generation 0 at construction, ``step()`` for
     each further generation.  ``pop`` is [P, k] int32 and ``F`` [P] int64,
-    ordered by (F, tag)."""
+    ordered by (F, tag).  F is PC, or with objective="mcn" the largest
+    surviving component (the CND fitness of Sec. III-D)."""
 
-    def __init__(self, graph, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, nthreads=None):
+    def __init__(self, graph, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, nthreads=None,
+                 objective="pc"):
         self.graph = graph
-        self.params = make_params(graph.n, k, pop, seed, pc, pm, tournament, offspring)
+        self.params = make_params(graph.n, k, pop, seed, pc, pm, tournament, offspring, objective)
         self.nthreads = default_threads() if nthreads is None else nthreads
         self.pop = np.zeros((pop, k), dtype=np.int32)
         self.F = np.zeros(pop, dtype=np.int64)

@@ -252,7 +252,7 @@ typedef struct {
     int32_t pop;        /* P: parents kept by elitism */
     int32_t offspring;  /* lambda: children made per generation */
     int32_t tournament; /* T: contestants per tournament */
-    int32_t pad;
+    int32_t objective;  /* 0: minimise PC; 1: minimise MCN (the CND fitness of Sec. III-D) */
     uint64_t seed;
     uint64_t t_pc;      /* crossover threshold, floor(pc * 2^32) */
     uint64_t t_pm;      /* mutation threshold, floor(pm * 2^32) */
@@ -397,6 +397,20 @@ static int cmp_fkey(const void *a, const void *b)
     return (x->tag > y->tag) - (x->tag < y->tag);
 }
 
+/* The GA's fitness of P rows: PC, or with objective 1 the largest surviving
+ * component (MCN). */
+static int eval_objective(const oracle_params *p, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                          const int32_t *rows, int32_t P, int32_t k, int64_t *f, int32_t nthreads)
+{
+    if (p->objective != 1) return oracle_eval_population(n, row_ptr, col_idx, rows, P, k, f, NULL, nthreads);
+    int32_t *mcn = (int32_t *)malloc((size_t)(P > 0 ? P : 1) * sizeof(int32_t));
+    if (!mcn) return -1;
+    const int rc = oracle_eval_population(n, row_ptr, col_idx, rows, P, k, f, mcn, nthreads);
+    for (int32_t i = 0; i < P; ++i) f[i] = mcn[i];
+    free(mcn);
+    return rc;
+}
+
 /* Population at generation 0: P initial rows, evaluated, ordered by (F, i). */
 int oracle_ga_init(const oracle_params *p, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                    int32_t *pop_rows, int64_t *F, int32_t nthreads)
@@ -408,7 +422,7 @@ int oracle_ga_init(const oracle_params *p, int32_t n, const int32_t *row_ptr, co
     int rc = 0;
     for (int32_t i = 0; i < P && rc == 0; ++i)
         rc = oracle_init_individual(p, i, rows + (int64_t)i * k);
-    if (rc == 0 && oracle_eval_population(n, row_ptr, col_idx, rows, P, k, f, NULL, nthreads) != 0) rc = -1;
+    if (rc == 0 && eval_objective(p, n, row_ptr, col_idx, rows, P, k, f, nthreads) != 0) rc = -1;
     if (rc == 0) {
         for (int32_t i = 0; i < P; ++i) { keys[i].f = f[i]; keys[i].tag = i; }
         qsort(keys, (size_t)P, sizeof(fkey), cmp_fkey);
@@ -460,7 +474,7 @@ int oracle_ga_step(const oracle_params *p, int32_t gen, int32_t n, const int32_t
         int64_t *f = (int64_t *)malloc((size_t)(np > 0 ? np : 1) * sizeof(int64_t));
         for (int32_t q = 0; q < np; ++q)
             memcpy(rows + (int64_t)q * k, kids + (int64_t)pooled[q] * k, (size_t)k * sizeof(int32_t));
-        if (oracle_eval_population(n, row_ptr, col_idx, rows, np, k, f, NULL, nthreads) != 0) rc = -1;
+        if (eval_objective(p, n, row_ptr, col_idx, rows, np, k, f, nthreads) != 0) rc = -1;
         for (int32_t q = 0; q < np; ++q) kf[pooled[q]] = f[q];
         free(rows); free(f);
     }
