@@ -73,11 +73,16 @@ enum {
     GAPA_UNIONFIND = 1u << 3,   /* gapa_graph_create: evaluate with edge-parallel
                                    union-find instead of bit-parallel sweeps
                                    (same results, slower; a cross-check)        */
-    GAPA_GRAPH_REPLAY = 1u << 4 /* gapa_params.flags: record one generation's
+    GAPA_GRAPH_REPLAY = 1u << 4, /* gapa_params.flags: record one generation's
                                    launches as a HIP graph once and replay it
                                    (same results; fewer launch gaps).  Kernel
                                    timing, when enabled, runs generations
                                    eagerly instead.                             */
+    GAPA_MINIMISE_MCN = 1u << 5 /* gapa_params.flags: the GA minimises the
+                                   largest surviving component (MCN, the CND
+                                   fitness of Section III-D) instead of PC: the
+                                   fitness arrays then hold MCN.  Not with a
+                                   surrogate.                                   */
 };
 
 /* ---------------------------------------------------------------------------
@@ -155,7 +160,7 @@ typedef struct gapa_params {
     uint64_t seed;
     double pc;
     double pm;
-    uint32_t flags;   /* 0 or GAPA_GRAPH_REPLAY */
+    uint32_t flags;   /* 0 or GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN */
     int32_t reserved; /* 0 */
 } gapa_params;
 

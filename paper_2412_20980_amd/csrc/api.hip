@@ -662,7 +662,7 @@ bool params_ok(const gapa_params *p, int32_t n)
 {
     return p->k >= 1 && p->k <= n / 2 && p->pop >= 1 && p->tournament >= 1 && p->tournament <= 64 &&
            p->offspring >= 0 && p->pc >= 0.0 && p->pc <= 1.0 && p->pm >= 0.0 && p->pm <= 1.0 &&
-           (p->flags & ~(uint32_t)GAPA_GRAPH_REPLAY) == 0 && p->reserved == 0;
+           (p->flags & ~(uint32_t)(GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN)) == 0 && p->reserved == 0;
 }
 
 // Fills the instance table and sizes every buffer of a GA over `count`
@@ -734,6 +734,9 @@ int ga_allocate(gapa_ga *ga, int32_t count, const gapa_params *p, const int32_t 
     }
     if (rc == GAPA_OK) rc = ga->children.reserve((size_t)child_el * 4);
     if (rc == GAPA_OK) rc = ga->child_fit.reserve((size_t)slots * 8);
+    ga->slots = slots;
+    ga->objective_mcn = (p[0].flags & GAPA_MINIMISE_MCN) != 0;
+    if (rc == GAPA_OK && ga->objective_mcn) rc = ga->child_mcn.reserve((size_t)slots * 4);
     if (rc == GAPA_OK) rc = ga->masks.reserve((size_t)mask_w * 4);
     if (rc == GAPA_OK) rc = ga->alive.reserve((size_t)slots * 4);
     if (rc == GAPA_OK) rc = ga->src.reserve((size_t)fit_n * 4);
@@ -934,7 +937,7 @@ void ga_release(gapa_ga *ga)
     ga->surr = nullptr;
     if (ga->cap_stream) (void)hipStreamDestroy(ga->cap_stream);
     ga->cap_stream = nullptr;
-    for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit, &ga->masks,
+    for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit, &ga->child_mcn, &ga->masks,
                     &ga->alive, &ga->src, &ga->rank, &ga->flag, &ga->gen_ctr, &ga->inst, &ga->noniso_buf,
                     &ga->tab_voff, &ga->tab_live_init, &ga->tab_live_gen, &ga->tab_moff, &ga->tab_node_inst,
                     &ga->tab_tiles})
@@ -970,7 +973,7 @@ int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **
     }
     if (!params_ok(p, g->n)) {
         set_error("invalid GA parameters (need 1 <= k <= n/2, pop >= 1, 1 <= T <= 64, pc, pm in [0, 1], "
-                  "flags 0 or GAPA_GRAPH_REPLAY)");
+                  "flags from GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN)");
         return GAPA_E_INVALID_ARG;
     }
     DeviceGuard dg(g->device);

@@ -367,6 +367,13 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs args)
     emit(l, a, o);
 }
 
+// Fitness of every slot from the pass's MCN (GAPA_MINIMISE_MCN).
+__global__ void k_mcn_objective(const int32_t *__restrict__ mcn, int64_t *__restrict__ fit, int32_t count)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) fit[i] = mcn[i];
+}
+
 // Elitism (eq. 10-11) as a merge by ranks, per instance (blockIdx.z or y).
 // Keys: parents (PC, tag r) for the npar rows already ordered by (PC, tag),
 // pooled offspring (PC, tag npar + o) for o = pool[q] (q < npool; pool NULL:
@@ -578,13 +585,20 @@ int ga_launch_offspring(gapa_ga *ga, hipStream_t s, bool rows_only)
 
 int ga_eval_children(gapa_ga *ga, bool init, hipStream_t s)
 {
+    int32_t *mcn = ga->objective_mcn ? ga->child_mcn.as<int32_t>() : nullptr;
+    int rc;
     if (ga->count > 1)
-        return eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(), 0,
-                          ga->child_fit.as<int64_t>(), nullptr, ga->ws, &ga->timer, s,
-                          init ? &ga->tab_init : &ga->tab_gen);
-    return eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(),
-                      init ? ga->params.pop : ga->lambda, ga->child_fit.as<int64_t>(), nullptr, ga->ws, &ga->timer,
-                      s);
+        rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(), 0, ga->child_fit.as<int64_t>(),
+                        mcn, ga->ws, &ga->timer, s, init ? &ga->tab_init : &ga->tab_gen);
+    else
+        rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(),
+                        init ? ga->params.pop : ga->lambda, ga->child_fit.as<int64_t>(), mcn, ga->ws, &ga->timer, s);
+    if (rc != GAPA_OK || !mcn) return rc;
+    // the objective is MCN: it replaces PC as the fitness of every slot
+    hipLaunchKernelGGL(k_mcn_objective, dim3((ga->slots + 255) / 256), dim3(256), 0, s, mcn,
+                       ga->child_fit.as<int64_t>(), ga->slots);
+    GAPA_HIP(hipGetLastError());
+    return GAPA_OK;
 }
 
 int ga_init_population(gapa_ga *ga, hipStream_t s)

@@ -273,6 +273,9 @@ struct gapa_ga {
     gapa::DevBuf fit[2];          // int64 [sum P]
     gapa::DevBuf children;        // int32 rows
     gapa::DevBuf child_fit;       // int64 slots
+    gapa::DevBuf child_mcn;       // int32 slots (GAPA_MINIMISE_MCN: the pass's MCN, copied into child_fit)
+    int32_t slots = 0;
+    bool objective_mcn = false;
     gapa::DevBuf masks;           // uint32 removed-node bit sets of the children
     gapa::DevBuf alive;           // int32 slots: surviving non-isolated nodes
     gapa::DevBuf src;             // int32 [sum P] elitism: source tag of each kept row

@@ -40,6 +40,7 @@ GAPA_TRUST_INPUT = 1 << 1
 GAPA_WANT_MCN = 1 << 2
 GAPA_UNIONFIND = 1 << 3
 GAPA_GRAPH_REPLAY = 1 << 4
+GAPA_MINIMISE_MCN = 1 << 5
 GAPA_SCREEN_RANDOM = 1 << 0
 SURROGATE_TENSORS = ("E", "W1", "b1", "W2", "b2", "w3", "b3")
 
@@ -337,16 +338,23 @@ def gapa_ga_destroy(h):
     _check(lib().gapa_ga_destroy(h))
 
 
+def _objective_flag(objective: str) -> int:
+    if objective not in ("pc", "mcn"):
+        raise ValueError(f"objective must be 'pc' or 'mcn', not {objective!r}")
+    return GAPA_MINIMISE_MCN if objective == "mcn" else 0
+
+
 class GA:
     """The GA on one graph; generation 0 is drawn and evaluated at creation.
-    replay=True records one generation as a HIP graph and replays it."""
+    replay=True records one generation as a HIP graph and replays it;
+    objective="mcn" minimises the largest surviving component instead of PC."""
 
     def __init__(self, graph: Graph, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, stream=None,
-                 replay: bool = False):
+                 replay: bool = False, objective: str = "pc"):
         self.graph = graph
         self.k, self.pop = int(k), int(pop)
-        self.handle = gapa_ga_create(graph.handle, k, pop, seed, pc, pm, tournament, offspring, stream,
-                                     GAPA_GRAPH_REPLAY if replay else 0)
+        flags = (GAPA_GRAPH_REPLAY if replay else 0) | _objective_flag(objective)
+        self.handle = gapa_ga_create(graph.handle, k, pop, seed, pc, pm, tournament, offspring, stream, flags)
 
     def step(self, n: int = 1, stream=None):
         gapa_generation_step(self.handle, n, stream)
@@ -493,11 +501,13 @@ class Batch:
 
     def __init__(self, graphs, params, stream=None, replay: bool = True):
         """graphs: sequence of Graph; params: sequence of dicts with keys k,
-        pop, seed and optionally pc, pm, tournament, offspring."""
+        pop, seed and optionally pc, pm, tournament, offspring, objective
+        ("pc" or "mcn", the same for every instance)."""
         self.graphs = list(graphs)
         self.params = [dict(p) for p in params]
         flags = GAPA_GRAPH_REPLAY if replay else 0
-        ps = [make_params(flags=flags, **p) for p in self.params]
+        ps = [make_params(flags=flags | _objective_flag(p.get("objective", "pc")),
+                          **{key: v for key, v in p.items() if key != "objective"}) for p in self.params]
         self.handle = gapa_batch_create([g.handle for g in self.graphs], ps, stream)
 
     def __len__(self):

@@ -185,3 +185,33 @@ def test_handles_destroyed_in_any_order(gp, ba200):
     ga2.step(2)
     ga2.close()
     g2.close()
+
+
+@pytest.mark.parametrize("replay", [False, True])
+def test_mcn_objective_matches_oracle(gp, replay):
+    """The GA minimising MCN (the CND fitness of Sec. III-D): population and
+    fitness equal the oracle's at every generation, one GA and a batch."""
+    g = inputs.erdos_renyi(1500, 3.0, seed=31)
+    graph = gp.Graph.from_csr(g)
+    ga = gp.GA(graph, 30, 40, 9, 0.7, 0.1, 2, 60, replay=replay, objective="mcn")
+    oga = O.OracleGA(g, 30, 40, 9, 0.7, 0.1, 2, 60, objective="mcn")
+    for gen in range(6):
+        pop, F = ga.population()
+        assert np.array_equal(F, oga.F) and np.array_equal(pop, oga.pop), gen
+        ga.step(1)
+        oga.step()
+    csrs = [inputs.barabasi_albert(400, 2, seed=32), inputs.erdos_renyi(900, 2.5, seed=33)]
+    params = [dict(k=8, pop=16, seed=1, objective="mcn"), dict(k=20, pop=32, seed=2, offspring=48, objective="mcn")]
+    bt = gp.Batch([gp.Graph.from_csr(c) for c in csrs], params, replay=replay)
+    ogas = [O.OracleGA(c, p["k"], p["pop"], p["seed"], 0.7, 0.05, 2, p.get("offspring", 0), objective="mcn")
+            for c, p in zip(csrs, params)]
+    for _ in range(5):
+        bt.step(1)
+        for o in ogas:
+            o.step()
+    for b, o in enumerate(ogas):
+        pop, F = bt.population(b)
+        assert np.array_equal(F, o.F) and np.array_equal(pop, o.pop), b
+    with pytest.raises(gp.GapaError):
+        ga2 = gp.GA(graph, 30, 40, 9, offspring=64, objective="mcn")
+        ga2.attach_surrogate(screen=16, batch=32, buffer=256)
