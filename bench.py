@@ -282,6 +282,19 @@ def run_sixdst(args, torch, gapa, inputs):
     products = 3  # hops 6: (A+I)^2, (A+I)^4, their product
     ops = 2.0 * np_ ** 3 * products * P
     achieved = ops / (ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's definition takes hops - 1 = 5 dense int64 products per
+        # individual; the sample is one of them (hops = 2) on the same graph
+        from oracle import cnd_oracle as O
+        g_genes = genes[0].cpu().numpy()
+        t0c = time.perf_counter()
+        O.sixdst(g, g_genes, 2)
+        tc = time.perf_counter() - t0c
+        cpu = {"value": 1.0 / (5 * tc), "unit": "individuals evaluated/s (dense reachability)", "cores": 1,
+               "kind": "oracle",
+               "sample": f"one of the five normalised int64 products of one individual (numpy, one thread): "
+                         f"{tc:.1f} s, scaled by 5"}
     return {
         "metric": METRIC, "value": P * args.steps / dt, "unit": "individuals evaluated/s (dense reachability)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
@@ -291,6 +304,7 @@ def run_sixdst(args, torch, gapa, inputs):
         "roofline": {"bound": "mfma", "kernel": "dense reachability pass (int8 products)", "achieved": achieved,
                      "peak": 5000.0, "unit": "TOP/s (int8)", "frac": achieved / 5000.0, "traffic": None,
                      "avg_launch_ms": ms, "ops_per_launch": ops},
+        "cpu_baseline": cpu,
     }
 
 

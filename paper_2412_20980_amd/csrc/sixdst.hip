@@ -3,7 +3,7 @@
 //
 //   M1 = A_S + I     A_S: the adjacency with every edge of a removed node
 //                    deleted (eq. 13), an n_pad x n_pad 0/1 int8 matrix
-//                    (n_pad = n rounded up to 64; padding rows and columns
+//                    (n_pad = n rounded up to 128; padding rows and columns
 //                    are zero)
 //   M  = Normalizer(M1^hops)   by binary exponentiation, the products
 //                    (A+I)(A+I)^2(A+I)^4... of the paper, each normalised
@@ -24,8 +24,8 @@
 namespace gapa {
 namespace {
 
-constexpr int kTile = 64;    // output tile of a block; also the k-step of one product
-constexpr int kLd = 80;      // LDS row stride in bytes (16 rows of a k-step fall in distinct banks)
+constexpr int kTile = 128;   // output tile of a block; matrices are padded to a multiple of it
+constexpr int kLd = 80;      // LDS row stride of a 64-byte k-step (16 rows of one read fall in distinct banks)
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bool removed(const uint32_t *mask, int32_t v)
@@ -54,19 +54,21 @@ __global__ __launch_bounds__(256) void k_six_build(const uint32_t *__restrict__ 
 }
 
 // C = Normalizer(A B) for individual blockIdx.y, A and B symmetric powers of
-// one matrix, so C is symmetric: block t computes the 64 x 64 tile (bi, bj),
-// bi <= bj, the t-th of the upper triangle, and writes it and its mirror
-// image.  Wave w takes rows 16 w .. 16 w + 15 of the tile and the four
-// 16-wide column tiles.  Per k-step of 64 bytes the 64 A rows and the 64 B
-// rows (B columns) of the step are staged in LDS, double-buffered: the next
+// one matrix, so C is symmetric: block t computes the 128 x 128 tile
+// (bi, bj), bi <= bj, the t-th of the upper triangle, and writes it and its
+// mirror image.  The four waves take 64 x 64 quadrants (4 x 4 MFMA tiles
+// each).  Per k-step of 64 bytes the 128 A rows and the 128 B rows (B
+// columns) of the step are staged in LDS (80-byte pitch: the 16 rows one
+// operand read touches fall in distinct banks), double-buffered: the next
 // step's global loads are in flight during the products.  MFMA operands:
-// lane l holds bytes 16 (l / 16) .. + 15 of the step for row / column l % 16
-// (the same byte order on both sides); C[4 (l / 16) + r][l % 16].
+// lane l holds bytes 16 (l / 16) .. + 15 of the step for row / column
+// l % 16 (the same byte order on both sides); C[4 (l / 16) + r][l % 16].
+constexpr int kStage = kTile * kLd;    // one operand tile of one k-step
+constexpr int kOutPitch = kTile + 16;  // output tile pitch in LDS
 __global__ __launch_bounds__(256) void k_six_gemm(const uint8_t *__restrict__ A, const uint8_t *__restrict__ B,
                                                   uint8_t *__restrict__ C, int32_t np)
 {
-    __shared__ __align__(16) uint8_t sA[2][kTile * kLd];
-    __shared__ __align__(16) uint8_t sB[2][kTile * kLd];
+    __shared__ __align__(16) uint8_t smem[4 * kStage];  // [buffer][A, B][128][kLd]
     const int64_t base = (int64_t)blockIdx.y * np * np;
     // t = bj (bj + 1) / 2 + bi
     const int32_t t_lin = blockIdx.x;
@@ -76,52 +78,74 @@ __global__ __launch_bounds__(256) void k_six_gemm(const uint8_t *__restrict__ A,
     const int32_t bi = t_lin - bj * (bj + 1) / 2;
     const int32_t i0 = bi * kTile, j0 = bj * kTile;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, lr = lane & 15, lg = lane >> 4;
-    // loader: thread t moves bytes 16 (t % 4) .. + 15 of row t / 4 of both tiles
+    const int wr = wv >> 1, wc = wv & 1;
+    // loader: thread t moves bytes 16 (t % 4) .. + 15 of rows t / 4 and 64 + t / 4 of both tiles
     const int lrow = t >> 2, lcol = (t & 3) * 16;
     const uint8_t *ga = A + base + (int64_t)(i0 + lrow) * np + lcol;
     const uint8_t *gb = B + base + (int64_t)(j0 + lrow) * np + lcol;
-    uint4 ra = *reinterpret_cast<const uint4 *>(ga);
-    uint4 rb = *reinterpret_cast<const uint4 *>(gb);
-    i32x4 acc[4];
+    const int64_t half = (int64_t)64 * np;
+    uint4 ra0 = *reinterpret_cast<const uint4 *>(ga), ra1 = *reinterpret_cast<const uint4 *>(ga + half);
+    uint4 rb0 = *reinterpret_cast<const uint4 *>(gb), rb1 = *reinterpret_cast<const uint4 *>(gb + half);
+    i32x4 acc[4][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = i32x4{0, 0, 0, 0};
-    const int32_t steps = np / kTile;
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = i32x4{0, 0, 0, 0};
+    const int32_t steps = np / 64;
     for (int32_t s = 0; s < steps; ++s) {
-        const int buf = s & 1;
-        *reinterpret_cast<uint4 *>(&sA[buf][lrow * kLd + lcol]) = ra;
-        *reinterpret_cast<uint4 *>(&sB[buf][lrow * kLd + lcol]) = rb;
+        uint8_t *sA = smem + (s & 1) * 2 * kStage, *sB = sA + kStage;
+        *reinterpret_cast<uint4 *>(&sA[lrow * kLd + lcol]) = ra0;
+        *reinterpret_cast<uint4 *>(&sA[(64 + lrow) * kLd + lcol]) = ra1;
+        *reinterpret_cast<uint4 *>(&sB[lrow * kLd + lcol]) = rb0;
+        *reinterpret_cast<uint4 *>(&sB[(64 + lrow) * kLd + lcol]) = rb1;
         __syncthreads();
         if (s + 1 < steps) {
-            ra = *reinterpret_cast<const uint4 *>(ga + (int64_t)(s + 1) * kTile);
-            rb = *reinterpret_cast<const uint4 *>(gb + (int64_t)(s + 1) * kTile);
+            const int64_t o = (int64_t)(s + 1) * 64;
+            ra0 = *reinterpret_cast<const uint4 *>(ga + o);
+            ra1 = *reinterpret_cast<const uint4 *>(ga + half + o);
+            rb0 = *reinterpret_cast<const uint4 *>(gb + o);
+            rb1 = *reinterpret_cast<const uint4 *>(gb + half + o);
         }
-        const i32x4 a = *reinterpret_cast<const i32x4 *>(&sA[buf][(wv * 16 + lr) * kLd + lg * 16]);
+        i32x4 a[4], b[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const i32x4 b = *reinterpret_cast<const i32x4 *>(&sB[buf][(q * 16 + lr) * kLd + lg * 16]);
-            acc[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[q], 0, 0, 0);
-        }
+        for (int x = 0; x < 4; ++x) a[x] = *reinterpret_cast<const i32x4 *>(&sA[(wr * 64 + 16 * x + lr) * kLd + lg * 16]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) b[y] = *reinterpret_cast<const i32x4 *>(&sB[(wc * 64 + 16 * y + lr) * kLd + lg * 16]);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[x], b[y], acc[x][y], 0, 0, 0);
     }
     // normalised tile through LDS, then written as 16-byte row pieces
     __syncthreads();
-    uint8_t *tile = sA[0];
+    uint8_t *out = smem;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(wr * 64 + 16 * x + 4 * lg + r) * kOutPitch + wc * 64 + 16 * y + lr] = acc[x][y][r] > 0 ? 1 : 0;
+    __syncthreads();
+    const int orow = t >> 1, ocol = (t & 1) * 64;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) tile[(wv * 16 + 4 * lg + r) * kLd + q * 16 + lr] = acc[q][r] > 0 ? 1 : 0;
-    __syncthreads();
-    *reinterpret_cast<uint4 *>(C + base + (int64_t)(i0 + lrow) * np + j0 + lcol) =
-        *reinterpret_cast<const uint4 *>(&tile[lrow * kLd + lcol]);
+        *reinterpret_cast<uint4 *>(C + base + (int64_t)(i0 + orow) * np + j0 + ocol + 16 * q) =
+            *reinterpret_cast<const uint4 *>(&out[orow * kOutPitch + ocol + 16 * q]);
     if (bi != bj) {
-        // the mirror tile: row lrow of it is column lrow of this one
-        uint32_t w[4];
+        // the mirror tile: row orow of it is column orow of this one
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            w[q] = 0;
+            uint32_t w[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) w[q] |= (uint32_t)tile[(lcol + 4 * q + e) * kLd + lrow] << (8 * e);
+            for (int d = 0; d < 4; ++d) {
+                w[d] = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w[d] |= (uint32_t)out[(ocol + 16 * q + 4 * d + e) * kOutPitch + orow] << (8 * e);
+            }
+            *reinterpret_cast<uint4 *>(C + base + (int64_t)(j0 + orow) * np + i0 + ocol + 16 * q) =
+                uint4{w[0], w[1], w[2], w[3]};
         }
-        *reinterpret_cast<uint4 *>(C + base + (int64_t)(j0 + lrow) * np + i0 + lcol) = uint4{w[0], w[1], w[2], w[3]};
     }
 }
 
