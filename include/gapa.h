@@ -184,6 +184,23 @@ GAPA_API int gapa_generation_step(gapa_ga *ga, int32_t n_generations, void *stre
  * eagerly. */
 GAPA_API int gapa_ga_record(gapa_ga *ga, int32_t n_generations);
 
+/* Checkpoint and resume of a single GA without a surrogate.  gapa_ga_save
+ * writes the GA's parameters, its graph's identity (n, nnz and a hash of the
+ * CSR), the generation number, the population rows in order and their
+ * fitness to the file at `path` (synchronous; GAPA_E_STATE for a batch or
+ * with a surrogate, GAPA_E_INVALID_ARG if the file cannot be written).
+ * gapa_ga_load creates a GA on graph g from such a file: since every random
+ * draw is keyed by (seed, generation, individual, slot), stepping it gives
+ * exactly the generations the saved GA would have run.  A file that is not a
+ * checkpoint, is truncated or fails its checksum, or was taken on another
+ * graph gives GAPA_E_INVALID_ARG.  The new GA is owned by the caller
+ * (gapa_ga_destroy). */
+GAPA_API int gapa_ga_save(gapa_ga *ga, const char *path);
+/* The GA's parameters and the number of generations enqueued so far (either
+ * output may be NULL). */
+GAPA_API int gapa_ga_params(gapa_ga *ga, gapa_params *params_out, int64_t *generation_out);
+GAPA_API int gapa_ga_load(gapa_graph *g, const char *path, void *stream, gapa_ga **out);
+
 /* Best individual after the last enqueued generation (eq. 1's arg max): its k
  * genes ascending (genes_out, k int32, may be NULL), PC (may be NULL) and the
  * generation count (may be NULL).  Host pointers; waits for the GA's work. */

@@ -344,6 +344,19 @@ int fail_handle(bool *failed, int rc)
 
 // Device copy of a validated CSR and its orderings; voff splits the nodes
 // into instances (a single graph: {0, n}).
+constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull;
+
+// FNV-1a, 64-bit (Fowler, Noll, Vo), continuing from h.
+uint64_t fnv1a(const void *data, size_t bytes, uint64_t h)
+{
+    const unsigned char *p = static_cast<const unsigned char *>(data);
+    for (size_t i = 0; i < bytes; ++i) {
+        h ^= p[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
 int graph_build(int dev, int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                 const std::vector<int32_t> &voff, int algorithm, gapa_graph **out)
 {
@@ -355,6 +368,9 @@ int graph_build(int dev, int32_t n, int64_t nnz, const int32_t *row_ptr, const i
     g->device = dev;
     g->n = n;
     g->nnz = nnz;
+    g->content_hash = fnv1a(&n, 4, kFnvBasis);
+    g->content_hash = fnv1a(row_ptr, (size_t)(n + 1) * 4, g->content_hash);
+    g->content_hash = fnv1a(col_idx, (size_t)nnz * 4, g->content_hash);
     g->words = (n + 31) / 32;
     g->algorithm = algorithm;
     std::vector<int32_t> src((size_t)std::max<int64_t>(nnz, 1));
@@ -1044,6 +1060,161 @@ int gapa_get_population(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out)
         return GAPA_E_INVALID_ARG;
     }
     return ga_copy_out(ga, 0, false, genes_out, fitness_out);
+}
+
+// Checkpoint file: magic, version, the GA parameters, the graph (n, nnz,
+// content hash), the generation, then the population rows [P][k] and their
+// fitness [P] in order, and an FNV-1a checksum of everything before it.
+static const char kCkptMagic[8] = {'G', 'A', 'P', 'A', 'C', 'K', 'P', 'T'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t pad;
+    gapa_params params;
+    int32_t n;
+    int32_t P;
+    int64_t nnz;
+    uint64_t graph_hash;
+    int64_t generation;
+};
+
+int gapa_ga_save(gapa_ga *ga, const char *path)
+{
+    g_last_error.clear();
+    if (!ga || !path) {
+        set_error("NULL argument");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (ga->count != 1 || ga->surr) {
+        set_error("checkpoints cover a single GA without a surrogate");
+        return GAPA_E_STATE;
+    }
+    const int32_t P = ga->params.pop, k = ga->params.k;
+    std::vector<int32_t> rows((size_t)P * k);
+    std::vector<int64_t> fit((size_t)P);
+    int rc = ga_copy_out(ga, 0, false, rows.data(), fit.data());
+    if (rc != GAPA_OK) return rc;
+    CkptHeader h{};
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.version = kCkptVersion;
+    h.params = ga->params;
+    h.n = ga->graph->n;
+    h.P = P;
+    h.nnz = ga->graph->nnz;
+    h.graph_hash = ga->graph->content_hash;
+    h.generation = ga->generation;
+    uint64_t sum = fnv1a(&h, sizeof h, kFnvBasis);
+    sum = fnv1a(rows.data(), rows.size() * 4, sum);
+    sum = fnv1a(fit.data(), fit.size() * 8, sum);
+    FILE *f = std::fopen(path, "wb");
+    if (!f) {
+        set_error("cannot open %s for writing", path);
+        return GAPA_E_INVALID_ARG;
+    }
+    bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 && std::fwrite(rows.data(), 4, rows.size(), f) == rows.size() &&
+              std::fwrite(fit.data(), 8, fit.size(), f) == fit.size() && std::fwrite(&sum, 8, 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) {
+        set_error("writing %s failed", path);
+        return GAPA_E_INVALID_ARG;
+    }
+    return GAPA_OK;
+}
+
+int gapa_ga_params(gapa_ga *ga, gapa_params *params_out, int64_t *generation_out)
+{
+    g_last_error.clear();
+    if (!ga) {
+        set_error("GA is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (params_out) *params_out = ga->params;
+    if (generation_out) *generation_out = ga->generation;
+    return GAPA_OK;
+}
+
+int gapa_ga_load(gapa_graph *g, const char *path, void *stream, gapa_ga **out)
+{
+    g_last_error.clear();
+    if (!g || !path || !out) {
+        set_error("NULL argument");
+        return GAPA_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (g->failed) {
+        set_error("graph handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    FILE *f = std::fopen(path, "rb");
+    if (!f) {
+        set_error("cannot open %s", path);
+        return GAPA_E_INVALID_ARG;
+    }
+    CkptHeader h{};
+    std::vector<int32_t> rows;
+    std::vector<int64_t> fit;
+    uint64_t sum = 0;
+    bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, kCkptMagic, 8) == 0 &&
+              h.version == kCkptVersion && h.P == h.params.pop && h.P >= 1 && h.params.k >= 1 && h.P <= (1 << 20) &&
+              h.params.k <= (1 << 24) && (int64_t)h.P * h.params.k <= (1ll << 31);
+    if (ok) {
+        rows.resize((size_t)h.P * h.params.k);
+        fit.resize((size_t)h.P);
+        ok = std::fread(rows.data(), 4, rows.size(), f) == rows.size() &&
+             std::fread(fit.data(), 8, fit.size(), f) == fit.size() && std::fread(&sum, 8, 1, f) == 1;
+    }
+    std::fclose(f);
+    if (ok) {
+        uint64_t s2 = fnv1a(&h, sizeof h, kFnvBasis);
+        s2 = fnv1a(rows.data(), rows.size() * 4, s2);
+        s2 = fnv1a(fit.data(), fit.size() * 8, s2);
+        ok = s2 == sum;
+    }
+    if (!ok) {
+        set_error("%s is not a GA checkpoint of this version, or is corrupt", path);
+        return GAPA_E_INVALID_ARG;
+    }
+    if (h.n != g->n || h.nnz != g->nnz || h.graph_hash != g->content_hash) {
+        set_error("the checkpoint was taken on a different graph");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (!params_ok(&h.params, g->n) || h.generation < 0 || h.generation >= (1ll << 32)) {
+        set_error("invalid parameters in the checkpoint");
+        return GAPA_E_INVALID_ARG;
+    }
+    for (int32_t v : rows)
+        if (v < 0 || v >= g->n) {
+            set_error("gene %d of the checkpoint is not a node id", v);
+            return GAPA_E_BAD_GENE;
+        }
+    DeviceGuard dg(g->device);
+    gapa_ga *ga = new (std::nothrow) gapa_ga();
+    if (!ga) {
+        set_error("host allocation failed");
+        return GAPA_E_OOM;
+    }
+    ga->graph = g;
+    graph_retain(g);
+    auto fail = [&](int code) {
+        gapa_ga_destroy(ga);
+        return code;
+    };
+    int rc = ga_allocate(ga, 1, &h.params, &g->n, &g->n_noniso, 0);
+    if (rc != GAPA_OK) return fail(rc);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = launch_fill_u32(ga->flag.ptr, 0u, 4, s)) != GAPA_OK) return fail(rc);
+    if ((rc = launch_fill_u32(ga->gen_ctr.ptr, (uint32_t)h.generation, 1, s)) != GAPA_OK) return fail(rc);
+    hipError_t e = hipMemcpyAsync(ga->pop[0].ptr, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ga->fit[0].ptr, fit.data(), fit.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(hip_fail(e, "checkpoint upload"));
+    ga->cur = 0;
+    ga->generation = h.generation;
+    ga->last_stream = s;
+    *out = ga;
+    return GAPA_OK;
 }
 
 int gapa_ga_destroy(gapa_ga *ga)

@@ -115,6 +115,7 @@ struct Tuning {
 struct gapa_graph {
     std::atomic<int32_t> refs{1};  // the caller's handle, plus one per GA or batch using the graph
     int device = 0;
+    uint64_t content_hash = 0;     // FNV-1a of n, row_ptr and col_idx (checkpoints name their graph by it)
     int32_t n = 0;
     int64_t nnz = 0;
     int32_t words = 0;          // ceil(n / 32): words of a node bit set

@@ -54,7 +54,8 @@ EXPORTED = (
     "gapa_surrogate_attach", "gapa_surrogate_stats", "gapa_surrogate_last_pool", "gapa_surrogate_predict",
     "gapa_surrogate_train_batch", "gapa_surrogate_tensor", "gapa_surrogate_last_predictions",
     "gapa_graph_get_tuning", "gapa_graph_set_tuning", "gapa_ga_autotune", "gapa_batch_autotune",
-    "gapa_ga_record", "gapa_batch_record", "gapa_sixdst_eval",
+    "gapa_ga_record", "gapa_batch_record", "gapa_sixdst_eval", "gapa_ga_save", "gapa_ga_load",
+    "gapa_ga_params",
 )
 
 
@@ -122,6 +123,9 @@ def lib() -> C.CDLL:
     L.gapa_batch_get_population.argtypes = [vp, C.c_int32, vp, vp]
     L.gapa_batch_destroy.argtypes = [vp]
     L.gapa_ga_record.argtypes = [vp, C.c_int32]
+    L.gapa_ga_save.argtypes = [vp, C.c_char_p]
+    L.gapa_ga_load.argtypes = [vp, C.c_char_p, vp, C.POINTER(vp)]
+    L.gapa_ga_params.argtypes = [vp, C.POINTER(gapa_params), C.POINTER(C.c_int64)]
     L.gapa_sixdst_eval.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, C.c_uint32, vp]
     L.gapa_batch_record.argtypes = [vp, C.c_int32]
     L.gapa_graph_get_tuning.argtypes = [vp, C.POINTER(gapa_tuning)]
@@ -358,6 +362,28 @@ class GA:
 
     def step(self, n: int = 1, stream=None):
         gapa_generation_step(self.handle, n, stream)
+
+    def save(self, path: str):
+        """Checkpoint: parameters, graph identity, generation, population."""
+        _check(lib().gapa_ga_save(self.handle, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, graph: Graph, path: str, stream=None) -> "GA":
+        """A GA resumed from a checkpoint taken on the same graph."""
+        h = C.c_void_p()
+        _check(lib().gapa_ga_load(graph.handle, os.fsencode(path), _stream_ptr(stream), C.byref(h)))
+        ga = cls.__new__(cls)
+        ga.graph = graph
+        ga.handle = h
+        t = gapa_params()
+        _check(lib().gapa_ga_params(h, C.byref(t), None))
+        ga.k, ga.pop = int(t.k), int(t.pop)
+        return ga
+
+    def generation(self) -> int:
+        g = C.c_int64()
+        _check(lib().gapa_ga_params(self.handle, None, C.byref(g)))
+        return int(g.value)
 
     def best(self):
         return gapa_best(self.handle, self.k)

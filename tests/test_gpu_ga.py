@@ -215,3 +215,46 @@ def test_mcn_objective_matches_oracle(gp, replay):
     with pytest.raises(gp.GapaError):
         ga2 = gp.GA(graph, 30, 40, 9, offspring=64, objective="mcn")
         ga2.attach_surrogate(screen=16, batch=32, buffer=256)
+
+
+def test_checkpoint_resume_continues_the_trajectory(gp, ba10k, tmp_path):
+    """A GA saved at generation 7 and loaded (on the same graph, in a new
+    handle) runs exactly the generations the original runs: both match the
+    oracle.  Files that are not checkpoints, are corrupt, or belong to another
+    graph are rejected; a GA with a surrogate cannot be saved."""
+    W = inputs.workload("ba10k_k100_p256")
+    graph = gp.Graph.from_csr(ba10k)
+    ga = gp.GA(graph, W.k, W.pop, W.seed, W.pc, W.pm, W.tournament, replay=True)
+    ga.step(7)
+    path = str(tmp_path / "ga.ckpt")
+    ga.save(path)
+    ga.step(5)
+    resumed = gp.GA.load(graph, path)
+    assert resumed.generation() == 7
+    resumed.step(5)
+    oga = O.OracleGA(ba10k, W.k, W.pop, W.seed, W.pc, W.pm, W.tournament)
+    for _ in range(12):
+        oga.step()
+    for g in (ga, resumed):
+        pop, F = g.population()
+        assert np.array_equal(F, oga.F) and np.array_equal(pop, oga.pop)
+    # a checkpoint of another graph, a truncated and a corrupted file
+    other = gp.Graph.from_csr(inputs.barabasi_albert(10000, 3, seed=99))
+    with pytest.raises(gp.GapaError) as e:
+        gp.GA.load(other, path)
+    assert e.value.code == gp.GAPA_E_INVALID_ARG
+    data = open(path, "rb").read()
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(data[:-20])
+    with pytest.raises(gp.GapaError):
+        gp.GA.load(graph, str(bad))
+    flipped = bytearray(data)
+    flipped[200] ^= 1
+    bad.write_bytes(bytes(flipped))
+    with pytest.raises(gp.GapaError):
+        gp.GA.load(graph, str(bad))
+    sga = gp.GA(graph, W.k, W.pop, W.seed, offspring=512)
+    sga.attach_surrogate(screen=64, batch=64, buffer=1024)
+    with pytest.raises(gp.GapaError) as e:
+        sga.save(str(tmp_path / "s.ckpt"))
+    assert e.value.code == gp.GAPA_E_STATE
