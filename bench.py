@@ -4,6 +4,7 @@
   python bench.py --workload batched64    # 64 independent GAs advanced together
   python bench.py --workload surrogate    # screened generations (4096 offspring, 512 evaluated)
   python bench.py --workload sixdst       # the paper's dense reachability fitness on the matrix cores
+  python bench.py --p-sweep               # fitness pass time against population size
   python bench.py --copy-calibration      # plain 1 GiB copies, for counter scaling
 
 A step is one whole generation of the method on the device: tournament
@@ -308,6 +309,33 @@ def run_sixdst(args, torch, gapa, inputs):
     }
 
 
+def p_sweep(args, torch, gapa, inputs):
+    """Batched-fitness pass time against population size on the 200k-node
+    graph: P rows drawn like a converging population (80 % of each row from
+    the top 4000 hubs), each pass timed with HIP events on the launch stream
+    (20 passes after 3 untimed ones); chunks of 1024 above that."""
+    w = inputs.workload("cl200k_k2000_p1024")
+    graph = gapa.Graph.from_csr(w.graph, trust=True)
+    stream = torch.cuda.Stream()
+    rows = []
+    for P in (64, 128, 256, 512, 1024, 2048, 4096):
+        genes = torch.from_numpy(inputs.hub_biased_population(w.graph, w.k, P, seed=P, hub_frac=0.8)).cuda()
+        fit = torch.empty(P, dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            gapa.gapa_eval_population(graph.handle, genes, fitness=fit, flags=gapa.GAPA_TRUST_INPUT, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            gapa.gapa_eval_population(graph.handle, genes, fitness=fit, flags=gapa.GAPA_TRUST_INPUT, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        rows.append({"P": P, "ms_per_pass": ms, "evals_per_s": P / (ms * 1e-3)})
+        print(f"# P={P}: {ms:.3f} ms, {P / (ms * 1e-3):.3e} evals/s", file=sys.stderr, flush=True)
+    return {"p_sweep": rows, "workload": w.name, "population": "hub-biased (80 % from the top 2k hubs)"}
+
+
 def copy_calibration():
     import torch
     n = 1 << 28  # 2^28 float32 = 1 GiB
@@ -329,6 +357,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="cl200k_k2000_p1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--p-sweep", action="store_true", help="fitness pass time for P = 64 .. 4096 at n = 200k")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-replay", action="store_true", help="launch generations eagerly instead of replaying a "
@@ -355,6 +384,9 @@ def main():
         args.warmup = 20 if args.warmup is None else args.warmup
         args.steps = 20 if args.steps is None else args.steps
         print(json.dumps(run_surrogate(args, torch, gapa, inputs)), flush=True)
+        return
+    if args.p_sweep:
+        print(json.dumps(p_sweep(args, torch, gapa, inputs)), flush=True)
         return
     if args.workload == "sixdst":
         args.warmup = 2 if args.warmup is None else args.warmup

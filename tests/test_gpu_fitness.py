@@ -156,3 +156,28 @@ def test_timing_reports_kernels(gp, ba10k):
     graph.eval(inputs.random_population(ba10k.n, 100, 64, seed=3))
     t = graph.kernel_times()
     assert t and all(v[0] >= 1 and v[1] >= 0 for v in t.values())
+
+
+def test_population_sharded_over_streams(gp, cl200k):
+    """One GPU's stand-in for sharding a population over g devices: the 1024
+    individuals of the benchmark's shape split into 4 shards, each evaluated
+    through its own graph handle (as each device would hold the graph) on its
+    own stream, concurrently; the concatenation equals the unsharded result,
+    which equals the oracle on a sample of rows."""
+    import torch
+    pop = np.concatenate([inputs.hub_biased_population(cl200k, 2000, 512, seed=18, hub_frac=1.0),
+                          inputs.random_population(cl200k.n, 2000, 512, seed=19)])
+    whole = gp.Graph.from_csr(cl200k, trust=True).eval(pop)
+    shards, streams = 4, [torch.cuda.Stream() for _ in range(4)]
+    graphs = [gp.Graph.from_csr(cl200k, trust=True) for _ in range(shards)]
+    d = torch.from_numpy(pop).cuda()
+    outs = [torch.empty(pop.shape[0] // shards, dtype=torch.int64, device="cuda") for _ in range(shards)]
+    torch.cuda.synchronize()
+    for r in range(shards):
+        rows = d[r * 256:(r + 1) * 256].contiguous()
+        gp.gapa_eval_population(graphs[r].handle, rows, fitness=outs[r], flags=gp.GAPA_TRUST_INPUT, stream=streams[r])
+    torch.cuda.synchronize()
+    got = torch.cat(outs).cpu().numpy()
+    assert np.array_equal(got, whole)
+    idx = np.arange(0, 1024, 97)
+    assert np.array_equal(whole[idx], O.eval_population(cl200k, pop[idx]))
