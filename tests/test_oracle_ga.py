@@ -197,3 +197,19 @@ def test_oracle_trajectory_hashes_stable(ba200):
         return h.hexdigest()
 
     assert run(1) == run(8)
+
+
+def test_oracle_state_is_complete_for_resume():
+    """Checkpoint/resume on the oracle: the GA state is the ordered population,
+    its fitness and the generation number (every draw is keyed by them), so a
+    fresh GA given a copy of that state continues exactly like the original."""
+    g = inputs.barabasi_albert(400, 2, seed=5)
+    a = O.OracleGA(g, 12, 20, 3, 0.7, 0.1, 2, 30)
+    for _ in range(6):
+        a.step()
+    b = O.OracleGA(g, 12, 20, 3, 0.7, 0.1, 2, 30)
+    b.pop[:], b.F[:], b.generation = a.pop.copy(), a.F.copy(), a.generation
+    for _ in range(5):
+        a.step()
+        b.step()
+        assert np.array_equal(a.pop, b.pop) and np.array_equal(a.F, b.F)
