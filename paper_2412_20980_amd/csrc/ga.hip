@@ -243,12 +243,26 @@ __device__ void emit(const OpLds &l, const Op &a, int32_t idx)
     __syncthreads();
     uint32_t *m = a.masks + (int64_t)idx * a.W;
     int32_t gone = 0;
-    if (!a.rows_only)
-        for (int32_t w = threadIdx.x; w < a.W; w += blockDim.x) {
+    if (!a.rows_only) {
+        // eight words a round: their loads of the non-isolated set are in flight together
+        int32_t w = threadIdx.x;
+        for (; w + 7 * (int32_t)blockDim.x < a.W; w += 8 * blockDim.x) {
+            uint32_t nz[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) nz[u] = a.noniso[w + u * blockDim.x];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t x = l.U[w + u * blockDim.x];
+                m[w + u * blockDim.x] = x;
+                gone += __popc(x & nz[u]);
+            }
+        }
+        for (; w < a.W; w += blockDim.x) {
             const uint32_t x = l.U[w];
             m[w] = x;
             gone += __popc(x & a.noniso[w]);
         }
+    }
     const int32_t per = (a.W + blockDim.x - 1) / blockDim.x;
     const int32_t w0 = min(a.W, (int32_t)threadIdx.x * per), w1 = min(a.W, w0 + per);
     int32_t cnt = 0;
@@ -324,6 +338,7 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs args)
     const int32_t *base = a.pop + (int64_t)(o % a.P) * a.k;
     const int32_t *donor = a.pop + (int64_t)s_donor * a.k;
     // crossover coins; values taken from the base row enter the membership set
+#pragma unroll 4
     for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
         const Words4 x = draw(a.seed, j, o, gen, kStreamXover, 0);
         const bool take = (uint64_t)x.w0 < a.t_pc;
@@ -339,11 +354,26 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs args)
     // twice in the child: once from each row.  A donor value c that is already
     // a member came from the base row at the slot p where base[p] = c; the
     // later of p and j is the copy.  Other donor values join the set.
+#pragma unroll 2
     for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
         if (!((l.from_donor[j >> 5] >> (j & 31)) & 1u)) continue;
         const int32_t c = l.row[j];
         if (lds_test(l.U, c)) {
-            int32_t lo = 0, hi = a.k;
+            // position of c in the base row: galloping from slot j (the rows
+            // of a converged population differ by small shifts), then a
+            // binary search inside the bracket
+            int32_t lo, hi;
+            if (base[j] < c) {
+                int32_t b = 1;
+                while (j + b < a.k && base[j + b] < c) b <<= 1;
+                lo = j + (b >> 1) + 1;
+                hi = min(j + b, a.k);
+            } else {
+                int32_t b = 1;
+                while (j - b >= 0 && base[j - b] >= c) b <<= 1;
+                lo = max(j - b + 1, 0);
+                hi = j - (b >> 1);
+            }
             while (lo < hi) {
                 const int32_t mid = (lo + hi) >> 1;
                 if (base[mid] < c) lo = mid + 1;
