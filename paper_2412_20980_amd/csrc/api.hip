@@ -1562,7 +1562,7 @@ int gapa_batch_create(int32_t count, gapa_graph *const *graphs, const gapa_param
             live_gen[b] = I.L;
             moff[b] = I.mask_off;
             for (int32_t v = voff[b]; v < voff[b + 1]; ++v) node_inst[v] = b;
-            for (int32_t j0 = 0; j0 < I.W; j0 += kTransposeWords) {
+            for (int32_t j0 = 0; j0 < I.W; j0 += transpose_tile_words(bseg / 32)) {
                 tiles.push_back(b);
                 tiles.push_back(j0);
             }

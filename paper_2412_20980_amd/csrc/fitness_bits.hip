@@ -102,13 +102,22 @@ __device__ __forceinline__ int64_t uf_block(const Insts &I, int32_t gi)
 }
 
 // dead rows from per-individual removed-node bit sets masks[B_real][W]: a
-// block takes kTileWords node words (32 * kTileWords nodes) of every
-// individual of the chunk, stages them in LDS (rows of kTileWords words are
+// block takes TW node words (32 TW nodes) of every individual of the chunk,
+// TW = kTileWords * 32 / Wd so that a tile always holds 1024 kTileWords
+// words whatever the chunk width; stages them in LDS (rows of TW words are
 // contiguous in global memory), transposes each 32 x 32 bit block with
-// ballots, and writes the tile's dead rows, which are one contiguous range of
-// the node-major array.  The same range of reach rows is cleared.
+// lane shuffles, and writes the tile's dead rows, which are one contiguous
+// range of the node-major array.  The same range of reach rows is cleared.
 // Individuals past B_real are padding and remove every node.
 constexpr int kTileWords = kTransposeWords;
+
+// LDS words of the transposer: the input tile [B][TW + 1], then the output
+// tile [32 TW][Wd + 1] in the same buffer.
+__host__ __device__ constexpr int32_t transpose_lds_words(int32_t log_wd)
+{
+    return 1024 * kTileWords + ((32 << log_wd) > (32 * (kTileWords << (5 - log_wd))) ? (32 << log_wd)
+                                                                                        : 32 * (kTileWords << (5 - log_wd)));
+}
 
 // 32 x 32 bit-matrix transpose across the 32 lanes of a half-wave: lane r
 // holds row r (bit c = entry (r, c)); afterwards lane c holds column c (bit r =
@@ -131,64 +140,61 @@ __global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restr
                                                          int32_t log_wd, uint32_t *__restrict__ dead,
                                                          uint32_t *__restrict__ reach)
 {
-    // this tile: instance b, its node words [j0, j0 + kTileWords)
+    extern __shared__ uint32_t tile[];
+    const int32_t Wd = 1 << log_wd;
+    const int32_t log_tw = 5 - log_wd + (kTileWords == 1 ? 0 : kTileWords == 2 ? 1 : kTileWords == 4 ? 2 : 3);
+    const int32_t TW = 1 << log_tw;
+    // this tile: instance b, its node words [j0, j0 + TW)
     // tiles side by side read the same 128-byte lines of each mask row
     const int32_t t = xcd_tile(blockIdx.x, gridDim.x);
     const int32_t b = I.count == 1 ? 0 : I.tiles[2 * t];
-    const int32_t j0 = I.count == 1 ? t * kTileWords : I.tiles[2 * t + 1];
+    const int32_t j0 = I.count == 1 ? t * TW : I.tiles[2 * t + 1];
     const int32_t vb = i_voff(I, b);
     const int32_t nb = i_voff(I, b + 1) - vb;
     const int32_t W = (nb + 31) / 32;
     const int32_t B_real = i_live(I, b);
     const int64_t mstride = W;
     if (I.count > 1) masks += I.moff[b];
-    // One LDS buffer serves first as the input tile [B][kTileWords] and then as
-    // the output tile [32 * kTileWords nodes][Wd]; rows are padded by one word
-    // so that column walks spread over the LDS banks.
-    constexpr int kIn = kTileWords + 1;
-    __shared__ uint32_t tile[32 * 32 * kIn];
-    const int32_t Wd = 1 << log_wd;
-    const int32_t B = Wd * 32;
+    // rows are padded by one word so that column walks spread over the LDS banks
+    const int32_t In = TW + 1;
     const int32_t Wo = Wd + 1;
     // all loads of a thread are issued before any LDS store: they are
-    // independent, so they are in flight together
+    // independent, so they are in flight together (B * TW = 1024 kTileWords)
     constexpr int kLoads = 32 * 32 * kTileWords / kBlk;
     uint32_t vals[kLoads];
 #pragma unroll
     for (int r = 0; r < kLoads; ++r) {
         const int32_t x = threadIdx.x + r * kBlk;
-        const int32_t ind = x / kTileWords, jj = x % kTileWords;
-        vals[r] = (x < B * kTileWords && ind < B_real && j0 + jj < W) ? masks[(int64_t)ind * mstride + j0 + jj]
-                                                                     : 0xFFFFFFFFu;
+        const int32_t ind = x >> log_tw, jj = x & (TW - 1);
+        vals[r] = (ind < B_real && j0 + jj < W) ? masks[(int64_t)ind * mstride + j0 + jj] : 0xFFFFFFFFu;
     }
 #pragma unroll
     for (int r = 0; r < kLoads; ++r) {
         const int32_t x = threadIdx.x + r * kBlk;
-        if (x < B * kTileWords) tile[(x / kTileWords) * kIn + (x % kTileWords)] = vals[r];
+        tile[(x >> log_tw) * In + (x & (TW - 1))] = vals[r];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int half = lane >> 5, l32 = lane & 31;
-    // (node word jj, individual word w) 32 x 32 blocks, one per half-wave pass
-    const int32_t combos = kTileWords * Wd;
-    uint32_t res[kTileWords * 32 / 8];
+    // (node word jj, individual word w) 32 x 32 blocks, one per half-wave
+    // pass: TW * Wd = 32 kTileWords of them
+    constexpr int kIters = kTileWords * 32 / 8;
+    uint32_t res[kIters];
 #pragma unroll
-    for (int it = 0; it < kTileWords * 32 / 8; ++it) {
+    for (int it = 0; it < kIters; ++it) {
         const int32_t cc = (it * nw + wv) * 2 + half;
-        const bool ok = cc < combos;
         const int32_t jj = cc >> log_wd, w = cc & (Wd - 1);
-        const uint32_t x = ok ? tile[(w * 32 + l32) * kIn + jj] : 0u;
-        res[it] = transpose32(x, l32);
+        res[it] = transpose32(tile[(w * 32 + l32) * In + jj], l32);
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kTileWords * 32 / 8; ++it) {
+    for (int it = 0; it < kIters; ++it) {
         const int32_t cc = (it * nw + wv) * 2 + half;
-        if (cc < combos) tile[((cc >> log_wd) * 32 + l32) * Wo + (cc & (Wd - 1))] = res[it];
+        tile[((cc >> log_wd) * 32 + l32) * Wo + (cc & (Wd - 1))] = res[it];
     }
     __syncthreads();
     const int64_t v0 = vb + (int64_t)j0 * 32;
-    const int32_t rows = min(32 * kTileWords, nb - j0 * 32);
+    const int32_t rows = min(32 * TW, nb - j0 * 32);
     for (int32_t x = threadIdx.x; x < (rows << log_wd); x += blockDim.x) {
         dead[v0 * Wd + x] = tile[(x >> log_wd) * Wo + (x & (Wd - 1))];
         if (reach) reach[v0 * Wd + x] = 0u;
@@ -640,8 +646,9 @@ int launch_bits_transpose(const uint32_t *masks, int32_t P, int32_t W, int32_t n
     if (P % 32 != 0 || Wd < 1 || Wd > 32 || (Wd & (Wd - 1)) != 0) return GAPA_E_INVALID_ARG;
     while ((1 << log_wd) < Wd) ++log_wd;
     const Insts I{1, P, n, P, nullptr, nullptr, nullptr, nullptr, nullptr};
-    hipLaunchKernelGGL(k_dead_transpose, dim3((W + kTileWords - 1) / kTileWords), dim3(kBlk), 0, s, masks, I, log_wd,
-                       rows, nullptr);
+    const int32_t tw = transpose_tile_words(Wd);
+    hipLaunchKernelGGL(k_dead_transpose, dim3((W + tw - 1) / tw), dim3(kBlk),
+                       (size_t)transpose_lds_words(log_wd) * 4, s, masks, I, log_wd, rows, nullptr);
     GAPA_HIP(hipGetLastError());
     return GAPA_OK;
 }
@@ -706,9 +713,10 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         TimedScope pass(timer, "fitness_pass", s, 1);
         {
             TimedScope ts(timer, "k_dead_transpose", s);
-            const int32_t tiles = multi ? it->ntiles : (W + kTileWords - 1) / kTileWords;
-            hipLaunchKernelGGL(k_dead_transpose, dim3(tiles), dim3(kBlk), 0, s, masks + (int64_t)c0 * W, I, log_wd,
-                               dead, reach);
+            const int32_t tw = transpose_tile_words(Wd);
+            const int32_t tiles = multi ? it->ntiles : (W + tw - 1) / tw;
+            hipLaunchKernelGGL(k_dead_transpose, dim3(tiles), dim3(kBlk), (size_t)transpose_lds_words(log_wd) * 4, s,
+                               masks + (int64_t)c0 * W, I, log_wd, dead, reach);
         }
         {
             TimedScope ts(timer, "k_seed", s);

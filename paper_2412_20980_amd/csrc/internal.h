@@ -142,6 +142,13 @@ namespace gapa {
 // lists of instance tables step by it.
 constexpr int kTransposeWords = 4;
 
+// Node words per transposer tile for chunks of Wd words per node row (Wd a
+// power of two <= 32): kTransposeWords * 32 / Wd.
+inline int32_t transpose_tile_words(int32_t Wd)
+{
+    return kTransposeWords * 32 / Wd;
+}
+
 // Several instances (disjoint node ranges of one graph, each with its own
 // individuals) evaluated in one bit-parallel fitness pass.  All arrays are on
 // the device.  Slot i of instance b is entry b * bseg + i of the alive,
