@@ -401,8 +401,9 @@ GAPA_API int gapa_graph_set_tuning(gapa_graph *g, const gapa_tuning *t);
 
 /* Autotuner: times `reps` >= 1 fitness passes over the children the GA (or
  * batch) currently holds for each launch shape of a fixed candidate grid
- * (sweep_grid 2048/4096/8192, band_scan 16/32/64, sweeps 2/3/4, band_blocks
- * 4096/16384), keeps the fastest on the evaluating graph and returns it
+ * (sweep_grid 1024/2048/4096/8192, band_scan 8/16/32/64, sweeps 2/3/4,
+ * band_blocks 2048/4096/16384; timed with events on the stream), keeps the
+ * fastest on the evaluating graph and returns it
  * through best_out (may be NULL).  Work is enqueued on `stream` and waited
  * for.  It overwrites only scratch fitness values; the GA state is
  * untouched. */

@@ -1299,8 +1299,22 @@ int gapa_ga_autotune(gapa_ga *ga, int32_t reps, void *stream, gapa_tuning *best_
     const Tuning saved = g->tune;
     Tuning best = saved;
     double best_t = 1e300;
-    const int32_t grids[3] = {2048, 4096, 8192}, scans[3] = {16, 32, 64}, sweeps[3] = {2, 3, 4};
-    const int32_t bands[2] = {4096, 16384};
+    const int32_t grids[4] = {1024, 2048, 4096, 8192}, scans[4] = {8, 16, 32, 64}, sweeps[3] = {2, 3, 4};
+    const int32_t bands[3] = {2048, 4096, 16384};
+    // candidates are timed with events on the stream (no host launch time in the figure)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if ((e = hipEventCreate(&ev0)) != hipSuccess || (e = hipEventCreate(&ev1)) != hipSuccess) {
+        if (ev0) (void)hipEventDestroy(ev0);
+        return fail_handle(&ga->failed, hip_fail(e, "hipEventCreate"));
+    }
+    struct EventPair {
+        hipEvent_t a, b;
+        ~EventPair()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } events{ev0, ev1};
     int rc = GAPA_OK;
     for (int32_t gi : grids)
         for (int32_t sc : scans)
@@ -1314,14 +1328,18 @@ int gapa_ga_autotune(gapa_ga *ga, int32_t reps, void *stream, gapa_tuning *best_
                         g->tune = saved;
                         return fail_handle(&ga->failed, rc);
                     }
-                    const auto t0 = std::chrono::steady_clock::now();
+                    if ((e = hipEventRecord(ev0, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
                     for (int32_t r = 0; r < reps && rc == GAPA_OK; ++r) rc = ga_eval_children(ga, init, s);
-                    if (rc == GAPA_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = hip_fail(e, "sync");
+                    if (rc == GAPA_OK && (e = hipEventRecord(ev1, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+                    if (rc == GAPA_OK && (e = hipEventSynchronize(ev1)) != hipSuccess) rc = hip_fail(e, "sync");
+                    float ms = 0.f;
+                    if (rc == GAPA_OK && (e = hipEventElapsedTime(&ms, ev0, ev1)) != hipSuccess)
+                        rc = hip_fail(e, "hipEventElapsedTime");
                     if (rc != GAPA_OK) {
                         g->tune = saved;
                         return fail_handle(&ga->failed, rc);
                     }
-                    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                    const double t = ms;
                     if (t < best_t) {
                         best_t = t;
                         best = g->tune;
