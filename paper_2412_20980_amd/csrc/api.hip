@@ -318,6 +318,17 @@ void release_workspace(FitnessWorkspace &w)
     for (DevBuf *b : {&w.parent, &w.count, &w.dead, &w.reach, &w.ucount, &w.pairs, &w.worklist, &w.small, &w.masks,
                       &w.alive, &w.genes, &w.fitness, &w.mcn, &w.flag, &w.six_mats, &w.six_tot})
         b->release();
+    for (FitnessWorkspace *l : w.lanes) {
+        release_workspace(*l);
+        delete l;
+    }
+    w.lanes.clear();
+    for (hipStream_t st : w.lane_streams) (void)hipStreamDestroy(st);
+    w.lane_streams.clear();
+    for (hipEvent_t ev : w.lane_done) (void)hipEventDestroy(ev);
+    w.lane_done.clear();
+    if (w.fork) (void)hipEventDestroy(w.fork);
+    w.fork = nullptr;
     w.stats_ctr = nullptr;
 }
 

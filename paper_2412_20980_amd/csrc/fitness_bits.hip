@@ -653,24 +653,21 @@ int launch_bits_transpose(const uint32_t *masks, int32_t P, int32_t W, int32_t n
     return GAPA_OK;
 }
 
-int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
-                    int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it)
+namespace {
+
+// Slot layout of one pass: Wd words per node row, B = 32 Wd slots per
+// instance, S slots in all.
+struct PassShape {
+    int32_t Wd, log_wd, B, S;
+    bool multi;
+};
+
+int reserve_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, hipStream_t s)
 {
-    const bool multi = it && it->count > 1;
-    if (!multi && P <= 0) return GAPA_OK;
-    const int32_t n = g->n, W = g->words;
-    // chunk width: 32 * Wd slots per instance, Wd a power of two <= 32
-    int32_t Wd = 1;
-    if (multi) Wd = it->bseg / 32;
-    else
-        while (Wd < 32 && Wd * 32 < P) Wd <<= 1;
-    int32_t log_wd = 0;
-    while ((1 << log_wd) < Wd) ++log_wd;
-    const int32_t B = Wd * 32;
-    const int32_t S = multi ? it->count * B : B;  // slots of one pass
+    const int32_t n = g->n, B = sh.B;
     int rc;
-    if ((rc = ws.dead.reserve((size_t)n * Wd * 4)) != GAPA_OK) return rc;
-    if ((rc = ws.reach.reserve((size_t)n * Wd * 4)) != GAPA_OK) return rc;
+    if ((rc = ws.dead.reserve((size_t)n * sh.Wd * 4)) != GAPA_OK) return rc;
+    if ((rc = ws.reach.reserve((size_t)n * sh.Wd * 4)) != GAPA_OK) return rc;
     if ((rc = ws.parent.reserve((size_t)B * n * 4)) != GAPA_OK) return rc;
     if (ws.ucount.bytes < (size_t)B * n * 4) {
         if ((rc = ws.ucount.reserve((size_t)B * n * 4)) != GAPA_OK) return rc;
@@ -680,10 +677,21 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
     const int64_t max_pairs = (int64_t)B * std::max(g->n_noniso, 1);
     if ((rc = ws.pairs.reserve((size_t)max_pairs * 8)) != GAPA_OK) return rc;
     if ((rc = ws.worklist.reserve((size_t)std::max(g->n_noniso, 1) * 4)) != GAPA_OK) return rc;
+    const size_t nparts = sh.multi ? 0 : (size_t)g->tune.sweep_grid * B;
+    if ((rc = ws.small.reserve((size_t)(2 * (size_t)sh.S + 64 + nparts) * 4)) != GAPA_OK) return rc;
+    return GAPA_OK;
+}
+
+// One pass over the slots [c0, c0 + B) of a single instance, or over every
+// instance (multi), with workspace ws on stream s.
+int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const InstTable *it, const uint32_t *masks,
+             const int32_t *alive, int32_t P, int32_t c0, int64_t *fitness, int32_t *mcn, KernelTimer *timer,
+             hipStream_t s)
+{
+    const int32_t n = g->n, W = g->words, Wd = sh.Wd, log_wd = sh.log_wd, B = sh.B, S = sh.S;
+    const bool multi = sh.multi;
     const Tuning &tu = g->tune;
     const int32_t grid = tu.sweep_grid;
-    const size_t nparts = multi ? 0 : (size_t)grid * B;
-    if ((rc = ws.small.reserve((size_t)(2 * (size_t)S + 64 + nparts) * 4)) != GAPA_OK) return rc;
     int32_t *root = ws.small.as<int32_t>();
     int32_t *other = root + S;
     int32_t *ctr = root + 2 * S;  // [0] worklist count, [1] pair count, [2..] changed flags
@@ -695,12 +703,9 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
     int32_t *parent = ws.parent.as<int32_t>(), *ucount = ws.ucount.as<int32_t>();
     int64_t *pairs = ws.pairs.as<int64_t>();
     int32_t *worklist = ws.worklist.as<int32_t>();
-
     const int32_t nb = (int32_t)g->band_off.size() - 1;
     const int32_t noniso = g->n_noniso;
-    const int32_t chunks = multi ? 1 : (P + B - 1) / B;
-    for (int32_t c = 0; c < chunks; ++c) {
-        const int32_t c0 = c * B;
+    {
         Insts I{};
         if (multi) {
             I = Insts{it->count, B, 0, 0, it->voff, it->live, it->moff, it->node_inst, it->tiles};
@@ -776,6 +781,81 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         }
         GAPA_HIP(hipGetLastError());
     }
+    return GAPA_OK;
+}
+
+}  // namespace
+
+// Extra lanes of a workspace: chunks of a population wider than one pass run
+// concurrently on their own streams and workspaces (the pass is bound by its
+// chain of dependent kernels, not by bandwidth, so chunks side by side
+// overlap well).  Created on first use, before any graph capture.
+constexpr int kPassLanes = 4;
+
+int ensure_lanes(FitnessWorkspace &ws, int32_t lanes)
+{
+    if (!ws.fork) GAPA_HIP(hipEventCreateWithFlags(&ws.fork, hipEventDisableTiming));
+    while ((int32_t)ws.lanes.size() < lanes - 1) {
+        FitnessWorkspace *w = new (std::nothrow) FitnessWorkspace();
+        if (!w) return GAPA_E_OOM;
+        ws.lanes.push_back(w);
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        GAPA_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        ws.lane_streams.push_back(st);
+        GAPA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        ws.lane_done.push_back(ev);
+    }
+    return GAPA_OK;
+}
+
+int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
+                    int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it)
+{
+    const bool multi = it && it->count > 1;
+    if (!multi && P <= 0) return GAPA_OK;
+    // chunk width: 32 * Wd slots per instance, Wd a power of two <= 32
+    PassShape sh{};
+    sh.multi = multi;
+    sh.Wd = 1;
+    if (multi) sh.Wd = it->bseg / 32;
+    else
+        while (sh.Wd < 32 && sh.Wd * 32 < P) sh.Wd <<= 1;
+    sh.log_wd = 0;
+    while ((1 << sh.log_wd) < sh.Wd) ++sh.log_wd;
+    sh.B = sh.Wd * 32;
+    sh.S = multi ? it->count * sh.B : sh.B;
+    const int32_t chunks = multi ? 1 : (P + sh.B - 1) / sh.B;
+    const int32_t lanes = std::min(chunks, kPassLanes);
+    int rc;
+    if (lanes <= 1) {
+        if ((rc = reserve_pass(g, ws, sh, s)) != GAPA_OK) return rc;
+        for (int32_t c = 0; c < chunks; ++c)
+            if ((rc = run_pass(g, ws, sh, it, masks, alive, P, c * sh.B, fitness, mcn, timer, s)) != GAPA_OK)
+                return rc;
+        return GAPA_OK;
+    }
+    if ((rc = ensure_lanes(ws, lanes)) != GAPA_OK) return rc;
+    auto lane_ws = [&](int32_t i) -> FitnessWorkspace & { return i == 0 ? ws : *ws.lanes[i - 1]; };
+    auto lane_stream = [&](int32_t i) { return i == 0 ? s : ws.lane_streams[i - 1]; };
+    // fork: every lane starts after the work already on s
+    GAPA_HIP(hipEventRecord(ws.fork, s));
+    for (int32_t i = 1; i < lanes; ++i) GAPA_HIP(hipStreamWaitEvent(lane_stream(i), ws.fork, 0));
+    for (int32_t i = 0; i < lanes; ++i)
+        if ((rc = reserve_pass(g, lane_ws(i), sh, lane_stream(i))) != GAPA_OK) return rc;
+    for (int32_t c = 0; c < chunks; ++c) {
+        const int32_t i = c % lanes;
+        if ((rc = run_pass(g, lane_ws(i), sh, it, masks, alive, P, c * sh.B, fitness, mcn, timer, lane_stream(i))) !=
+            GAPA_OK)
+            return rc;
+    }
+    // join: s continues once every lane is done
+    for (int32_t i = 1; i < lanes; ++i) {
+        GAPA_HIP(hipEventRecord(ws.lane_done[i - 1], lane_stream(i)));
+        GAPA_HIP(hipStreamWaitEvent(s, ws.lane_done[i - 1], 0));
+    }
+    ws.stats_ctr = ws.small.as<int32_t>() + 2 * sh.S;
+    ws.stats_B = sh.S;
     return GAPA_OK;
 }
 

@@ -99,6 +99,12 @@ struct FitnessWorkspace {
     DevBuf flag;     // int32 [4]     device error flags
     DevBuf six_mats; // int8 [3][chunk][n_pad][n_pad] dense reachability matrices
     DevBuf six_tot;  // uint64 [chunk] their entry sums
+    // extra lanes (owned): chunks of a population wider than one pass run
+    // side by side, each with its own workspace and stream
+    std::vector<FitnessWorkspace *> lanes;
+    std::vector<hipStream_t> lane_streams;
+    std::vector<hipEvent_t> lane_done;
+    hipEvent_t fork = nullptr;
 };
 
 // Launch shapes of the bit-parallel fitness pass (results do not depend on
