@@ -374,6 +374,9 @@ def main():
                     "recorded HIP graph")
     ap.add_argument("--no-time-to-target", action="store_true", help="skip the surrogate time-to-target runs")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes of the fitness pass")
+    ap.add_argument("--tuning", default=None,
+                    help="sweep_grid,band_scan,sweeps,band_blocks: use these launch shapes instead of autotuning "
+                         "(profiling runs pin the shapes the autotuner picks)")
     ap.add_argument("--ttt-seeds", default="0", help="comma-separated seeds of the time-to-target runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -422,7 +425,12 @@ def main():
     ga.step(args.warmup, stream=stream)
     torch.cuda.synchronize()
     # launch shapes of the fitness pass, chosen on the warmed-up population
-    tuning = graph.get_tuning() if args.no_autotune else ga.autotune(reps=3, stream=stream)
+    if args.tuning:
+        sg, bs, sw, bb = (int(x) for x in args.tuning.split(","))
+        graph.set_tuning(sweep_grid=sg, band_scan=bs, sweeps=sw, band_blocks=bb)
+        tuning = graph.get_tuning()
+    else:
+        tuning = graph.get_tuning() if args.no_autotune else ga.autotune(reps=3, stream=stream)
     ga.step(2, stream=stream)  # one eager generation re-records the replayed one with the new shapes
     torch.cuda.synchronize()
     args.warmup += 2
