@@ -164,9 +164,10 @@ typedef struct gapa_params {
     int32_t reserved; /* 0 */
 } gapa_params;
 
-/* Creates the GA on graph g (g must outlive it): draws the initial population
- * (eq. 2), evaluates it and orders it by (PC, index): generation 0.  The work
- * is enqueued on `stream`; the call returns once it is enqueued. */
+/* Creates the GA on graph g (the GA holds a reference to g): draws the
+ * initial population (eq. 2), evaluates it and orders it by (fitness,
+ * index): generation 0.  The work is enqueued on `stream`; the call returns
+ * once it is enqueued. */
 GAPA_API int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **out);
 
 /* Runs n_generations >= 0 further generations, each: tournament selection,
@@ -324,19 +325,21 @@ GAPA_API int gapa_surrogate_tensor(gapa_ga *ga, int32_t which, int32_t kind, flo
  *
  * count      1 <= count <= 4096 instances
  * graphs     [count] graph handles on the current device (the same handle may
- *            appear several times); each must outlive the batch.  Their
- *            disjoint union is built once on the device (sum of n <= 2^30).
+ *            appear several times).  Their disjoint union is built once on
+ *            the device (sum of n <= 2^30); the batch keeps its own
+ *            reference, so the handles may be destroyed before it.
  * params     [count] parameters as for gapa_ga_create, per instance
- *            (max(pop, offspring) <= 1024 for each; flags 0 or
- *            GAPA_GRAPH_REPLAY, taken from params[0] for the whole batch)
+ *            (max(pop, offspring) <= 1024 for each; flags from
+ *            GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN, the same for every
+ *            instance)
  *
  * Instance b evolves exactly as gapa_ga_create(graphs[b], &params[b]) and
  * its generation steps would alone: same draws, same populations, same
  * fitness, generation by generation.  One generation of the batch is one
  * operator launch over all instances' offspring, one bit-parallel fitness
  * pass over all of them and one elitism launch.  Enqueue semantics and
- * host-pointer waits are those of the single-GA calls; idx selects an
- * instance (0 <= idx < count).
+ * host-pointer waits are those of the single-GA calls (gapa_batch_record as
+ * gapa_ga_record); idx selects an instance (0 <= idx < count).
  * ------------------------------------------------------------------------- */
 GAPA_API int gapa_batch_create(int32_t count, gapa_graph *const *graphs, const gapa_params *params, void *stream,
                                gapa_batch **out);
