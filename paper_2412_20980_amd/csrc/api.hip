@@ -279,7 +279,8 @@ void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, const std:
               [&](int32_t a, int32_t b) { return level[a] != level[b] ? level[a] < level[b] : a < b; });
     // Bands: level 0 (the sources) alone; later levels joined until a band
     // holds kMinBand nodes, so that sparse tail levels do not each cost a
-    // launch; at most kMaxBands bands.
+    // launch (a last remainder below kMinBand joins the band before it); at
+    // most kMaxBands bands.
     std::vector<int32_t> lev_count(nlev, 0);
     for (int32_t v : band_v) ++lev_count[level[v]];
     band_off.assign(1, 0);
@@ -292,7 +293,11 @@ void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, const std:
             cur = 0;
         }
     }
-    if (band_off.back() != acc) band_off.push_back(acc);
+    if (band_off.back() != acc) {
+        // a sparse tail joins the band before it (unless that is the sources)
+        if (band_off.size() > 2 && cur < kMinBand) band_off.back() = acc;
+        else band_off.push_back(acc);
+    }
     while ((int32_t)band_off.size() - 1 > kMaxBands) {  // merge the two smallest neighbours
         size_t best = 1;
         int32_t best_size = INT32_MAX;
