@@ -81,6 +81,16 @@ def measured_traffic(workload: str):
     return t
 
 
+def traffic_shapes(t):
+    """Launch shapes the counter runs pinned (their --tuning argument), for
+    comparison with the shapes this run's autotuner chose."""
+    if not t:
+        return None
+    cmd = t.get("command", "")
+    i = cmd.find("--tuning ")
+    return cmd[i + len("--tuning "):].split()[0] if i >= 0 else None
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     """The oracle as it stands, on this host's cores, over a bounded sample of
     the same workload: generation 0 plus as many generations as fit in the
@@ -496,6 +506,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["bytes_per_pass"] if traffic else None,
                      "traffic_GBs": traffic["bytes_per_pass"] / (avg_ms * 1e-3) / 1e9 if traffic else None,
+                     "traffic_profiled_shapes": traffic_shapes(traffic),
                      "avg_launch_ms": avg_ms, "launches": f_launches,
                      "algorithmic_bytes_per_unit": unit_bytes, "units_per_launch": per_launch},
         "operator_ms_per_step": {k: v[1] / args.steps for k, v in sorted(passes.items()) if k != "fitness_pass"},
