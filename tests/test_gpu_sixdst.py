@@ -72,3 +72,24 @@ def test_errors(gp):
     # everything removed: no pairs, no surviving row
     pc, mcn = graph.sixdst(np.arange(100, dtype=np.int32)[None, :], 6)
     assert int(pc[0]) == 0 and int(mcn[0]) == 0
+
+
+def test_tiny_graphs_empty_rows_and_huge_hop_counts(gp):
+    class G:  # CSR of a path on n nodes
+        def __init__(self, n):
+            self.n = n
+            adj = [[u for u in (v - 1, v + 1) if 0 <= u < n] for v in range(n)]
+            self.row_ptr = np.array([0] + list(np.cumsum([len(a) for a in adj])), dtype=np.int32)
+            self.col_idx = np.array([u for a in adj for u in a], dtype=np.int32)
+            self.nnz = int(self.row_ptr[-1])
+    for n in (1, 2, 3, 130):
+        g = G(n)
+        graph = gp.Graph(g.n, g.row_ptr, g.col_idx)
+        empty = np.zeros((3, 0), dtype=np.int32)
+        for hops in (1, 6, 10 ** 9):
+            pc, mcn = graph.sixdst(empty, hops)
+            ref = O.sixdst(g, [], min(hops, n))
+            assert all((int(pc[i]), int(mcn[i])) == ref for i in range(3)), (n, hops)
+        if n > 1:
+            pc, mcn = graph.sixdst(np.array([[n // 2]], dtype=np.int32), 10 ** 9)
+            assert (int(pc[0]), int(mcn[0])) == O.pc(g, [n // 2])
