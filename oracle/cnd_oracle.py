@@ -49,6 +49,8 @@ def lib():
             for fn in (L.oracle_pc_bfs, L.oracle_pc_unionfind):
                 fn.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_int32, i32p]
                 fn.restype = C.c_int64
+            L.oracle_components.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_int32, i32p]
+            L.oracle_components.restype = C.c_int64
             L.oracle_eval_population.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_int32, C.c_int32, i64p, i32p, C.c_int32]
             L.oracle_eval_population.restype = C.c_int64
             pp = C.POINTER(OracleParams)
@@ -123,6 +125,18 @@ def pc(graph, genes, method: str = "bfs") -> tuple[int, int]:
     return int(val), int(mcn.value)
 
 
+def components(graph, genes) -> tuple[int, int]:
+    """(number of connected components of G - S, |V minus S|) for the nodes
+    in ``genes`` removed; isolated survivors are components of their own."""
+    g = _i32(genes).ravel()
+    alive = C.c_int32(0)
+    val = lib().oracle_components(graph.n, _p(graph.row_ptr, C.c_int32), _p(graph.col_idx, C.c_int32),
+                                  _p(g, C.c_int32), int(g.shape[0]), C.byref(alive))
+    if val < 0:
+        raise ValueError("gene out of range")
+    return int(val), int(alive.value)
+
+
 def eval_population(graph, genes: np.ndarray, nthreads: int | None = None, want_mcn: bool = False):
     G = _i32(genes)
     P, k = G.shape
@@ -176,7 +190,7 @@ def sixdst(graph, genes, hops: int) -> tuple[int, int]:
 
 # --- genetic algorithm --------------------------------------------------------
 
-OBJECTIVES = {"pc": 0, "mcn": 1}
+OBJECTIVES = {"pc": 0, "mcn": 1, "components": 2}
 
 
 def make_params(n, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, objective="pc") -> OracleParams:
@@ -187,8 +201,10 @@ def make_params(n, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, obj
 class OracleGA:
     """The GA run on the host: generation 0 at construction, ``step()`` for
     each further generation.  ``pop`` is [P, k] int32 and ``F`` [P] int64,
-    ordered by (F, tag).  F is PC, or with objective="mcn" the largest
-    surviving component (the CND fitness of Sec. III-D)."""
+    ordered by (F, tag).  F is PC; with objective="mcn" the largest
+    surviving component (the CND fitness of Sec. III-D); with
+    objective="components" |V minus S| minus the number of components of
+    G - S, so that minimising F maximises the number of components."""
 
     def __init__(self, graph, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, nthreads=None,
                  objective="pc"):

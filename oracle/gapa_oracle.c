@@ -173,6 +173,46 @@ done:
     return pc;
 }
 
+/* Number of connected components of G - S (every surviving node, isolated
+ * ones included, lies in exactly one), by breadth-first search from every
+ * unvisited survivor; *survivors_out receives |V minus S|.  genes: k node ids
+ * (repeated ids are one removal).  Returns -1 if a gene is out of range. */
+int64_t oracle_components(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                          const int32_t *genes, int32_t k, int32_t *survivors_out)
+{
+    uint8_t *removed = (uint8_t *)calloc((size_t)n, 1);
+    uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+    int32_t *queue = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int64_t count = 0;
+    int32_t survivors = n;
+    for (int32_t j = 0; j < k; ++j) {
+        if (genes[j] < 0 || genes[j] >= n) { count = -1; goto done; }
+        if (!removed[genes[j]]) --survivors;
+        removed[genes[j]] = 1;
+    }
+    for (int32_t s = 0; s < n; ++s) {
+        if (removed[s] || seen[s]) continue;
+        int32_t head = 0, tail = 0;
+        queue[tail++] = s;
+        seen[s] = 1;
+        while (head < tail) {
+            int32_t v = queue[head++];
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                int32_t u = col_idx[e];
+                if (!removed[u] && !seen[u]) {
+                    seen[u] = 1;
+                    queue[tail++] = u;
+                }
+            }
+        }
+        ++count;
+    }
+done:
+    if (survivors_out) *survivors_out = survivors;
+    free(removed); free(seen); free(queue);
+    return count;
+}
+
 static int32_t uf_find(int32_t *parent, int32_t x)
 {
     while (parent[x] != x) {
@@ -252,7 +292,9 @@ typedef struct {
     int32_t pop;        /* P: parents kept by elitism */
     int32_t offspring;  /* lambda: children made per generation */
     int32_t tournament; /* T: contestants per tournament */
-    int32_t objective;  /* 0: minimise PC; 1: minimise MCN (the CND fitness of Sec. III-D) */
+    int32_t objective;  /* 0: minimise PC; 1: minimise MCN (the CND fitness of Sec. III-D);
+                           2: maximise the number of components NC, as minimising
+                           |V minus S| - NC */
     uint64_t seed;
     uint64_t t_pc;      /* crossover threshold, floor(pc * 2^32) */
     uint64_t t_pm;      /* mutation threshold, floor(pm * 2^32) */
@@ -397,11 +439,23 @@ static int cmp_fkey(const void *a, const void *b)
     return (x->tag > y->tag) - (x->tag < y->tag);
 }
 
-/* The GA's fitness of P rows: PC, or with objective 1 the largest surviving
- * component (MCN). */
+/* The GA's fitness of P rows: PC; with objective 1 the largest surviving
+ * component (MCN); with objective 2 the survivors minus the number of
+ * components (smallest when G - S falls into the most pieces). */
 static int eval_objective(const oracle_params *p, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                           const int32_t *rows, int32_t P, int32_t k, int64_t *f, int32_t nthreads)
 {
+    if (p->objective == 2) {
+        int bad = 0;
+        for (int32_t i = 0; i < P; ++i) {
+            int32_t alive = 0;
+            const int64_t nc = oracle_components(n, row_ptr, col_idx, rows + (int64_t)i * k, k, &alive);
+            if (nc < 0) bad = 1;
+            f[i] = alive - nc;
+        }
+        (void)nthreads;
+        return bad ? -1 : 0;
+    }
     if (p->objective != 1) return oracle_eval_population(n, row_ptr, col_idx, rows, P, k, f, NULL, nthreads);
     int32_t *mcn = (int32_t *)malloc((size_t)(P > 0 ? P : 1) * sizeof(int32_t));
     if (!mcn) return -1;
