@@ -78,11 +78,21 @@ enum {
                                    (same results; fewer launch gaps).  Kernel
                                    timing, when enabled, runs generations
                                    eagerly instead.                             */
-    GAPA_MINIMISE_MCN = 1u << 5 /* gapa_params.flags: the GA minimises the
+    GAPA_MINIMISE_MCN = 1u << 5, /* gapa_params.flags: the GA minimises the
                                    largest surviving component (MCN, the CND
                                    fitness of Section III-D) instead of PC: the
                                    fitness arrays then hold MCN.  Not with a
                                    surrogate.                                   */
+    GAPA_MAXIMISE_COMPONENTS = 1u << 6 /* gapa_params.flags, and the flags of
+                                   gapa_eval_population: the objective is the
+                                   number NC of connected components of G - S,
+                                   read off the same partition as PC and MCN
+                                   (an extension; the paper reports PC and MCN).
+                                   Fitness values then hold |V minus S| - NC =
+                                   sum over components of (|C| - 1), the size
+                                   of a spanning forest of G - S, which the GA
+                                   minimises (most components first).  Not with
+                                   GAPA_MINIMISE_MCN nor a surrogate.           */
 };
 
 /* ---------------------------------------------------------------------------
@@ -108,7 +118,8 @@ GAPA_API int gapa_graph_destroy(gapa_graph *g);
  *
  * genes:   int32 [P][k] row-major node ids, any order within a row; a repeated
  *          id in a row is one removal (set semantics).
- * fitness: int64 [P] out, PC of each row.
+ * fitness: int64 [P] out, PC of each row (with GAPA_MAXIMISE_COMPONENTS:
+ *          the row's survivors minus the components of G - S).
  * mcn:     int32 [P] out or NULL; written only with GAPA_WANT_MCN.
  * An id outside [0, n) gives GAPA_E_BAD_GENE (with GAPA_DEVICE_PTRS the check
  * runs on the device and the call waits for it unless GAPA_TRUST_INPUT).
@@ -160,7 +171,8 @@ typedef struct gapa_params {
     uint64_t seed;
     double pc;
     double pm;
-    uint32_t flags;   /* 0 or GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN */
+    uint32_t flags;   /* 0 or GAPA_GRAPH_REPLAY, with at most one of
+                         GAPA_MINIMISE_MCN and GAPA_MAXIMISE_COMPONENTS */
     int32_t reserved; /* 0 */
 } gapa_params;
 
@@ -330,8 +342,8 @@ GAPA_API int gapa_surrogate_tensor(gapa_ga *ga, int32_t which, int32_t kind, flo
  *            reference, so the handles may be destroyed before it.
  * params     [count] parameters as for gapa_ga_create, per instance
  *            (max(pop, offspring) <= 1024 for each; flags from
- *            GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN, the same for every
- *            instance)
+ *            GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN | GAPA_MAXIMISE_COMPONENTS,
+ *            the same for every instance)
  *
  * Instance b evolves exactly as gapa_ga_create(graphs[b], &params[b]) and
  * its generation steps would alone: same draws, same populations, same

@@ -520,6 +520,7 @@ int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t
     const bool dev_ptrs = flags & GAPA_DEVICE_PTRS;
     const bool trust = flags & GAPA_TRUST_INPUT;
     const bool want_mcn = (flags & GAPA_WANT_MCN) && mcn;
+    const Measure measure = (flags & GAPA_MAXIMISE_COMPONENTS) ? kMeasureForest : kMeasurePC;
     if (!dev_ptrs && !trust) {
         for (int64_t i = 0; i < (int64_t)P * k; ++i) {
             if (genes[i] < 0 || genes[i] >= g->n) {
@@ -552,7 +553,8 @@ int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t
         d_mcn = want_mcn ? w.mcn.as<int32_t>() : nullptr;
     }
     if ((rc = launch_fill_u32(w.flag.ptr, 0u, 4, s)) != GAPA_OK) return fail_handle(&g->failed, rc);
-    if ((rc = eval_genes(g, d_genes, P, k, d_fit, d_mcn, w.flag.as<int32_t>(), w, &g->timer, s)) != GAPA_OK)
+    if ((rc = eval_genes(g, d_genes, P, k, d_fit, d_mcn, w.flag.as<int32_t>(), w, &g->timer, s, measure)) !=
+        GAPA_OK)
         return fail_handle(&g->failed, rc);
     if (dev_ptrs && trust) return GAPA_OK;
     int32_t hflag[4] = {0, 0, 0, 0};
@@ -694,7 +696,10 @@ bool params_ok(const gapa_params *p, int32_t n)
 {
     return p->k >= 1 && p->k <= n / 2 && p->pop >= 1 && p->tournament >= 1 && p->tournament <= 64 &&
            p->offspring >= 0 && p->pc >= 0.0 && p->pc <= 1.0 && p->pm >= 0.0 && p->pm <= 1.0 &&
-           (p->flags & ~(uint32_t)(GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN)) == 0 && p->reserved == 0;
+           (p->flags & ~(uint32_t)(GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN | GAPA_MAXIMISE_COMPONENTS)) == 0 &&
+           (p->flags & (GAPA_MINIMISE_MCN | GAPA_MAXIMISE_COMPONENTS)) !=
+               (uint32_t)(GAPA_MINIMISE_MCN | GAPA_MAXIMISE_COMPONENTS) &&
+           p->reserved == 0;
 }
 
 // Fills the instance table and sizes every buffer of a GA over `count`
@@ -768,6 +773,7 @@ int ga_allocate(gapa_ga *ga, int32_t count, const gapa_params *p, const int32_t 
     if (rc == GAPA_OK) rc = ga->child_fit.reserve((size_t)slots * 8);
     ga->slots = slots;
     ga->objective_mcn = (p[0].flags & GAPA_MINIMISE_MCN) != 0;
+    ga->objective_forest = (p[0].flags & GAPA_MAXIMISE_COMPONENTS) != 0;
     if (rc == GAPA_OK && ga->objective_mcn) rc = ga->child_mcn.reserve((size_t)slots * 4);
     if (rc == GAPA_OK) rc = ga->masks.reserve((size_t)mask_w * 4);
     if (rc == GAPA_OK) rc = ga->alive.reserve((size_t)slots * 4);
@@ -1005,7 +1011,8 @@ int gapa_ga_create(gapa_graph *g, const gapa_params *p, void *stream, gapa_ga **
     }
     if (!params_ok(p, g->n)) {
         set_error("invalid GA parameters (need 1 <= k <= n/2, pop >= 1, 1 <= T <= 64, pc, pm in [0, 1], "
-                  "flags from GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN)");
+                  "flags from GAPA_GRAPH_REPLAY | GAPA_MINIMISE_MCN | GAPA_MAXIMISE_COMPONENTS, at most one "
+                  "objective)");
         return GAPA_E_INVALID_ARG;
     }
     DeviceGuard dg(g->device);

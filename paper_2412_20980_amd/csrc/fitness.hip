@@ -168,10 +168,11 @@ __global__ void k_cc_count(int32_t *__restrict__ parent, const uint32_t *__restr
     atomicAdd(count + (int64_t)b * n + r, 1);
 }
 
-// PC and MCN of each individual from its root counts; clears the counts for
-// the next chunk.  Grid: (slices, B); fitness/mcn zeroed beforehand.
+// PC (or with `forest` the sum of |C| - 1) and MCN of each individual from its
+// root counts; clears the counts for the next chunk.  Grid: (slices, B);
+// fitness/mcn zeroed beforehand.
 __global__ void k_cc_reduce(int32_t *__restrict__ count, int32_t n, unsigned long long *__restrict__ fitness,
-                            int32_t *__restrict__ mcn)
+                            int32_t *__restrict__ mcn, int32_t forest)
 {
     const int32_t b = blockIdx.y;
     int32_t *cb = count + (int64_t)b * n;
@@ -180,7 +181,7 @@ __global__ void k_cc_reduce(int32_t *__restrict__ count, int32_t n, unsigned lon
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t s = cb[v];
         if (s) {
-            acc += (unsigned long long)s * (unsigned long long)(s - 1) / 2ull;
+            acc += forest ? (unsigned long long)(s - 1) : (unsigned long long)s * (unsigned long long)(s - 1) / 2ull;
             big = s > big ? s : big;
             cb[v] = 0;
         }
@@ -245,19 +246,19 @@ int launch_mask_build(const int32_t *genes, int32_t P, int32_t k, int32_t n, int
 }
 
 int eval_masks(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness, int32_t *mcn,
-               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it)
+               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it, Measure measure)
 {
     if (it && it->count > 1) {
         if (g->algorithm != 0) return GAPA_E_INVALID_ARG;
-        return eval_masks_bits(g, masks, alive, P, fitness, mcn, ws, timer, s, it);
+        return eval_masks_bits(g, masks, alive, P, fitness, mcn, ws, timer, s, it, measure);
     }
     if (P <= 0) return GAPA_OK;
-    if (g->algorithm == 1) return eval_masks_unionfind(g, masks, P, fitness, mcn, ws, timer, s);
-    return eval_masks_bits(g, masks, alive, P, fitness, mcn, ws, timer, s);
+    if (g->algorithm == 1) return eval_masks_unionfind(g, masks, P, fitness, mcn, ws, timer, s, measure);
+    return eval_masks_bits(g, masks, alive, P, fitness, mcn, ws, timer, s, nullptr, measure);
 }
 
 int eval_genes(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int64_t *fitness, int32_t *mcn,
-               int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
+               int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, Measure measure)
 {
     if (P <= 0) return GAPA_OK;
     int rc;
@@ -269,11 +270,12 @@ int eval_genes(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int64_
                                     ws.alive.as<int32_t>(), flag, s)) != GAPA_OK)
             return rc;
     }
-    return eval_masks(g, ws.masks.as<uint32_t>(), ws.alive.as<int32_t>(), P, fitness, mcn, ws, timer, s);
+    return eval_masks(g, ws.masks.as<uint32_t>(), ws.alive.as<int32_t>(), P, fitness, mcn, ws, timer, s, nullptr,
+                      measure);
 }
 
 int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,
-                         FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s)
+                         FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, Measure measure)
 {
     if (P <= 0) return GAPA_OK;
     const int32_t n = g->n, W = g->words;
@@ -313,7 +315,8 @@ int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_
             TimedScope ts(timer, "cc_reduce", s);
             const int slices = std::max(1, std::min(64, (n + kBlock * 8 - 1) / (kBlock * 8)));
             hipLaunchKernelGGL(k_cc_reduce, dim3(slices, nb), dim3(kBlock), 0, s, count, n,
-                               reinterpret_cast<unsigned long long *>(fitness + c0), mcn ? mcn + c0 : nullptr);
+                               reinterpret_cast<unsigned long long *>(fitness + c0), mcn ? mcn + c0 : nullptr,
+                               (int32_t)measure);
         }
         GAPA_HIP(hipGetLastError());
     }

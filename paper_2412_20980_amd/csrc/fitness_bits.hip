@@ -575,9 +575,11 @@ __global__ void k_pairs_count(const int64_t *__restrict__ pairs, const int32_t *
     }
 }
 
-__device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit, int32_t *mcn)
+// A component of s nodes adds s(s - 1)/2 to PC, or s - 1 with `forest`.
+__device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit, int32_t *mcn, int32_t forest)
 {
-    if (s > 1) atomicAdd(fit, (unsigned long long)s * (unsigned long long)(s - 1) / 2ull);
+    if (s > 1)
+        atomicAdd(fit, forest ? (unsigned long long)(s - 1) : (unsigned long long)s * (unsigned long long)(s - 1) / 2ull);
     if (mcn && s > 0) atomicMax(mcn, (int32_t)s);
 }
 
@@ -587,7 +589,7 @@ __device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit
 __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, const Insts I,
                                int32_t *__restrict__ parent, const int32_t *__restrict__ root,
                                int32_t *__restrict__ ucount, int32_t *__restrict__ other,
-                               unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn)
+                               unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest)
 {
     const int32_t count = *pair_count;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
@@ -600,7 +602,7 @@ __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t 
         const int32_t s = ucount[blk + vl];
         ucount[blk + vl] = 0;
         atomicAdd(other + gi, s);
-        add_component(s, fitness + gi, mcn ? mcn + gi : nullptr);
+        add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
     }
 }
 
@@ -626,7 +628,7 @@ __global__ void k_single_sum(const int32_t *__restrict__ single_part, const int3
 __global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, int32_t *__restrict__ parent,
                              const int32_t *__restrict__ alive_noniso, const int32_t *__restrict__ other,
                              const int32_t *__restrict__ row_ptr, int32_t *__restrict__ ucount,
-                             unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn)
+                             unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest)
 {
     const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= I.count * I.bseg || root[gi] < 0) return;
@@ -635,7 +637,7 @@ __global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, in
     const int64_t blk = uf_block(I, gi);
     ucount[blk + uf_find(parent + blk, r - off)] = 0;
     const int64_t s = row_ptr[r + 1] > row_ptr[r] ? (int64_t)alive_noniso[gi] - other[gi] : 1;
-    add_component(s, fitness + gi, mcn ? mcn + gi : nullptr);
+    add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
 }
 
 }  // namespace
@@ -685,8 +687,8 @@ int reserve_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, hipSt
 // One pass over the slots [c0, c0 + B) of a single instance, or over every
 // instance (multi), with workspace ws on stream s.
 int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const InstTable *it, const uint32_t *masks,
-             const int32_t *alive, int32_t P, int32_t c0, int64_t *fitness, int32_t *mcn, KernelTimer *timer,
-             hipStream_t s)
+             const int32_t *alive, int32_t P, int32_t c0, int64_t *fitness, int32_t *mcn, Measure measure,
+             KernelTimer *timer, hipStream_t s)
 {
     const int32_t n = g->n, W = g->words, Wd = sh.Wd, log_wd = sh.log_wd, B = sh.B, S = sh.S;
     const bool multi = sh.multi;
@@ -769,7 +771,7 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
         {
             TimedScope ts(timer, "k_pairs_reduce", s);
             hipLaunchKernelGGL(k_pairs_reduce, dim3(grid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, root,
-                               ucount, other, fit, mc);
+                               ucount, other, fit, mc, (int32_t)measure);
         }
         {
             TimedScope ts(timer, "k_root_final", s);
@@ -777,7 +779,7 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
                 hipLaunchKernelGGL(k_single_sum, dim3((B + 63) / 64, (grid + kSumRows - 1) / kSumRows), dim3(64), 0,
                                    s, single_part, wl_count, grid, B, other);
             hipLaunchKernelGGL(k_root_final, dim3((S + 63) / 64), dim3(64), 0, s, root, I, parent, al, other,
-                               g->d_row_ptr, ucount, fit, mc);
+                               g->d_row_ptr, ucount, fit, mc, (int32_t)measure);
         }
         GAPA_HIP(hipGetLastError());
     }
@@ -810,7 +812,8 @@ int ensure_lanes(FitnessWorkspace &ws, int32_t lanes)
 }
 
 int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
-                    int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it)
+                    int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it,
+                    Measure measure)
 {
     const bool multi = it && it->count > 1;
     if (!multi && P <= 0) return GAPA_OK;
@@ -831,7 +834,7 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
     if (lanes <= 1) {
         if ((rc = reserve_pass(g, ws, sh, s)) != GAPA_OK) return rc;
         for (int32_t c = 0; c < chunks; ++c)
-            if ((rc = run_pass(g, ws, sh, it, masks, alive, P, c * sh.B, fitness, mcn, timer, s)) != GAPA_OK)
+            if ((rc = run_pass(g, ws, sh, it, masks, alive, P, c * sh.B, fitness, mcn, measure, timer, s)) != GAPA_OK)
                 return rc;
         return GAPA_OK;
     }
@@ -845,8 +848,8 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         if ((rc = reserve_pass(g, lane_ws(i), sh, lane_stream(i))) != GAPA_OK) return rc;
     for (int32_t c = 0; c < chunks; ++c) {
         const int32_t i = c % lanes;
-        if ((rc = run_pass(g, lane_ws(i), sh, it, masks, alive, P, c * sh.B, fitness, mcn, timer, lane_stream(i))) !=
-            GAPA_OK)
+        if ((rc = run_pass(g, lane_ws(i), sh, it, masks, alive, P, c * sh.B, fitness, mcn, measure, timer,
+                           lane_stream(i))) != GAPA_OK)
             return rc;
     }
     // join: s continues once every lane is done

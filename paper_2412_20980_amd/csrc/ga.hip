@@ -616,13 +616,15 @@ int ga_launch_offspring(gapa_ga *ga, hipStream_t s, bool rows_only)
 int ga_eval_children(gapa_ga *ga, bool init, hipStream_t s)
 {
     int32_t *mcn = ga->objective_mcn ? ga->child_mcn.as<int32_t>() : nullptr;
+    const Measure measure = ga->objective_forest ? kMeasureForest : kMeasurePC;
     int rc;
     if (ga->count > 1)
         rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(), 0, ga->child_fit.as<int64_t>(),
-                        mcn, ga->ws, &ga->timer, s, init ? &ga->tab_init : &ga->tab_gen);
+                        mcn, ga->ws, &ga->timer, s, init ? &ga->tab_init : &ga->tab_gen, measure);
     else
         rc = eval_masks(ga->graph, ga->masks.as<uint32_t>(), ga->alive.as<int32_t>(),
-                        init ? ga->params.pop : ga->lambda, ga->child_fit.as<int64_t>(), mcn, ga->ws, &ga->timer, s);
+                        init ? ga->params.pop : ga->lambda, ga->child_fit.as<int64_t>(), mcn, ga->ws, &ga->timer, s,
+                        nullptr, measure);
     if (rc != GAPA_OK || !mcn) return rc;
     // the objective is MCN: it replaces PC as the fitness of every slot
     hipLaunchKernelGGL(k_mcn_objective, dim3((ga->slots + 255) / 256), dim3(256), 0, s, mcn,

@@ -171,23 +171,29 @@ struct InstTable {
     int32_t ntiles = 0;
 };
 
+// What the fitness sums over the components C of G - S: |C|(|C| - 1)/2
+// (pairwise connectivity), or |C| - 1, whose sum is |V minus S| minus the
+// number of components (the size of a spanning forest of G - S).
+enum Measure : int32_t { kMeasurePC = 0, kMeasureForest = 1 };
+
 // Fitness of P individuals given as removed-node bit sets masks[P][W]
 // (device) with alive[P] = surviving non-isolated nodes of each.  Writes
-// fitness[P] (int64) and, if mcn != nullptr, mcn[P] (int32).  Runs the graph's
-// selected algorithm.
+// fitness[P] (int64, the sum selected by `measure`) and, if mcn != nullptr,
+// mcn[P] (int32).  Runs the graph's selected algorithm.
 // With an instance table of count > 1 (bit-parallel algorithm only), P is
 // ignored and all slots of all instances are evaluated in one pass.
 int eval_masks(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness, int32_t *mcn,
-               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it = nullptr);
+               FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it = nullptr,
+               Measure measure = kMeasurePC);
 int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
                     int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s,
-                    const InstTable *it = nullptr);
+                    const InstTable *it = nullptr, Measure measure = kMeasurePC);
 int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,
-                         FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+                         FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, Measure measure = kMeasurePC);
 // Same from gene rows genes[P][k] (device node ids; a repeated id in a row is
 // one removal); a gene outside [0, n) sets flag[0] and is ignored.
 int eval_genes(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int64_t *fitness, int32_t *mcn,
-               int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s);
+               int32_t *flag, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, Measure measure = kMeasurePC);
 
 // Removed-node bit sets masks[P][W] of P = 32 Wd individuals (Wd a power of
 // two <= 32) to node-major rows rows[n][Wd]: bit i of row v is set when
@@ -290,6 +296,7 @@ struct gapa_ga {
     gapa::DevBuf child_mcn;       // int32 slots (GAPA_MINIMISE_MCN: the pass's MCN, copied into child_fit)
     int32_t slots = 0;
     bool objective_mcn = false;
+    bool objective_forest = false;  // GAPA_MAXIMISE_COMPONENTS: fitness = |V minus S| - components
     gapa::DevBuf masks;           // uint32 removed-node bit sets of the children
     gapa::DevBuf alive;           // int32 slots: surviving non-isolated nodes
     gapa::DevBuf src;             // int32 [sum P] elitism: source tag of each kept row

@@ -1178,7 +1178,7 @@ int read_stats(gapa_ga *ga)
 
 int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s)
 {
-    if (ga->count != 1 || ga->surr || ga->generation != 0 || ga->objective_mcn) {
+    if (ga->count != 1 || ga->surr || ga->generation != 0 || ga->objective_mcn || ga->objective_forest) {
         set_error("a surrogate attaches to a single-instance GA minimising PC at generation 0, once");
         return GAPA_E_INVALID_ARG;
     }

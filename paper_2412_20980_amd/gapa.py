@@ -41,6 +41,7 @@ GAPA_WANT_MCN = 1 << 2
 GAPA_UNIONFIND = 1 << 3
 GAPA_GRAPH_REPLAY = 1 << 4
 GAPA_MINIMISE_MCN = 1 << 5
+GAPA_MAXIMISE_COMPONENTS = 1 << 6
 GAPA_SCREEN_RANDOM = 1 << 0
 SURROGATE_TENSORS = ("E", "W1", "b1", "W2", "b2", "w3", "b3")
 
@@ -267,8 +268,11 @@ class Graph:
     def from_csr(cls, g, trust: bool = False, unionfind: bool = False) -> "Graph":
         return cls(g.n, g.row_ptr, g.col_idx, trust, unionfind)
 
-    def eval(self, genes, want_mcn: bool = False, trust: bool = False, stream=None):
-        flags = (GAPA_WANT_MCN if want_mcn else 0) | (GAPA_TRUST_INPUT if trust else 0)
+    def eval(self, genes, want_mcn: bool = False, trust: bool = False, stream=None, objective: str = "pc"):
+        """PC of each row (objective="components": survivors minus components)."""
+        if objective not in ("pc", "components"):
+            raise ValueError(f"objective must be 'pc' or 'components', not {objective!r}")
+        flags = (GAPA_WANT_MCN if want_mcn else 0) | (GAPA_TRUST_INPUT if trust else 0) | _objective_flag(objective)
         return gapa_eval_population(self.handle, genes, flags=flags, stream=stream)
 
     def sixdst(self, genes, hops: int = 6, trust: bool = False, stream=None):
@@ -342,16 +346,21 @@ def gapa_ga_destroy(h):
     _check(lib().gapa_ga_destroy(h))
 
 
+_OBJECTIVE_FLAGS = {"pc": 0, "mcn": GAPA_MINIMISE_MCN, "components": GAPA_MAXIMISE_COMPONENTS}
+
+
 def _objective_flag(objective: str) -> int:
-    if objective not in ("pc", "mcn"):
-        raise ValueError(f"objective must be 'pc' or 'mcn', not {objective!r}")
-    return GAPA_MINIMISE_MCN if objective == "mcn" else 0
+    if objective not in _OBJECTIVE_FLAGS:
+        raise ValueError(f"objective must be one of {sorted(_OBJECTIVE_FLAGS)}, not {objective!r}")
+    return _OBJECTIVE_FLAGS[objective]
 
 
 class GA:
     """The GA on one graph; generation 0 is drawn and evaluated at creation.
     replay=True records one generation as a HIP graph and replays it;
-    objective="mcn" minimises the largest surviving component instead of PC."""
+    objective="mcn" minimises the largest surviving component instead of PC;
+    objective="components" maximises the number of components (fitness =
+    survivors minus components, minimised)."""
 
     def __init__(self, graph: Graph, k, pop, seed, pc=0.7, pm=0.05, tournament=2, offspring=0, stream=None,
                  replay: bool = False, objective: str = "pc"):
