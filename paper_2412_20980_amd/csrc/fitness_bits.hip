@@ -315,21 +315,24 @@ __device__ __forceinline__ int32_t block_reserve(int32_t mine, int32_t *counter,
 }
 
 constexpr int kCompactRange = 64;   // input items per compaction step
-constexpr int kPendSteps = 8;       // steps per block in k_collect_pending
+constexpr int kPendStepsMax = 8;    // steps per block in k_collect_pending, at most
+constexpr int kPendBlocks = 1536;   // blocks of k_collect_pending aimed at
 
 // Nodes still pending after the ordered sweep -> worklist.  A block owns
-// kPendSteps * kCompactRange nodes, taken kCompactRange at a time; in each
+// steps * kCompactRange nodes, taken kCompactRange at a time; in each
 // step every thread issues the loads of all its (node, word) entries before
 // testing any of them.  Found nodes gather in LDS, and the block reserves its
-// room in the worklist with a single global atomic (atomics on one address
-// serialise: fewer, larger blocks keep them off the critical path).
+// room in the worklist with a single global atomic.  A block's steps run one
+// after another, each waiting on its loads, so blocks are kept short: the
+// host picks steps for about kPendBlocks blocks (at n = 200k two steps, 1.5k
+// blocks, beat eight steps, 390 blocks, and one step, 3k blocks).
 __global__ __launch_bounds__(kBlk) void k_collect_pending(const int32_t *__restrict__ band_v, int32_t count,
-                                                          int32_t Wd, const uint32_t *__restrict__ dead,
+                                                          int32_t steps, int32_t Wd, const uint32_t *__restrict__ dead,
                                                           const uint32_t *__restrict__ reach,
                                                           int32_t *__restrict__ worklist, int32_t *__restrict__ wl_count)
 {
     __shared__ int32_t s_tot, s_base, s_off;
-    __shared__ int32_t s_list[kPendSteps * kCompactRange];
+    __shared__ int32_t s_list[kPendStepsMax * kCompactRange];
     const int w = threadIdx.x & (Wd - 1);
     const uint64_t gmask = group_mask(Wd);
     const int32_t gpb = blockDim.x / Wd;
@@ -338,8 +341,8 @@ __global__ __launch_bounds__(kBlk) void k_collect_pending(const int32_t *__restr
     // iterations per step: kCompactRange / gpb = kCompactRange * Wd / kBlk <= kIter
     constexpr int kIter = kCompactRange * 32 / kBlk;
     const int32_t iters = (kCompactRange + gpb - 1) / gpb;
-    for (int step = 0; step < kPendSteps; ++step) {
-        const int32_t r0 = (blockIdx.x * kPendSteps + step) * kCompactRange;
+    for (int step = 0; step < steps; ++step) {
+        const int32_t r0 = (blockIdx.x * steps + step) * kCompactRange;
         if (r0 >= count) break;  // uniform over the block
         const int32_t r1 = min(count, r0 + kCompactRange);
         uint32_t pend[kIter];
@@ -401,9 +404,9 @@ __global__ void k_pull_worklist(const int32_t *__restrict__ worklist, const int3
 // several instances directly into other[i]).
 // The rest go to the pair list for the union-find (parent[i][v] = v).
 // Padding individuals remove every node, so their bits are never pending.
-// A block takes kPairRange worklist entries at a time: one pass splits every
-// (node, word) entry and keeps the result in registers, one global atomic
-// reserves room, a second pass writes the pairs.
+// A block takes one worklist entry per group at a time: it splits every
+// (node, word) entry, reserves room for the block's pairs with one global
+// atomic, then writes them.
 __device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t gmask,
                                               const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
                                               const uint32_t *__restrict__ dead, const uint32_t *__restrict__ reach,
@@ -429,7 +432,13 @@ __device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t
     multi = pend & nb;
 }
 
-constexpr int kPairRange = 64;  // worklist entries per reservation in k_collect_pairs
+// A block of k_collect_pairs takes one worklist entry per group of Wd lanes
+// (kBlk / Wd entries) at a time.  A range is split with dependent loads (the
+// node, its bits, its neighbours' bits), so the ranges one block takes form a
+// chain: short ranges spread the worklist over more blocks in flight.  At
+// n = 200k, P = 1024 (8 entries per range) the pass took 236 us against 280 us
+// with 64-entry ranges.
+__device__ __forceinline__ int32_t pair_range(int32_t Wd) { return kBlk / Wd; }
 
 __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restrict__ worklist,
                                                         const int32_t *__restrict__ wl_count, int32_t Wd, const Insts I,
@@ -444,51 +453,30 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restric
     __shared__ int32_t s_single[1024];
     const int w = threadIdx.x & (Wd - 1);
     const uint64_t gmask = group_mask(Wd);
-    const int32_t gpb = blockDim.x / Wd;
+    const int32_t range = pair_range(Wd);
     // singleton counts: per-block LDS counters written as a partial row when
     // all slots fit (one instance, at most 1024 slots), else global atomics
     const int32_t B = I.count * I.bseg;
     const bool lds_singles = I.count == 1;
     const int32_t count = *wl_count;
-    if ((int64_t)blockIdx.x * kPairRange >= count) return;  // no range: no partial row (see k_single_sum)
+    if ((int64_t)blockIdx.x * range >= count) return;  // no range: no partial row (see k_single_sum)
     if (lds_singles)
         for (int32_t t = threadIdx.x; t < B; t += blockDim.x) s_single[t] = 0;
     __syncthreads();
-    // entries per thread and range: kPairRange / gpb <= kIter (Wd <= 32)
-    constexpr int kIter = kPairRange * 32 / kBlk;
-    const int32_t iters = (kPairRange + gpb - 1) / gpb;
-    for (int32_t r0 = blockIdx.x * kPairRange; r0 < count; r0 += gridDim.x * kPairRange) {
-        const int32_t r1 = min(count, r0 + kPairRange);
+    for (int32_t r0 = blockIdx.x * range; r0 < count; r0 += gridDim.x * range) {
         // one split per (node, word), kept for the write pass
-        uint32_t multi[kIter];
-        int32_t vv[kIter];
-        int32_t mine = 0;
-#pragma unroll
-        for (int it = 0; it < kIter; ++it) {
-            const int32_t idx = r0 + it * gpb + (int32_t)(threadIdx.x / Wd);
-            const bool valid = it < iters && idx < r1;
-            const int32_t v = valid ? worklist[idx] : 0;
-            vv[it] = v;
-            uint32_t single, mul;
-            if (it < iters) {  // uniform over the block
-                pending_split(v, Wd, w, gmask, row_ptr, colD, dead, reach, valid, single, mul);
-            } else {
-                single = mul = 0u;
-            }
-            multi[it] = mul;
-            mine += __popc(mul);
-            const int32_t gbase = inst_of_node(I, v) * I.bseg + w * 32;
-            for (; single; single &= single - 1) {
-                if (lds_singles) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
-                else atomicAdd(other + gbase + __ffs(single) - 1, 1);
-            }
+        const int32_t idx = r0 + (int32_t)(threadIdx.x / Wd);
+        const bool valid = idx < count;
+        const int32_t v = valid ? worklist[idx] : 0;
+        uint32_t single, mul;
+        pending_split(v, Wd, w, gmask, row_ptr, colD, dead, reach, valid, single, mul);
+        const int32_t gbase = inst_of_node(I, v) * I.bseg + w * 32;
+        for (; single; single &= single - 1) {
+            if (lds_singles) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
+            else atomicAdd(other + gbase + __ffs(single) - 1, 1);
         }
-        const int32_t base = block_reserve(mine, pair_count, &s_tot, &s_base, &s_off);
-#pragma unroll
-        for (int it = 0; it < kIter; ++it) {
-            uint32_t mul = multi[it];
-            if (!mul) continue;
-            const int32_t v = vv[it];
+        const int32_t base = block_reserve(__popc(mul), pair_count, &s_tot, &s_base, &s_off);
+        if (mul) {
             int32_t q = base + atomicAdd(&s_off, __popc(mul));
             const int32_t b = inst_of_node(I, v);
             const int32_t vl = v - i_voff(I, b);
@@ -612,10 +600,11 @@ __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t 
 constexpr int kSumRows = 64;
 
 __global__ void k_single_sum(const int32_t *__restrict__ single_part, const int32_t *__restrict__ wl_count,
-                             int32_t nparts, int32_t B, int32_t *__restrict__ other)
+                             int32_t nparts, int32_t B, int32_t Wd, int32_t *__restrict__ other)
 {
     const int32_t i = blockIdx.x * 64 + threadIdx.x;
-    const int32_t used = min(nparts, (*wl_count + kPairRange - 1) / kPairRange);
+    const int32_t range = pair_range(Wd);
+    const int32_t used = min(nparts, (*wl_count + range - 1) / range);
     const int32_t b0 = blockIdx.y * kSumRows;
     if (i >= B || b0 >= used) return;
     const int32_t b1 = min(used, b0 + kSumRows);
@@ -744,9 +733,11 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
         }
         if (noniso > 0) {
             TimedScope ts(timer, "k_collect_pending", s);
-            const int32_t per_block = kPendSteps * kCompactRange;
+            const int32_t steps = std::max(
+                1, std::min(kPendStepsMax, (noniso + kCompactRange * kPendBlocks / 2) / (kCompactRange * kPendBlocks)));
+            const int32_t per_block = steps * kCompactRange;
             hipLaunchKernelGGL(k_collect_pending, dim3((unsigned)((noniso + per_block - 1) / per_block)),
-                               dim3(kBlk), 0, s, g->d_band_v, noniso, Wd, dead, reach, worklist, wl_count);
+                               dim3(kBlk), 0, s, g->d_band_v, noniso, steps, Wd, dead, reach, worklist, wl_count);
         }
         {
             TimedScope ts(timer, "k_pull_worklist", s);
@@ -777,7 +768,7 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
             TimedScope ts(timer, "k_root_final", s);
             if (!multi)
                 hipLaunchKernelGGL(k_single_sum, dim3((B + 63) / 64, (grid + kSumRows - 1) / kSumRows), dim3(64), 0,
-                                   s, single_part, wl_count, grid, B, other);
+                                   s, single_part, wl_count, grid, B, Wd, other);
             hipLaunchKernelGGL(k_root_final, dim3((S + 63) / 64), dim3(64), 0, s, root, I, parent, al, other,
                                g->d_row_ptr, ucount, fit, mc, (int32_t)measure);
         }
