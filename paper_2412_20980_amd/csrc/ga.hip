@@ -476,6 +476,7 @@ __global__ void k_rank_place(RankArgs a)
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= r.npar + r.npool) return;
     int32_t p = r.pos[t];
+    r.pos[t] = 0;  // ready for the next elitism (k_rank_count adds into it)
     int64_t f;
     int32_t tag;
     if (t < r.npar) {
@@ -544,7 +545,12 @@ int ga_rank_and_gather(gapa_ga *ga, bool init, const int64_t *f_pool, const int3
     const int32_t count = ga->count;
     int32_t *pos = ga->rank.as<int32_t>();
     int rc;
-    if ((rc = launch_fill_u32(pos, 0u, ga->rank_total, s)) != GAPA_OK) return rc;
+    // the counters start at zero once; k_rank_place clears every entry it reads,
+    // so later generations need no fill
+    if (!ga->rank_clear) {
+        if ((rc = launch_fill_u32(pos, 0u, ga->rank_total, s)) != GAPA_OK) return rc;
+        ga->rank_clear = true;
+    }
     RankArgs a;
     a.inst = ga->inst.as<GaInst>();
     a.f_par = ga->fit[ga->cur].as<int64_t>();

@@ -289,6 +289,7 @@ struct gapa_ga {
     std::vector<gapa::GaInst> hinst;
     gapa::DevBuf inst;            // GaInst [count]
     int32_t max_pop = 0, max_lambda = 0, max_pop_lambda = 0, rank_total = 0;
+    bool rank_clear = false;  // rank counters zeroed (k_rank_place leaves them zero)
     gapa::DevBuf pop[2];          // int32 rows of every instance
     gapa::DevBuf fit[2];          // int64 [sum P]
     gapa::DevBuf children;        // int32 rows
