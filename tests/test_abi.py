@@ -106,3 +106,18 @@ def test_batch_arguments_rejected_on_host(L):
     assert L.gapa_batch_best(None, 0, None, None, None) == gapa.GAPA_E_INVALID_ARG
     assert L.gapa_batch_get_population(None, 0, None, None) == gapa.GAPA_E_INVALID_ARG
     assert L.gapa_batch_destroy(None) == 0
+
+
+def test_flag_constants_match_the_header():
+    """Every flag the header defines as `GAPA_X = 1u << b` has the same value
+    in the binding (the binding passes them through unchanged)."""
+    from paper_2412_20980_amd import gapa
+    with open(os.path.join(ROOT, "include", "gapa.h")) as f:
+        flags = dict(re.findall(r"\b(GAPA_[A-Z0-9_]+)\s*=\s*1u\s*<<\s*(\d+)", f.read()))
+    assert {"GAPA_DEVICE_PTRS", "GAPA_WANT_MCN", "GAPA_MINIMISE_MCN", "GAPA_MAXIMISE_COMPONENTS"} <= set(flags)
+    for name, bit in flags.items():
+        assert getattr(gapa, name) == 1 << int(bit), name
+    # the call and GA flags share one word: distinct bits (the surrogate's own
+    # flag word is separate)
+    call_flags = {k: v for k, v in flags.items() if k != "GAPA_SCREEN_RANDOM"}
+    assert len(set(call_flags.values())) == len(call_flags)
