@@ -205,36 +205,47 @@ __global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restr
 // desc, id) order; its reach bit is set and its union-find entry initialised.
 // No survivor (or a padding slot): root = -1.  Also clears the slot's outputs
 // and counters and the pass's counters (ctr[2] is the "sweep 0 changed"
-// flag, set).
+// flag, set).  One wave per slot tests 64 candidates of the order at a time
+// (the highest-degree nodes are the ones a population removes most).
 __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restrict__ order, const Insts I, int32_t Wd,
                        int32_t *__restrict__ root, uint32_t *__restrict__ reach, int32_t *__restrict__ parent,
                        int32_t *__restrict__ other, int32_t *__restrict__ ctr, unsigned long long *__restrict__ fitness,
                        int32_t *__restrict__ mcn)
 {
-    const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi < 64) ctr[gi] = gi == 2 ? 1 : 0;
-    if (gi >= I.count * I.bseg) return;
+    const int lane = threadIdx.x & 63;
+    const int32_t gi = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (blockIdx.x == 0 && threadIdx.x < 64) ctr[threadIdx.x] = threadIdx.x == 2 ? 1 : 0;
+    if (gi >= I.count * I.bseg) return;  // uniform over the wave
     const int32_t b = gi / I.bseg, i = gi - b * I.bseg;
-    root[gi] = -1;
-    other[gi] = 0;
-    if (i >= i_live(I, b)) return;
-    fitness[gi] = 0ull;
-    if (mcn) mcn[gi] = 0;
+    if (i >= i_live(I, b)) {
+        if (lane == 0) {
+            root[gi] = -1;
+            other[gi] = 0;
+        }
+        return;
+    }
     const int32_t w = i >> 5;
     const uint32_t bit = 1u << (i & 31);
     const int32_t p0 = i_voff(I, b), p1 = i_voff(I, b + 1);
     int32_t r = -1;
-    for (int32_t p = p0; p < p1; ++p) {
-        const int32_t v = order[p];
-        if (!(dead[(int64_t)v * Wd + w] & bit)) {
-            r = v;
+    for (int32_t p = p0; p < p1; p += 64) {
+        const int32_t v = p + lane < p1 ? order[p + lane] : -1;
+        const bool alive = v >= 0 && !(dead[(int64_t)v * Wd + w] & bit);
+        const uint64_t hit = __ballot(alive);
+        if (hit) {
+            r = __shfl(v, (int)__ffsll((unsigned long long)hit) - 1, 64);
             break;
         }
     }
-    root[gi] = r;
-    if (r >= 0) {
-        atomicOr(reach + (int64_t)r * Wd + w, bit);
-        parent[uf_block(I, gi) + (r - p0)] = r - p0;
+    if (lane == 0) {
+        root[gi] = r;
+        other[gi] = 0;
+        fitness[gi] = 0ull;
+        if (mcn) mcn[gi] = 0;
+        if (r >= 0) {
+            atomicOr(reach + (int64_t)r * Wd + w, bit);
+            parent[uf_block(I, gi) + (r - p0)] = r - p0;
+        }
     }
 }
 
@@ -716,8 +727,8 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
         }
         {
             TimedScope ts(timer, "k_seed", s);
-            const int32_t th = std::max(S, 64);
-            hipLaunchKernelGGL(k_seed, dim3((th + 63) / 64), dim3(64), 0, s, dead, g->d_order, I, Wd, root, reach,
+            // one wave per slot, four slots per block
+            hipLaunchKernelGGL(k_seed, dim3((S + 3) / 4), dim3(256), 0, s, dead, g->d_order, I, Wd, root, reach,
                                parent, other, ctr, fit, mc);
         }
         {
