@@ -411,8 +411,8 @@ __global__ void k_pull_worklist(const int32_t *__restrict__ worklist, const int3
 
 // Pending (individual, node) pairs.  A pending node with no surviving
 // neighbour is a component of its own: it is only counted (per block, into
-// one partial row of single_part, which k_single_sum adds to other[i]; with
-// several instances directly into other[i]).
+// one partial row of single_part, which k_pairs_count's extra blocks add to
+// other[i]; with several instances directly into other[i]).
 // The rest go to the pair list for the union-find (parent[i][v] = v).
 // Padding individuals remove every node, so their bits are never pending.
 // A block takes one worklist entry per group at a time: it splits every
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restric
     const int32_t B = I.count * I.bseg;
     const bool lds_singles = I.count == 1;
     const int32_t count = *wl_count;
-    if ((int64_t)blockIdx.x * range >= count) return;  // no range: no partial row (see k_single_sum)
+    if ((int64_t)blockIdx.x * range >= count) return;  // no range: no partial row (see single_sum)
     if (lds_singles)
         for (int32_t t = threadIdx.x; t < B; t += blockDim.x) s_single[t] = 0;
     __syncthreads();
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restric
         }
         __syncthreads();
     }
-    // singleton counts of this block: one partial row, summed by k_single_sum
+    // singleton counts of this block: one partial row, summed by single_sum
     if (lds_singles)
         for (int32_t t = threadIdx.x; t < B; t += blockDim.x) single_part[(int64_t)blockIdx.x * B + t] = s_single[t];
 }
@@ -561,11 +561,42 @@ __global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const int32_t *_
 }
 
 // Pending nodes counted at the representative of their set.
-__global__ void k_pairs_count(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, const Insts I,
-                              int32_t *__restrict__ parent, int32_t *__restrict__ ucount)
+// Adds the singleton partial rows of the collect blocks that owned a range to
+// other[i]: block (x, y) sums rows [64 y, 64 y + 64) for individuals
+// [kBlk x, kBlk x + kBlk), loads unrolled, then one atomic per individual.
+constexpr int kSumRows = 64;
+
+__device__ __forceinline__ void single_sum(int32_t bx, int32_t by, const int32_t *__restrict__ single_part,
+                                           const int32_t *__restrict__ wl_count, int32_t nparts, int32_t B,
+                                           int32_t Wd, int32_t *__restrict__ other)
 {
+    const int32_t i = bx * blockDim.x + threadIdx.x;
+    const int32_t range = pair_range(Wd);
+    const int32_t used = min(nparts, (*wl_count + range - 1) / range);
+    const int32_t b0 = by * kSumRows;
+    if (i >= B || b0 >= used) return;
+    const int32_t b1 = min(used, b0 + kSumRows);
+    int32_t acc = 0;
+#pragma unroll 16
+    for (int32_t b = b0; b < b1; ++b) acc += single_part[(int64_t)b * B + i];
+    if (acc) atomicAdd(other + i, acc);
+}
+
+// Blocks [0, grid): each pair's node counted at the representative of its
+// set.  Blocks from grid on (one instance only; sum_x blocks per row group)
+// add the singleton partial rows: independent work sharing the launch.
+__global__ void k_pairs_count(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, const Insts I,
+                              int32_t *__restrict__ parent, int32_t *__restrict__ ucount, int32_t grid,
+                              const int32_t *__restrict__ single_part, const int32_t *__restrict__ wl_count,
+                              int32_t B, int32_t Wd, int32_t sum_x, int32_t *__restrict__ other)
+{
+    if ((int32_t)blockIdx.x >= grid) {
+        const int32_t sb = (int32_t)blockIdx.x - grid;
+        single_sum(sb % sum_x, sb / sum_x, single_part, wl_count, grid, B, Wd, other);
+        return;
+    }
     const int32_t count = *pair_count;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)grid * blockDim.x) {
         const int64_t key = pairs[q];
         const int32_t gi = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
         const int64_t blk = uf_block(I, gi);
@@ -603,26 +634,6 @@ __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t 
         atomicAdd(other + gi, s);
         add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
     }
-}
-
-// Adds the singleton partial rows of the collect blocks that owned a range to
-// other[i]: block (x, y) sums rows [64 y, 64 y + 64) for individuals
-// [64 x, 64 x + 64), loads unrolled, then one atomic per individual.
-constexpr int kSumRows = 64;
-
-__global__ void k_single_sum(const int32_t *__restrict__ single_part, const int32_t *__restrict__ wl_count,
-                             int32_t nparts, int32_t B, int32_t Wd, int32_t *__restrict__ other)
-{
-    const int32_t i = blockIdx.x * 64 + threadIdx.x;
-    const int32_t range = pair_range(Wd);
-    const int32_t used = min(nparts, (*wl_count + range - 1) / range);
-    const int32_t b0 = blockIdx.y * kSumRows;
-    if (i >= B || b0 >= used) return;
-    const int32_t b1 = min(used, b0 + kSumRows);
-    int32_t acc = 0;
-#pragma unroll 16
-    for (int32_t b = b0; b < b1; ++b) acc += single_part[(int64_t)b * B + i];
-    if (acc) atomicAdd(other + i, acc);
 }
 
 __global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, int32_t *__restrict__ parent,
@@ -768,7 +779,11 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
         }
         {
             TimedScope ts(timer, "k_pairs_count", s);
-            hipLaunchKernelGGL(k_pairs_count, dim3(grid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, ucount);
+            // with one instance, the singleton sums ride in the same launch
+            const int32_t sum_x = (B + kBlk - 1) / kBlk;
+            const int32_t extra = multi ? 0 : sum_x * ((grid + kSumRows - 1) / kSumRows);
+            hipLaunchKernelGGL(k_pairs_count, dim3(grid + extra), dim3(kBlk), 0, s, pairs, pair_count, I, parent,
+                               ucount, grid, single_part, wl_count, B, Wd, sum_x, other);
         }
         {
             TimedScope ts(timer, "k_pairs_reduce", s);
@@ -777,9 +792,6 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
         }
         {
             TimedScope ts(timer, "k_root_final", s);
-            if (!multi)
-                hipLaunchKernelGGL(k_single_sum, dim3((B + 63) / 64, (grid + kSumRows - 1) / kSumRows), dim3(64), 0,
-                                   s, single_part, wl_count, grid, B, Wd, other);
             hipLaunchKernelGGL(k_root_final, dim3((S + 63) / 64), dim3(64), 0, s, root, I, parent, al, other,
                                g->d_row_ptr, ucount, fit, mc, (int32_t)measure);
         }
