@@ -163,8 +163,10 @@ def sixdst(graph, genes, hops: int) -> tuple[int, int]:
     ((sum(M) - n) / 2, the largest row sum over surviving nodes (0 when
     none survive)).  With hops at least the diameter of every component of
     G[V minus S] the pair is (PC, MCN) exactly (eq. 16-17); the paper's
-    choice hops = 6 (eq. 15) is the truncation.  int64 dense products: for
-    small graphs only."""
+    choice hops = 6 (eq. 15) is the truncation.  Dense products: for small
+    graphs only.  They are taken in float64 (a BLAS product): every entry is
+    a count of at most n < 2^53 paths of 0/1 entries, so the float64 product
+    is the exact integer product."""
     n = graph.n
     S = np.unique(np.asarray(genes, dtype=np.int64).ravel())
     if S.size and (S.min() < 0 or S.max() >= n):
@@ -176,10 +178,11 @@ def sixdst(graph, genes, hops: int) -> tuple[int, int]:
         A[v, graph.col_idx[graph.row_ptr[v]:graph.row_ptr[v + 1]]] = 1
     A[S, :] = 0
     A[:, S] = 0
-    step = A + np.eye(n, dtype=np.int64)
+    step = (A + np.eye(n, dtype=np.int64)).astype(np.float64)
     M = step.copy()
     for _ in range(hops - 1):
-        M = ((M @ step) > 0).astype(np.int64)
+        M = ((M @ step) > 0).astype(np.float64)
+    M = M.astype(np.int64)
     alive = np.ones(n, dtype=bool)
     alive[S] = False
     rows = M.sum(axis=1)

@@ -85,9 +85,21 @@ def init_params(seed: int, n: int, D: int = 64, H: int = 256) -> dict:
 
 # --- forward / backward -------------------------------------------------------
 
+def membership(sets: np.ndarray, n: int):
+    """The B x n matrix of a batch of sets: entry (b, v) counts the
+    occurrences of v in row b (a sparse matrix, so that sums over the rows of
+    the embedding table cost O(B k D) at any n)."""
+    from scipy.sparse import csr_matrix
+    S = np.asarray(sets, dtype=np.int64)
+    B, k = S.shape
+    rows = np.repeat(np.arange(B, dtype=np.int64), k)
+    return csr_matrix((np.ones(B * k), (rows, S.ravel())), shape=(B, n))
+
+
 def embed(E: np.ndarray, sets: np.ndarray) -> np.ndarray:
-    """x(S) for each row of sets [B, k]: the sum of the rows of E."""
-    return E[np.asarray(sets, dtype=np.int64)].sum(axis=1)
+    """x(S) for each row of sets [B, k]: the sum of the rows of E, i.e. the
+    membership matrix times E."""
+    return np.asarray(membership(sets, E.shape[0]) @ E)
 
 
 def forward(p: dict, sets: np.ndarray, bf16_ops: bool = False) -> dict:
@@ -125,9 +137,9 @@ def loss_and_grads(p: dict, sets: np.ndarray, target: np.ndarray, bf16_ops: bool
     g["W1"] = dz1b.T @ f["x"]
     g["b1"] = dz1b.sum(axis=0)
     dx = r(dz1b @ r(p["W1"]))
-    dE = np.zeros_like(p["E"])
-    np.add.at(dE, np.asarray(sets, dtype=np.int64).ravel(), np.repeat(dx, sets.shape[1], axis=0))
-    g["E"] = dE
+    # dE = M^T dx with M the membership matrix: row v sums dx over the
+    # samples whose set holds v, once per occurrence
+    g["E"] = np.asarray(membership(sets, p["E"].shape[0]).T @ dx)
     return loss, g, f
 
 
@@ -215,6 +227,29 @@ def spearman(a, b) -> float:
     return float((ra * rb).sum() / den) if den > 0 else 0.0
 
 
+JUDGE_MAX = 1024
+
+
+def judge_sample(m: int, cap: int = JUDGE_MAX) -> np.ndarray:
+    """Entries of m evaluated children the judge looks at: all of them when
+    m <= cap, else cap of them evenly spaced (entry i is floor(i m / cap))."""
+    J = min(m, cap)
+    return np.array([(i * m) // J for i in range(J)], dtype=np.int64)
+
+
+def judge_stats(yhat, F, mu: float, sd: float, cap: int = JUDGE_MAX):
+    """The judge of a generation over its evaluated children (yhat: their
+    predictions on the standardised scale, F: their exact PC, same order):
+    Spearman's correlation between prediction and PC, and the mean relative
+    error of the predicted PC expm1(yhat sd + mu) (the label is ln(1 + PC)),
+    relative to max(PC, 1); both over judge_sample(len(F))."""
+    idx = judge_sample(len(F), cap)
+    y = np.asarray(yhat, dtype=np.float64)[idx]
+    f = np.asarray(F, dtype=np.int64)[idx]
+    rel = np.abs(np.expm1(y * sd + mu) - f.astype(np.float64)) / np.maximum(f.astype(np.float64), 1.0)
+    return spearman(y, f.astype(np.float64)), float(rel.mean())
+
+
 def sample_batch(seed: int, gen: int, step: int, B: int, count: int) -> np.ndarray:
     """Buffer entries of training step `step` of generation `gen`: entry j is
     bounded(w, count), w the first word of draw(seed, slot j, ind step, gen,
@@ -251,6 +286,7 @@ class SurrogateGA:
         self.buf_y = np.zeros(buffer)
         self.appended = 0
         self.losses = []
+        self.label_stats = {}  # generation -> (mean, spread) its training standardised with
 
     @property
     def generation(self):
@@ -266,6 +302,7 @@ class SurrogateGA:
     def train(self, gen):
         count = min(self.appended, self.cap)
         mu, sd = standardise(self.buf_y[:count])
+        self.label_stats[gen] = (mu, sd)
         for t in range(self.steps):
             idx = sample_batch(self.seed, gen, t, self.batch, count)
             sets = self.buf_sets[idx]

@@ -238,3 +238,120 @@ def test_replayed_ga_without_screening_is_the_plain_ga():
         ga.step()
         assert np.array_equal(sga.ga.pop, ga.pop) and np.array_equal(sga.ga.F, ga.F)
     assert sga.appended == 4 * 40 and len(sga.losses) == 4
+
+
+def test_bf16_mode_is_the_mixed_precision_network():
+    """The oracle's bfloat16 mode against torch autograd in float64 given only
+    where the network keeps bfloat16 values: the weight copies (E, W1, W2, w3)
+    and activations (x, h1, h2) are rounded in the forward pass (gradients
+    pass to the float32 masters unchanged), the activation gradients (of z1,
+    z2 and x) are rounded in the backward pass; sums, biases, pre-activations
+    and the loss stay wide.  Autograd derives the chain rule itself."""
+    rng = np.random.default_rng(14)
+    n, B, k = 40, 16, 5
+    p = {"E": rng.normal(0, 0.3, (n, 8)), "W1": rng.normal(0, 0.4, (16, 8)), "b1": rng.normal(0, 0.1, 16),
+         "W2": rng.normal(0, 0.3, (16, 16)), "b2": rng.normal(0, 0.1, 16), "w3": rng.normal(0, 0.3, 16),
+         "b3": rng.normal(0, 0.1, 1)}
+    sets = np.stack([rng.choice(n, size=k, replace=False) for _ in range(B)])
+    target = rng.normal(size=B)
+
+    def rt(x):  # torch's own bfloat16 conversion (through float32)
+        return x.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    class Value(torch.autograd.Function):  # rounded value, gradient passed through
+        @staticmethod
+        def forward(ctx, x):
+            return rt(x)
+
+        @staticmethod
+        def backward(ctx, g):
+            return g
+
+    class Grad(torch.autograd.Function):  # value passed through, gradient rounded
+        @staticmethod
+        def forward(ctx, x):
+            return x.clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            return rt(g)
+
+    t = {kk: torch.tensor(v, dtype=torch.float64, requires_grad=True) for kk, v in p.items()}
+    x = Grad.apply(Value.apply(Value.apply(t["E"])[torch.tensor(sets)].sum(dim=1)))
+    z1 = Grad.apply(x @ Value.apply(t["W1"]).T + t["b1"])
+    h1 = Value.apply(torch.relu(z1))
+    z2 = Grad.apply(h1 @ Value.apply(t["W2"]).T + t["b2"])
+    h2 = Value.apply(torch.relu(z2))
+    yhat = h2 @ Value.apply(t["w3"]) + t["b3"]
+    loss_t = torch.mean((yhat - torch.tensor(target)) ** 2)
+    loss_t.backward()
+    loss, g, f = S.loss_and_grads(p, sets, target, bf16_ops=True)
+    assert abs(loss - loss_t.item()) <= 1e-12
+    assert np.allclose(f["yhat"], yhat.detach().numpy(), rtol=1e-12, atol=1e-12)
+    for kk in S.TENSORS:
+        assert np.allclose(g[kk], t[kk].grad.numpy(), rtol=1e-10, atol=1e-12), kk
+
+
+def test_judge_sample_is_evenly_spaced():
+    assert np.array_equal(S.judge_sample(10), np.arange(10))
+    assert np.array_equal(S.judge_sample(1024), np.arange(1024))
+    for m in (1025, 3000, 4096, 10 ** 6):
+        idx = S.judge_sample(m)
+        gaps = np.diff(idx)
+        assert len(idx) == 1024 and idx[0] == 0 and idx[-1] < m
+        assert gaps.min() >= m // 1024 and gaps.max() <= -(-m // 1024)
+        # spread over the whole range: the last entry is within one gap of the end
+        assert m - idx[-1] <= -(-m // 1024)
+
+
+def test_judge_statistics_pins():
+    from scipy.stats import spearmanr
+    rng = np.random.default_rng(15)
+    F = rng.integers(0, 10 ** 9, size=3000)
+    F[:500] = F[0]  # ties
+    mu, sd = 15.0, 2.0
+    # exact predictions: zero relative error and, over the judged sample,
+    # Spearman equal to scipy's on the same values
+    y_exact = (np.log1p(F.astype(np.float64)) - mu) / sd
+    rho, rel = S.judge_stats(y_exact, F, mu, sd)
+    assert abs(rho - 1.0) < 1e-12 and rel < 1e-9
+    # predicting 2 PC + 1 everywhere: relative error (PC + 1) / max(PC, 1)
+    y2 = (np.log(2.0 * F.astype(np.float64) + 2.0) - mu) / sd
+    idx = S.judge_sample(len(F))
+    _, rel2 = S.judge_stats(y2, F, mu, sd)
+    f = F[idx].astype(np.float64)
+    assert abs(rel2 - np.mean((f + 1.0) / np.maximum(f, 1.0))) < 1e-9 * rel2
+    # a noisy predictor: scipy's Spearman on the judged entries
+    y = y_exact + rng.normal(size=3000)
+    rho3, _ = S.judge_stats(y, F, mu, sd)
+    assert abs(rho3 - spearmanr(y[idx], F[idx]).correlation) < 1e-12
+
+
+def test_judge_extra_selection():
+    """The judge's extra sample: the `count` non-pooled children with the
+    smallest (stream-7 key, index), checked against an independent ranking
+    (numpy lexsort over all keys), and its frequency is uniform over the
+    non-pooled children across generations."""
+    seed, lam = 9, 200
+    rng = np.random.default_rng(16)
+    pool = np.sort(rng.choice(lam, size=64, replace=False))
+    for gen, count in ((3, 32), (4, 1), (5, 136)):
+        got = S.judge_extra(seed, gen, lam, pool, count)
+        keys = np.array([int(O.draw(seed, o, 1, gen, 7)[0]) for o in range(lam)], dtype=np.int64)
+        keys[pool] = np.iinfo(np.int64).max  # pooled children never qualify
+        order = np.lexsort((np.arange(lam), keys))
+        assert np.array_equal(got, np.sort(order[:count]))
+        assert not np.intersect1d(got, pool).size and np.all(np.diff(got) > 0)
+    # count = every child outside the pool: exactly those
+    assert np.array_equal(S.judge_extra(seed, 6, lam, pool, lam - 64), np.setdiff1d(np.arange(lam), pool))
+    # uniform over the 136 non-pooled children: chi-square over 300 generations
+    hits = np.zeros(lam)
+    gens = 300
+    for gen in range(1, gens + 1):
+        hits[S.judge_extra(seed, gen, lam, pool, 8)] += 1
+    free = np.setdiff1d(np.arange(lam), pool)
+    assert not hits[pool].any()
+    expected = gens * 8 / len(free)
+    chi2 = float(((hits[free] - expected) ** 2 / expected).sum())
+    # 135 degrees of freedom: mean 135, sd ~16.4; 6 sd above is far in the tail
+    assert chi2 < 135 + 6 * math.sqrt(2 * 135)
