@@ -341,14 +341,18 @@ int fitness_stats(FitnessWorkspace &w, int64_t out[4])
 {
     for (int i = 0; i < 4; ++i) out[i] = 0;
     if (!w.stats_ctr) return GAPA_OK;
-    int32_t h[8] = {0};
+    // the pass's counters: [0] worklist count, [2..] changed flags (the first is
+    // set by the pass itself), [36, 38) the 64-bit pair count
+    int32_t h[40] = {0};
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(h, w.stats_ctr, sizeof h, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "fitness stats");
     out[0] = w.stats_B;
     out[1] = h[0];
-    out[2] = h[1];
-    for (int i = 3; i < 8; ++i) out[3] += h[i] != 0;  // changed flags of sweeps 1..
+    uint64_t pairs = 0;
+    std::memcpy(&pairs, h + 36, 8);
+    out[2] = (int64_t)pairs;
+    for (int i = 3; i < 36; ++i) out[3] += h[i] != 0;  // changed flags of sweeps 1..
     return GAPA_OK;
 }
 
@@ -1212,6 +1216,23 @@ int gapa_ga_load(gapa_graph *g, const char *path, void *stream, gapa_ga **out)
             set_error("gene %d of the checkpoint is not a node id", v);
             return GAPA_E_BAD_GENE;
         }
+    // The kernels rely on the GA's invariants, which the checksum alone does not
+    // guarantee (anyone can recompute it): every row strictly ascending (the
+    // operators' duplicate search) and the fitness non-decreasing down the
+    // population (the elitism merge's binary search).
+    const int32_t k = h.params.k;
+    for (int32_t r = 0; r < h.P; ++r) {
+        const int32_t *row = rows.data() + (size_t)r * k;
+        for (int32_t j = 1; j < k; ++j)
+            if (row[j] <= row[j - 1]) {
+                set_error("row %d of the checkpoint is not strictly ascending", r);
+                return GAPA_E_INVALID_ARG;
+            }
+        if (fit[r] < 0 || (r > 0 && fit[r] < fit[r - 1])) {
+            set_error("the checkpoint's fitness is not non-negative and non-decreasing (row %d)", r);
+            return GAPA_E_INVALID_ARG;
+        }
+    }
     DeviceGuard dg(g->device);
     gapa_ga *ga = new (std::nothrow) gapa_ga();
     if (!ga) {
@@ -1385,6 +1406,21 @@ int gapa_batch_autotune(gapa_batch *b, int32_t reps, void *stream, gapa_tuning *
     return gapa_ga_autotune(b->ga, reps, stream, best_out);
 }
 
+int gapa_batch_get_tuning(gapa_batch *b, gapa_tuning *out)
+{
+    if (!b) return GAPA_E_INVALID_ARG;
+    return gapa_graph_get_tuning(b->ga->graph, out);
+}
+
+int gapa_batch_set_tuning(gapa_batch *b, const gapa_tuning *t)
+{
+    if (!b) {
+        set_error("batch is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    return gapa_graph_set_tuning(b->ga->graph, t);
+}
+
 // --------------------------------------------------------------- surrogate ---
 
 static int surr_check(gapa_ga *ga)
@@ -1439,6 +1475,20 @@ int gapa_surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out)
     if (!out) return GAPA_E_INVALID_ARG;
     DeviceGuard dg(ga->graph->device);
     return fail_handle(&ga->failed, surrogate_stats(ga, out));
+}
+
+int gapa_surrogate_judge(const float *yhat, const int32_t *pool, const int64_t *fitness, int32_t m,
+                         double label_mean, double label_spread, double *out, void *stream)
+{
+    g_last_error.clear();
+    if (!yhat || !fitness || !out || m < 1 || !(label_spread > 0.0) || !std::isfinite(label_mean)) {
+        set_error("invalid judge arguments (m = %d)", m);
+        return GAPA_E_INVALID_ARG;
+    }
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc != GAPA_OK) return rc;
+    return surrogate_judge(yhat, pool, fitness, m, label_mean, label_spread, out, static_cast<hipStream_t>(stream));
 }
 
 int gapa_surrogate_last_pool(gapa_ga *ga, int32_t *pool_out, int32_t cap, int32_t *count)

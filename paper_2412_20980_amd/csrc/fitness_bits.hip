@@ -307,8 +307,11 @@ __global__ void k_pull_band(const int32_t *__restrict__ band_v, int32_t b0, int3
 // counts its items, reserves room with one global atomic and writes them at
 // offsets taken from an LDS counter.  Order inside the output is not fixed,
 // and nothing downstream depends on it.
-__device__ __forceinline__ int32_t block_reserve(int32_t mine, int32_t *counter, int32_t *s_tot, int32_t *s_base,
-                                                 int32_t *s_off)
+// The counter is int32 (worklist: at most n_noniso < 2^31 entries) or
+// unsigned 64-bit (pending pairs: up to B * n_noniso, which passes 2^31 on
+// graphs of a few million nodes).
+template <class C>
+__device__ __forceinline__ C block_reserve(int32_t mine, C *counter, int32_t *s_tot, C *s_base, int32_t *s_off)
 {
     // returns the block's base slot; *s_off is reset to 0 for the write pass
     if (threadIdx.x == 0) *s_tot = 0;
@@ -318,12 +321,19 @@ __device__ __forceinline__ int32_t block_reserve(int32_t mine, int32_t *counter,
     if ((threadIdx.x & 63) == 0 && x) atomicAdd(s_tot, x);
     __syncthreads();
     if (threadIdx.x == 0) {
-        *s_base = *s_tot ? atomicAdd(counter, *s_tot) : 0;
+        *s_base = *s_tot ? atomicAdd(counter, (C)*s_tot) : (C)0;
         *s_off = 0;
     }
     __syncthreads();
     return *s_base;
 }
+
+// Counters of a pass (int32 entries after the per-slot roots and sizes): [0]
+// the worklist count, [2 ..] the changed flags of the follow-up sweeps (at
+// most 33), [kPairCountSlot, kPairCountSlot + 2) the 64-bit pair count; k_seed
+// clears all 64.
+constexpr int kPairCountSlot = 36;
+static_assert(kPairCountSlot % 2 == 0 && kPairCountSlot >= 2 + 33 && kPairCountSlot + 2 <= 64, "counter layout");
 
 constexpr int kCompactRange = 64;   // input items per compaction step
 constexpr int kPendStepsMax = 8;    // steps per block in k_collect_pending, at most
@@ -457,10 +467,12 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restric
                                                         const int32_t *__restrict__ colD,
                                                         const uint32_t *__restrict__ dead,
                                                         const uint32_t *__restrict__ reach, int64_t *__restrict__ pairs,
-                                                        int32_t *__restrict__ pair_count, int32_t *__restrict__ parent,
+                                                        unsigned long long *__restrict__ pair_count,
+                                                        int32_t *__restrict__ parent,
                                                         int32_t *__restrict__ single_part, int32_t *__restrict__ other)
 {
-    __shared__ int32_t s_tot, s_base, s_off;
+    __shared__ int32_t s_tot, s_off;
+    __shared__ unsigned long long s_base;
     __shared__ int32_t s_single[1024];
     const int w = threadIdx.x & (Wd - 1);
     const uint64_t gmask = group_mask(Wd);
@@ -486,9 +498,9 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restric
             if (lds_singles) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
             else atomicAdd(other + gbase + __ffs(single) - 1, 1);
         }
-        const int32_t base = block_reserve(__popc(mul), pair_count, &s_tot, &s_base, &s_off);
+        const unsigned long long base = block_reserve(__popc(mul), pair_count, &s_tot, &s_base, &s_off);
         if (mul) {
-            int32_t q = base + atomicAdd(&s_off, __popc(mul));
+            int64_t q = (int64_t)base + atomicAdd(&s_off, __popc(mul));
             const int32_t b = inst_of_node(I, v);
             const int32_t vl = v - i_voff(I, b);
             for (; mul; mul &= mul - 1) {
@@ -537,12 +549,12 @@ __device__ __forceinline__ void uf_unite(int32_t *parent, int32_t a, int32_t b)
 // Union over the surviving edges of each pending pair (key: slot << 32 |
 // node): a surviving neighbour that is reached joins the root's set; a
 // pending one (each such edge once, from its smaller end) is united with it.
-__global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, const Insts I,
+__global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count, const Insts I,
                              int32_t Wd, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                              const uint32_t *__restrict__ dead, const uint32_t *__restrict__ reach,
                              const int32_t *__restrict__ root, int32_t *__restrict__ parent)
 {
-    const int32_t count = *pair_count;
+    const int64_t count = (int64_t)*pair_count;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t key = pairs[q];
         const int32_t gi = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
@@ -585,7 +597,7 @@ __device__ __forceinline__ void single_sum(int32_t bx, int32_t by, const int32_t
 // Blocks [0, grid): each pair's node counted at the representative of its
 // set.  Blocks from grid on (one instance only; sum_x blocks per row group)
 // add the singleton partial rows: independent work sharing the launch.
-__global__ void k_pairs_count(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, const Insts I,
+__global__ void k_pairs_count(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count, const Insts I,
                               int32_t *__restrict__ parent, int32_t *__restrict__ ucount, int32_t grid,
                               const int32_t *__restrict__ single_part, const int32_t *__restrict__ wl_count,
                               int32_t B, int32_t Wd, int32_t sum_x, int32_t *__restrict__ other)
@@ -595,7 +607,7 @@ __global__ void k_pairs_count(const int64_t *__restrict__ pairs, const int32_t *
         single_sum(sb % sum_x, sb / sum_x, single_part, wl_count, grid, B, Wd, other);
         return;
     }
-    const int32_t count = *pair_count;
+    const int64_t count = (int64_t)*pair_count;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)grid * blockDim.x) {
         const int64_t key = pairs[q];
         const int32_t gi = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
@@ -616,12 +628,12 @@ __device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit
 // Components made only of pending nodes (set representative is a pending node
 // other than the root's representative): counted, and their sizes summed into
 // other[gi].  Their counters are cleared for reuse.
-__global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const int32_t *__restrict__ pair_count, const Insts I,
+__global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count, const Insts I,
                                int32_t *__restrict__ parent, const int32_t *__restrict__ root,
                                int32_t *__restrict__ ucount, int32_t *__restrict__ other,
                                unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest)
 {
-    const int32_t count = *pair_count;
+    const int64_t count = (int64_t)*pair_count;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t key = pairs[q];
         const int32_t gi = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
@@ -707,8 +719,11 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
     const int32_t grid = tu.sweep_grid;
     int32_t *root = ws.small.as<int32_t>();
     int32_t *other = root + S;
-    int32_t *ctr = root + 2 * S;  // [0] worklist count, [1] pair count, [2..] changed flags
-    int32_t *wl_count = ctr, *pair_count = ctr + 1, *changed = ctr + 2;
+    // [0] worklist count, [2, 2 + sweeps] changed flags, [kPairCountSlot, +2)
+    // the 64-bit pair count (8-byte aligned: S is a multiple of 32)
+    int32_t *ctr = root + 2 * S;
+    int32_t *wl_count = ctr, *changed = ctr + 2;
+    unsigned long long *pair_count = reinterpret_cast<unsigned long long *>(ctr + kPairCountSlot);
     int32_t *single_part = ctr + 64;  // [grid][B] singleton counts per collect block (one instance)
     ws.stats_ctr = ctr;
     ws.stats_B = S;

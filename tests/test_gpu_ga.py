@@ -258,3 +258,50 @@ def test_checkpoint_resume_continues_the_trajectory(gp, ba10k, tmp_path):
     with pytest.raises(gp.GapaError) as e:
         sga.save(str(tmp_path / "s.ckpt"))
     assert e.value.code == gp.GAPA_E_STATE
+
+
+def fnv1a64(data: bytes) -> int:
+    """FNV-1a, 64-bit (Fowler, Noll, Vo): the checkpoint's checksum."""
+    h = 0xCBF29CE484222325
+    for b in data:
+        h = ((h ^ b) * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_checkpoint_rejects_broken_invariants(gp, ba200, tmp_path):
+    """A checkpoint whose checksum is valid but whose rows are not strictly
+    ascending, or whose fitness is not non-decreasing, is rejected before
+    anything reaches the device (the operator and elitism kernels rely on
+    both)."""
+    graph = gp.Graph.from_csr(ba200)
+    ga = gp.GA(graph, 10, 16, 3)
+    ga.step(2)
+    path = tmp_path / "ga.ckpt"
+    ga.save(str(path))
+    data = bytearray(path.read_bytes())
+    header = 96  # magic, version, parameters, graph identity, generation
+    P, k = 16, 10
+    rows = np.frombuffer(bytes(data[header:header + 4 * P * k]), dtype=np.int32).reshape(P, k).copy()
+    fit = np.frombuffer(bytes(data[header + 4 * P * k:header + 4 * P * k + 8 * P]), dtype=np.int64).copy()
+
+    def write(rows_, fit_, name):
+        body = bytes(data[:header]) + rows_.astype(np.int32).tobytes() + fit_.astype(np.int64).tobytes()
+        out = tmp_path / name
+        out.write_bytes(body + fnv1a64(body).to_bytes(8, "little"))
+        return str(out)
+
+    # the untouched contents re-written with a recomputed checksum still load
+    gp.GA.load(graph, write(rows, fit, "same.ckpt")).close()
+    swapped = rows.copy()
+    swapped[3, [2, 3]] = swapped[3, [3, 2]]
+    repeated = rows.copy()
+    repeated[5, 4] = repeated[5, 3]
+    unordered = fit.copy()
+    unordered[0] = fit[P - 1] + 1
+    negative = fit.copy()
+    negative[0] = -1
+    for r, f, name in ((swapped, fit, "swap"), (repeated, fit, "repeat"), (rows, unordered, "order"),
+                       (rows, negative, "negative")):
+        with pytest.raises(gp.GapaError) as e:
+            gp.GA.load(graph, write(r, f, name + ".ckpt"))
+        assert e.value.code == gp.GAPA_E_INVALID_ARG, name
