@@ -128,6 +128,7 @@ GAPA_API int gapa_graph_destroy(gapa_graph *g);
 GAPA_API int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k,
                          int64_t *fitness, int32_t *mcn, uint32_t flags, void *stream);
 
+
 /* ---------------------------------------------------------------------------
  * The paper's dense reachability fitness (Section III-D, eq. 13-17, the
  * "SixDST" function), on the matrix cores.
@@ -292,13 +293,31 @@ typedef struct gapa_surrogate_report {
     int32_t reserved;
     double spearman;     /* judge correlation (0 when no prediction was made)     */
     double rel_err;      /* mean |expm1(prediction) - PC| / max(PC, 1)             */
-    double loss;         /* mean squared error of its last training step          */
+    double loss;         /* mean squared error of the last training step finished
+                            before it (after gapa_surrogate_train_batch: that
+                            step's)                                            */
     int32_t fallbacks;   /* full generations forced by the judge so far            */
     int32_t train_steps; /* Adam steps taken so far                               */
+    double label_mean;   /* the label standardisation the generation's predictions */
+    double label_spread; /* were made in (0 when it made none): a standardised
+                            prediction y stands for ln(1 + PC) = y spread + mean */
 } gapa_surrogate_report;
 
 /* Figures of the last generation (host pointer; waits for the GA's work). */
 GAPA_API int gapa_surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out);
+
+/* The judge's statistics on explicit data (the computation behind the
+ * spearman and rel_err of gapa_surrogate_report).  Device pointers: yhat
+ * float predictions (standardised scale), indexed by pool[q] (int32 [m]; NULL:
+ * by q), fitness int64 [m] the exact PC of the same children.  Over J =
+ * min(m, 1024) entries, entry i being q = floor(i m / J): out[0] Spearman's
+ * rank correlation between yhat and fitness (average ranks for ties, 0 when
+ * either side is constant), out[1] the mean over them of
+ * |expm1(yhat label_spread + label_mean) - PC| / max(PC, 1).  out is host
+ * double [2]; the call waits on `stream`.  m >= 1, label_spread > 0, else
+ * GAPA_E_INVALID_ARG; pool entries must index yhat (not checked). */
+GAPA_API int gapa_surrogate_judge(const float *yhat, const int32_t *pool, const int64_t *fitness, int32_t m,
+                                  double label_mean, double label_spread, double *out, void *stream);
 
 /* Children evaluated exactly in the last generation (host; waits): the pooled
  * ones ascending, then the judge's extra sample ascending; up to `cap`
@@ -424,6 +443,11 @@ GAPA_API int gapa_graph_set_tuning(gapa_graph *g, const gapa_tuning *t);
  * untouched. */
 GAPA_API int gapa_ga_autotune(gapa_ga *ga, int32_t reps, void *stream, gapa_tuning *best_out);
 GAPA_API int gapa_batch_autotune(gapa_batch *b, int32_t reps, void *stream, gapa_tuning *best_out);
+/* Launch shapes of a batch's fitness pass (its disjoint-union graph), as
+ * gapa_graph_get_tuning / gapa_graph_set_tuning; NULL gives
+ * GAPA_E_INVALID_ARG. */
+GAPA_API int gapa_batch_get_tuning(gapa_batch *b, gapa_tuning *out);
+GAPA_API int gapa_batch_set_tuning(gapa_batch *b, const gapa_tuning *t);
 
 /* Message of the last failed call on this thread ("" if none). */
 GAPA_API const char *gapa_last_error(void);

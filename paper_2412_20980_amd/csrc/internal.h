@@ -267,6 +267,10 @@ int surrogate_tensor(gapa_ga *ga, int32_t which, int32_t kind, float *host, int6
 int surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out);
 int surrogate_last_pool(gapa_ga *ga, int32_t *pool, int32_t cap, int32_t *count);
 int surrogate_last_predictions(gapa_ga *ga, float *yhat, int32_t cap, int32_t *count);
+// The judge's statistics of m predictions against exact fitness (device
+// arrays), written to host out[2]; waits on s.
+int surrogate_judge(const float *yhat, const int32_t *pool, const int64_t *F, int32_t m, double mu, double sd,
+                    double *out, hipStream_t s);
 
 // Error reporting for HIP calls.
 int hip_fail(hipError_t e, const char *what);

@@ -877,9 +877,12 @@ __global__ void k_sample(uint64_t seed, uint32_t gen, uint32_t step, int32_t cou
 // Judge: over J = min(m, 1024) evaluated children (entry i is pool entry
 // floor(i m / J)), Spearman's correlation between predictions and exact PC
 // (average ranks), and the mean relative error of expm1(yhat sd + mu).
+// out[0] the correlation, out[1] the error; out_musd (optional) receives the
+// label mean and spread the predictions were made in.
 __global__ __launch_bounds__(1024) void k_judge(const float *__restrict__ yhat, const int32_t *__restrict__ pool,
                                                 const int64_t *__restrict__ F, int32_t m,
-                                                const double *__restrict__ mu_sd, double *__restrict__ out)
+                                                const double *__restrict__ mu_sd, double *__restrict__ out,
+                                                double *__restrict__ out_musd)
 {
     __shared__ float s_y[kJudgeMax];
     __shared__ int64_t s_f[kJudgeMax];
@@ -926,6 +929,10 @@ __global__ __launch_bounds__(1024) void k_judge(const float *__restrict__ yhat, 
         const double den = sqrt(sum[1] * sum[2]);
         out[0] = den > 0.0 ? sum[0] / den : 0.0;
         out[1] = sum[3] / J;
+        if (out_musd) {
+            out_musd[0] = mu_sd[0];
+            out_musd[1] = mu_sd[1];
+        }
     }
 }
 
@@ -958,7 +965,8 @@ struct SurrogateState {
     DevBuf dstats;                                      // double [2]: label mean and spread of the predictions
     DevBuf dloss;                                       // double: loss of the last training step
     DevBuf tstats;                                      // double [2]: label mean and spread the training uses
-    double *hstats = nullptr;                           // pinned, mapped: [2] rho, [3] rel_err, [4] loss
+    double *hstats = nullptr;                           // pinned, mapped: [2] rho, [3] rel_err, [4] loss,
+                                                        // [5, 6] the predictions' label mean and spread
     double *hstats_dev = nullptr;                       // its device address (the judge and k_append write it)
     hipEvent_t ready = nullptr;
     // Generation g's training runs on its own stream beside generation g + 1;
@@ -969,6 +977,7 @@ struct SurrogateState {
     hipEvent_t ev_snap = nullptr;   // training stream: training done and snapshot taken
     hipEvent_t ev_data = nullptr;   // main stream: the generation's labels are in the buffer
     bool have_keep = false;
+    bool explicit_loss = false;  // the last training step was an explicit batch: its loss is in dloss
 };
 
 namespace {
@@ -1313,6 +1322,7 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
     SurrogateState &st = *ga->surr;
     int rc = read_stats(ga);
     if (rc != GAPA_OK) return rc;
+    st.explicit_loss = false;
     const uint32_t gen = (uint32_t)(ga->generation + 1);
     const bool random = st.sp.flags & GAPA_SCREEN_RANDOM;
     bool full = (int64_t)gen <= st.sp.warmup_gens || st.force_full;
@@ -1368,7 +1378,9 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         if ((rc = ga_rank_and_gather(ga, false, F, pool, npool, s)) != GAPA_OK) return rc;
     }
     double *ds = st.dstats.as<double>();
-    if (predict) hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, neval, ds, st.hstats_dev + 2);
+    if (predict)
+        hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, neval, ds, st.hstats_dev + 2,
+                           st.hstats_dev + 5);
     if (!random) {
         // generation gen - 1's training is done with the buffer (and its loss is final)
         GAPA_HIP(hipStreamWaitEvent(s, st.ev_snap, 0));
@@ -1431,7 +1443,9 @@ int surrogate_train_batch(gapa_ga *ga, const int32_t *genes, const float *target
         return GAPA_E_INVALID_ARG;
     }
     GAPA_HIP(hipStreamSynchronize(st.ts));
-    return train_step(ga, genes, target, B, keep_grads, s);
+    const int rc = train_step(ga, genes, target, B, keep_grads, s);
+    if (rc == GAPA_OK) st.explicit_loss = true;
+    return rc;
 }
 
 int surrogate_tensor(gapa_ga *ga, int32_t which, int32_t kind, float *host, int64_t count, bool set)
@@ -1475,8 +1489,37 @@ int surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out)
     out->spearman = st.last_predicted ? st.hstats[2] : 0.0;
     out->rel_err = st.last_predicted ? st.hstats[3] : 0.0;
     out->loss = st.hstats[4];
+    if (st.explicit_loss) {
+        GAPA_HIP(hipDeviceSynchronize());
+        GAPA_HIP(hipMemcpy(&out->loss, st.dloss.ptr, 8, hipMemcpyDeviceToHost));
+    }
     out->fallbacks = st.fallbacks;
     out->train_steps = (int32_t)st.steps;
+    out->label_mean = st.last_predicted ? st.hstats[5] : 0.0;
+    out->label_spread = st.last_predicted ? st.hstats[6] : 0.0;
+    return GAPA_OK;
+}
+
+int surrogate_judge(const float *yhat, const int32_t *pool, const int64_t *F, int32_t m, double mu, double sd,
+                    double *out, hipStream_t s)
+{
+    DevBuf buf;  // [0, 2) mean and spread in, [2, 4) the statistics out
+    int rc = buf.reserve(32);
+    if (rc != GAPA_OK) return rc;
+    const double musd[2] = {mu, sd};
+    double res[2] = {0.0, 0.0};
+    hipError_t e = hipMemcpyAsync(buf.ptr, musd, 16, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, m, buf.as<double>(),
+                           buf.as<double>() + 2, nullptr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(res, buf.as<double>() + 2, 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    buf.release();
+    if (e != hipSuccess) return hip_fail(e, "surrogate judge");
+    out[0] = res[0];
+    out[1] = res[1];
     return GAPA_OK;
 }
 

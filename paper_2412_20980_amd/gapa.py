@@ -56,7 +56,7 @@ EXPORTED = (
     "gapa_surrogate_train_batch", "gapa_surrogate_tensor", "gapa_surrogate_last_predictions",
     "gapa_graph_get_tuning", "gapa_graph_set_tuning", "gapa_ga_autotune", "gapa_batch_autotune",
     "gapa_ga_record", "gapa_batch_record", "gapa_sixdst_eval", "gapa_ga_save", "gapa_ga_load",
-    "gapa_ga_params",
+    "gapa_ga_params", "gapa_batch_get_tuning", "gapa_batch_set_tuning", "gapa_surrogate_judge",
 )
 
 
@@ -87,6 +87,7 @@ class gapa_surrogate_report(C.Structure):
         ("generation", C.c_int64), ("evaluated", C.c_int32), ("pooled", C.c_int32), ("screened", C.c_int32),
         ("reserved", C.c_int32), ("spearman", C.c_double),
         ("rel_err", C.c_double), ("loss", C.c_double), ("fallbacks", C.c_int32), ("train_steps", C.c_int32),
+        ("label_mean", C.c_double), ("label_spread", C.c_double),
     ]
 
 
@@ -133,9 +134,12 @@ def lib() -> C.CDLL:
     L.gapa_graph_set_tuning.argtypes = [vp, C.POINTER(gapa_tuning)]
     L.gapa_ga_autotune.argtypes = [vp, C.c_int32, vp, C.POINTER(gapa_tuning)]
     L.gapa_batch_autotune.argtypes = [vp, C.c_int32, vp, C.POINTER(gapa_tuning)]
+    L.gapa_batch_get_tuning.argtypes = [vp, C.POINTER(gapa_tuning)]
+    L.gapa_batch_set_tuning.argtypes = [vp, C.POINTER(gapa_tuning)]
     L.gapa_surrogate_attach.argtypes = [vp, C.POINTER(gapa_surrogate_params), vp]
     L.gapa_surrogate_stats.argtypes = [vp, C.POINTER(gapa_surrogate_report)]
     L.gapa_surrogate_last_pool.argtypes = [vp, vp, C.c_int32, i32p]
+    L.gapa_surrogate_judge.argtypes = [vp, vp, vp, C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_double), vp]
     L.gapa_surrogate_predict.argtypes = [vp, vp, C.c_int32, vp, vp]
     L.gapa_surrogate_last_predictions.argtypes = [vp, vp, C.c_int32, i32p]
     L.gapa_surrogate_train_batch.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp]
@@ -217,6 +221,24 @@ def gapa_eval_population(h, genes, fitness=None, mcn=None, flags: int = 0, strea
                                           mcn.ctypes.data if mcn is not None else None,
                                           flags & ~GAPA_DEVICE_PTRS, _stream_ptr(stream)))
     return (fitness, mcn) if flags & GAPA_WANT_MCN else fitness
+
+
+def gapa_surrogate_judge(yhat, fitness, label_mean: float, label_spread: float, pool=None, stream=None):
+    """The judge's (Spearman, mean relative error) of predictions yhat (float32
+    device tensor, indexed by pool, an int32 device tensor, or directly)
+    against the exact fitness of the same children (int64 device tensor)."""
+    assert _is_dev_tensor(yhat) and yhat.dtype == torch.float32 and yhat.is_contiguous()
+    assert _is_dev_tensor(fitness) and fitness.dtype == torch.int64 and fitness.is_contiguous()
+    m = fitness.numel()
+    if pool is not None:
+        assert _is_dev_tensor(pool) and pool.dtype == torch.int32 and pool.is_contiguous() and pool.numel() == m
+    elif yhat.numel() < m:
+        raise ValueError("yhat needs one entry per fitness value when no pool is given")
+    out = (C.c_double * 2)()
+    _check(lib().gapa_surrogate_judge(yhat.data_ptr(), pool.data_ptr() if pool is not None else None,
+                                      fitness.data_ptr(), m, float(label_mean), float(label_spread), out,
+                                      _stream_ptr(stream)))
+    return out[0], out[1]
 
 
 def gapa_sixdst_eval(h, genes, hops: int, pc=None, mcn=None, flags: int = 0, stream=None):
@@ -571,6 +593,15 @@ class Batch:
 
     def kernel_times(self) -> dict:
         return _kernel_times(lib().gapa_batch_kernel_times, self.handle)
+
+    def get_tuning(self) -> dict:
+        t = gapa_tuning()
+        _check(lib().gapa_batch_get_tuning(self.handle, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in t._fields_}
+
+    def set_tuning(self, sweep_grid=4096, band_scan=32, sweeps=3, band_blocks=8192):
+        t = gapa_tuning(sweep_grid=sweep_grid, band_scan=band_scan, sweeps=sweeps, band_blocks=band_blocks)
+        _check(lib().gapa_batch_set_tuning(self.handle, C.byref(t)))
 
     def close(self):
         if self.handle:

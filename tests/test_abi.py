@@ -121,3 +121,45 @@ def test_flag_constants_match_the_header():
     # flag word is separate)
     call_flags = {k: v for k, v in flags.items() if k != "GAPA_SCREEN_RANDOM"}
     assert len(set(call_flags.values())) == len(call_flags)
+
+
+def test_new_entry_points_reject_bad_arguments_on_host(L):
+    from paper_2412_20980_amd import gapa
+    out = (C.c_double * 2)()
+    # no predictions, an empty judge sample, a zero spread: rejected before any device work
+    assert L.gapa_surrogate_judge(None, None, None, 4, 0.0, 1.0, out, None) == gapa.GAPA_E_INVALID_ARG
+    assert L.gapa_surrogate_judge(C.c_void_p(16), None, C.c_void_p(16), 0, 0.0, 1.0, out, None) == \
+        gapa.GAPA_E_INVALID_ARG
+    assert L.gapa_surrogate_judge(C.c_void_p(16), None, C.c_void_p(16), 4, 0.0, 0.0, out, None) == \
+        gapa.GAPA_E_INVALID_ARG
+    t = gapa.gapa_tuning(sweep_grid=1024, band_scan=16, sweeps=2, band_blocks=2048)
+    assert L.gapa_batch_set_tuning(None, C.byref(t)) == gapa.GAPA_E_INVALID_ARG
+    assert L.gapa_batch_get_tuning(None, C.byref(t)) == gapa.GAPA_E_INVALID_ARG
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Sizes and field offsets of the header's structs, printed by a C
+    program compiled against include/gapa.h, equal the binding's ctypes
+    mirrors."""
+    from paper_2412_20980_amd import gapa
+    structs = {"gapa_params": gapa.gapa_params, "gapa_surrogate_params": gapa.gapa_surrogate_params,
+               "gapa_surrogate_report": gapa.gapa_surrogate_report, "gapa_tuning": gapa.gapa_tuning}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gapa.h"', "int main(void) {"]
+    for s, cls in structs.items():
+        lines.append(f'printf("{s} size %zu\\n", sizeof({s}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{s} {f} %zu\\n", offsetof({s}, {f}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    os.system(f"gcc -std=c11 -I{os.path.join(ROOT, 'include')} {src} -o {exe}")
+    got = {}
+    for line in os.popen(str(exe)).read().splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    assert got, "the layout program did not run"
+    for s, cls in structs.items():
+        assert got[(s, "size")] == C.sizeof(cls), s
+        for f, _ in cls._fields_:
+            assert got[(s, f)] == getattr(cls, f).offset, (s, f)

@@ -38,6 +38,25 @@ def test_truncated_hops_match_oracle(gp, name, hops):
         assert (int(pc[i]), int(mcn[i])) == O.sixdst(g, genes[i], hops), i
 
 
+@pytest.mark.parametrize("hops", [6, 3])
+def test_multi_tile_truncated_hops_match_oracle(gp, hops):
+    """n = 1100: 9 x 9 product tiles of 128, so most tiles are off the
+    diagonal and written twice (mirrored); every row of a population of
+    removal sets is compared with the oracle's definition.  A sparse random
+    graph (mean degree 2.5) keeps many pairs beyond both hop counts, so the
+    truncation shows in every value."""
+    g = inputs.erdos_renyi(1100, 2.5, seed=21)
+    graph = gp.Graph.from_csr(g)
+    genes = inputs.random_population(g.n, 30, 10, seed=22)
+    # one row that removes the hubs, where truncation matters least
+    order = np.argsort(-np.diff(g.row_ptr), kind="stable")
+    genes[0] = np.sort(order[:30]).astype(np.int32)
+    print(f"n=1100 hops={hops}, 10 rows", flush=True)
+    pc, mcn = graph.sixdst(genes, hops)
+    for i in range(len(genes)):
+        assert (int(pc[i]), int(mcn[i])) == O.sixdst(g, genes[i], hops), i
+
+
 def test_enough_hops_give_the_components(gp):
     import torch
     g = inputs.barabasi_albert(2000, 2, seed=5)
