@@ -18,16 +18,18 @@ Generations are replayed from recorded HIP graphs unless --no-replay: the K
 timed generations are recorded beforehand as one graph, launched once.
 Inputs are resident in HBM before timing starts.  Prints one JSON line.
 
-Roofline: the batched fitness of one chunk of individuals (up to 1024) is the
-measured unit ("fitness_pass": removed-node bit sets, then the fixed sequence
-of component kernels, then PC).  Its algorithmic bytes are B_eval per
-evaluated individual (CSR row pointers and columns, the removed-node bit set,
-one label written and read per node, the int64 result); its duration is taken
-with HIP events on the launch stream around K passes over the GA's current
-population.
-Measured HBM traffic comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled
-by the same counters on a plain copy (profiles/fitness_traffic.json), and is
-reported only while the kernel sources still match the ones profiled.
+Roofline: the dominant kernel is the batched fitness pass of one chunk of up
+to 1024 individuals ("fitness_pass": the fixed sequence of component kernels
+from the removed-node bit sets to PC).  Its duration is taken with HIP events
+the library records on the launch stream around each pass, over the last K
+generations of the run (run eagerly for that purpose).  `achieved` is the
+pass's measured HBM traffic (rocprofv3 FETCH_SIZE and WRITE_SIZE over the same
+last K passes of the same command, scaled by the same counters on a plain copy:
+profiles/<workload>_traffic.json) divided by that duration, reported only while
+the kernel sources and launch shapes match the profiled ones.  The
+per-individual model of one full masked sweep per evaluation (B_eval) is
+reported beside it as `effective_GBs`: the bit-parallel pass shares every graph
+read among the individuals of a chunk, so that figure is not bounded by HBM.
 """
 from __future__ import annotations
 
@@ -56,6 +58,20 @@ def algorithmic_bytes_per_eval(n: int, nnz: int) -> int:
 
 FITNESS_SOURCES = ("fitness_bits.hip", "fitness.hip", "device_common.h")
 
+# Launch shapes of the fitness pass per workload (sweep_grid, band_scan,
+# sweeps, band_blocks): the autotuner's choice on each workload's warmed-up
+# population, pinned so that timed runs and counter runs use the same ones.
+DEFAULT_TUNING = {
+    "cl200k_k2000_p1024": "2048,16,2,2048",
+    "batched64_p128": "4096,32,3,8192",
+}
+
+
+def set_tuning(target, spec: str) -> dict:
+    sg, bs, sw, bb = (int(x) for x in spec.split(","))
+    target.set_tuning(sweep_grid=sg, band_scan=bs, sweeps=sw, band_blocks=bb)
+    return target.get_tuning()
+
 
 def kernel_source_hash() -> str:
     """Hash of the sources of the fitness-pass kernels (the ones the traffic
@@ -71,7 +87,7 @@ def kernel_source_hash() -> str:
 def measured_traffic(workload: str):
     """HBM bytes per fitness pass from the committed counter summary, or None
     when it is missing or the kernels changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "fitness_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -81,20 +97,31 @@ def measured_traffic(workload: str):
     return t
 
 
-def traffic_shapes(t):
-    """Launch shapes the counter runs pinned (their --tuning argument), for
-    comparison with the shapes this run's autotuner chose."""
-    if not t:
-        return None
-    cmd = t.get("command", "")
-    i = cmd.find("--tuning ")
-    return cmd[i + len("--tuning "):].split()[0] if i >= 0 else None
+def roofline(traffic, tuning, pass_ms, launches, units, unit_bytes):
+    """The fitness pass against the HBM roofline.  achieved = measured bytes
+    per pass / measured pass time, only when the counters were taken on these
+    kernel sources and launch shapes."""
+    valid = traffic is not None and traffic.get("tuning") == tuning
+    achieved = traffic["bytes_per_pass"] / (pass_ms * 1e-3) / 1e9 if valid else None
+    return {"bound": "hbm", "kernel": "fitness_pass",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if valid else None,
+            "traffic": traffic["bytes_per_pass"] if valid else None,
+            "avg_launch_ms": pass_ms, "launches": launches,
+            "profiled_pass_ms": traffic.get("pass_ms") if valid else None,
+            "frac_at_profiled_time": (traffic["bytes_per_pass"] / (traffic["pass_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                      if valid and traffic.get("pass_ms") else None),
+            "traffic_tuning": traffic.get("tuning") if traffic else None,
+            "effective_GBs": unit_bytes * units / (pass_ms * 1e-3) / 1e9,
+            "algorithmic_bytes_per_unit": unit_bytes, "units_per_launch": units}
 
 
-def cpu_baseline(w, budget_s: float = 12.0):
+def cpu_baseline(w, budget_s: float = 12.0, budget_1t_s: float = 10.0):
     """The oracle as it stands, on this host's cores, over a bounded sample of
     the same workload: generation 0 plus as many generations as fit in the
-    budget (each evaluates the same number of individuals as a GPU step)."""
+    budget (each evaluates the same number of individuals as a GPU step).
+    Then one thread: fitness evaluations of the oracle's population at the
+    end of that sample, as many as fit in the second budget."""
     from oracle import cnd_oracle as O
     threads = O.default_threads()
     t0 = time.perf_counter()
@@ -106,9 +133,20 @@ def cpu_baseline(w, budget_s: float = 12.0):
         gens += 1
         evals += w.offspring or w.pop
     dt = time.perf_counter() - t0
+    # one thread: evaluate rows of the current population until the budget is spent
+    rows = ga.pop
+    t1 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t1 < budget_1t_s and done < len(rows):
+        O.eval_population(w.graph, rows[done:done + 16], nthreads=1)
+        done += len(rows[done:done + 16])
+    dt1 = time.perf_counter() - t1
     return {"value": evals / dt, "unit": "fitness evals/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle GA (C, OpenMP over individuals) on the same graph: generation 0 + {gens} "
-                      f"generations, {evals} BFS fitness evaluations with operators and elitism, {dt:.1f} s wall"}
+                      f"generations, {evals} BFS fitness evaluations with operators and elitism, {dt:.1f} s wall",
+            "value_1thread": done / dt1,
+            "sample_1thread": f"{done} BFS fitness evaluations of the oracle population at generation {gens} "
+                              f"on one thread, {dt1:.1f} s wall"}
 
 
 def run_batched(args, torch, gapa, inputs):
@@ -124,12 +162,13 @@ def run_batched(args, torch, gapa, inputs):
     graphs = [gapa.Graph.from_csr(w.graph, trust=True) for w in ws]
     params = [dict(k=w.k, pop=w.pop, seed=w.seed, pc=w.pc, pm=w.pm, tournament=w.tournament) for w in ws]
     bt = gapa.Batch(graphs, params, stream=stream, replay=not args.no_replay)
+    tuning = set_tuning(bt, args.tuning or DEFAULT_TUNING["batched64_p128"])
     bt.step(args.warmup, stream=stream)
     torch.cuda.synchronize()
-    tuning = None if args.no_autotune else bt.autotune(reps=3, stream=stream)
-    bt.step(2, stream=stream)
+    if args.autotune:
+        tuning = bt.autotune(reps=3, stream=stream)
+    bt.step(2, stream=stream)  # eager generations: buffers sized and recordings re-made for the shapes
     torch.cuda.synchronize()
-    args.warmup += 2
     if not args.no_replay and args.steps <= 4096:
         bt.record(args.steps)  # the K timed generations as one graph launch
     t0 = time.perf_counter()
@@ -146,12 +185,13 @@ def run_batched(args, torch, gapa, inputs):
     lam = sum(w.offspring or w.pop for w in ws)
     fit_ms = passes["fitness_pass"][1] / passes["fitness_pass"][0]
     unit_bytes = sum((w.offspring or w.pop) * algorithmic_bytes_per_eval(w.graph.n, w.graph.nnz) for w in ws)
-    achieved = unit_bytes / (fit_ms * 1e-3) / 1e9
+    # one pass evaluates every instance's offspring: one unit = the whole batch
+    roof = roofline(measured_traffic("batched64_p128"), tuning, fit_ms, passes["fitness_pass"][0], 1, unit_bytes)
     return {
         "metric": METRIC,
         "value": lam * args.steps / dt,
         "unit": "fitness evals/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "untimed_extra_generations": 2,
         "ms_per_step": dt * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64", "data": "synthetic",
@@ -159,10 +199,8 @@ def run_batched(args, torch, gapa, inputs):
                    "sum_m": sum(w.graph.m for w in ws), "pop": 128, "k": "n/100", "replay": not args.no_replay,
                    "tuning": tuning,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "fitness_pass", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_ms": fit_ms, "launches": passes["fitness_pass"][0],
-                     "algorithmic_bytes_per_launch": unit_bytes},
+        "roofline": roof,
+        "kernel_source_sha256": kernel_source_hash(),
         "operator_ms_per_step": {k: v[1] / v[0] for k, v in sorted(passes.items()) if k != "fitness_pass"},
     }
 
@@ -383,10 +421,11 @@ def main():
     ap.add_argument("--no-replay", action="store_true", help="launch generations eagerly instead of replaying a "
                     "recorded HIP graph")
     ap.add_argument("--no-time-to-target", action="store_true", help="skip the surrogate time-to-target runs")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes of the fitness pass")
+    ap.add_argument("--autotune", action="store_true", help="choose the fitness pass's launch shapes with the "
+                    "library's autotuner on the warmed-up population instead of the pinned ones")
     ap.add_argument("--tuning", default=None,
-                    help="sweep_grid,band_scan,sweeps,band_blocks: use these launch shapes instead of autotuning "
-                         "(profiling runs pin the shapes the autotuner picks)")
+                    help="sweep_grid,band_scan,sweeps,band_blocks: launch shapes of the fitness pass (default: the "
+                         "pinned shapes of the workload, the ones its counter profile was taken with)")
     ap.add_argument("--ttt-seeds", default="0", help="comma-separated seeds of the time-to-target runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -432,18 +471,15 @@ def main():
     graph = gapa.Graph.from_csr(g, trust=True)
     ga = gapa.GA(graph, w.k, w.pop, w.seed, w.pc, w.pm, w.tournament, w.offspring, stream=stream,
                  replay=not args.no_replay)
+    # launch shapes of the fitness pass: pinned (the counter runs profile the
+    # same ones), or chosen by the autotuner on the warmed-up population
+    tuning = set_tuning(graph, args.tuning or DEFAULT_TUNING[w.name])
     ga.step(args.warmup, stream=stream)
     torch.cuda.synchronize()
-    # launch shapes of the fitness pass, chosen on the warmed-up population
-    if args.tuning:
-        sg, bs, sw, bb = (int(x) for x in args.tuning.split(","))
-        graph.set_tuning(sweep_grid=sg, band_scan=bs, sweeps=sw, band_blocks=bb)
-        tuning = graph.get_tuning()
-    else:
-        tuning = graph.get_tuning() if args.no_autotune else ga.autotune(reps=3, stream=stream)
-    ga.step(2, stream=stream)  # one eager generation re-records the replayed one with the new shapes
+    if args.autotune:
+        tuning = ga.autotune(reps=3, stream=stream)
+    ga.step(2, stream=stream)  # eager generations: buffers sized and recordings re-made for the shapes
     torch.cuda.synchronize()
-    args.warmup += 2
     if not args.no_replay and args.steps <= 4096:
         ga.record(args.steps)  # the K timed generations as one graph launch
 
@@ -454,36 +490,19 @@ def main():
     dt = time.perf_counter() - t0
     _, best_f, gen_count = ga.best()
 
-    # operator-kernel and elitism durations: HIP events the library records
-    # around those single kernels on the launch stream
+    # roofline unit: the fitness pass of each of K further generations, run
+    # eagerly with HIP events the library records around each pass, the
+    # operator kernel and elitism on the launch stream (the last K passes of
+    # the run: the ones the counter runs of the same command sum)
     ga.set_timing(1)
     ga.step(args.steps, stream=stream)
     torch.cuda.synchronize()
     passes = ga.kernel_times()
     ga.set_timing(0)
     stats = ga.fitness_stats()
-
-    # batched-fitness pass: HIP events on the launch stream around K passes
-    # over the GA's current population (1024 evolved individuals, device
-    # resident); one pass = removed-node bit sets + components + PC
-    pop_now, _ = ga.population()
-    genes = torch.from_numpy(pop_now).to("cuda")
-    fit = torch.empty(genes.shape[0], dtype=torch.int64, device="cuda")
-    for _ in range(2):
-        gapa.gapa_eval_population(graph.handle, genes, fitness=fit, flags=gapa.GAPA_TRUST_INPUT, stream=stream)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        gapa.gapa_eval_population(graph.handle, genes, fitness=fit, flags=gapa.GAPA_TRUST_INPUT, stream=stream)
-    ev1.record(stream)
-    ev1.synchronize()
-    avg_ms = ev0.elapsed_time(ev1) / args.steps
-    f_launches = args.steps
-    per_launch = genes.shape[0]
+    f_launches, f_total = passes["fitness_pass"]
+    avg_ms = f_total / f_launches
     unit_bytes = algorithmic_bytes_per_eval(g.n, g.nnz)
-    achieved = unit_bytes * per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(w.name)
 
     evals_per_s = lam * args.steps / dt
     out = {
@@ -493,6 +512,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "untimed_extra_generations": 2,
         "ms_per_step": dt * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
@@ -502,14 +522,8 @@ def main():
         "config": {"workload": w.name, "graph": g.name, "n": g.n, "m": g.m, "k": w.k, "pop": w.pop,
                    "offspring": lam, "pc": w.pc, "pm": w.pm, "tournament": w.tournament,
                    "replay": not args.no_replay, "tuning": tuning, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "fitness_pass", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic["bytes_per_pass"] if traffic else None,
-                     "traffic_GBs": traffic["bytes_per_pass"] / (avg_ms * 1e-3) / 1e9 if traffic else None,
-                     "traffic_profiled_shapes": traffic_shapes(traffic),
-                     "avg_launch_ms": avg_ms, "launches": f_launches,
-                     "algorithmic_bytes_per_unit": unit_bytes, "units_per_launch": per_launch},
-        "operator_ms_per_step": {k: v[1] / args.steps for k, v in sorted(passes.items()) if k != "fitness_pass"},
+        "roofline": roofline(measured_traffic(w.name), tuning, avg_ms, f_launches, lam, unit_bytes),
+        "operator_ms_per_step": {k: v[1] / v[0] for k, v in sorted(passes.items()) if k != "fitness_pass"},
         "fitness_stats": stats,
         "kernel_source_sha256": kernel_source_hash(),
         "best_pc": best_f,
