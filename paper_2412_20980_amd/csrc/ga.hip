@@ -150,11 +150,19 @@ __device__ int32_t wave_list_slots(const uint32_t *bits, int32_t k, uint16_t *li
 // first draw (slot, ind, gen, stream | t), t = 0, 1, ..., that is not in the
 // membership set U; U gains it and, with `swap`, loses the slot's previous
 // value.  One wave resolves 64 slots at a time: every lane takes its attempt
-// 0, and lane l's draw is accepted if it is not a member given the lanes
-// before it (not in U unless an earlier lane freed it, and not taken by an
-// earlier lane).  All lanes before the first rejected one are committed at
-// once; the rejected one is resolved alone with further attempts, exactly as
-// the sequential rule would; the next batch starts after it.
+// 0, and lane l's draw is accepted if it is not a member (checked against U
+// as it stood before the batch) and no earlier lane drew the same value.  All
+// lanes before the first rejected one are committed at once; the rejected
+// one is resolved alone with further attempts from its attempt 0, exactly as
+// the sequential rule would given the committed lanes; the next batch starts
+// after it.  A draw equal to a value an earlier lane frees (swap) is
+// rejected too and then accepted by the lone resolution: the same result.
+//
+// Equal draws within the batch are found through U itself: every candidate
+// not yet a member sets its bit with an atomic OR, and a lane that finds its
+// bit already set by another lane of the batch marks a collision.  Without
+// one (the usual case) no lane is taken; with one the lanes compare values
+// directly.  Bits set for lanes that are not committed are cleared again.
 __device__ void wave_draw_in_order(const OpLds &l, const Op &a, const uint16_t *list, int32_t count, bool swap,
                                    uint32_t ind, uint32_t gen, uint32_t stream)
 {
@@ -164,27 +172,41 @@ __device__ void wave_draw_in_order(const OpLds &l, const Op &a, const uint16_t *
         const int32_t nvalid = min(64, count - pos);
         const bool valid = lane < nvalid;
         const int32_t j = valid ? (list ? list[pos + lane] : pos + lane) : 0;
-        const uint32_t c = valid ? bounded(draw(a.seed, j, ind, gen, stream, 0).w0, a.n) : 0xFFFFFFFFu;
+        const uint32_t c = valid ? bounded(draw(a.seed, j, ind, gen, stream, 0).w0, a.n) : 0u;
         const int32_t old = (valid && swap) ? l.row[j] : -1;
-        const bool in_u = valid && lds_test(l.U, c);
-        bool taken = false, freed = false;
-        // q is uniform across the wave: lane q's values are read with readlane
-        for (int q = 0; q < nvalid; ++q) {
-            const uint32_t cq = (uint32_t)__builtin_amdgcn_readlane((int)c, q);
-            const int32_t oq = __builtin_amdgcn_readlane(old, q);
-            if (q < lane) {
-                taken |= cq == c;
-                freed |= oq == (int32_t)c;
+        const uint32_t w = c >> 5, bit = 1u << (c & 31);
+        // membership before the batch: every lane reads before any lane writes
+        const bool in_u = valid && (l.U[w] & bit);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        bool mine = false, clash = false;
+        if (valid && !in_u) {
+            const uint32_t prev = atomicOr(&l.U[w], bit);
+            mine = !(prev & bit);
+            clash = !mine;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        bool taken = false;
+        if (__ballot(clash) != 0) {
+            // q is uniform across the wave: lane q's value is read with readlane
+            for (int q = 0; q < nvalid; ++q) {
+                const uint32_t cq = (uint32_t)__builtin_amdgcn_readlane((int)c, q);
+                taken |= q < lane && cq == c;
             }
         }
-        const bool reject = valid && ((in_u && !freed) || taken);
+        const bool reject = valid && (in_u || taken);
         const uint64_t rej = __ballot(reject);
         const int32_t f = rej ? (int32_t)__ffsll((unsigned long long)rej) - 1 : nvalid;
-        if (swap && lane < f) atomicAnd(&l.U[old >> 5], ~(1u << (old & 31)));
+        // lanes from f on are not committed: clear the bits they set
+        if (mine && lane >= f) atomicAnd(&l.U[w], ~bit);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (lane < f) {
-            atomicOr(&l.U[c >> 5], 1u << (c & 31));
+            // (a committed value whose bit a later, uncommitted lane with the
+            // same draw had set and just cleared is set again)
+            atomicOr(&l.U[w], bit);
+            if (swap) atomicAnd(&l.U[old >> 5], ~(1u << (old & 31)));
             l.row[j] = (int32_t)c;
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (f < nvalid) {
             if (lane == f) {
                 const int32_t u = first_non_member(l.U, c, 0, a.seed, j, ind, gen, stream, a.n);
@@ -200,6 +222,7 @@ __device__ void wave_draw_in_order(const OpLds &l, const Op &a, const uint16_t *
         } else {
             pos += nvalid;
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 }
 
@@ -337,15 +360,16 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs args)
 
     const int32_t *base = a.pop + (int64_t)(o % a.P) * a.k;
     const int32_t *donor = a.pop + (int64_t)s_donor * a.k;
-    // crossover coins; values taken from the base row enter the membership set
+    // crossover coins; the base row is staged in LDS (row[] holds it while
+    // duplicates are located), values taken from it enter the membership set
 #pragma unroll 4
     for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
         const Words4 x = draw(a.seed, j, o, gen, kStreamXover, 0);
         const bool take = (uint64_t)x.w0 < a.t_pc;
-        const int32_t c = take ? donor[j] : base[j];
-        l.row[j] = c;
+        const int32_t b = base[j];
+        l.row[j] = b;
         if (take) atomicOr(&l.from_donor[j >> 5], 1u << (j & 31));
-        else atomicOr(&l.U[c >> 5], 1u << (c & 31));
+        else atomicOr(&l.U[b >> 5], 1u << (b & 31));
         if ((uint64_t)x.w1 < a.t_pm) atomicOr(&l.mut[j >> 5], 1u << (j & 31));
     }
     __syncthreads();
@@ -357,26 +381,27 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs args)
 #pragma unroll 2
     for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
         if (!((l.from_donor[j >> 5] >> (j & 31)) & 1u)) continue;
-        const int32_t c = l.row[j];
+        const int32_t c = donor[j];
         if (lds_test(l.U, c)) {
-            // position of c in the base row: galloping from slot j (the rows
-            // of a converged population differ by small shifts), then a
-            // binary search inside the bracket
+            // position of c in the base row (staged in row[]): galloping from
+            // slot j (the rows of a converged population differ by small
+            // shifts), then a binary search inside the bracket
+            const int32_t *bs = l.row;
             int32_t lo, hi;
-            if (base[j] < c) {
+            if (bs[j] < c) {
                 int32_t b = 1;
-                while (j + b < a.k && base[j + b] < c) b <<= 1;
+                while (j + b < a.k && bs[j + b] < c) b <<= 1;
                 lo = j + (b >> 1) + 1;
                 hi = min(j + b, a.k);
             } else {
                 int32_t b = 1;
-                while (j - b >= 0 && base[j - b] >= c) b <<= 1;
+                while (j - b >= 0 && bs[j - b] >= c) b <<= 1;
                 lo = max(j - b + 1, 0);
                 hi = j - (b >> 1);
             }
             while (lo < hi) {
                 const int32_t mid = (lo + hi) >> 1;
-                if (base[mid] < c) lo = mid + 1;
+                if (bs[mid] < c) lo = mid + 1;
                 else hi = mid;
             }
             const int32_t later = lo < j ? j : lo;
@@ -385,6 +410,10 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs args)
             atomicOr(&l.U[c >> 5], 1u << (c & 31));
         }
     }
+    __syncthreads();
+    // the child's row by slot: donor values where the coin took the donor
+    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x)
+        if ((l.from_donor[j >> 5] >> (j & 31)) & 1u) l.row[j] = donor[j];
     __syncthreads();
 
     // repair, then mutation, each in ascending slot order (one wave)
