@@ -320,7 +320,8 @@ void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, const std:
 
 void release_workspace(FitnessWorkspace &w)
 {
-    for (DevBuf *b : {&w.parent, &w.count, &w.dead, &w.reach, &w.ucount, &w.pairs, &w.worklist, &w.small, &w.masks,
+    for (DevBuf *b : {&w.parent, &w.count, &w.dead, &w.reach, &w.ucount, &w.pairs, &w.worklist, &w.pflag, &w.small,
+                      &w.masks,
                       &w.alive, &w.genes, &w.fitness, &w.mcn, &w.flag, &w.six_mats, &w.six_tot})
         b->release();
     for (FitnessWorkspace *l : w.lanes) {
@@ -335,6 +336,7 @@ void release_workspace(FitnessWorkspace &w)
     if (w.fork) (void)hipEventDestroy(w.fork);
     w.fork = nullptr;
     w.stats_ctr = nullptr;
+    w.pflag_clear = false;
 }
 
 int fitness_stats(FitnessWorkspace &w, int64_t out[4])

@@ -250,40 +250,58 @@ __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restr
 }
 
 // Pull for one node by its lane group: OR the neighbours' reach rows (in
-// degree-descending order), four at a time, until every pending bit is
-// covered or max_scan neighbours have been read.  Returns true if the node
-// gained bits.  Whatever stays pending is picked up by a later sweep or, in
-// the end, by the union-find pass, so the cap only moves work.
+// degree-descending order) until every pending bit is covered or max_scan
+// neighbours have been read.  Returns true if the node gained bits.
+// Whatever stays pending is picked up by a later sweep or, in the end, by the
+// union-find pass, so the cap only moves work.
+//
+// The node's own bits and its neighbour range are loaded together; then the
+// neighbours are taken kPullChunk at a time: all their ids, then all their
+// reach rows, each set of loads in flight at once (two dependent round trips
+// per chunk).  Reach rows are read with plain loads: within a kernel another
+// XCD's newer bits may not be visible yet, which only delays them (a row
+// read early holds a subset of its final bits, and every bit it holds is a
+// true connection to the root); each kernel sees all bits of the kernels
+// before it.
+constexpr int kPullChunk = 16;
 
 __device__ __forceinline__ bool pull_node(int32_t v, int Wd, int w, uint64_t gmask,
                                           const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
                                           const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach,
-                                          int32_t max_scan)
+                                          int32_t max_scan, bool *still_pending = nullptr)
 {
-    const uint32_t mine = ld_relaxed_u(reach + (int64_t)v * Wd + w);
-    const uint32_t pend = ~dead[(int64_t)v * Wd + w] & ~mine;
+    const int64_t vo = (int64_t)v * Wd + w;
+    const uint32_t mine = reach[vo];
+    const uint32_t dv = dead[vo];
+    const int32_t e0 = row_ptr[v], eN = row_ptr[v + 1];
+    const uint32_t pend = ~dv & ~mine;
+    if (still_pending) *still_pending = false;
     if ((__ballot(pend != 0) & gmask) == 0) return false;
+    const int32_t e1 = eN - e0 > max_scan ? e0 + max_scan : eN;
     uint32_t acc = 0;
-    const int32_t e0 = row_ptr[v];
-    const int32_t e1 = row_ptr[v + 1] - e0 > max_scan ? e0 + max_scan : row_ptr[v + 1];
-    int32_t e = e0;
-    for (; e + 4 <= e1; e += 4) {
-        const int32_t u0 = colD[e], u1 = colD[e + 1], u2 = colD[e + 2], u3 = colD[e + 3];
-        acc |= ld_relaxed_u(reach + (int64_t)u0 * Wd + w) | ld_relaxed_u(reach + (int64_t)u1 * Wd + w) |
-               ld_relaxed_u(reach + (int64_t)u2 * Wd + w) | ld_relaxed_u(reach + (int64_t)u3 * Wd + w);
+    for (int32_t e = e0; e < e1; e += kPullChunk) {
+        int32_t u[kPullChunk];
+#pragma unroll
+        for (int t = 0; t < kPullChunk; ++t) u[t] = e + t < e1 ? colD[e + t] : -1;
+#pragma unroll
+        for (int t = 0; t < kPullChunk; ++t)
+            if (u[t] >= 0) acc |= reach[(int64_t)u[t] * Wd + w];
         if ((__ballot((acc & pend) != pend) & gmask) == 0) break;
     }
-    if ((__ballot((acc & pend) != pend) & gmask) != 0)
-        for (; e < e1; ++e) acc |= ld_relaxed_u(reach + (int64_t)colD[e] * Wd + w);
     const uint32_t gain = acc & pend;
-    if (gain) __hip_atomic_store(reach + (int64_t)v * Wd + w, mine | gain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gain) reach[vo] = mine | gain;
+    if (still_pending) *still_pending = (__ballot((pend & ~gain) != 0) & gmask) != 0;
     return (__ballot(gain != 0) & gmask) != 0;
 }
 
-// One band of the ordered sweep: nodes band_v[b0, b1).
+// One band of the ordered sweep: nodes band_v[b0, b1).  A node's reach row
+// is written only by its own pull, so its pending bits are final once it has
+// pulled: pflag[v] records whether any is left (every non-isolated node is in
+// exactly one band, so every flag the compaction reads is written here).
 __global__ void k_pull_band(const int32_t *__restrict__ band_v, int32_t b0, int32_t b1, int32_t Wd,
                             const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
-                            const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach, int32_t max_scan)
+                            const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach, int32_t max_scan,
+                            uint8_t *__restrict__ pflag)
 {
     const int lane = threadIdx.x & 63;
     const int w = lane & (Wd - 1);
@@ -299,7 +317,11 @@ __global__ void k_pull_band(const int32_t *__restrict__ band_v, int32_t b0, int3
         const bool valid = idx < count;
         const int32_t v = valid ? band_v[b0 + idx] : 0;
         if (__ballot(valid) == 0) continue;
-        if (valid) pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach, max_scan);
+        if (valid) {
+            bool left;
+            pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach, max_scan, &left);
+            if (w == 0) pflag[v] = left ? 1 : 0;
+        }
     }
 }
 
@@ -335,59 +357,53 @@ __device__ __forceinline__ C block_reserve(int32_t mine, C *counter, int32_t *s_
 constexpr int kPairCountSlot = 36;
 static_assert(kPairCountSlot % 2 == 0 && kPairCountSlot >= 2 + 33 && kPairCountSlot + 2 <= 64, "counter layout");
 
-constexpr int kCompactRange = 64;   // input items per compaction step
-constexpr int kPendStepsMax = 8;    // steps per block in k_collect_pending, at most
-constexpr int kPendBlocks = 1536;   // blocks of k_collect_pending aimed at
+// Nodes still pending after the ordered sweep -> worklist: the compaction of
+// the pending flags over node ids (isolated nodes keep flag 0).  A thread
+// reads 16 flags at once; a block scans its counts and reserves its room in
+// the worklist with one global atomic.
+constexpr int kFlagsPerThread = 16;
 
-// Nodes still pending after the ordered sweep -> worklist.  A block owns
-// steps * kCompactRange nodes, taken kCompactRange at a time; in each
-// step every thread issues the loads of all its (node, word) entries before
-// testing any of them.  Found nodes gather in LDS, and the block reserves its
-// room in the worklist with a single global atomic.  A block's steps run one
-// after another, each waiting on its loads, so blocks are kept short: the
-// host picks steps for about kPendBlocks blocks (at n = 200k two steps, 1.5k
-// blocks, beat eight steps, 390 blocks, and one step, 3k blocks).
-__global__ __launch_bounds__(kBlk) void k_collect_pending(const int32_t *__restrict__ band_v, int32_t count,
-                                                          int32_t steps, int32_t Wd, const uint32_t *__restrict__ dead,
-                                                          const uint32_t *__restrict__ reach,
+__global__ __launch_bounds__(kBlk) void k_collect_pending(const uint8_t *__restrict__ pflag, int32_t n,
                                                           int32_t *__restrict__ worklist, int32_t *__restrict__ wl_count)
 {
-    __shared__ int32_t s_tot, s_base, s_off;
-    __shared__ int32_t s_list[kPendStepsMax * kCompactRange];
-    const int w = threadIdx.x & (Wd - 1);
-    const uint64_t gmask = group_mask(Wd);
-    const int32_t gpb = blockDim.x / Wd;
-    if (threadIdx.x == 0) s_off = 0;
-    __syncthreads();
-    // iterations per step: kCompactRange / gpb = kCompactRange * Wd / kBlk <= kIter
-    constexpr int kIter = kCompactRange * 32 / kBlk;
-    const int32_t iters = (kCompactRange + gpb - 1) / gpb;
-    for (int step = 0; step < steps; ++step) {
-        const int32_t r0 = (blockIdx.x * steps + step) * kCompactRange;
-        if (r0 >= count) break;  // uniform over the block
-        const int32_t r1 = min(count, r0 + kCompactRange);
-        uint32_t pend[kIter];
-        int32_t vv[kIter];
-#pragma unroll
-        for (int it = 0; it < kIter; ++it) {
-            const int32_t idx = r0 + it * gpb + (int32_t)(threadIdx.x / Wd);
-            vv[it] = (it < iters && idx < r1) ? band_v[idx] : -1;
-        }
-#pragma unroll
-        for (int it = 0; it < kIter; ++it) {
-            const int32_t v = vv[it];
-            pend[it] = v >= 0 ? (~dead[(int64_t)v * Wd + w] & ~reach[(int64_t)v * Wd + w]) : 0u;
-        }
-#pragma unroll
-        for (int it = 0; it < kIter; ++it) {
-            const bool any = (__ballot(pend[it] != 0) & gmask) != 0;
-            if (vv[it] >= 0 && any && w == 0) s_list[atomicAdd(&s_off, 1)] = vv[it];
-        }
+    __shared__ int32_t s_wave[kBlk / 64];
+    __shared__ int32_t s_base;
+    const int32_t v0 = (blockIdx.x * kBlk + threadIdx.x) * kFlagsPerThread;
+    uint32_t f[kFlagsPerThread / 4] = {0u, 0u, 0u, 0u};
+    if (v0 + kFlagsPerThread <= n) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(pflag + v0);
+        f[0] = q.x;
+        f[1] = q.y;
+        f[2] = q.z;
+        f[3] = q.w;
+    } else {
+        for (int t = 0; t < kFlagsPerThread && v0 + t < n; ++t) f[t >> 2] |= (uint32_t)pflag[v0 + t] << (8 * (t & 3));
     }
+    int32_t mine = 0;
+#pragma unroll
+    for (int t = 0; t < kFlagsPerThread / 4; ++t) mine += __popc(f[t] & 0x01010101u);
+    // exclusive scan of the counts over the block, then one reservation
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) s_wave[wv] = incl;
     __syncthreads();
-    const int32_t found = s_off;
-    const int32_t base = block_reserve(threadIdx.x == 0 ? found : 0, wl_count, &s_tot, &s_base, &s_off);
-    for (int32_t q = threadIdx.x; q < found; q += blockDim.x) worklist[base + q] = s_list[q];
+    int32_t before = 0, total = 0;
+#pragma unroll
+    for (int q = 0; q < kBlk / 64; ++q) {
+        before += q < wv ? s_wave[q] : 0;
+        total += s_wave[q];
+    }
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(wl_count, total) : 0;
+    __syncthreads();
+    int32_t pos = s_base + before + incl - mine;
+#pragma unroll
+    for (int t = 0; t < kFlagsPerThread; ++t)
+        if ((f[t >> 2] >> (8 * (t & 3))) & 1u) worklist[pos++] = v0 + t;
 }
 
 // Further sweeps over the worklist; sweep s runs only if sweep s - 1 changed
@@ -433,21 +449,26 @@ __device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t
                                               const uint32_t *__restrict__ dead, const uint32_t *__restrict__ reach,
                                               bool valid, uint32_t &single, uint32_t &multi)
 {
-    const uint32_t pend = valid ? (~dead[(int64_t)v * Wd + w] & ~reach[(int64_t)v * Wd + w]) : 0u;
+    // the node's bits and its neighbour range are loaded together
+    const int64_t vo = (int64_t)v * Wd + w;
+    const uint32_t dv = valid ? dead[vo] : ~0u;
+    const uint32_t rv = valid ? reach[vo] : 0u;
+    const int32_t e0 = valid ? row_ptr[v] : 0, e1 = valid ? row_ptr[v + 1] : 0;
+    const uint32_t pend = ~dv & ~rv;
     uint32_t nb = 0;
     if ((__ballot(pend != 0) & gmask) != 0) {
-        // four neighbours per step; stopping once every pending bit has a
+        // kPullChunk neighbours at a time (their ids, then their bits, each set
+        // of loads in flight together); stopping once every pending bit has a
         // surviving neighbour (or at the end of the list) gives the same split
-        int32_t e = row_ptr[v];
-        const int32_t e1 = row_ptr[v + 1];
-        for (; e + 4 <= e1; e += 4) {
-            const int32_t u0 = colD[e], u1 = colD[e + 1], u2 = colD[e + 2], u3 = colD[e + 3];
-            nb |= ~dead[(int64_t)u0 * Wd + w] | ~dead[(int64_t)u1 * Wd + w] | ~dead[(int64_t)u2 * Wd + w] |
-                  ~dead[(int64_t)u3 * Wd + w];
+        for (int32_t e = e0; e < e1; e += kPullChunk) {
+            int32_t u[kPullChunk];
+#pragma unroll
+            for (int t = 0; t < kPullChunk; ++t) u[t] = e + t < e1 ? colD[e + t] : -1;
+#pragma unroll
+            for (int t = 0; t < kPullChunk; ++t)
+                if (u[t] >= 0) nb |= ~dead[(int64_t)u[t] * Wd + w];
             if ((__ballot((nb & pend) != pend) & gmask) == 0) break;
         }
-        if ((__ballot((nb & pend) != pend) & gmask) != 0)
-            for (; e < e1; ++e) nb |= ~dead[(int64_t)colD[e] * Wd + w];
     }
     single = pend & ~nb;
     multi = pend & nb;
@@ -549,10 +570,15 @@ __device__ __forceinline__ void uf_unite(int32_t *parent, int32_t a, int32_t b)
 // Union over the surviving edges of each pending pair (key: slot << 32 |
 // node): a surviving neighbour that is reached joins the root's set; a
 // pending one (each such edge once, from its smaller end) is united with it.
-__global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count, const Insts I,
-                             int32_t Wd, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                             const uint32_t *__restrict__ dead, const uint32_t *__restrict__ reach,
-                             const int32_t *__restrict__ root, int32_t *__restrict__ parent)
+// Neighbours are taken kHookChunk at a time: their ids, then their bits, each
+// set of loads in flight together, then the unions.
+constexpr int kHookChunk = 8;
+
+__global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count,
+                             const Insts I, int32_t Wd, const int32_t *__restrict__ row_ptr,
+                             const int32_t *__restrict__ col, const uint32_t *__restrict__ dead,
+                             const uint32_t *__restrict__ reach, const int32_t *__restrict__ root,
+                             int32_t *__restrict__ parent)
 {
     const int64_t count = (int64_t)*pair_count;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
@@ -563,11 +589,23 @@ __global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const unsigned l
         const int32_t w = i >> 5;
         const uint32_t bit = 1u << (i & 31);
         int32_t *pi = parent + uf_block(I, gi);
-        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-            const int32_t u = col[e];
-            if (dead[(int64_t)u * Wd + w] & bit) continue;
-            if (reach[(int64_t)u * Wd + w] & bit) uf_unite(pi, v - off, root[gi] - off);
-            else if (v < u) uf_unite(pi, v - off, u - off);
+        const int32_t e1 = row_ptr[v + 1];
+        for (int32_t e = row_ptr[v]; e < e1; e += kHookChunk) {
+            int32_t u[kHookChunk];
+            uint32_t du[kHookChunk], ru[kHookChunk];
+#pragma unroll
+            for (int t = 0; t < kHookChunk; ++t) u[t] = e + t < e1 ? col[e + t] : -1;
+#pragma unroll
+            for (int t = 0; t < kHookChunk; ++t) {
+                du[t] = u[t] >= 0 ? dead[(int64_t)u[t] * Wd + w] : bit;
+                ru[t] = u[t] >= 0 ? reach[(int64_t)u[t] * Wd + w] : 0u;
+            }
+#pragma unroll
+            for (int t = 0; t < kHookChunk; ++t) {
+                if (du[t] & bit) continue;
+                if (ru[t] & bit) uf_unite(pi, v - off, root[gi] - off);
+                else if (v < u[t]) uf_unite(pi, v - off, u[t] - off);
+            }
         }
     }
 }
@@ -702,6 +740,14 @@ int reserve_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, hipSt
     const int64_t max_pairs = (int64_t)B * std::max(g->n_noniso, 1);
     if ((rc = ws.pairs.reserve((size_t)max_pairs * 8)) != GAPA_OK) return rc;
     if ((rc = ws.worklist.reserve((size_t)std::max(g->n_noniso, 1) * 4)) != GAPA_OK) return rc;
+    // pending flags per node: written for every non-isolated node by each
+    // pass; isolated nodes keep the zero they get here
+    const size_t flag_bytes = ((size_t)n + 15) & ~(size_t)15;
+    if (ws.pflag.bytes < flag_bytes || !ws.pflag_clear) {
+        if ((rc = ws.pflag.reserve(flag_bytes)) != GAPA_OK) return rc;
+        if ((rc = launch_fill_u32(ws.pflag.ptr, 0u, (int64_t)(flag_bytes / 4), s)) != GAPA_OK) return rc;
+        ws.pflag_clear = true;
+    }
     const size_t nparts = sh.multi ? 0 : (size_t)g->tune.sweep_grid * B;
     if ((rc = ws.small.reserve((size_t)(2 * (size_t)sh.S + 64 + nparts) * 4)) != GAPA_OK) return rc;
     return GAPA_OK;
@@ -765,16 +811,14 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
                 const int64_t threads = (int64_t)(b1 - b0) * Wd;
                 const int blocks = (int)std::min<int64_t>((threads + kBlk - 1) / kBlk, tu.band_blocks);
                 hipLaunchKernelGGL(k_pull_band, dim3(blocks), dim3(kBlk), 0, s, g->d_band_v, b0, b1, Wd,
-                                   g->d_row_ptr, g->d_colD, dead, reach, tu.band_scan);
+                                   g->d_row_ptr, g->d_colD, dead, reach, tu.band_scan, ws.pflag.as<uint8_t>());
             }
         }
         if (noniso > 0) {
             TimedScope ts(timer, "k_collect_pending", s);
-            const int32_t steps = std::max(
-                1, std::min(kPendStepsMax, (noniso + kCompactRange * kPendBlocks / 2) / (kCompactRange * kPendBlocks)));
-            const int32_t per_block = steps * kCompactRange;
-            hipLaunchKernelGGL(k_collect_pending, dim3((unsigned)((noniso + per_block - 1) / per_block)),
-                               dim3(kBlk), 0, s, g->d_band_v, noniso, steps, Wd, dead, reach, worklist, wl_count);
+            const int32_t per_block = kBlk * kFlagsPerThread;
+            hipLaunchKernelGGL(k_collect_pending, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(kBlk), 0, s,
+                               ws.pflag.as<uint8_t>(), n, worklist, wl_count);
         }
         {
             TimedScope ts(timer, "k_pull_worklist", s);

@@ -88,6 +88,8 @@ struct FitnessWorkspace {
     DevBuf ucount;   // int32 [B][n]  set sizes of the leftover union-find, kept zero
     DevBuf pairs;    // int64 [B * n_noniso] pending (individual, node) keys
     DevBuf worklist; // int32 [n_noniso] nodes still pending after the ordered sweep
+    DevBuf pflag;    // uint8 [n] 1: node still pending after the ordered sweep
+    bool pflag_clear = false;  // pflag zeroed since it was (re)allocated
     DevBuf small;    // int32 roots, root-set sizes, counters, count partials
     int32_t *stats_ctr = nullptr;  // device counters of the last bit-parallel chunk
     int32_t stats_B = 0;
