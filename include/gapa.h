@@ -128,6 +128,33 @@ GAPA_API int gapa_graph_destroy(gapa_graph *g);
 GAPA_API int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k,
                          int64_t *fitness, int32_t *mcn, uint32_t flags, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched fitness that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and gene semantics as
+ * gapa_eval_population with GAPA_DEVICE_PTRS, which `flags` must include
+ * (besides it only GAPA_TRUST_INPUT, GAPA_WANT_MCN and
+ * GAPA_MAXIMISE_COMPONENTS): genes, fitness and mcn are device pointers and
+ * the call enqueues its work on `stream`; without GAPA_TRUST_INPUT it waits
+ * for the device's gene check (pass GAPA_TRUST_INPUT under graph capture).
+ * The graph's bit-parallel algorithm is used whatever it was created with.
+ *
+ * Every buffer the evaluation needs comes from a fixed scratch array of
+ * GAPA_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * from the library's load to the end of the process.  The population is
+ * evaluated in chunks of 32 Wd individuals, Wd the largest power of two <= 32
+ * whose buffers fit: about 32 Wd (8.25 n + 8 n_noniso + 4 W + 4 sweep_grid)
+ * bytes for n nodes, n_noniso of them with an edge, W = ceil(n / 32) and the
+ * graph's sweep_grid (gapa_tuning); a graph on which not even 32 individuals
+ * fit (n above about 250 000 at the default launch shapes) gives
+ * GAPA_E_INVALID_ARG before any work is enqueued.  All calls on one GPU
+ * share its scratch, which keeps the last call's contents (each call clears
+ * what must start at zero): calls that overlap on one GPU (several streams or
+ * host threads at once) race and must be serialised by the caller.
+ * ------------------------------------------------------------------------- */
+#define GAPA_NOALLOC_SCRATCH_BYTES (128ull << 20)
+GAPA_API int gapa_eval_population_noalloc(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k,
+                                          int64_t *fitness, int32_t *mcn, uint32_t flags, void *stream);
 
 /* ---------------------------------------------------------------------------
  * The paper's dense reachability fitness (Section III-D, eq. 13-17, the

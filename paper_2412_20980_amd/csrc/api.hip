@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,6 +40,10 @@ int hip_fail(hipError_t e, const char *what)
 int DevBuf::reserve(size_t want)
 {
     if (want <= bytes && ptr) return GAPA_OK;
+    if (borrowed) {
+        set_error("a borrowed scratch buffer of %zu bytes cannot hold %zu", bytes, want);
+        return GAPA_E_INVALID_ARG;
+    }
     release();
     if (want == 0) want = 4;
     hipError_t e = hipMalloc(&ptr, want);
@@ -55,9 +60,10 @@ int DevBuf::reserve(size_t want)
 
 void DevBuf::release()
 {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr && !borrowed) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
+    borrowed = false;
 }
 
 // ------------------------------------------------------------------ timer ----
@@ -570,6 +576,99 @@ int gapa_eval_population(gapa_graph *g, const int32_t *genes, int32_t P, int32_t
         e = hipMemcpyAsync(mcn, d_mcn, (size_t)P * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_handle(&g->failed, hip_fail(e, "eval_population copy-back"));
+    if (hflag[0]) {
+        set_error("a gene is not a node id in [0, %d)", g->n);
+        return GAPA_E_BAD_GENE;
+    }
+    return GAPA_OK;
+}
+
+}  // extern "C"
+
+namespace gapa {
+namespace {
+
+// The scratch of gapa_eval_population_noalloc: a fixed device array that
+// every GPU the library runs on holds from module load to the end of the
+// process.  In host code its name is only a stand-in for the symbol: the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current and kept in g_scratch.
+constexpr size_t kNoAllocBytes = GAPA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// The calling thread's current device must be `dev`.
+int scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d is beyond the %d devices the fixed scratch serves", dev, kMaxDevices);
+        return GAPA_E_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        GAPA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("hipGetSymbolAddress gave no address for the fixed scratch on device %d", dev);
+            return GAPA_E_DEVICE;
+        }
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return GAPA_OK;
+}
+
+}  // namespace
+}  // namespace gapa
+
+extern "C" {
+
+int gapa_eval_population_noalloc(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int64_t *fitness,
+                                 int32_t *mcn, uint32_t flags, void *stream)
+{
+    g_last_error.clear();
+    if (!g) {
+        set_error("graph is NULL");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (g->failed) {
+        set_error("graph handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    const uint32_t allowed = GAPA_DEVICE_PTRS | GAPA_TRUST_INPUT | GAPA_WANT_MCN | GAPA_MAXIMISE_COMPONENTS;
+    if (!(flags & GAPA_DEVICE_PTRS) || (flags & ~allowed) != 0) {
+        set_error("gapa_eval_population_noalloc takes device pointers (GAPA_DEVICE_PTRS) and only "
+                  "GAPA_TRUST_INPUT, GAPA_WANT_MCN or GAPA_MAXIMISE_COMPONENTS besides");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (P < 0 || k < 0 || k > g->n || (P > 0 && ((k > 0 && !genes) || !fitness))) {
+        set_error("invalid population arguments (P=%d, k=%d)", P, k);
+        return GAPA_E_INVALID_ARG;
+    }
+    if (P == 0) return GAPA_OK;
+    const bool want_mcn = (flags & GAPA_WANT_MCN) && mcn;
+    const Measure measure = (flags & GAPA_MAXIMISE_COMPONENTS) ? kMeasureForest : kMeasurePC;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) {
+        set_error("cannot select device %d", g->device);
+        return GAPA_E_DEVICE;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *scr = nullptr;
+    int rc = scratch_address(g->device, &scr);
+    if (rc != GAPA_OK) return fail_handle(&g->failed, rc);
+    int32_t *flag = nullptr;
+    rc = eval_genes_bits_scratch(g, genes, P, k, fitness, want_mcn ? mcn : nullptr, measure, scr, kNoAllocBytes,
+                                 &flag, s);
+    if (rc != GAPA_OK) return fail_handle(&g->failed, rc);
+    if (flags & GAPA_TRUST_INPUT) return GAPA_OK;
+    int32_t hflag[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(hflag, flag, 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_handle(&g->failed, hip_fail(e, "eval_population_noalloc gene check"));
     if (hflag[0]) {
         set_error("a gene is not a node id in [0, %d)", g->n);
         return GAPA_E_BAD_GENE;

@@ -861,6 +861,109 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
 
 }  // namespace
 
+namespace {
+
+// Parts of a caller-provided scratch region for chunks of B = 32 Wd
+// individuals (byte offsets, each part 256-byte aligned; the sizes are those
+// reserve_pass asks for).
+struct ScratchLayout {
+    size_t flag, masks, alive, dead, reach, parent, ucount, pairs, worklist, pflag, small, total;
+};
+
+ScratchLayout scratch_layout(const gapa_graph *g, int32_t Wd)
+{
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t B = 32 * (size_t)Wd, n = (size_t)g->n, W = (size_t)g->words;
+    const size_t nn = (size_t)std::max(g->n_noniso, 1);
+    ScratchLayout l{};
+    size_t o = 0;
+    l.flag = o;
+    o += up(16);
+    l.masks = o;
+    o += up(B * W * 4);
+    l.alive = o;
+    o += up(B * 4);
+    l.dead = o;
+    o += up(n * Wd * 4);
+    l.reach = o;
+    o += up(n * Wd * 4);
+    l.parent = o;
+    o += up(B * n * 4);
+    l.ucount = o;
+    o += up(B * n * 4);
+    l.pairs = o;
+    o += up(B * nn * 8);
+    l.worklist = o;
+    o += up(nn * 4);
+    l.pflag = o;
+    o += up((n + 15) & ~(size_t)15);
+    l.small = o;
+    o += up((2 * B + 64 + (size_t)g->tune.sweep_grid * B) * 4);
+    l.total = o;
+    return l;
+}
+
+}  // namespace
+
+size_t bits_scratch_bytes(const gapa_graph *g, int32_t Wd)
+{
+    return scratch_layout(g, Wd).total;
+}
+
+int eval_genes_bits_scratch(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int64_t *fitness,
+                            int32_t *mcn, Measure measure, void *scratch, size_t bytes, int32_t **flag_out,
+                            hipStream_t s)
+{
+    // the widest chunk that fits, and no wider than the population needs
+    int32_t Wd = 1;
+    while (Wd < 32 && Wd * 32 < P) Wd <<= 1;
+    while (Wd >= 1 && scratch_layout(g, Wd).total > bytes) Wd >>= 1;
+    if (Wd < 1) {
+        set_error("graph too large for the fixed scratch: 32 individuals per pass need %zu bytes, the scratch "
+                  "holds %zu",
+                  scratch_layout(g, 1).total, bytes);
+        return GAPA_E_INVALID_ARG;
+    }
+    const ScratchLayout l = scratch_layout(g, Wd);
+    char *b = static_cast<char *>(scratch);
+    FitnessWorkspace ws;  // views of the scratch only: nothing here allocates or frees
+    ws.masks.borrow(b + l.masks, l.alive - l.masks);
+    ws.alive.borrow(b + l.alive, l.dead - l.alive);
+    ws.dead.borrow(b + l.dead, l.reach - l.dead);
+    ws.reach.borrow(b + l.reach, l.parent - l.reach);
+    ws.parent.borrow(b + l.parent, l.ucount - l.parent);
+    ws.ucount.borrow(b + l.ucount, l.pairs - l.ucount);
+    ws.pairs.borrow(b + l.pairs, l.worklist - l.pairs);
+    ws.worklist.borrow(b + l.worklist, l.pflag - l.worklist);
+    ws.pflag.borrow(b + l.pflag, l.small - l.pflag);
+    ws.pflag_clear = false;  // cleared by reserve_pass below: the scratch keeps the last call's flags
+    ws.small.borrow(b + l.small, l.total - l.small);
+    int32_t *flag = reinterpret_cast<int32_t *>(b + l.flag);
+    *flag_out = flag;
+    PassShape sh{};
+    sh.Wd = Wd;
+    sh.log_wd = 0;
+    while ((1 << sh.log_wd) < Wd) ++sh.log_wd;
+    sh.B = sh.S = 32 * Wd;
+    sh.multi = false;
+    int rc;
+    // the scratch keeps whatever the last call left: the gene flag and the
+    // leftover union-find's set sizes must start at zero
+    if ((rc = launch_fill_u32(flag, 0u, 4, s)) != GAPA_OK) return rc;
+    if ((rc = launch_fill_u32(ws.ucount.ptr, 0u, (int64_t)sh.B * g->n, s)) != GAPA_OK) return rc;
+    if ((rc = reserve_pass(g, ws, sh, s)) != GAPA_OK) return rc;
+    for (int32_t c0 = 0; c0 < P; c0 += sh.B) {
+        const int32_t rows = std::min(sh.B, P - c0);
+        if ((rc = launch_mask_build(genes ? genes + (int64_t)c0 * k : nullptr, rows, k, g->n, g->words, g->d_noniso,
+                                    g->n_noniso, ws.masks.as<uint32_t>(), ws.alive.as<int32_t>(), flag, s)) != GAPA_OK)
+            return rc;
+        if ((rc = run_pass(g, ws, sh, nullptr, ws.masks.as<uint32_t>(), ws.alive.as<int32_t>(), rows, 0, fitness + c0,
+                           mcn ? mcn + c0 : nullptr, measure, nullptr, s)) != GAPA_OK)
+            return rc;
+    }
+    return GAPA_OK;
+}
+
 // Extra lanes of a workspace: chunks of a population wider than one pass run
 // concurrently on their own streams and workspaces (the pass is bound by its
 // chain of dependent kernels, not by bandwidth, so chunks side by side

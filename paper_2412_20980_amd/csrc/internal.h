@@ -25,12 +25,22 @@ struct Status {
 
 // ------------------------------------------------------- device buffers -----
 
-// Grow-only device allocation (contents not preserved on growth).
+// Grow-only device allocation (contents not preserved on growth).  A
+// borrowed buffer is a view of memory owned elsewhere: reserve() never
+// allocates for it (a request beyond its size is an error) and release()
+// only forgets it.
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
-    int reserve(size_t want);  // GAPA_OK or GAPA_E_OOM
+    bool borrowed = false;
+    int reserve(size_t want);  // GAPA_OK, GAPA_E_OOM, or GAPA_E_INVALID_ARG for a borrowed view too small
     void release();
+    void borrow(void *p, size_t n)
+    {
+        ptr = p;
+        bytes = n;
+        borrowed = true;
+    }
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
@@ -190,6 +200,18 @@ int eval_masks(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32
 int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
                     int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s,
                     const InstTable *it = nullptr, Measure measure = kMeasurePC);
+// Bytes of scratch the bit-parallel fitness needs for chunks of 32 * Wd
+// individuals on graph g (every buffer of one pass plus the chunk's bit sets,
+// each part 256-byte aligned).
+size_t bits_scratch_bytes(const gapa_graph *g, int32_t Wd);
+// Bit-parallel fitness of P gene rows (device, [P][k]) with every buffer
+// carved from `scratch` (`bytes` long): chunks of 32 * Wd rows, Wd the widest
+// power of two <= 32 that fits, one after another on stream s; a gene outside
+// [0, n) sets flag[0] (flag: 4 int32 in the scratch, cleared here).  Nothing
+// is allocated; GAPA_E_INVALID_ARG if not even 32 rows fit.
+int eval_genes_bits_scratch(gapa_graph *g, const int32_t *genes, int32_t P, int32_t k, int64_t *fitness,
+                            int32_t *mcn, Measure measure, void *scratch, size_t bytes, int32_t **flag_out,
+                            hipStream_t s);
 int eval_masks_unionfind(gapa_graph *g, const uint32_t *masks, int32_t P, int64_t *fitness, int32_t *mcn,
                          FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, Measure measure = kMeasurePC);
 // Same from gene rows genes[P][k] (device node ids; a repeated id in a row is

@@ -57,6 +57,7 @@ EXPORTED = (
     "gapa_graph_get_tuning", "gapa_graph_set_tuning", "gapa_ga_autotune", "gapa_batch_autotune",
     "gapa_ga_record", "gapa_batch_record", "gapa_sixdst_eval", "gapa_ga_save", "gapa_ga_load",
     "gapa_ga_params", "gapa_batch_get_tuning", "gapa_batch_set_tuning", "gapa_surrogate_judge",
+    "gapa_eval_population_noalloc",
 )
 
 
@@ -114,6 +115,7 @@ def lib() -> C.CDLL:
     L.gapa_graph_create.argtypes = [C.c_int32, C.c_int64, vp, vp, C.c_uint32, C.POINTER(vp)]
     L.gapa_graph_destroy.argtypes = [vp]
     L.gapa_eval_population.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, C.c_uint32, vp]
+    L.gapa_eval_population_noalloc.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, C.c_uint32, vp]
     L.gapa_ga_create.argtypes = [vp, C.POINTER(gapa_params), vp, C.POINTER(vp)]
     L.gapa_generation_step.argtypes = [vp, C.c_int32, vp]
     L.gapa_best.argtypes = [vp, vp, i64p, i64p]
@@ -220,6 +222,22 @@ def gapa_eval_population(h, genes, fitness=None, mcn=None, flags: int = 0, strea
         _check(lib().gapa_eval_population(h, G.ctypes.data, P, k, fitness.ctypes.data,
                                           mcn.ctypes.data if mcn is not None else None,
                                           flags & ~GAPA_DEVICE_PTRS, _stream_ptr(stream)))
+    return (fitness, mcn) if flags & GAPA_WANT_MCN else fitness
+
+
+def gapa_eval_population_noalloc(h, genes, fitness=None, mcn=None, flags: int = 0, stream=None):
+    """The allocation-free batched fitness: genes a torch int32 CUDA tensor
+    [P, k]; fitness (and mcn with GAPA_WANT_MCN) torch CUDA tensors, made here
+    when not given (torch's allocation, not the library's)."""
+    assert _is_dev_tensor(genes) and genes.dtype == torch.int32 and genes.is_contiguous() and genes.dim() == 2
+    P, k = genes.shape
+    if fitness is None:
+        fitness = torch.empty(P, dtype=torch.int64, device=genes.device)
+    if flags & GAPA_WANT_MCN and mcn is None:
+        mcn = torch.zeros(P, dtype=torch.int32, device=genes.device)
+    _check(lib().gapa_eval_population_noalloc(h, genes.data_ptr(), P, k, fitness.data_ptr(),
+                                              mcn.data_ptr() if mcn is not None else None,
+                                              flags | GAPA_DEVICE_PTRS, _stream_ptr(stream)))
     return (fitness, mcn) if flags & GAPA_WANT_MCN else fitness
 
 

@@ -125,6 +125,8 @@ def test_flag_constants_match_the_header():
 
 def test_new_entry_points_reject_bad_arguments_on_host(L):
     from paper_2412_20980_amd import gapa
+    D = gapa.GAPA_DEVICE_PTRS
+    assert L.gapa_eval_population_noalloc(None, None, 1, 1, None, None, D, None) == gapa.GAPA_E_INVALID_ARG
     out = (C.c_double * 2)()
     # no predictions, an empty judge sample, a zero spread: rejected before any device work
     assert L.gapa_surrogate_judge(None, None, None, 4, 0.0, 1.0, out, None) == gapa.GAPA_E_INVALID_ARG
