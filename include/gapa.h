@@ -247,6 +247,13 @@ GAPA_API int gapa_ga_load(gapa_graph *g, const char *path, void *stream, gapa_ga
  * generation count (may be NULL).  Host pointers; waits for the GA's work. */
 GAPA_API int gapa_best(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out, int64_t *generation_out);
 
+/* The best fitness after the last enqueued generation, copied to
+ * fitness_out (8 bytes of device memory or of pinned, mapped host memory)
+ * by work enqueued on `stream` -- the stream the generations were enqueued
+ * on -- without waiting for it: a caller can follow the best value
+ * generation by generation without synchronising the host. */
+GAPA_API int gapa_best_async(gapa_ga *ga, int64_t *fitness_out, void *stream);
+
 /* Whole population, ordered by (PC, tag): genes_out int32 [P][k], fitness_out
  * int64 [P] (either may be NULL).  Host pointers; waits for the GA's work. */
 GAPA_API int gapa_get_population(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out);

@@ -1180,6 +1180,24 @@ int gapa_best(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out, int64_t *ge
     return rc;
 }
 
+int gapa_best_async(gapa_ga *ga, int64_t *fitness_out, void *stream)
+{
+    g_last_error.clear();
+    if (!ga || !fitness_out) {
+        set_error("NULL argument");
+        return GAPA_E_INVALID_ARG;
+    }
+    if (ga->failed) {
+        set_error("GA handle is in a failed state");
+        return GAPA_E_STATE;
+    }
+    DeviceGuard dg(ga->graph->device);
+    // the buffer the last enqueued generation's elitism writes
+    const int64_t *src = ga->fit[ga->cur].as<int64_t>() + ga->hinst[0].fit_off;
+    GAPA_HIP(hipMemcpyAsync(fitness_out, src, 8, hipMemcpyDefault, static_cast<hipStream_t>(stream)));
+    return GAPA_OK;
+}
+
 int gapa_get_population(gapa_ga *ga, int32_t *genes_out, int64_t *fitness_out)
 {
     g_last_error.clear();

@@ -57,7 +57,7 @@ EXPORTED = (
     "gapa_graph_get_tuning", "gapa_graph_set_tuning", "gapa_ga_autotune", "gapa_batch_autotune",
     "gapa_ga_record", "gapa_batch_record", "gapa_sixdst_eval", "gapa_ga_save", "gapa_ga_load",
     "gapa_ga_params", "gapa_batch_get_tuning", "gapa_batch_set_tuning", "gapa_surrogate_judge",
-    "gapa_eval_population_noalloc",
+    "gapa_eval_population_noalloc", "gapa_best_async",
 )
 
 
@@ -119,6 +119,7 @@ def lib() -> C.CDLL:
     L.gapa_ga_create.argtypes = [vp, C.POINTER(gapa_params), vp, C.POINTER(vp)]
     L.gapa_generation_step.argtypes = [vp, C.c_int32, vp]
     L.gapa_best.argtypes = [vp, vp, i64p, i64p]
+    L.gapa_best_async.argtypes = [vp, vp, vp]
     L.gapa_get_population.argtypes = [vp, vp, vp]
     L.gapa_ga_destroy.argtypes = [vp]
     L.gapa_batch_create.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(gapa_params), vp, C.POINTER(vp)]
@@ -436,6 +437,13 @@ class GA:
 
     def best(self):
         return gapa_best(self.handle, self.k)
+
+    def best_async(self, out, index: int = 0, stream=None):
+        """Enqueue a copy of the current best fitness into out[index] (an int64
+        torch tensor in device or pinned host memory) without waiting."""
+        assert out.dtype == torch.int64 and out.is_contiguous() and 0 <= index < out.numel()
+        assert out.is_cuda or out.is_pinned()
+        _check(lib().gapa_best_async(self.handle, out.data_ptr() + 8 * index, _stream_ptr(stream)))
 
     def population(self):
         return gapa_get_population(self.handle, self.pop, self.k)
