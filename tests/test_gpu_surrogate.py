@@ -223,7 +223,7 @@ def test_screened_trajectory_replays_exactly(gp):
     # step whatever its gradient (Kingma and Ba 2015, Sec. 2.1), so
     # coordinates whose gradient is near zero (its sign set by rounding) can
     # step apart on the two sides: after T steps no coordinate is further apart
-    # than twice T such steps, the weights as a whole stay within a few percent
+    # than twice T such steps, the weight matrices as a whole stay within 2 %
     # and the predictions they make stay aligned.
     import torch
     got, ref = weights(ga, g.n), sga.params
@@ -235,7 +235,7 @@ def test_screened_trajectory_replays_exactly(gp):
         print(f"{name}: max |diff| {d.max():.2e} (bound {bound:.2e}), relative norm {rel:.3e}", flush=True)
         assert d.max() <= bound, name
     for name in ("W1", "W2", "w3"):
-        assert np.linalg.norm(got[name] - ref[name]) <= 0.06 * np.linalg.norm(ref[name]), name
+        assert np.linalg.norm(got[name] - ref[name]) <= 2e-2 * np.linalg.norm(ref[name]), name
     sets = inputs.random_population(g.n, 20, 256, seed=11)
     y_dev = ga.predict(torch.from_numpy(sets).cuda()).cpu().numpy().astype(np.float64)
     y_ref = S.forward(ref, sets, bf16_ops=True)["yhat"]
