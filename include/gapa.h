@@ -327,9 +327,10 @@ typedef struct gapa_surrogate_report {
     int32_t reserved;
     double spearman;     /* judge correlation (0 when no prediction was made)     */
     double rel_err;      /* mean |expm1(prediction) - PC| / max(PC, 1)             */
-    double loss;         /* mean squared error of the last training step finished
-                            before it (after gapa_surrogate_train_batch: that
-                            step's)                                            */
+    double loss;         /* mean squared error of the last step of the training
+                            on generation g - 2's labels (generation g - 1's
+                            training still runs beside generation g; after
+                            gapa_surrogate_train_batch: that step's)          */
     int32_t fallbacks;   /* full generations forced by the judge so far            */
     int32_t train_steps; /* Adam steps taken so far                               */
     double label_mean;   /* the label standardisation the generation's predictions */

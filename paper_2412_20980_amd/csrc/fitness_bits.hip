@@ -256,14 +256,13 @@ __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restr
 // union-find pass, so the cap only moves work.
 //
 // The node's own bits and its neighbour range are loaded together; then the
-// neighbours are taken kPullChunk at a time: all their ids, then all their
-// reach rows, each set of loads in flight at once (two dependent round trips
-// per chunk).  Reach rows are read with plain loads: within a kernel another
-// XCD's newer bits may not be visible yet, which only delays them (a row
-// read early holds a subset of its final bits, and every bit it holds is a
-// true connection to the root); each kernel sees all bits of the kernels
-// before it.
-constexpr int kPullChunk = 16;
+// neighbours are taken kPullChunk at a time (their ids, then their rows).
+// Reach rows are shared between the XCDs within one kernel: they are read
+// and written with agent-scope atomics, which bypass each XCD's own L2, so
+// bits another XCD set earlier in the same sweep are seen and spread at once
+// (plain loads that hit a stale line in the local L2 leave about 40 % more
+// nodes pending at n = 200k and make the pass 20 % slower).
+constexpr int kPullChunk = 4;
 
 __device__ __forceinline__ bool pull_node(int32_t v, int Wd, int w, uint64_t gmask,
                                           const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
@@ -271,7 +270,7 @@ __device__ __forceinline__ bool pull_node(int32_t v, int Wd, int w, uint64_t gma
                                           int32_t max_scan, bool *still_pending = nullptr)
 {
     const int64_t vo = (int64_t)v * Wd + w;
-    const uint32_t mine = reach[vo];
+    const uint32_t mine = ld_relaxed_u(reach + vo);
     const uint32_t dv = dead[vo];
     const int32_t e0 = row_ptr[v], eN = row_ptr[v + 1];
     const uint32_t pend = ~dv & ~mine;
@@ -285,11 +284,11 @@ __device__ __forceinline__ bool pull_node(int32_t v, int Wd, int w, uint64_t gma
         for (int t = 0; t < kPullChunk; ++t) u[t] = e + t < e1 ? colD[e + t] : -1;
 #pragma unroll
         for (int t = 0; t < kPullChunk; ++t)
-            if (u[t] >= 0) acc |= reach[(int64_t)u[t] * Wd + w];
+            if (u[t] >= 0) acc |= ld_relaxed_u(reach + (int64_t)u[t] * Wd + w);
         if ((__ballot((acc & pend) != pend) & gmask) == 0) break;
     }
     const uint32_t gain = acc & pend;
-    if (gain) reach[vo] = mine | gain;
+    if (gain) __hip_atomic_store(reach + vo, mine | gain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (still_pending) *still_pending = (__ballot((pend & ~gain) != 0) & gmask) != 0;
     return (__ballot(gain != 0) & gmask) != 0;
 }
@@ -355,7 +354,10 @@ __device__ __forceinline__ C block_reserve(int32_t mine, C *counter, int32_t *s_
 // most 33), [kPairCountSlot, kPairCountSlot + 2) the 64-bit pair count; k_seed
 // clears all 64.
 constexpr int kPairCountSlot = 36;
-static_assert(kPairCountSlot % 2 == 0 && kPairCountSlot >= 2 + 33 && kPairCountSlot + 2 <= 64, "counter layout");
+// [kDoneSlot]: blocks of k_pairs_reduce finished (the last one finishes the pass)
+constexpr int kDoneSlot = kPairCountSlot + 2;
+constexpr int32_t kFinishSlots = 1024;
+static_assert(kPairCountSlot % 2 == 0 && kPairCountSlot >= 2 + 33 && kDoneSlot < 64, "counter layout");
 
 // Nodes still pending after the ordered sweep -> worklist: the compaction of
 // the pending flags over node ids (isolated nodes keep flag 0).  A thread
@@ -444,6 +446,8 @@ __global__ void k_pull_worklist(const int32_t *__restrict__ worklist, const int3
 // A block takes one worklist entry per group at a time: it splits every
 // (node, word) entry, reserves room for the block's pairs with one global
 // atomic, then writes them.
+constexpr int kSplitChunk = 16;
+
 __device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t gmask,
                                               const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
                                               const uint32_t *__restrict__ dead, const uint32_t *__restrict__ reach,
@@ -457,15 +461,16 @@ __device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t
     const uint32_t pend = ~dv & ~rv;
     uint32_t nb = 0;
     if ((__ballot(pend != 0) & gmask) != 0) {
-        // kPullChunk neighbours at a time (their ids, then their bits, each set
-        // of loads in flight together); stopping once every pending bit has a
-        // surviving neighbour (or at the end of the list) gives the same split
-        for (int32_t e = e0; e < e1; e += kPullChunk) {
-            int32_t u[kPullChunk];
+        // kSplitChunk neighbours at a time (their ids, then their bits, each
+        // set of loads in flight together); stopping once every pending bit
+        // has a surviving neighbour (or at the end of the list) gives the same
+        // split
+        for (int32_t e = e0; e < e1; e += kSplitChunk) {
+            int32_t u[kSplitChunk];
 #pragma unroll
-            for (int t = 0; t < kPullChunk; ++t) u[t] = e + t < e1 ? colD[e + t] : -1;
+            for (int t = 0; t < kSplitChunk; ++t) u[t] = e + t < e1 ? colD[e + t] : -1;
 #pragma unroll
-            for (int t = 0; t < kPullChunk; ++t)
+            for (int t = 0; t < kSplitChunk; ++t)
                 if (u[t] >= 0) nb |= ~dead[(int64_t)u[t] * Wd + w];
             if ((__ballot((nb & pend) != pend) & gmask) == 0) break;
         }
@@ -663,14 +668,38 @@ __device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit
     if (mcn && s > 0) atomicMax(mcn, (int32_t)s);
 }
 
+// The root's component of slot gi: what remains of its surviving
+// non-isolated nodes once every other component is counted (or the root
+// alone when it is isolated).  Its union-find counter is cleared for reuse.
+__device__ __forceinline__ void root_component(int32_t gi, const int32_t *__restrict__ root, const Insts &I,
+                                               int32_t *__restrict__ parent, const int32_t *__restrict__ alive_noniso,
+                                               const int32_t *__restrict__ other, const int32_t *__restrict__ row_ptr,
+                                               int32_t *__restrict__ ucount, unsigned long long *__restrict__ fitness,
+                                               int32_t *__restrict__ mcn, int32_t forest)
+{
+    const int32_t r = root[gi];
+    if (r < 0) return;
+    const int32_t off = i_voff(I, gi / I.bseg);
+    const int64_t blk = uf_block(I, gi);
+    ucount[blk + uf_find(parent + blk, r - off)] = 0;
+    const int32_t oth = __hip_atomic_load(other + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t s = row_ptr[r + 1] > row_ptr[r] ? (int64_t)alive_noniso[gi] - oth : 1;
+    add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
+}
+
 // Components made only of pending nodes (set representative is a pending node
 // other than the root's representative): counted, and their sizes summed into
-// other[gi].  Their counters are cleared for reuse.
+// other[gi].  Their counters are cleared for reuse.  With `finish`, the last
+// block to finish (counted in *done, which the pass's first kernel cleared)
+// then adds every slot's root component, which needs all the other sums.
 __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count, const Insts I,
                                int32_t *__restrict__ parent, const int32_t *__restrict__ root,
                                int32_t *__restrict__ ucount, int32_t *__restrict__ other,
-                               unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest)
+                               unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest,
+                               int32_t finish, int32_t *__restrict__ done, const int32_t *__restrict__ alive_noniso,
+                               const int32_t *__restrict__ row_ptr)
 {
+    __shared__ bool s_last;
     const int64_t count = (int64_t)*pair_count;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t key = pairs[q];
@@ -684,6 +713,17 @@ __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const unsigned
         atomicAdd(other + gi, s);
         add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
     }
+    if (!finish) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();  // this block's sums are visible before it counts itself done
+        s_last = atomicAdd(done, 1) == (int32_t)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int32_t gi = threadIdx.x; gi < I.count * I.bseg; gi += blockDim.x)
+        root_component(gi, root, I, parent, alive_noniso, other, row_ptr, ucount, fitness, mcn, forest);
 }
 
 __global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, int32_t *__restrict__ parent,
@@ -692,13 +732,8 @@ __global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, in
                              unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest)
 {
     const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= I.count * I.bseg || root[gi] < 0) return;
-    const int32_t r = root[gi];
-    const int32_t off = i_voff(I, gi / I.bseg);
-    const int64_t blk = uf_block(I, gi);
-    ucount[blk + uf_find(parent + blk, r - off)] = 0;
-    const int64_t s = row_ptr[r + 1] > row_ptr[r] ? (int64_t)alive_noniso[gi] - other[gi] : 1;
-    add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
+    if (gi >= I.count * I.bseg) return;
+    root_component(gi, root, I, parent, alive_noniso, other, row_ptr, ucount, fitness, mcn, forest);
 }
 
 }  // namespace
@@ -846,13 +881,14 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
         }
         {
             TimedScope ts(timer, "k_pairs_reduce", s);
+            // up to kFinishSlots slots, the root components are added by the
+            // reduction's last block (one dependent launch fewer)
+            const int32_t finish = S <= kFinishSlots ? 1 : 0;
             hipLaunchKernelGGL(k_pairs_reduce, dim3(grid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, root,
-                               ucount, other, fit, mc, (int32_t)measure);
-        }
-        {
-            TimedScope ts(timer, "k_root_final", s);
-            hipLaunchKernelGGL(k_root_final, dim3((S + 63) / 64), dim3(64), 0, s, root, I, parent, al, other,
-                               g->d_row_ptr, ucount, fit, mc, (int32_t)measure);
+                               ucount, other, fit, mc, (int32_t)measure, finish, ctr + kDoneSlot, al, g->d_row_ptr);
+            if (!finish)
+                hipLaunchKernelGGL(k_root_final, dim3((S + 63) / 64), dim3(64), 0, s, root, I, parent, al, other,
+                                   g->d_row_ptr, ucount, fit, mc, (int32_t)measure);
         }
         GAPA_HIP(hipGetLastError());
     }

@@ -158,13 +158,16 @@ __device__ int32_t wave_list_slots(const uint32_t *bits, int32_t k, uint16_t *li
 // after it.  A draw equal to a value an earlier lane frees (swap) is
 // rejected too and then accepted by the lone resolution: the same result.
 //
+// With `pre` (no swap), slot j's attempt-0 value was computed beforehand by
+// the whole block and stored in row[j] (the slot's old value is not needed).
+//
 // Equal draws within the batch are found through U itself: every candidate
 // not yet a member sets its bit with an atomic OR, and a lane that finds its
 // bit already set by another lane of the batch marks a collision.  Without
 // one (the usual case) no lane is taken; with one the lanes compare values
 // directly.  Bits set for lanes that are not committed are cleared again.
 __device__ void wave_draw_in_order(const OpLds &l, const Op &a, const uint16_t *list, int32_t count, bool swap,
-                                   uint32_t ind, uint32_t gen, uint32_t stream)
+                                   uint32_t ind, uint32_t gen, uint32_t stream, bool pre = false)
 {
     const int lane = threadIdx.x & 63;
     int32_t pos = 0;
@@ -172,7 +175,8 @@ __device__ void wave_draw_in_order(const OpLds &l, const Op &a, const uint16_t *
         const int32_t nvalid = min(64, count - pos);
         const bool valid = lane < nvalid;
         const int32_t j = valid ? (list ? list[pos + lane] : pos + lane) : 0;
-        const uint32_t c = valid ? bounded(draw(a.seed, j, ind, gen, stream, 0).w0, a.n) : 0u;
+        // attempt 0 of slot j: drawn here, or (pre, no swap) already in row[j]
+        const uint32_t c = !valid ? 0u : pre ? (uint32_t)l.row[j] : bounded(draw(a.seed, j, ind, gen, stream, 0).w0, a.n);
         const int32_t old = (valid && swap) ? l.row[j] : -1;
         const uint32_t w = c >> 5, bit = 1u << (c & 31);
         // membership before the batch: every lane reads before any lane writes
@@ -228,6 +232,27 @@ __device__ void wave_draw_in_order(const OpLds &l, const Op &a, const uint16_t *
 
 // Exclusive prefix sum over the block (blockDim.x <= 1024, a multiple of 64);
 // also returns the block total.  Every thread must call it.
+__device__ int32_t block_exclusive_scan(int32_t x, int32_t *total);
+
+// Slots whose bit is set in bits[0 .. ceil(k/32)), ascending, into list[];
+// returns how many.  Whole block: each thread enumerates a contiguous run of
+// words at the offset a block scan of their popcounts gives.  The list is
+// visible to every thread on return.
+__device__ int32_t block_list_slots(const uint32_t *bits, int32_t k, uint16_t *list)
+{
+    const int32_t KW = (k + 31) / 32;
+    const int32_t per = (KW + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
+    const int32_t w0 = min(KW, (int32_t)threadIdx.x * per), w1 = min(KW, w0 + per);
+    int32_t cnt = 0;
+    for (int32_t w = w0; w < w1; ++w) cnt += __popc(bits[w]);
+    int32_t total = 0;
+    int32_t off = block_exclusive_scan(cnt, &total);
+    for (int32_t w = w0; w < w1; ++w)
+        for (uint32_t x = bits[w]; x; x &= x - 1) list[off++] = (uint16_t)(w * 32 + __ffs(x) - 1);
+    __syncthreads();
+    return total;
+}
+
 __device__ int32_t block_exclusive_scan(int32_t x, int32_t *total)
 {
     __shared__ int32_t s_wave[16];
@@ -260,38 +285,27 @@ __device__ void clear_lds(const OpLds &l, const Op &a)
 // mask the fitness kernels consume), its row in ascending order (the set bits
 // enumerated in order: each thread owns a contiguous run of words, a block
 // scan of their popcounts gives its output offset) and its count of
-// surviving non-isolated nodes.
+// surviving non-isolated nodes (n_noniso minus the genes that have an edge).
 __device__ void emit(const OpLds &l, const Op &a, int32_t idx)
 {
     __syncthreads();
-    uint32_t *m = a.masks + (int64_t)idx * a.W;
-    int32_t gone = 0;
     if (!a.rows_only) {
-        // eight words a round: their loads of the non-isolated set are in flight together
+        uint32_t *m = a.masks + (int64_t)idx * a.W;
         int32_t w = threadIdx.x;
         for (; w + 7 * (int32_t)blockDim.x < a.W; w += 8 * blockDim.x) {
-            uint32_t nz[8];
+            uint32_t x[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) nz[u] = a.noniso[w + u * blockDim.x];
+            for (int u = 0; u < 8; ++u) x[u] = l.U[w + u * blockDim.x];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t x = l.U[w + u * blockDim.x];
-                m[w + u * blockDim.x] = x;
-                gone += __popc(x & nz[u]);
-            }
+            for (int u = 0; u < 8; ++u) m[w + u * blockDim.x] = x[u];
         }
-        for (; w < a.W; w += blockDim.x) {
-            const uint32_t x = l.U[w];
-            m[w] = x;
-            gone += __popc(x & a.noniso[w]);
-        }
+        for (; w < a.W; w += blockDim.x) m[w] = l.U[w];
     }
     const int32_t per = (a.W + blockDim.x - 1) / blockDim.x;
     const int32_t w0 = min(a.W, (int32_t)threadIdx.x * per), w1 = min(a.W, w0 + per);
     int32_t cnt = 0;
     for (int32_t w = w0; w < w1; ++w) cnt += __popc(l.U[w]);
-    int32_t total = 0, gone_total = 0;
-    (void)block_exclusive_scan(gone, &gone_total);
+    int32_t total = 0;
     int32_t off = block_exclusive_scan(cnt, &total);
     // the sorted row is staged in LDS (the row by slot is no longer needed)
     // and written out coalesced
@@ -300,7 +314,14 @@ __device__ void emit(const OpLds &l, const Op &a, int32_t idx)
             if (off < a.k) l.row[off++] = w * 32 + __ffs(bits) - 1;
     __syncthreads();
     int32_t *dst = a.children + (int64_t)idx * a.k;
-    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) dst[j] = l.row[j];
+    int32_t gone = 0;
+    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
+        const int32_t v = l.row[j];
+        dst[j] = v;
+        if (!a.rows_only) gone += (a.noniso[v >> 5] >> (v & 31)) & 1u;
+    }
+    int32_t gone_total = 0;
+    if (!a.rows_only) (void)block_exclusive_scan(gone, &gone_total);
     if (threadIdx.x == 0) {
         if (!a.rows_only) a.alive[idx] = a.n_noniso - gone_total;
         if (total != a.k) atomicOr(a.flag, 1);
@@ -321,6 +342,48 @@ __global__ __launch_bounds__(kOpBlock) void k_init(OpArgs args)
     if (threadIdx.x < 64) wave_draw_in_order(l, a, nullptr, a.k, false, i, 0, kStreamInit);
     emit(l, a, i);
 }
+
+// Offspring o of generation gen >= 1.
+//   base  = POP[o mod P]; donor = tournament winner (smallest (PC, position)
+//           among T uniform draws with replacement; contestant c is word c mod 4
+//           of SELECT draw slot c / 4).
+//   eq. 6 gene j = donor[j] where the crossover mask (eq. 4) word-0 coin of
+//           XOVER draw j is below floor(pc 2^32), else base[j]; word 1 of the
+//           same draw is the mutation coin of eq. 8.
+//   repair  a slot whose value already sits at a lower slot gets a uniform
+//           non-member (REPAIR draws), slots ascending.
+//   eq. 9   each mutated slot, ascending, swaps its gene for a uniform
+//           non-member (MUTATE draws).
+//   sort    the row ascending.
+// Position of value c in the ascending base row staged in bs[0, k): galloping
+// from slot j (the rows of a converged population differ by small shifts),
+// then a binary search inside the bracket.  c must be in the row.
+__device__ __forceinline__ int32_t base_position(const int32_t *bs, int32_t k, int32_t j, int32_t c)
+{
+    int32_t lo, hi;
+    if (bs[j] < c) {
+        int32_t b = 1;
+        while (j + b < k && bs[j + b] < c) b <<= 1;
+        lo = j + (b >> 1) + 1;
+        hi = min(j + b, k);
+    } else {
+        int32_t b = 1;
+        while (j - b >= 0 && bs[j - b] >= c) b <<= 1;
+        lo = max(j - b + 1, 0);
+        hi = j - (b >> 1);
+    }
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (bs[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Rows up to kOpBlock * kOpSlots genes keep each thread's base and donor
+// genes in registers from the crossover to the row fill (slot j = thread +
+// kOpBlock i); longer rows read them again from global memory.
+constexpr int kOpSlots = 8;
 
 // Offspring o of generation gen >= 1.
 //   base  = POP[o mod P]; donor = tournament winner (smallest (PC, position)
@@ -360,17 +423,40 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs args)
 
     const int32_t *base = a.pop + (int64_t)(o % a.P) * a.k;
     const int32_t *donor = a.pop + (int64_t)s_donor * a.k;
-    // crossover coins; the base row is staged in LDS (row[] holds it while
-    // duplicates are located), values taken from it enter the membership set
+    const bool regs = a.k <= kOpBlock * kOpSlots;
+    int32_t bv[kOpSlots], dv[kOpSlots];
+    uint32_t takes = 0u;  // bit i: slot threadIdx.x + kOpBlock i takes the donor gene
+    // Crossover coins; the base row is staged in LDS (row[] holds it while
+    // duplicates are located), values taken from it enter the membership set.
+    if (regs) {
+#pragma unroll
+        for (int i = 0; i < kOpSlots; ++i) {
+            const int32_t j = threadIdx.x + kOpBlock * i;
+            bv[i] = j < a.k ? base[j] : 0;
+            dv[i] = j < a.k ? donor[j] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < kOpSlots; ++i) {
+            const int32_t j = threadIdx.x + kOpBlock * i;
+            if (j >= a.k) break;
+            const Words4 x = draw(a.seed, j, o, gen, kStreamXover, 0);
+            const bool take = (uint64_t)x.w0 < a.t_pc;
+            l.row[j] = bv[i];
+            if (take) takes |= 1u << i;
+            else atomicOr(&l.U[bv[i] >> 5], 1u << (bv[i] & 31));
+            if ((uint64_t)x.w1 < a.t_pm) atomicOr(&l.mut[j >> 5], 1u << (j & 31));
+        }
+    } else {
 #pragma unroll 4
-    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
-        const Words4 x = draw(a.seed, j, o, gen, kStreamXover, 0);
-        const bool take = (uint64_t)x.w0 < a.t_pc;
-        const int32_t b = base[j];
-        l.row[j] = b;
-        if (take) atomicOr(&l.from_donor[j >> 5], 1u << (j & 31));
-        else atomicOr(&l.U[b >> 5], 1u << (b & 31));
-        if ((uint64_t)x.w1 < a.t_pm) atomicOr(&l.mut[j >> 5], 1u << (j & 31));
+        for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
+            const Words4 x = draw(a.seed, j, o, gen, kStreamXover, 0);
+            const bool take = (uint64_t)x.w0 < a.t_pc;
+            const int32_t b = base[j];
+            l.row[j] = b;
+            if (take) atomicOr(&l.from_donor[j >> 5], 1u << (j & 31));
+            else atomicOr(&l.U[b >> 5], 1u << (b & 31));
+            if ((uint64_t)x.w1 < a.t_pm) atomicOr(&l.mut[j >> 5], 1u << (j & 31));
+        }
     }
     __syncthreads();
 
@@ -378,51 +464,60 @@ __global__ __launch_bounds__(kOpBlock) void k_offspring(OpArgs args)
     // twice in the child: once from each row.  A donor value c that is already
     // a member came from the base row at the slot p where base[p] = c; the
     // later of p and j is the copy.  Other donor values join the set.
-#pragma unroll 2
-    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
-        if (!((l.from_donor[j >> 5] >> (j & 31)) & 1u)) continue;
-        const int32_t c = donor[j];
-        if (lds_test(l.U, c)) {
-            // position of c in the base row (staged in row[]): galloping from
-            // slot j (the rows of a converged population differ by small
-            // shifts), then a binary search inside the bracket
-            const int32_t *bs = l.row;
-            int32_t lo, hi;
-            if (bs[j] < c) {
-                int32_t b = 1;
-                while (j + b < a.k && bs[j + b] < c) b <<= 1;
-                lo = j + (b >> 1) + 1;
-                hi = min(j + b, a.k);
+    if (regs) {
+#pragma unroll
+        for (int i = 0; i < kOpSlots; ++i) {
+            if (!((takes >> i) & 1u)) continue;
+            const int32_t j = threadIdx.x + kOpBlock * i;
+            const int32_t c = dv[i];
+            if (lds_test(l.U, c)) {
+                const int32_t p = base_position(l.row, a.k, j, c);
+                const int32_t later = p < j ? j : p;
+                atomicOr(&l.dup[later >> 5], 1u << (later & 31));
             } else {
-                int32_t b = 1;
-                while (j - b >= 0 && bs[j - b] >= c) b <<= 1;
-                lo = max(j - b + 1, 0);
-                hi = j - (b >> 1);
+                atomicOr(&l.U[c >> 5], 1u << (c & 31));
             }
-            while (lo < hi) {
-                const int32_t mid = (lo + hi) >> 1;
-                if (bs[mid] < c) lo = mid + 1;
-                else hi = mid;
+        }
+    } else {
+#pragma unroll 2
+        for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
+            if (!((l.from_donor[j >> 5] >> (j & 31)) & 1u)) continue;
+            const int32_t c = donor[j];
+            if (lds_test(l.U, c)) {
+                const int32_t p = base_position(l.row, a.k, j, c);
+                const int32_t later = p < j ? j : p;
+                atomicOr(&l.dup[later >> 5], 1u << (later & 31));
+            } else {
+                atomicOr(&l.U[c >> 5], 1u << (c & 31));
             }
-            const int32_t later = lo < j ? j : lo;
-            atomicOr(&l.dup[later >> 5], 1u << (later & 31));
-        } else {
-            atomicOr(&l.U[c >> 5], 1u << (c & 31));
         }
     }
     __syncthreads();
     // the child's row by slot: donor values where the coin took the donor
-    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x)
-        if ((l.from_donor[j >> 5] >> (j & 31)) & 1u) l.row[j] = donor[j];
+    if (regs) {
+#pragma unroll
+        for (int i = 0; i < kOpSlots; ++i)
+            if ((takes >> i) & 1u) l.row[threadIdx.x + kOpBlock * i] = dv[i];
+    } else {
+        for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x)
+            if ((l.from_donor[j >> 5] >> (j & 31)) & 1u) l.row[j] = donor[j];
+    }
     __syncthreads();
 
-    // repair, then mutation, each in ascending slot order (one wave)
-    if (threadIdx.x < 64) {
-        const int32_t nd = wave_list_slots(l.dup, a.k, l.list);
-        wave_draw_in_order(l, a, l.list, nd, false, o, gen, kStreamRepair);
-        const int32_t nm = wave_list_slots(l.mut, a.k, l.list);
-        wave_draw_in_order(l, a, l.list, nm, true, o, gen, kStreamMutate);
+    // Repair, then mutation, each in ascending slot order by one wave.  The
+    // slot lists are built by the whole block, and so are the repair slots'
+    // attempt-0 draws (a repaired slot's duplicate value is not needed, so the
+    // draw takes its place in row[]).
+    const int32_t nd = block_list_slots(l.dup, a.k, l.list);
+    for (int32_t q = threadIdx.x; q < nd; q += blockDim.x) {
+        const int32_t j = l.list[q];
+        l.row[j] = (int32_t)bounded(draw(a.seed, j, o, gen, kStreamRepair, 0).w0, a.n);
     }
+    __syncthreads();
+    if (threadIdx.x < 64) wave_draw_in_order(l, a, l.list, nd, false, o, gen, kStreamRepair, true);
+    __syncthreads();
+    const int32_t nm = block_list_slots(l.mut, a.k, l.list);
+    if (threadIdx.x < 64) wave_draw_in_order(l, a, l.list, nm, true, o, gen, kStreamMutate);
     emit(l, a, o);
 }
 

@@ -174,36 +174,50 @@ __global__ void k_snapshot(SnapArgs a)
 
 // x(S) of each row, rounded to bf16: one 256-thread block per row.  Lane
 // (wave w, group g = lane / 16, q = lane % 16) adds dims 4q..4q+3 of genes
-// j = 16 i + 4 w + g; the four groups and the four waves are then added in a
-// fixed order.
+// j = 16 i + 4 w + g in ascending i; the four groups and the four waves are
+// then added in a fixed order.  The row's gene ids are staged in LDS
+// (kEmbedIds at a time, coalesced), so each lane keeps kEmbedUnroll
+// embedding rows in flight without waiting on their ids.
+constexpr int kEmbedIds = 2048;  // a multiple of 16: a chunk keeps each lane's residue j mod 16
+constexpr int kEmbedUnroll = 8;
+
 __global__ __launch_bounds__(256) void k_embed(const int32_t *__restrict__ genes, const int32_t *__restrict__ rows,
                                                int32_t k, const uint16_t *__restrict__ Eb, uint16_t *__restrict__ xb)
 {
     __shared__ float s_part[4][kD];
+    __shared__ int32_t s_ids[kEmbedIds];
     const int32_t row = rows ? rows[blockIdx.x] : (int32_t)blockIdx.x;
     const int32_t *g = genes + (int64_t)row * k;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int grp = lane >> 4, q = lane & 15;
+    const int32_t r = 4 * wv + grp;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    int32_t j = 4 * wv + grp;
-    for (; j + 48 < k; j += 64) {
-        uint2 e[4];
+    for (int32_t c0 = 0; c0 < k; c0 += kEmbedIds) {
+        const int32_t cn = min(kEmbedIds, k - c0);
+        __syncthreads();  // the previous chunk's ids are no longer read
+        for (int32_t t = threadIdx.x; t < cn; t += blockDim.x) s_ids[t] = g[c0 + t];
+        __syncthreads();
+        int32_t j = r;
+        for (; j + 16 * (kEmbedUnroll - 1) < cn; j += 16 * kEmbedUnroll) {
+            uint2 e[kEmbedUnroll];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) e[u] = *reinterpret_cast<const uint2 *>(Eb + (int64_t)g[j + 16 * u] * kD + 4 * q);
+            for (int u = 0; u < kEmbedUnroll; ++u)
+                e[u] = *reinterpret_cast<const uint2 *>(Eb + (int64_t)s_ids[j + 16 * u] * kD + 4 * q);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            a0 += bf2f((uint16_t)e[u].x);
-            a1 += bf2f((uint16_t)(e[u].x >> 16));
-            a2 += bf2f((uint16_t)e[u].y);
-            a3 += bf2f((uint16_t)(e[u].y >> 16));
+            for (int u = 0; u < kEmbedUnroll; ++u) {
+                a0 += bf2f((uint16_t)e[u].x);
+                a1 += bf2f((uint16_t)(e[u].x >> 16));
+                a2 += bf2f((uint16_t)e[u].y);
+                a3 += bf2f((uint16_t)(e[u].y >> 16));
+            }
         }
-    }
-    for (; j < k; j += 16) {
-        const uint2 e = *reinterpret_cast<const uint2 *>(Eb + (int64_t)g[j] * kD + 4 * q);
-        a0 += bf2f((uint16_t)e.x);
-        a1 += bf2f((uint16_t)(e.x >> 16));
-        a2 += bf2f((uint16_t)e.y);
-        a3 += bf2f((uint16_t)(e.y >> 16));
+        for (; j < cn; j += 16) {
+            const uint2 e = *reinterpret_cast<const uint2 *>(Eb + (int64_t)s_ids[j] * kD + 4 * q);
+            a0 += bf2f((uint16_t)e.x);
+            a1 += bf2f((uint16_t)(e.x >> 16));
+            a2 += bf2f((uint16_t)e.y);
+            a3 += bf2f((uint16_t)(e.y >> 16));
+        }
     }
 #pragma unroll
     for (int off = 16; off <= 32; off <<= 1) {
@@ -614,24 +628,41 @@ __global__ __launch_bounds__(1024) void k_grad_adam_E(const uint32_t *__restrict
             for (int t = 0; t < 4; ++t) acc[t] = mfma(A, ld8(sB + (t * 16 + lr) * SB + ks * 32 + lg * 8), acc[t]);
         }
         // lane (lr, lg) holds dE[v0 + 4 lg + r][16 t + lr]; node v0 + i's
-        // membership flag sits in lane i
+        // membership flag sits in lane i.  The weights and moments of all
+        // sixteen entries are loaded before any is updated, so the loads are
+        // in flight together.
+        bool tch[4];
+        float th[4][4], mm[4][4], vv[4][4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t node = v0 + 4 * lg + r;
             const bool touched = __shfl((int)rowany, 4 * lg + r, 64) != 0;
-            if (node >= n) continue;
+            tch[r] = touched && node < n;
+            if (keep && node < n)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) keep[node * kD + t * 16 + lr] = touched ? acc[t][r] : 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t base = (v0 + 4 * lg + r) * kD + lr;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int64_t idx = node * kD + t * 16 + lr;
-                const float g = acc[t][r];
-                if (keep) keep[idx] = touched ? g : 0.f;
-                if (!touched) continue;
-                float th = E[idx], mm = m[idx], vv = v[idx];
-                adam(th, mm, vv, g, o);
-                E[idx] = th;
-                m[idx] = mm;
-                v[idx] = vv;
-                Eb[idx] = f2bf(th);
+                th[r][t] = tch[r] ? E[base + t * 16] : 0.f;
+                mm[r][t] = tch[r] ? m[base + t * 16] : 0.f;
+                vv[r][t] = tch[r] ? v[base + t * 16] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (!tch[r]) continue;
+            const int64_t base = (v0 + 4 * lg + r) * kD + lr;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                adam(th[r][t], mm[r][t], vv[r][t], acc[t][r], o);
+                E[base + t * 16] = th[r][t];
+                m[base + t * 16] = mm[r][t];
+                v[base + t * 16] = vv[r][t];
+                Eb[base + t * 16] = f2bf(th[r][t]);
             }
         }
     }
@@ -874,6 +905,56 @@ __global__ void k_sample(uint64_t seed, uint32_t gen, uint32_t step, int32_t cou
     for (int32_t t = threadIdx.x; t < k; t += blockDim.x) genes[(int64_t)j * k + t] = buf_genes[(int64_t)r * k + t];
 }
 
+// Node-major membership bits of a sampled batch (rows ascending, as the GA
+// keeps them): bit (j mod 32) of word j / 32 of node v's row is set when v
+// is in sample j.  One block per range of kBitRange nodes: each thread finds,
+// for its samples, the first gene at or above the range by binary search,
+// sets the bits of the genes inside the range in an LDS tile, and the tile
+// is written out.
+constexpr int kBitRange = 256;
+
+__global__ __launch_bounds__(256) void k_batch_bits(const int32_t *__restrict__ genes, int32_t k, int32_t B,
+                                                    int32_t n, uint32_t *__restrict__ rows)
+{
+    extern __shared__ uint32_t tile[];  // [kBitRange][B / 32]
+    constexpr int kPer = 4;             // samples per thread searched together (B <= 1024)
+    const int32_t Wb = B / 32;
+    const int32_t v0 = blockIdx.x * kBitRange, v1 = v0 + kBitRange;
+    for (int32_t t = threadIdx.x; t < kBitRange * Wb; t += blockDim.x) tile[t] = 0u;
+    int32_t lo[kPer], hi[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        lo[u] = 0;
+        hi[u] = threadIdx.x + u * blockDim.x < B ? k : 0;
+    }
+    // lower bound of v0 in each of the thread's rows, the searches interleaved
+    for (int32_t span = k; span > 0; span >>= 1) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            if (lo[u] >= hi[u]) continue;
+            const int32_t j = threadIdx.x + u * blockDim.x;
+            const int32_t mid = (lo[u] + hi[u]) >> 1;
+            if (genes[(int64_t)j * k + mid] < v0) lo[u] = mid + 1;
+            else hi[u] = mid;
+        }
+    }
+    __syncthreads();  // the tile is cleared
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int32_t j = threadIdx.x + u * blockDim.x;
+        if (j >= B) continue;
+        const uint32_t bit = 1u << (j & 31);
+        for (int32_t p = lo[u]; p < k; ++p) {
+            const int32_t v = genes[(int64_t)j * k + p];
+            if (v >= v1) break;
+            atomicOr(&tile[(v - v0) * Wb + (j >> 5)], bit);
+        }
+    }
+    __syncthreads();
+    const int32_t words = min(kBitRange, n - v0) * Wb;
+    for (int32_t t = threadIdx.x; t < words; t += blockDim.x) rows[(int64_t)v0 * Wb + t] = tile[t];
+}
+
 // Judge: over J = min(m, 1024) evaluated children (entry i is pool entry
 // floor(i m / J)), Spearman's correlation between predictions and exact PC
 // (average ranks), and the mean relative error of expm1(yhat sd + mu).
@@ -963,7 +1044,9 @@ struct SurrogateState {
     DevBuf buf_genes, buf_y;                            // ring buffer
     DevBuf pool, crows, cmasks, calive;                 // screened children
     DevBuf dstats;                                      // double [2]: label mean and spread of the predictions
-    DevBuf dloss;                                       // double: loss of the last training step
+    DevBuf dloss;                                       // double [5]: [0] the loss of the last explicit
+                                                        // batch; [1 + (g & 3)] the loss of the last step of
+                                                        // generation g's training
     DevBuf tstats;                                      // double [2]: label mean and spread the training uses
     double *hstats = nullptr;                           // pinned, mapped: [2] rho, [3] rel_err, [4] loss,
                                                         // [5, 6] the predictions' label mean and spread
@@ -976,6 +1059,7 @@ struct SurrogateState {
     hipEvent_t ev_pred = nullptr;   // main stream: the generation's predictions are made
     hipEvent_t ev_snap = nullptr;   // training stream: training done and snapshot taken
     hipEvent_t ev_data = nullptr;   // main stream: the generation's labels are in the buffer
+    hipEvent_t ev_sampled = nullptr;  // training stream: the generation's batches are copied out of the buffer
     bool have_keep = false;
     bool explicit_loss = false;  // the last training step was an explicit batch: its loss is in dloss
 };
@@ -1108,7 +1192,8 @@ AdamArgs adam_args(SurrogateState &st)
 
 // One Adam step on B rows of genes (device, [B][k]) with standardised
 // targets (device): embeddings, MLP forward and backward, gradients, Adam.
-int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B, bool keep, hipStream_t s)
+int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B, bool keep, double *loss_out,
+               bool sorted_rows, hipStream_t s)
 {
     SurrogateState &st = *ga->surr;
     gapa_graph *g = ga->graph;
@@ -1144,17 +1229,25 @@ int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B
     w.keep = keep ? st.keep_mlp.as<float>() : nullptr;
     w.cp = copies(st);
     w.o = o;
-    w.loss_out = st.dloss.as<double>();
+    w.loss_out = loss_out;
     hipLaunchKernelGGL(k_mlp_wgrad, dim3(kWgradTasks), dim3(64), 0, s, w);
-    // membership bits of the batch, node-major: removed-node bit sets of the
-    // rows, transposed
-    int rc = launch_mask_build(genes, B, st.k, g->n, g->words, g->d_noniso, g->n_noniso, st.bmasks.as<uint32_t>(),
-                               st.balive.as<int32_t>(), st.tflag.as<int32_t>(), s);
-    if (rc != GAPA_OK) return rc;
+    // membership bits of the batch, node-major: straight from the rows when
+    // they are ascending (batches sampled from the buffer), or else the
+    // removed-node bit sets of the rows, transposed
     const int32_t Wb = B / 32;
-    if ((rc = launch_bits_transpose(st.bmasks.as<uint32_t>(), B, g->words, g->n, st.brows.as<uint32_t>(), s)) !=
-        GAPA_OK)
-        return rc;
+    int rc = GAPA_OK;
+    if (sorted_rows) {
+        const int32_t nranges = (st.n + kBitRange - 1) / kBitRange;
+        hipLaunchKernelGGL(k_batch_bits, dim3(nranges), dim3(256), (size_t)kBitRange * Wb * 4, s, genes, st.k, B,
+                           st.n, st.brows.as<uint32_t>());
+    } else {
+        rc = launch_mask_build(genes, B, st.k, g->n, g->words, g->d_noniso, g->n_noniso, st.bmasks.as<uint32_t>(),
+                               st.balive.as<int32_t>(), st.tflag.as<int32_t>(), s);
+        if (rc != GAPA_OK) return rc;
+        if ((rc = launch_bits_transpose(st.bmasks.as<uint32_t>(), B, g->words, g->n, st.brows.as<uint32_t>(), s)) !=
+            GAPA_OK)
+            return rc;
+    }
     const int64_t tiles = ((int64_t)st.n + 15) / 16;
     // one 16-wave block per compute unit shares one staged copy of dx
     const unsigned eblocks = (unsigned)std::min<int64_t>((tiles + 15) / 16, 256);
@@ -1247,9 +1340,13 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->dz1T, (size_t)B * kH * 2);
     res(st->dz2T, (size_t)B * kH * 2);
     res(st->dxT, (size_t)B * kD * 2);
-    res(st->target, (size_t)B * 4);
+    // one batch per training step of a generation: all are sampled before
+    // the first step runs
+    const size_t nbatch = (size_t)std::max(sp->train_steps, 1);
+    res(st->target, nbatch * B * 4);
     res(st->lossv, (size_t)B * 4);
-    res(st->bgenes, (size_t)B * st->k * 4);
+    res(st->bgenes, nbatch * B * st->k * 4);
+
     res(st->bmasks, (size_t)B * st->W * 4);
     res(st->balive, (size_t)B * 4);
     res(st->bflag, 16);
@@ -1262,7 +1359,7 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->cmasks, (size_t)(sp->screen + kJudgeExtra) * st->W * 4);
     res(st->calive, (size_t)(sp->screen + kJudgeExtra) * 4);
     res(st->dstats, 64);
-    res(st->dloss, 8);
+    res(st->dloss, 5 * 8);
     res(st->tstats, 16);
     if (rc != GAPA_OK) return rc;
     GAPA_HIP(hipHostMalloc(reinterpret_cast<void **>(&st->hstats), 64, hipHostMallocMapped | hipHostMallocCoherent));
@@ -1272,6 +1369,7 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_pred, hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_snap, hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_data, hipEventDisableTiming));
+    GAPA_HIP(hipEventCreateWithFlags(&st->ev_sampled, hipEventDisableTiming));
     GAPA_HIP(hipStreamCreateWithFlags(&st->ts, hipStreamNonBlocking));
     GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_grad_adam_E), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)grad_E_lds(1024)));
@@ -1286,7 +1384,7 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     if ((rc = launch_fill_u32(st->dstats.ptr, 0u, 16, s)) != GAPA_OK) return rc;
     if ((rc = launch_fill_u32(st->bflag.ptr, 0u, 4, s)) != GAPA_OK) return rc;
     if ((rc = launch_fill_u32(st->tflag.ptr, 0u, 4, s)) != GAPA_OK) return rc;
-    if ((rc = launch_fill_u32(st->dloss.ptr, 0u, 2, s)) != GAPA_OK) return rc;
+    if ((rc = launch_fill_u32(st->dloss.ptr, 0u, 10, s)) != GAPA_OK) return rc;
     {
         static const double musd0[2] = {0.0, 1.0};  // before any training: unstandardised
         GAPA_HIP(hipMemcpyAsync(st->tstats.ptr, musd0, 16, hipMemcpyHostToDevice, s));
@@ -1296,12 +1394,14 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     if ((rc = take_snapshot(*st, s)) != GAPA_OK) return rc;
     GAPA_HIP(hipEventRecord(st->ev_data, s));
     GAPA_HIP(hipStreamWaitEvent(st->ts, st->ev_data, 0));
+    GAPA_HIP(hipEventRecord(st->ev_sampled, st->ts));
     return GAPA_OK;
 }
 
 void surrogate_release(SurrogateState *st)
 {
     if (!st) return;
+    if (st->ts) (void)hipStreamSynchronize(st->ts);  // training still queued reads the buffers below
     for (DevBuf *b : {&st->theta, &st->m, &st->v, &st->keep_mlp, &st->keep_E, &st->Eb, &st->W1b, &st->W2b, &st->w3b,
                       &st->W1bT, &st->W2bT, &st->xb, &st->yhat, &st->snap, &st->xtrain, &st->ytrain,
                       &st->target, &st->lossv, &st->dy, &st->tflag, &st->dloss, &st->tstats,
@@ -1310,8 +1410,7 @@ void surrogate_release(SurrogateState *st)
                       &st->cmasks, &st->calive, &st->dstats})
         b->release();
     if (st->hstats) (void)hipHostFree(st->hstats);
-    if (st->ts) (void)hipStreamSynchronize(st->ts);
-    for (hipEvent_t e : {st->ready, st->ev_pred, st->ev_snap, st->ev_data})
+    for (hipEvent_t e : {st->ready, st->ev_pred, st->ev_snap, st->ev_data, st->ev_sampled})
         if (e) (void)hipEventDestroy(e);
     if (st->ts) (void)hipStreamDestroy(st->ts);
     delete st;
@@ -1382,27 +1481,35 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, neval, ds, st.hstats_dev + 2,
                            st.hstats_dev + 5);
     if (!random) {
-        // generation gen - 1's training is done with the buffer (and its loss is final)
-        GAPA_HIP(hipStreamWaitEvent(s, st.ev_snap, 0));
+        // generation gen - 1's training has copied its batches out of the
+        // buffer (it goes on beside this generation); the loss reported is
+        // that of generation gen - 2's training, finished before this
+        // generation's predictions (the wait on the snapshot above)
+        GAPA_HIP(hipStreamWaitEvent(s, st.ev_sampled, 0));
+        double *dloss = st.dloss.as<double>();
         hipLaunchKernelGGL(k_append, dim3(neval), dim3(256), 0, s, ga->children.as<int32_t>(), st.k, pool, F,
                            st.appended, st.sp.buffer, st.buf_genes.as<int32_t>(), st.buf_y.as<double>(),
-                           st.dloss.as<double>(), st.hstats_dev + 4);
+                           dloss + 1 + ((gen + 2u) & 3u), st.hstats_dev + 4);
         st.appended += neval;
         const int32_t count = (int32_t)std::min<int64_t>(st.appended, st.sp.buffer);
         GAPA_HIP(hipGetLastError());
-        // this generation's training, on the training stream: label statistics, then the steps
+        // this generation's training, on the training stream: label statistics,
+        // every step's batch, then the steps
         GAPA_HIP(hipEventRecord(st.ev_data, s));
         GAPA_HIP(hipStreamWaitEvent(st.ts, st.ev_data, 0));
         hipLaunchKernelGGL(k_label_stats, dim3(1), dim3(1024), 0, st.ts, st.buf_y.as<double>(), count,
                            st.tstats.as<double>());
-        for (int32_t t = 0; t < st.sp.train_steps; ++t) {
-            hipLaunchKernelGGL(k_sample, dim3(st.sp.batch), dim3(256), 0, st.ts, st.seed, gen, (uint32_t)t, count,
+        const int32_t B = st.sp.batch;
+        for (int32_t t = 0; t < st.sp.train_steps; ++t)
+            hipLaunchKernelGGL(k_sample, dim3(B), dim3(256), 0, st.ts, st.seed, gen, (uint32_t)t, count,
                                st.buf_genes.as<int32_t>(), st.buf_y.as<double>(), st.tstats.as<double>(), st.k,
-                               st.bgenes.as<int32_t>(), st.target.as<float>());
-            if ((rc = train_step(ga, st.bgenes.as<int32_t>(), st.target.as<float>(), st.sp.batch, false, st.ts)) !=
-                GAPA_OK)
+                               st.bgenes.as<int32_t>() + (int64_t)t * B * st.k, st.target.as<float>() + (int64_t)t * B);
+        GAPA_HIP(hipEventRecord(st.ev_sampled, st.ts));
+        for (int32_t t = 0; t < st.sp.train_steps; ++t)
+            if ((rc = train_step(ga, st.bgenes.as<int32_t>() + (int64_t)t * B * st.k,
+                                 st.target.as<float>() + (int64_t)t * B, B, false, dloss + 1 + (gen & 3u), true,
+                                 st.ts)) != GAPA_OK)
                 return rc;
-        }
     }
     GAPA_HIP(hipGetLastError());
     GAPA_HIP(hipEventRecord(st.ready, s));
@@ -1443,7 +1550,7 @@ int surrogate_train_batch(gapa_ga *ga, const int32_t *genes, const float *target
         return GAPA_E_INVALID_ARG;
     }
     GAPA_HIP(hipStreamSynchronize(st.ts));
-    const int rc = train_step(ga, genes, target, B, keep_grads, s);
+    const int rc = train_step(ga, genes, target, B, keep_grads, st.dloss.as<double>(), false, s);
     if (rc == GAPA_OK) st.explicit_loss = true;
     return rc;
 }

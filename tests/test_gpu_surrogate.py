@@ -203,10 +203,10 @@ def run_replayed(gp, g, gens, **kw):
             rho_ref, rel_ref = S.judge_stats(yhat[evaluated].astype(np.float64), F_eval, mu, sd)
             assert abs(st["spearman"] - rho_ref) <= 1e-9, (gen, st["spearman"], rho_ref)
             assert abs(st["rel_err"] - rel_ref) <= 1e-9 * max(1.0, rel_ref), (gen, st["rel_err"], rel_ref)
-        if gen >= 2:
-            # the loss of the last step of generation g - 1's training
-            losses.append((st["loss"], sga.losses[(gen - 1) * opts["train_steps"] - 1]))
-    for gen, (dev, ref) in enumerate(losses, start=2):
+        if gen >= 3:
+            # the loss of the last step of generation g - 2's training
+            losses.append((st["loss"], sga.losses[(gen - 2) * opts["train_steps"] - 1]))
+    for gen, (dev, ref) in enumerate(losses, start=3):
         print(f"generation {gen}: loss device {dev:.6f} oracle {ref:.6f}", flush=True)
     return ga, sga, screened, losses
 
