@@ -208,9 +208,12 @@ def run_batched(args, torch, gapa, inputs):
 WARMUP_GENS = 40  # surrogate generations that evaluate every child while the network learns
 TTT_CHECK = 8     # generations between two looks at the recorded best values
 TTT_MAX_GENS = 4096
+TTT_BUFFER = 65536  # training pairs kept (a ring of the most recent evaluated children)
+TTT_FALLBACK = 3    # screened generations with rho < 0.3 in a row before a full one
 
 
-def time_to_target(torch, gapa, inputs, seeds=(0,), cap_factor=2.0, warmup_gens=WARMUP_GENS, train_steps=2):
+def time_to_target(torch, gapa, inputs, seeds=(0,), cap_factor=2.0, warmup_gens=WARMUP_GENS, train_steps=2,
+                   buffer=TTT_BUFFER, fallback_gens=TTT_FALLBACK):
     """Wall time until the best pairwise connectivity reaches the plain GA's
     generation-500 value on the 200k-node workload: the plain GA (1024
     offspring, all evaluated), the surrogate-screened GA (4096 offspring, the
@@ -243,7 +246,8 @@ def time_to_target(torch, gapa, inputs, seeds=(0,), cap_factor=2.0, warmup_gens=
         else:
             ga = gapa.GA(graph, sw.k, sw.pop, seed, sw.pc, sw.pm, sw.tournament, sw.offspring, stream=stream)
             ga.attach_surrogate(screen=sw.exact_top, batch=1024, train_steps=train_steps, warmup_gens=warmup_gens,
-                                buffer=65536, fallback_gens=3, random_screen=(kind == "random"), stream=stream)
+                                buffer=buffer, fallback_gens=fallback_gens, random_screen=(kind == "random"),
+                                stream=stream)
         g, checked, hit, t_last = 0, 0, None, 0.0
         while g < TTT_MAX_GENS:
             ga.step(1, stream=stream)
@@ -294,7 +298,7 @@ def time_to_target(torch, gapa, inputs, seeds=(0,), cap_factor=2.0, warmup_gens=
         rec["speedup_vs_plain"] = (rec["plain_s"] / rec["surrogate_s"]) if rec["surrogate_s"] else None
         out.append(rec)
     return {"cap": f"{cap_factor} x plain 500-generation wall time", "warmup_gens": warmup_gens,
-            "train_steps": train_steps, "runs": out}
+            "train_steps": train_steps, "buffer": buffer, "fallback_gens": fallback_gens, "runs": out}
 
 
 def run_surrogate(args, torch, gapa, inputs):
@@ -445,6 +449,9 @@ def main():
     ap.add_argument("--ttt-warmup", type=int, default=WARMUP_GENS,
                     help="full generations of the surrogate GA before screening starts")
     ap.add_argument("--ttt-train-steps", type=int, default=2, help="Adam steps per generation of the surrogate GA")
+    ap.add_argument("--ttt-buffer", type=int, default=TTT_BUFFER, help="training pairs the surrogate GA keeps")
+    ap.add_argument("--ttt-fallback", type=int, default=TTT_FALLBACK,
+                    help="low-correlation screened generations in a row before a full one (0: never)")
     ap.add_argument("--ttt-only", action="store_true", help="run the time-to-target comparison alone")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -463,7 +470,8 @@ def main():
 
     if args.ttt_only:
         print(json.dumps(time_to_target(torch, gapa, inputs, [int(x) for x in args.ttt_seeds.split(",")],
-                                        warmup_gens=args.ttt_warmup, train_steps=args.ttt_train_steps)), flush=True)
+                                        warmup_gens=args.ttt_warmup, train_steps=args.ttt_train_steps,
+                                        buffer=args.ttt_buffer, fallback_gens=args.ttt_fallback)), flush=True)
         return
     if args.workload == "surrogate":
         args.warmup = 20 if args.warmup is None else args.warmup
@@ -554,7 +562,8 @@ def main():
     }
     if not args.no_time_to_target:
         out["time_to_target"] = time_to_target(torch, gapa, inputs, [int(x) for x in args.ttt_seeds.split(",")],
-                                               warmup_gens=args.ttt_warmup, train_steps=args.ttt_train_steps)
+                                               warmup_gens=args.ttt_warmup, train_steps=args.ttt_train_steps,
+                                               buffer=args.ttt_buffer, fallback_gens=args.ttt_fallback)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -287,8 +287,12 @@ GAPA_API int gapa_ga_destroy(gapa_ga *ga);
  * - screen) of the other children, drawn uniformly with Philox stream 7, for
  * the judge only (they join the training buffer, not elitism).  The judge is
  * the Spearman correlation between predictions and exact fitness over the
- * evaluated children (at most 1024 of them, evenly spaced): after `fallback_gens` consecutive screened generations with
- * a correlation below min_rho, the next generation evaluates every child.
+ * evaluated children (at most 1024 of them, evenly spaced).  Generation g is
+ * screened or evaluated in full as decided from the judge of generation g - 2
+ * (so a call never waits for the generation before it): after `fallback_gens`
+ * consecutive judged screened generations with a correlation below min_rho,
+ * generation g evaluates every child, and generation g - 1, launched before
+ * that decision, does not count towards the next one.
  * ------------------------------------------------------------------------- */
 enum {
     GAPA_SCREEN_RANDOM = 1u << 0 /* gapa_surrogate_params.flags: screen a uniformly

@@ -425,8 +425,6 @@ int graph_build(int dev, int32_t n, int64_t nnz, const int32_t *row_ptr, const i
     if ((e = hipMalloc(&g->d_colD, (size_t)std::max<int64_t>(nnz, 1) * 4)) != hipSuccess)
         return fail(hip_fail(e, "hipMalloc"));
     if ((e = hipMalloc(&g->d_order, (size_t)n * 4)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
-    if ((e = hipMalloc(&g->d_band_v, (size_t)std::max<size_t>(band_v.size(), 1) * 4)) != hipSuccess)
-        return fail(hip_fail(e, "hipMalloc"));
     if (nnz > 0) {
         if ((e = hipMemcpy(g->d_col, col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice)) != hipSuccess)
             return fail(hip_fail(e, "hipMemcpy"));
@@ -440,9 +438,17 @@ int graph_build(int dev, int32_t n, int64_t nnz, const int32_t *row_ptr, const i
     if ((e = hipMalloc(&g->d_noniso, (size_t)g->words * 4)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
     if ((e = hipMemcpy(g->d_noniso, noniso_bits.data(), (size_t)g->words * 4, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(hip_fail(e, "hipMemcpy"));
-    if (!band_v.empty() &&
-        (e = hipMemcpy(g->d_band_v, band_v.data(), band_v.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
-        return fail(hip_fail(e, "hipMemcpy"));
+    {
+        std::vector<int4> rec(std::max<size_t>(band_v.size(), 1), make_int4(0, 0, 0, 0));
+        for (size_t i = 0; i < band_v.size(); ++i) {
+            const int32_t v = band_v[i];
+            rec[i] = make_int4(v, row_ptr[v], row_ptr[v + 1], 0);
+        }
+        if ((e = hipMalloc(&g->d_band_rec, rec.size() * sizeof(int4))) != hipSuccess)
+            return fail(hip_fail(e, "hipMalloc"));
+        if ((e = hipMemcpy(g->d_band_rec, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(hip_fail(e, "hipMemcpy"));
+    }
     *out = g;
     return GAPA_OK;
 }
@@ -461,9 +467,10 @@ void graph_release(gapa_graph *g)
         (void)hipDeviceSynchronize();
         if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
         if (g->d_col) (void)hipFree(g->d_col);
-        for (int32_t *p : {g->d_src, g->d_colD, g->d_order, g->d_band_v})
+        for (int32_t *p : {g->d_src, g->d_colD, g->d_order})
             if (p) (void)hipFree(p);
         if (g->d_noniso) (void)hipFree(g->d_noniso);
+        if (g->d_band_rec) (void)hipFree(g->d_band_rec);
         release_workspace(g->ws);
     }
     delete g;

@@ -24,6 +24,8 @@
 // Isolated nodes of G are singletons in every G - S and never enter.
 #include <algorithm>
 #include <climits>
+#include <utility>
+#include <vector>
 
 #include "device_common.h"
 #include "internal.h"
@@ -249,58 +251,82 @@ __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restr
     }
 }
 
-// Pull for one node by its lane group: OR the neighbours' reach rows (in
-// degree-descending order) until every pending bit is covered or max_scan
-// neighbours have been read.  Returns true if the node gained bits.
-// Whatever stays pending is picked up by a later sweep or, in the end, by the
-// union-find pass, so the cap only moves work.
+// A node's record for the sweeps: (node, first edge, end of its edges), by
+// position in the band order; the worklist holds the records of the nodes
+// still pending.  With the record in hand a node's first neighbour ids are
+// one load away.
 //
-// The node's own bits and its neighbour range are loaded together; then the
-// neighbours are taken kPullChunk at a time (their ids, then their rows).
-// Reach rows are shared between the XCDs within one kernel: they are read
-// and written with agent-scope atomics, which bypass each XCD's own L2, so
-// bits another XCD set earlier in the same sweep are seen and spread at once
-// (plain loads that hit a stale line in the local L2 leave about 40 % more
-// nodes pending at n = 200k and make the pass 20 % slower).
-constexpr int kPullChunk = 4;
+// Pull for one node by its lane group: OR the neighbours' reach rows (in
+// degree-descending order), four at a time, until every pending bit is
+// covered or max_scan neighbours have been read; the node keeps the bits of
+// individuals in which it survives.  Whatever stays pending is picked up by
+// a later sweep or, in the end, by the union-find pass, so the cap only
+// moves work.
+//
+// Reach rows are shared between the XCDs within one kernel: neighbours' rows
+// are read and a node's own row written with agent-scope atomics, which
+// bypass each XCD's own L2, so bits another XCD set earlier in the same sweep
+// are seen and spread at once (plain loads that hit a stale line in the local
+// L2 leave about 40 % more nodes pending at n = 200k and make the pass 20 %
+// slower).  A node's own row is written only by its own pull, once per sweep,
+// and its dead row not at all, so both are read with plain loads.
+//
+// A group walks its nodes one after another; the record and first four
+// neighbour ids of its next node are loaded while the current one pulls, so
+// each node costs two dependent round trips (its own rows, then its
+// neighbours' rows) instead of four.
+struct PullOut {
+    bool gained;   // the node gained bits
+    bool pending;  // bits still pending after the pull
+};
 
-__device__ __forceinline__ bool pull_node(int32_t v, int Wd, int w, uint64_t gmask,
-                                          const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
-                                          const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach,
-                                          int32_t max_scan, bool *still_pending = nullptr)
+__device__ __forceinline__ void first_ids(const int4 r, int32_t max_scan, const int32_t *__restrict__ colD,
+                                          int32_t u[4])
 {
-    const int64_t vo = (int64_t)v * Wd + w;
-    const uint32_t mine = ld_relaxed_u(reach + vo);
-    const uint32_t dv = dead[vo];
-    const int32_t e0 = row_ptr[v], eN = row_ptr[v + 1];
-    const uint32_t pend = ~dv & ~mine;
-    if (still_pending) *still_pending = false;
-    if ((__ballot(pend != 0) & gmask) == 0) return false;
-    const int32_t e1 = eN - e0 > max_scan ? e0 + max_scan : eN;
+    const int32_t e1 = r.z - r.y > max_scan ? r.y + max_scan : r.z;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) u[t] = r.x >= 0 && r.y + t < e1 ? colD[r.y + t] : -1;
+}
+
+__device__ __forceinline__ PullOut pull_node(const int4 r, const int32_t u[4], int Wd, int w, uint64_t gmask,
+                                             const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
+                                             uint32_t *__restrict__ reach, int32_t max_scan)
+{
+    const int64_t vo = (int64_t)r.x * Wd + w;
+    const uint32_t mine = reach[vo];
+    const uint32_t pend = ~dead[vo] & ~mine;
+    PullOut out{false, false};
+    if ((__ballot(pend != 0) & gmask) == 0) return out;
     uint32_t acc = 0;
-    for (int32_t e = e0; e < e1; e += kPullChunk) {
-        int32_t u[kPullChunk];
 #pragma unroll
-        for (int t = 0; t < kPullChunk; ++t) u[t] = e + t < e1 ? colD[e + t] : -1;
+    for (int t = 0; t < 4; ++t)
+        if (u[t] >= 0) acc |= ld_relaxed_u(reach + (int64_t)u[t] * Wd + w);
+    const int32_t e1 = r.z - r.y > max_scan ? r.y + max_scan : r.z;
+    for (int32_t e = r.y + 4; e < e1 && (__ballot((acc & pend) != pend) & gmask) != 0; e += 4) {
+        int32_t x[4];
 #pragma unroll
-        for (int t = 0; t < kPullChunk; ++t)
-            if (u[t] >= 0) acc |= ld_relaxed_u(reach + (int64_t)u[t] * Wd + w);
-        if ((__ballot((acc & pend) != pend) & gmask) == 0) break;
+        for (int t = 0; t < 4; ++t) x[t] = e + t < e1 ? colD[e + t] : -1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (x[t] >= 0) acc |= ld_relaxed_u(reach + (int64_t)x[t] * Wd + w);
     }
     const uint32_t gain = acc & pend;
     if (gain) __hip_atomic_store(reach + vo, mine | gain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (still_pending) *still_pending = (__ballot((pend & ~gain) != 0) & gmask) != 0;
-    return (__ballot(gain != 0) & gmask) != 0;
+    out.pending = (__ballot((pend & ~gain) != 0) & gmask) != 0;
+    out.gained = (__ballot(gain != 0) & gmask) != 0;
+    return out;
 }
 
-// One band of the ordered sweep: nodes band_v[b0, b1).  A node's reach row
-// is written only by its own pull, so its pending bits are final once it has
-// pulled: pflag[v] records whether any is left (every non-isolated node is in
-// exactly one band, so every flag the compaction reads is written here).
-__global__ void k_pull_band(const int32_t *__restrict__ band_v, int32_t b0, int32_t b1, int32_t Wd,
-                            const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
-                            const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach, int32_t max_scan,
-                            uint8_t *__restrict__ pflag)
+// A sweep over count records (recs[i], or recs[b0 + i]), a group of Wd lanes
+// per node.  Band sweep (pflag given): pflag[b0 + i] records whether node i
+// is still pending; a node's reach row is written only by its own pull, so
+// its pending bits are final once it has pulled (every non-isolated node has
+// one band position, so every flag the compaction reads is written here, and
+// consecutive groups write neighbouring bytes).  Returns whether any node
+// of the calling wave gained bits.
+__device__ __forceinline__ bool pull_sweep(const int4 *__restrict__ recs, int32_t b0, int32_t count, int32_t Wd,
+                                           const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
+                                           uint32_t *__restrict__ reach, int32_t max_scan, uint8_t *__restrict__ pflag)
 {
     const int lane = threadIdx.x & 63;
     const int w = lane & (Wd - 1);
@@ -309,19 +335,33 @@ __global__ void k_pull_band(const int32_t *__restrict__ band_v, int32_t b0, int3
     const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / Wd;
     // every lane of a wave iterates the same number of times so that ballots
     // see whole groups
-    const int32_t count = b1 - b0;
     const int64_t iters = (count + ngroups - 1) / ngroups;
-    for (int64_t it = 0; it < iters; ++it) {
-        const int64_t idx = group + it * ngroups;
-        const bool valid = idx < count;
-        const int32_t v = valid ? band_v[b0 + idx] : 0;
-        if (__ballot(valid) == 0) continue;
-        if (valid) {
-            bool left;
-            pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach, max_scan, &left);
-            if (w == 0) pflag[v] = left ? 1 : 0;
+    const int4 none = make_int4(-1, 0, 0, 0);
+    int4 r = group < count ? recs[b0 + group] : none;
+    int32_t u[4];
+    first_ids(r, max_scan, colD, u);
+    bool any_gain = false;
+    for (int64_t it = 0, idx = group; it < iters; ++it, idx += ngroups) {
+        // the next node's record, loaded before this node's rows
+        const int64_t nidx = idx + ngroups;
+        const int4 nr = nidx < count ? recs[b0 + nidx] : none;
+        if (r.x >= 0) {
+            const PullOut o = pull_node(r, u, Wd, w, gmask, colD, dead, reach, max_scan);
+            any_gain |= o.gained;
+            if (pflag && w == 0) pflag[b0 + idx] = o.pending ? 1 : 0;
         }
+        r = nr;
+        first_ids(r, max_scan, colD, u);
     }
+    return __ballot(any_gain) != 0;
+}
+
+// One band of the ordered sweep: the nodes at band positions [b0, b1).
+__global__ void k_pull_band(const int4 *__restrict__ band_rec, int32_t b0, int32_t b1, int32_t Wd,
+                            const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
+                            uint32_t *__restrict__ reach, int32_t max_scan, uint8_t *__restrict__ pflag)
+{
+    (void)pull_sweep(band_rec, b0, b1 - b0, Wd, colD, dead, reach, max_scan, pflag);
 }
 
 // Block-level compaction: every block owns a contiguous range of the input,
@@ -354,19 +394,18 @@ __device__ __forceinline__ C block_reserve(int32_t mine, C *counter, int32_t *s_
 // most 33), [kPairCountSlot, kPairCountSlot + 2) the 64-bit pair count; k_seed
 // clears all 64.
 constexpr int kPairCountSlot = 36;
-// [kDoneSlot]: blocks of k_pairs_reduce finished (the last one finishes the pass)
-constexpr int kDoneSlot = kPairCountSlot + 2;
-constexpr int32_t kFinishSlots = 1024;
-static_assert(kPairCountSlot % 2 == 0 && kPairCountSlot >= 2 + 33 && kDoneSlot < 64, "counter layout");
+static_assert(kPairCountSlot % 2 == 0 && kPairCountSlot >= 2 + 33 && kPairCountSlot + 2 <= 64, "counter layout");
 
 // Nodes still pending after the ordered sweep -> worklist: the compaction of
-// the pending flags over node ids (isolated nodes keep flag 0).  A thread
-// reads 16 flags at once; a block scans its counts and reserves its room in
-// the worklist with one global atomic.
+// the pending flags, which are kept by position in the band order (each band
+// writes one contiguous run of them).  A thread reads 16 flags at once; a
+// block scans its counts and reserves its room in the worklist with one
+// global atomic.
 constexpr int kFlagsPerThread = 16;
 
 __global__ __launch_bounds__(kBlk) void k_collect_pending(const uint8_t *__restrict__ pflag, int32_t n,
-                                                          int32_t *__restrict__ worklist, int32_t *__restrict__ wl_count)
+                                                          const int4 *__restrict__ band_rec,
+                                                          int4 *__restrict__ worklist, int32_t *__restrict__ wl_count)
 {
     __shared__ int32_t s_wave[kBlk / 64];
     __shared__ int32_t s_base;
@@ -405,35 +444,21 @@ __global__ __launch_bounds__(kBlk) void k_collect_pending(const uint8_t *__restr
     int32_t pos = s_base + before + incl - mine;
 #pragma unroll
     for (int t = 0; t < kFlagsPerThread; ++t)
-        if ((f[t >> 2] >> (8 * (t & 3))) & 1u) worklist[pos++] = v0 + t;
+        if ((f[t >> 2] >> (8 * (t & 3))) & 1u) worklist[pos++] = band_rec[v0 + t];
 }
 
 // Further sweeps over the worklist; sweep s runs only if sweep s - 1 changed
 // something (changed[s - 1] != 0; changed[0] is set by the caller).
-__global__ void k_pull_worklist(const int32_t *__restrict__ worklist, const int32_t *__restrict__ wl_count,
-                                int32_t Wd, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
-                                const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach,
-                                int32_t *__restrict__ changed, int32_t s)
+__global__ void k_pull_worklist(const int4 *__restrict__ worklist, const int32_t *__restrict__ wl_count,
+                                int32_t Wd, const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
+                                uint32_t *__restrict__ reach, int32_t *__restrict__ changed, int32_t s)
 {
     if (ld_relaxed(changed + s - 1) == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int w = lane & (Wd - 1);
-    const uint64_t gmask = group_mask(Wd);
-    const int64_t group = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / Wd;
-    const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / Wd;
     const int32_t count = ld_relaxed(wl_count);
-    const int64_t iters = (count + ngroups - 1) / ngroups;
-    bool any_gain = false;
-    for (int64_t it = 0; it < iters; ++it) {
-        const int64_t idx = group + it * ngroups;
-        const bool valid = idx < count;
-        const int32_t v = valid ? worklist[idx] : 0;
-        if (__ballot(valid) == 0) continue;
-        if (valid) any_gain |= pull_node(v, Wd, w, gmask, row_ptr, colD, dead, reach, INT_MAX);
-    }
+    const bool any_gain = pull_sweep(worklist, 0, count, Wd, colD, dead, reach, INT_MAX, nullptr);
     // one flag for the whole grid: set it with a plain store, and only if no
     // other wave has (same-address atomics from every wave would serialise)
-    if (__ballot(any_gain) != 0 && lane == 0 && ld_relaxed(changed + s) == 0)
+    if (any_gain && (threadIdx.x & 63) == 0 && ld_relaxed(changed + s) == 0)
         __hip_atomic_store(changed + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -446,18 +471,17 @@ __global__ void k_pull_worklist(const int32_t *__restrict__ worklist, const int3
 // A block takes one worklist entry per group at a time: it splits every
 // (node, word) entry, reserves room for the block's pairs with one global
 // atomic, then writes them.
-constexpr int kSplitChunk = 16;
+constexpr int kSplitChunk = 4;
 
-__device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t gmask,
-                                              const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
-                                              const uint32_t *__restrict__ dead, const uint32_t *__restrict__ reach,
-                                              bool valid, uint32_t &single, uint32_t &multi)
+__device__ __forceinline__ void pending_split(const int4 r, int Wd, int w, uint64_t gmask,
+                                              const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
+                                              const uint32_t *__restrict__ reach, bool valid, uint32_t &single,
+                                              uint32_t &multi)
 {
-    // the node's bits and its neighbour range are loaded together
-    const int64_t vo = (int64_t)v * Wd + w;
+    const int64_t vo = (int64_t)r.x * Wd + w;
     const uint32_t dv = valid ? dead[vo] : ~0u;
     const uint32_t rv = valid ? reach[vo] : 0u;
-    const int32_t e0 = valid ? row_ptr[v] : 0, e1 = valid ? row_ptr[v + 1] : 0;
+    const int32_t e0 = valid ? r.y : 0, e1 = valid ? r.z : 0;
     const uint32_t pend = ~dv & ~rv;
     uint32_t nb = 0;
     if ((__ballot(pend != 0) & gmask) != 0) {
@@ -487,9 +511,8 @@ __device__ __forceinline__ void pending_split(int32_t v, int Wd, int w, uint64_t
 // with 64-entry ranges.
 __device__ __forceinline__ int32_t pair_range(int32_t Wd) { return kBlk / Wd; }
 
-__global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restrict__ worklist,
+__global__ __launch_bounds__(kBlk) void k_collect_pairs(const int4 *__restrict__ worklist,
                                                         const int32_t *__restrict__ wl_count, int32_t Wd, const Insts I,
-                                                        const int32_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ colD,
                                                         const uint32_t *__restrict__ dead,
                                                         const uint32_t *__restrict__ reach, int64_t *__restrict__ pairs,
@@ -516,9 +539,10 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int32_t *__restric
         // one split per (node, word), kept for the write pass
         const int32_t idx = r0 + (int32_t)(threadIdx.x / Wd);
         const bool valid = idx < count;
-        const int32_t v = valid ? worklist[idx] : 0;
+        const int4 rec = valid ? worklist[idx] : make_int4(0, 0, 0, 0);
+        const int32_t v = rec.x;
         uint32_t single, mul;
-        pending_split(v, Wd, w, gmask, row_ptr, colD, dead, reach, valid, single, mul);
+        pending_split(rec, Wd, w, gmask, colD, dead, reach, valid, single, mul);
         const int32_t gbase = inst_of_node(I, v) * I.bseg + w * 32;
         for (; single; single &= single - 1) {
             if (lds_singles) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
@@ -671,35 +695,14 @@ __device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit
 // The root's component of slot gi: what remains of its surviving
 // non-isolated nodes once every other component is counted (or the root
 // alone when it is isolated).  Its union-find counter is cleared for reuse.
-__device__ __forceinline__ void root_component(int32_t gi, const int32_t *__restrict__ root, const Insts &I,
-                                               int32_t *__restrict__ parent, const int32_t *__restrict__ alive_noniso,
-                                               const int32_t *__restrict__ other, const int32_t *__restrict__ row_ptr,
-                                               int32_t *__restrict__ ucount, unsigned long long *__restrict__ fitness,
-                                               int32_t *__restrict__ mcn, int32_t forest)
-{
-    const int32_t r = root[gi];
-    if (r < 0) return;
-    const int32_t off = i_voff(I, gi / I.bseg);
-    const int64_t blk = uf_block(I, gi);
-    ucount[blk + uf_find(parent + blk, r - off)] = 0;
-    const int32_t oth = __hip_atomic_load(other + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int64_t s = row_ptr[r + 1] > row_ptr[r] ? (int64_t)alive_noniso[gi] - oth : 1;
-    add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
-}
-
 // Components made only of pending nodes (set representative is a pending node
 // other than the root's representative): counted, and their sizes summed into
-// other[gi].  Their counters are cleared for reuse.  With `finish`, the last
-// block to finish (counted in *done, which the pass's first kernel cleared)
-// then adds every slot's root component, which needs all the other sums.
+// other[gi].  Their counters are cleared for reuse.
 __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count, const Insts I,
                                int32_t *__restrict__ parent, const int32_t *__restrict__ root,
                                int32_t *__restrict__ ucount, int32_t *__restrict__ other,
-                               unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest,
-                               int32_t finish, int32_t *__restrict__ done, const int32_t *__restrict__ alive_noniso,
-                               const int32_t *__restrict__ row_ptr)
+                               unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest)
 {
-    __shared__ bool s_last;
     const int64_t count = (int64_t)*pair_count;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t key = pairs[q];
@@ -713,27 +716,24 @@ __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const unsigned
         atomicAdd(other + gi, s);
         add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
     }
-    if (!finish) return;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();  // this block's sums are visible before it counts itself done
-        s_last = atomicAdd(done, 1) == (int32_t)gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    for (int32_t gi = threadIdx.x; gi < I.count * I.bseg; gi += blockDim.x)
-        root_component(gi, root, I, parent, alive_noniso, other, row_ptr, ucount, fitness, mcn, forest);
 }
 
+// The root's component of each slot: what remains of its surviving
+// non-isolated nodes once every other component is counted (or the root
+// alone when it is isolated).  Its union-find counter is cleared for reuse.
 __global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, int32_t *__restrict__ parent,
                              const int32_t *__restrict__ alive_noniso, const int32_t *__restrict__ other,
                              const int32_t *__restrict__ row_ptr, int32_t *__restrict__ ucount,
                              unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest)
 {
     const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= I.count * I.bseg) return;
-    root_component(gi, root, I, parent, alive_noniso, other, row_ptr, ucount, fitness, mcn, forest);
+    if (gi >= I.count * I.bseg || root[gi] < 0) return;
+    const int32_t r = root[gi];
+    const int32_t off = i_voff(I, gi / I.bseg);
+    const int64_t blk = uf_block(I, gi);
+    ucount[blk + uf_find(parent + blk, r - off)] = 0;
+    const int64_t s = row_ptr[r + 1] > row_ptr[r] ? (int64_t)alive_noniso[gi] - other[gi] : 1;
+    add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
 }
 
 }  // namespace
@@ -774,10 +774,10 @@ int reserve_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, hipSt
     // pending pairs of slot (b, i) are nodes of instance b: at most B per node
     const int64_t max_pairs = (int64_t)B * std::max(g->n_noniso, 1);
     if ((rc = ws.pairs.reserve((size_t)max_pairs * 8)) != GAPA_OK) return rc;
-    if ((rc = ws.worklist.reserve((size_t)std::max(g->n_noniso, 1) * 4)) != GAPA_OK) return rc;
-    // pending flags per node: written for every non-isolated node by each
-    // pass; isolated nodes keep the zero they get here
-    const size_t flag_bytes = ((size_t)n + 15) & ~(size_t)15;
+    if ((rc = ws.worklist.reserve((size_t)std::max(g->n_noniso, 1) * 16)) != GAPA_OK) return rc;
+    // pending flags by band position: each pass writes every position below
+    // n_noniso before the compaction reads it (zeroed once here all the same)
+    const size_t flag_bytes = ((size_t)std::max(g->n_noniso, 1) + 15) & ~(size_t)15;
     if (ws.pflag.bytes < flag_bytes || !ws.pflag_clear) {
         if ((rc = ws.pflag.reserve(flag_bytes)) != GAPA_OK) return rc;
         if ((rc = launch_fill_u32(ws.pflag.ptr, 0u, (int64_t)(flag_bytes / 4), s)) != GAPA_OK) return rc;
@@ -811,7 +811,7 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
     uint32_t *dead = ws.dead.as<uint32_t>(), *reach = ws.reach.as<uint32_t>();
     int32_t *parent = ws.parent.as<int32_t>(), *ucount = ws.ucount.as<int32_t>();
     int64_t *pairs = ws.pairs.as<int64_t>();
-    int32_t *worklist = ws.worklist.as<int32_t>();
+    int4 *worklist = ws.worklist.as<int4>();
     const int32_t nb = (int32_t)g->band_off.size() - 1;
     const int32_t noniso = g->n_noniso;
     {
@@ -845,26 +845,26 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
                 if (b1 <= b0) continue;
                 const int64_t threads = (int64_t)(b1 - b0) * Wd;
                 const int blocks = (int)std::min<int64_t>((threads + kBlk - 1) / kBlk, tu.band_blocks);
-                hipLaunchKernelGGL(k_pull_band, dim3(blocks), dim3(kBlk), 0, s, g->d_band_v, b0, b1, Wd,
-                                   g->d_row_ptr, g->d_colD, dead, reach, tu.band_scan, ws.pflag.as<uint8_t>());
+                hipLaunchKernelGGL(k_pull_band, dim3(blocks), dim3(kBlk), 0, s, g->d_band_rec, b0, b1, Wd, g->d_colD,
+                                   dead, reach, tu.band_scan, ws.pflag.as<uint8_t>());
             }
         }
         if (noniso > 0) {
             TimedScope ts(timer, "k_collect_pending", s);
             const int32_t per_block = kBlk * kFlagsPerThread;
-            hipLaunchKernelGGL(k_collect_pending, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(kBlk), 0, s,
-                               ws.pflag.as<uint8_t>(), n, worklist, wl_count);
+            hipLaunchKernelGGL(k_collect_pending, dim3((unsigned)((noniso + per_block - 1) / per_block)), dim3(kBlk),
+                               0, s, ws.pflag.as<uint8_t>(), noniso, g->d_band_rec, worklist, wl_count);
         }
         {
             TimedScope ts(timer, "k_pull_worklist", s);
             for (int32_t sw = 1; sw <= tu.sweeps; ++sw)
-                hipLaunchKernelGGL(k_pull_worklist, dim3(grid), dim3(kBlk), 0, s, worklist, wl_count, Wd,
-                                   g->d_row_ptr, g->d_colD, dead, reach, changed, sw);
+                hipLaunchKernelGGL(k_pull_worklist, dim3(grid), dim3(kBlk), 0, s, worklist, wl_count, Wd, g->d_colD,
+                                   dead, reach, changed, sw);
         }
         {
             TimedScope ts(timer, "k_collect_pairs", s);
-            hipLaunchKernelGGL(k_collect_pairs, dim3(grid), dim3(kBlk), 0, s, worklist, wl_count, Wd, I,
-                               g->d_row_ptr, g->d_colD, dead, reach, pairs, pair_count, parent, single_part, other);
+            hipLaunchKernelGGL(k_collect_pairs, dim3(grid), dim3(kBlk), 0, s, worklist, wl_count, Wd, I, g->d_colD,
+                               dead, reach, pairs, pair_count, parent, single_part, other);
         }
         {
             TimedScope ts(timer, "k_pairs_hook", s);
@@ -881,14 +881,13 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
         }
         {
             TimedScope ts(timer, "k_pairs_reduce", s);
-            // up to kFinishSlots slots, the root components are added by the
-            // reduction's last block (one dependent launch fewer)
-            const int32_t finish = S <= kFinishSlots ? 1 : 0;
             hipLaunchKernelGGL(k_pairs_reduce, dim3(grid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, root,
-                               ucount, other, fit, mc, (int32_t)measure, finish, ctr + kDoneSlot, al, g->d_row_ptr);
-            if (!finish)
-                hipLaunchKernelGGL(k_root_final, dim3((S + 63) / 64), dim3(64), 0, s, root, I, parent, al, other,
-                                   g->d_row_ptr, ucount, fit, mc, (int32_t)measure);
+                               ucount, other, fit, mc, (int32_t)measure);
+        }
+        {
+            TimedScope ts(timer, "k_root_final", s);
+            hipLaunchKernelGGL(k_root_final, dim3((S + 63) / 64), dim3(64), 0, s, root, I, parent, al, other,
+                               g->d_row_ptr, ucount, fit, mc, (int32_t)measure);
         }
         GAPA_HIP(hipGetLastError());
     }
@@ -930,7 +929,7 @@ ScratchLayout scratch_layout(const gapa_graph *g, int32_t Wd)
     l.pairs = o;
     o += up(B * nn * 8);
     l.worklist = o;
-    o += up(nn * 4);
+    o += up(nn * 16);
     l.pflag = o;
     o += up((n + 15) & ~(size_t)15);
     l.small = o;
@@ -1023,30 +1022,63 @@ int ensure_lanes(FitnessWorkspace &ws, int32_t lanes)
     return GAPA_OK;
 }
 
+namespace {
+
+// Shape of a pass over chunks of Wd words per node row.
+PassShape pass_shape(int32_t Wd, const InstTable *it)
+{
+    PassShape sh{};
+    sh.multi = it && it->count > 1;
+    sh.Wd = Wd;
+    sh.log_wd = 0;
+    while ((1 << sh.log_wd) < sh.Wd) ++sh.log_wd;
+    sh.B = sh.Wd * 32;
+    sh.S = sh.multi ? it->count * sh.B : sh.B;
+    return sh;
+}
+
+}  // namespace
+
 int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, int32_t P, int64_t *fitness,
                     int32_t *mcn, FitnessWorkspace &ws, KernelTimer *timer, hipStream_t s, const InstTable *it,
                     Measure measure)
 {
     const bool multi = it && it->count > 1;
     if (!multi && P <= 0) return GAPA_OK;
-    // chunk width: 32 * Wd slots per instance, Wd a power of two <= 32
-    PassShape sh{};
-    sh.multi = multi;
-    sh.Wd = 1;
-    if (multi) sh.Wd = it->bseg / 32;
-    else
-        while (sh.Wd < 32 && sh.Wd * 32 < P) sh.Wd <<= 1;
-    sh.log_wd = 0;
-    while ((1 << sh.log_wd) < sh.Wd) ++sh.log_wd;
-    sh.B = sh.Wd * 32;
-    sh.S = multi ? it->count * sh.B : sh.B;
-    const int32_t chunks = multi ? 1 : (P + sh.B - 1) / sh.B;
+    // Chunks of 32 * Wd individuals, Wd a power of two <= 32: full chunks of
+    // 1024, then the rest in the narrowest chunk that holds it, or, when the
+    // rest is just above 512, as 512 and a chunk of at most 256 side by side
+    // (a pass's cost grows with its width: 512 + 32 individuals on two
+    // lanes take less time than one pass 1024 wide).
+    std::vector<std::pair<int32_t, int32_t>> plan;  // (first individual, Wd)
+    if (multi) {
+        plan.emplace_back(0, it->bseg / 32);
+    } else {
+        int32_t c0 = 0;
+        for (; P - c0 >= 1024; c0 += 1024) plan.emplace_back(c0, 32);
+        const int32_t r = P - c0;
+        if (r > 0) {
+            int32_t wd = 1;
+            while (wd * 32 < r) wd <<= 1;
+            int32_t lo = 1;
+            while (r > 512 && lo * 32 < r - 512) lo <<= 1;
+            if (wd == 32 && r > 512 && lo <= 8) {
+                plan.emplace_back(c0, 16);
+                plan.emplace_back(c0 + 512, lo);
+            } else {
+                plan.emplace_back(c0, wd);
+            }
+        }
+    }
+    const int32_t chunks = (int32_t)plan.size();
     const int32_t lanes = std::min(chunks, kPassLanes);
     int rc;
     if (lanes <= 1) {
+        const PassShape sh = pass_shape(plan[0].second, it);
         if ((rc = reserve_pass(g, ws, sh, s)) != GAPA_OK) return rc;
         for (int32_t c = 0; c < chunks; ++c)
-            if ((rc = run_pass(g, ws, sh, it, masks, alive, P, c * sh.B, fitness, mcn, measure, timer, s)) != GAPA_OK)
+            if ((rc = run_pass(g, ws, sh, it, masks, alive, P, plan[c].first, fitness, mcn, measure, timer, s)) !=
+                GAPA_OK)
                 return rc;
         return GAPA_OK;
     }
@@ -1056,11 +1088,11 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
     // fork: every lane starts after the work already on s
     GAPA_HIP(hipEventRecord(ws.fork, s));
     for (int32_t i = 1; i < lanes; ++i) GAPA_HIP(hipStreamWaitEvent(lane_stream(i), ws.fork, 0));
-    for (int32_t i = 0; i < lanes; ++i)
-        if ((rc = reserve_pass(g, lane_ws(i), sh, lane_stream(i))) != GAPA_OK) return rc;
     for (int32_t c = 0; c < chunks; ++c) {
         const int32_t i = c % lanes;
-        if ((rc = run_pass(g, lane_ws(i), sh, it, masks, alive, P, c * sh.B, fitness, mcn, measure, timer,
+        const PassShape sh = pass_shape(plan[c].second, it);
+        if ((rc = reserve_pass(g, lane_ws(i), sh, lane_stream(i))) != GAPA_OK) return rc;
+        if ((rc = run_pass(g, lane_ws(i), sh, it, masks, alive, P, plan[c].first, fitness, mcn, measure, timer,
                            lane_stream(i))) != GAPA_OK)
             return rc;
     }
@@ -1069,8 +1101,9 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         GAPA_HIP(hipEventRecord(ws.lane_done[i - 1], lane_stream(i)));
         GAPA_HIP(hipStreamWaitEvent(s, ws.lane_done[i - 1], 0));
     }
-    ws.stats_ctr = ws.small.as<int32_t>() + 2 * sh.S;
-    ws.stats_B = sh.S;
+    const PassShape sh0 = pass_shape(plan[0].second, it);
+    ws.stats_ctr = ws.small.as<int32_t>() + 2 * sh0.S;
+    ws.stats_B = sh0.S;
     return GAPA_OK;
 }
 

@@ -97,8 +97,8 @@ struct FitnessWorkspace {
     DevBuf reach;    // uint32 [n][Wd] root-component bits
     DevBuf ucount;   // int32 [B][n]  set sizes of the leftover union-find, kept zero
     DevBuf pairs;    // int64 [B * n_noniso] pending (individual, node) keys
-    DevBuf worklist; // int32 [n_noniso] nodes still pending after the ordered sweep
-    DevBuf pflag;    // uint8 [n] 1: node still pending after the ordered sweep
+    DevBuf worklist; // int4 [n_noniso] records (node, first edge, edge end) of the nodes still pending after the ordered sweep
+    DevBuf pflag;    // uint8 [n_noniso] 1: the node at this band position is still pending after the ordered sweep
     bool pflag_clear = false;  // pflag zeroed since it was (re)allocated
     DevBuf small;    // int32 roots, root-set sizes, counters, count partials
     int32_t *stats_ctr = nullptr;  // device counters of the last bit-parallel chunk
@@ -142,9 +142,10 @@ struct gapa_graph {
     int32_t *d_src = nullptr;   // source node of every CSR entry (COO rows)
     int32_t *d_order = nullptr; // [n] nodes by (degree desc, id)
     int32_t *d_colD = nullptr;  // [nnz] each neighbour list by (degree desc, id)
-    int32_t *d_band_v = nullptr;  // [n_noniso] non-isolated nodes by (BFS level, id)
+    int4 *d_band_rec = nullptr;   // [n_noniso] non-isolated nodes by (BFS level, id) as records
+                                  // (node, row_ptr[node], row_ptr[node + 1], 0)
     uint32_t *d_noniso = nullptr; // [words] bit v set: v has at least one edge
-    std::vector<int32_t> band_off;  // host: band b is d_band_v[band_off[b], band_off[b+1])
+    std::vector<int32_t> band_off;  // host: band b is d_band_rec[band_off[b], band_off[b+1])
     int32_t n_noniso = 0;       // nodes with at least one edge
     int32_t algorithm = 0;      // 0: bit-parallel sweeps, 1: edge-parallel union-find
     gapa::Tuning tune;

@@ -874,12 +874,25 @@ __global__ __launch_bounds__(1024) void k_label_stats(const double *__restrict__
                                                       double *__restrict__ out)
 {
     __shared__ double s_w[16];
-    double a = 0.0;
-    for (int32_t i = threadIdx.x; i < count; i += blockDim.x) a += y[i];
-    const double mu = block_sum_d(a, s_w) / count;
-    a = 0.0;
-    for (int32_t i = threadIdx.x; i < count; i += blockDim.x) a += (y[i] - mu) * (y[i] - mu);
-    const double var = block_sum_d(a, s_w) / count;
+    // four partial sums per thread, so that four loads are in flight at once
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    const int32_t step = 4 * blockDim.x;
+    int32_t i = threadIdx.x;
+    for (; i + 3 * (int32_t)blockDim.x < count; i += step)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] += y[i + u * blockDim.x];
+    for (; i < count; i += blockDim.x) a[0] += y[i];
+    const double mu = block_sum_d((a[0] + a[1]) + (a[2] + a[3]), s_w) / count;
+    double b[4] = {0.0, 0.0, 0.0, 0.0};
+    i = threadIdx.x;
+    for (; i + 3 * (int32_t)blockDim.x < count; i += step)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double d = y[i + u * blockDim.x] - mu;
+            b[u] += d * d;
+        }
+    for (; i < count; i += blockDim.x) b[0] += (y[i] - mu) * (y[i] - mu);
+    const double var = block_sum_d((b[0] + b[1]) + (b[2] + b[3]), s_w) / count;
     if (threadIdx.x == 0) {
         out[0] = mu;
         out[1] = sqrt(var + kSpreadFloor * kSpreadFloor);
@@ -889,11 +902,21 @@ __global__ __launch_bounds__(1024) void k_label_stats(const double *__restrict__
 // Training batch of step `step` in generation `gen`: entry j is buffer row
 // bounded(w, count), w the first word of draw(seed, j, step, gen, stream 6);
 // its genes are copied and its label standardised.
+// Membership bits of a sampled training batch are built per chunk of
+// kBitChunk nodes.  k_sample records, for each sample j and each chunk
+// boundary c (node c kBitChunk, c = 0 .. nchunks), the position in the
+// sample's ascending gene row of the first gene at or above it:
+// pos[j][c] (binary searches over the row staged in LDS).
+constexpr int kBitChunk = 1024;
+constexpr int kSampleRowLds = 4096;      // longest row staged in LDS for the searches
+
 __global__ void k_sample(uint64_t seed, uint32_t gen, uint32_t step, int32_t count, const int32_t *__restrict__ buf_genes,
                          const double *__restrict__ buf_y, const double *__restrict__ mu_sd, int32_t k,
-                         int32_t *__restrict__ genes, float *__restrict__ target)
+                         int32_t *__restrict__ genes, float *__restrict__ target, int32_t nchunks,
+                         int32_t *__restrict__ pos)
 {
     __shared__ int32_t s_idx;
+    __shared__ int32_t s_row[kSampleRowLds];
     const int32_t j = blockIdx.x;
     if (threadIdx.x == 0) {
         const uint32_t w = draw(seed, (uint32_t)j, step, gen, kStreamSurrSample, 0).w0;
@@ -902,56 +925,52 @@ __global__ void k_sample(uint64_t seed, uint32_t gen, uint32_t step, int32_t cou
     }
     __syncthreads();
     const int32_t r = s_idx;
-    for (int32_t t = threadIdx.x; t < k; t += blockDim.x) genes[(int64_t)j * k + t] = buf_genes[(int64_t)r * k + t];
-}
-
-// Node-major membership bits of a sampled batch (rows ascending, as the GA
-// keeps them): bit (j mod 32) of word j / 32 of node v's row is set when v
-// is in sample j.  One block per range of kBitRange nodes: each thread finds,
-// for its samples, the first gene at or above the range by binary search,
-// sets the bits of the genes inside the range in an LDS tile, and the tile
-// is written out.
-constexpr int kBitRange = 256;
-
-__global__ __launch_bounds__(256) void k_batch_bits(const int32_t *__restrict__ genes, int32_t k, int32_t B,
-                                                    int32_t n, uint32_t *__restrict__ rows)
-{
-    extern __shared__ uint32_t tile[];  // [kBitRange][B / 32]
-    constexpr int kPer = 4;             // samples per thread searched together (B <= 1024)
-    const int32_t Wb = B / 32;
-    const int32_t v0 = blockIdx.x * kBitRange, v1 = v0 + kBitRange;
-    for (int32_t t = threadIdx.x; t < kBitRange * Wb; t += blockDim.x) tile[t] = 0u;
-    int32_t lo[kPer], hi[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        lo[u] = 0;
-        hi[u] = threadIdx.x + u * blockDim.x < B ? k : 0;
-    }
-    // lower bound of v0 in each of the thread's rows, the searches interleaved
-    for (int32_t span = k; span > 0; span >>= 1) {
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            if (lo[u] >= hi[u]) continue;
-            const int32_t j = threadIdx.x + u * blockDim.x;
-            const int32_t mid = (lo[u] + hi[u]) >> 1;
-            if (genes[(int64_t)j * k + mid] < v0) lo[u] = mid + 1;
-            else hi[u] = mid;
-        }
-    }
-    __syncthreads();  // the tile is cleared
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int32_t j = threadIdx.x + u * blockDim.x;
-        if (j >= B) continue;
-        const uint32_t bit = 1u << (j & 31);
-        for (int32_t p = lo[u]; p < k; ++p) {
-            const int32_t v = genes[(int64_t)j * k + p];
-            if (v >= v1) break;
-            atomicOr(&tile[(v - v0) * Wb + (j >> 5)], bit);
-        }
+    const int32_t *src = buf_genes + (int64_t)r * k;
+    const bool lds = k <= kSampleRowLds;
+    for (int32_t t = threadIdx.x; t < k; t += blockDim.x) {
+        const int32_t gt = src[t];
+        genes[(int64_t)j * k + t] = gt;
+        if (lds) s_row[t] = gt;
     }
     __syncthreads();
-    const int32_t words = min(kBitRange, n - v0) * Wb;
+    const int32_t *row = lds ? s_row : src;
+    for (int32_t c = threadIdx.x; c <= nchunks; c += blockDim.x) {
+        const int32_t v = c * kBitChunk;
+        int32_t lo = 0, hi = k;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (row[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        pos[(int64_t)j * (nchunks + 1) + c] = lo;
+    }
+}
+
+// Node-major membership bits of a sampled batch: bit (j mod 32) of word
+// j / 32 of node v's row is set when v is in sample j.  One block per chunk
+// of kBitChunk nodes: each thread loads the genes of its samples that lie in
+// the chunk (their span is known from the start positions, so the loads are
+// issued together), sets their bits in an LDS tile of the chunk's rows, and
+// the tile is written out.
+__global__ __launch_bounds__(256) void k_batch_bits(const int32_t *__restrict__ genes, int32_t k, int32_t B,
+                                                    const int32_t *__restrict__ pos, int32_t nchunks, int32_t n,
+                                                    uint32_t *__restrict__ rows)
+{
+    extern __shared__ uint32_t tile[];  // [kBitChunk][B / 32]
+    const int32_t Wb = B / 32;
+    const int32_t c = blockIdx.x;
+    const int32_t v0 = c * kBitChunk;
+    for (int32_t t = threadIdx.x; t < kBitChunk * Wb; t += blockDim.x) tile[t] = 0u;
+    __syncthreads();
+    for (int32_t j = threadIdx.x; j < B; j += blockDim.x) {
+        const int32_t p0 = pos[(int64_t)j * (nchunks + 1) + c], p1 = pos[(int64_t)j * (nchunks + 1) + c + 1];
+        const uint32_t bit = 1u << (j & 31);
+        const int32_t *row = genes + (int64_t)j * k;
+#pragma unroll 4
+        for (int32_t p = p0; p < p1; ++p) atomicOr(&tile[(row[p] - v0) * Wb + (j >> 5)], bit);
+    }
+    __syncthreads();
+    const int32_t words = min(kBitChunk, n - v0) * Wb;
     for (int32_t t = threadIdx.x; t < words; t += blockDim.x) rows[(int64_t)v0 * Wb + t] = tile[t];
 }
 
@@ -1027,13 +1046,19 @@ struct SurrogateState {
     uint64_t seed = 0;
     int64_t steps = 0;        // Adam steps taken
     int64_t appended = 0;     // pairs appended to the ring buffer
-    int32_t low_run = 0;      // consecutive screened generations below min_rho
+    int32_t low_run = 0;      // consecutive judged screened generations below min_rho
     int32_t fallbacks = 0;
-    bool force_full = false;
-    bool stats_pending = false;
+    int64_t skip_before = 0;  // judged generations launched before the last forced full one do not count
     int64_t last_gen = 0;
-    int32_t last_evaluated = 0, last_pooled = 0;
-    bool last_screened = false, last_predicted = false;
+    // Figures of generation g live in slot g & 1 (host metadata, the mapped
+    // statistics and the event that marks them final): the host decides the
+    // fallback for generation g from the judge of generation g - 2, so it
+    // never waits for the generation just launched.
+    struct Slot {
+        int64_t gen = -1;
+        int32_t evaluated = 0, pooled = 0;
+        bool screened = false, predicted = false, judged = true;
+    } slot[2];
     DevBuf theta, m, v, keep_mlp, keep_E;               // float
     DevBuf Eb, W1b, W2b, w3b, W1bT, W2bT;               // bf16
     DevBuf xb, yhat;                                    // predictions: x(S) and yhat of the generation
@@ -1041,6 +1066,7 @@ struct SurrogateState {
     DevBuf xtrain, ytrain, target, lossv, dy;           // training batch, per sample
     DevBuf xT, h1T, h2T, dz1T, dz2T, dxT;               // feature-major training activations, bf16
     DevBuf bgenes, bmasks, balive, bflag, tflag, brows; // training batch
+    DevBuf bpos;                                        // int32 [steps][B][chunks + 1]: chunk starts in the batch rows
     DevBuf buf_genes, buf_y;                            // ring buffer
     DevBuf pool, crows, cmasks, calive;                 // screened children
     DevBuf dstats;                                      // double [2]: label mean and spread of the predictions
@@ -1048,14 +1074,22 @@ struct SurrogateState {
                                                         // batch; [1 + (g & 3)] the loss of the last step of
                                                         // generation g's training
     DevBuf tstats;                                      // double [2]: label mean and spread the training uses
-    double *hstats = nullptr;                           // pinned, mapped: [2] rho, [3] rel_err, [4] loss,
+    double *hstats = nullptr;                           // pinned, mapped, per slot (8 doubles): [2] rho,
+                                                        // [3] rel_err, [4] loss,
                                                         // [5, 6] the predictions' label mean and spread
     double *hstats_dev = nullptr;                       // its device address (the judge and k_append write it)
-    hipEvent_t ready = nullptr;
+    hipEvent_t ready[2] = {nullptr, nullptr};
     // Generation g's training runs on its own stream beside generation g + 1;
     // the predictions of generation g read a snapshot of the weights trained
     // through generation g - 2.
     hipStream_t ts = nullptr;
+    // The judge runs on a stream of its own beside the end of its generation
+    // and the start of the next, which waits for it before overwriting the
+    // predictions, pool and fitness it reads.
+    hipStream_t js = nullptr;
+    hipEvent_t ev_evald = nullptr;  // main stream: the generation's children are evaluated
+    hipEvent_t ev_judged = nullptr; // judge stream: the judge has read them
+    hipEvent_t ev_end = nullptr;    // main stream: the generation is complete
     hipEvent_t ev_pred = nullptr;   // main stream: the generation's predictions are made
     hipEvent_t ev_snap = nullptr;   // training stream: training done and snapshot taken
     hipEvent_t ev_data = nullptr;   // main stream: the generation's labels are in the buffer
@@ -1193,7 +1227,7 @@ AdamArgs adam_args(SurrogateState &st)
 // One Adam step on B rows of genes (device, [B][k]) with standardised
 // targets (device): embeddings, MLP forward and backward, gradients, Adam.
 int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B, bool keep, double *loss_out,
-               bool sorted_rows, hipStream_t s)
+               const int32_t *pos, hipStream_t s)
 {
     SurrogateState &st = *ga->surr;
     gapa_graph *g = ga->graph;
@@ -1231,15 +1265,15 @@ int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B
     w.o = o;
     w.loss_out = loss_out;
     hipLaunchKernelGGL(k_mlp_wgrad, dim3(kWgradTasks), dim3(64), 0, s, w);
-    // membership bits of the batch, node-major: straight from the rows when
-    // they are ascending (batches sampled from the buffer), or else the
-    // removed-node bit sets of the rows, transposed
+    // membership bits of the batch, node-major: straight from the rows and
+    // their chunk start positions (batches sampled from the buffer), or else
+    // the removed-node bit sets of the rows, transposed
     const int32_t Wb = B / 32;
     int rc = GAPA_OK;
-    if (sorted_rows) {
-        const int32_t nranges = (st.n + kBitRange - 1) / kBitRange;
-        hipLaunchKernelGGL(k_batch_bits, dim3(nranges), dim3(256), (size_t)kBitRange * Wb * 4, s, genes, st.k, B,
-                           st.n, st.brows.as<uint32_t>());
+    if (pos) {
+        const int32_t nchunks = (st.n + kBitChunk - 1) / kBitChunk;
+        hipLaunchKernelGGL(k_batch_bits, dim3(nchunks), dim3(256), (size_t)kBitChunk * Wb * 4, s, genes, st.k, B, pos,
+                           nchunks, st.n, st.brows.as<uint32_t>());
     } else {
         rc = launch_mask_build(genes, B, st.k, g->n, g->words, g->d_noniso, g->n_noniso, st.bmasks.as<uint32_t>(),
                                st.balive.as<int32_t>(), st.tflag.as<int32_t>(), s);
@@ -1259,19 +1293,27 @@ int train_step(gapa_ga *ga, const int32_t *genes, const float *target, int32_t B
     return GAPA_OK;
 }
 
-int read_stats(gapa_ga *ga)
+// The fallback decision for generation gen, from the judge of generation
+// gen - 2 (final by now in all but the first generations, as gen - 1 is
+// queued behind it): after fallback_gens consecutive judged screened
+// generations with a correlation below min_rho, generation gen evaluates
+// every child.  Generation gen - 1 was launched before that decision and is
+// not counted when its figures arrive.
+int decide_fallback(gapa_ga *ga, int64_t gen, bool *force)
 {
     SurrogateState &st = *ga->surr;
-    if (!st.stats_pending) return GAPA_OK;
-    GAPA_HIP(hipEventSynchronize(st.ready));
-    st.stats_pending = false;
-    if (st.last_predicted && st.last_screened) {  // full generations do not count
-        const double rho = st.hstats[2];
-        st.low_run = rho < st.sp.min_rho ? st.low_run + 1 : 0;
-        if (st.sp.fallback_gens > 0 && st.low_run >= st.sp.fallback_gens) {
-            st.force_full = true;
-            st.low_run = 0;
-        }
+    *force = false;
+    SurrogateState::Slot &sl = st.slot[gen & 1];
+    if (sl.gen != gen - 2 || sl.judged) return GAPA_OK;
+    GAPA_HIP(hipEventSynchronize(st.ready[gen & 1]));
+    sl.judged = true;
+    if (!sl.predicted || !sl.screened || sl.gen < st.skip_before) return GAPA_OK;  // full generations do not count
+    const double rho = st.hstats[8 * (gen & 1) + 2];
+    st.low_run = rho < st.sp.min_rho ? st.low_run + 1 : 0;
+    if (st.sp.fallback_gens > 0 && st.low_run >= st.sp.fallback_gens) {
+        *force = true;
+        st.low_run = 0;
+        st.skip_before = gen;
     }
     return GAPA_OK;
 }
@@ -1346,6 +1388,7 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->target, nbatch * B * 4);
     res(st->lossv, (size_t)B * 4);
     res(st->bgenes, nbatch * B * st->k * 4);
+    res(st->bpos, nbatch * B * ((size_t)(st->n + kBitChunk - 1) / kBitChunk + 1) * 4);
 
     res(st->bmasks, (size_t)B * st->W * 4);
     res(st->balive, (size_t)B * 4);
@@ -1362,17 +1405,24 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->dloss, 5 * 8);
     res(st->tstats, 16);
     if (rc != GAPA_OK) return rc;
-    GAPA_HIP(hipHostMalloc(reinterpret_cast<void **>(&st->hstats), 64, hipHostMallocMapped | hipHostMallocCoherent));
-    std::memset(st->hstats, 0, 64);
+    GAPA_HIP(hipHostMalloc(reinterpret_cast<void **>(&st->hstats), 128, hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(st->hstats, 0, 128);
     GAPA_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&st->hstats_dev), st->hstats, 0));
-    GAPA_HIP(hipEventCreateWithFlags(&st->ready, hipEventDisableTiming));
+    GAPA_HIP(hipEventCreateWithFlags(&st->ready[0], hipEventDisableTiming));
+    GAPA_HIP(hipEventCreateWithFlags(&st->ready[1], hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_pred, hipEventDisableTiming));
+    GAPA_HIP(hipEventCreateWithFlags(&st->ev_evald, hipEventDisableTiming));
+    GAPA_HIP(hipEventCreateWithFlags(&st->ev_judged, hipEventDisableTiming));
+    GAPA_HIP(hipEventCreateWithFlags(&st->ev_end, hipEventDisableTiming));
+    GAPA_HIP(hipStreamCreateWithFlags(&st->js, hipStreamNonBlocking));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_snap, hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_data, hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_sampled, hipEventDisableTiming));
     GAPA_HIP(hipStreamCreateWithFlags(&st->ts, hipStreamNonBlocking));
     GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_grad_adam_E), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)grad_E_lds(1024)));
+    GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch_bits), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kBitChunk * 32 * 4));
     const unsigned blocks = (unsigned)((P + 255) / 256);
     hipLaunchKernelGGL(k_surr_init, dim3(blocks), dim3(256), 0, s, st->theta.as<float>(), (int64_t)st->n, st->seed,
                        0.05, std::sqrt(6.0 / kD), std::sqrt(6.0 / kH), std::sqrt(3.0 / kH));
@@ -1407,11 +1457,14 @@ void surrogate_release(SurrogateState *st)
                       &st->target, &st->lossv, &st->dy, &st->tflag, &st->dloss, &st->tstats,
                       &st->xT, &st->h1T, &st->h2T, &st->dz1T, &st->dz2T, &st->dxT, &st->bgenes, &st->bmasks,
                       &st->balive, &st->bflag, &st->brows, &st->buf_genes, &st->buf_y, &st->pool, &st->crows,
-                      &st->cmasks, &st->calive, &st->dstats})
+                      &st->cmasks, &st->calive, &st->dstats, &st->bpos})
         b->release();
     if (st->hstats) (void)hipHostFree(st->hstats);
-    for (hipEvent_t e : {st->ready, st->ev_pred, st->ev_snap, st->ev_data, st->ev_sampled})
+    if (st->js) (void)hipStreamSynchronize(st->js);
+    for (hipEvent_t e : {st->ready[0], st->ready[1], st->ev_pred, st->ev_snap, st->ev_data, st->ev_sampled,
+                         st->ev_evald, st->ev_judged, st->ev_end})
         if (e) (void)hipEventDestroy(e);
+    if (st->js) (void)hipStreamDestroy(st->js);
     if (st->ts) (void)hipStreamDestroy(st->ts);
     delete st;
 }
@@ -1419,21 +1472,23 @@ void surrogate_release(SurrogateState *st)
 int surrogate_generation(gapa_ga *ga, hipStream_t s)
 {
     SurrogateState &st = *ga->surr;
-    int rc = read_stats(ga);
-    if (rc != GAPA_OK) return rc;
     st.explicit_loss = false;
     const uint32_t gen = (uint32_t)(ga->generation + 1);
+    bool force = false;
+    int rc = decide_fallback(ga, gen, &force);
+    if (rc != GAPA_OK) return rc;
     const bool random = st.sp.flags & GAPA_SCREEN_RANDOM;
-    bool full = (int64_t)gen <= st.sp.warmup_gens || st.force_full;
-    if (st.force_full) {
-        st.fallbacks += 1;
-        st.force_full = false;
-    }
+    const bool full = (int64_t)gen <= st.sp.warmup_gens || force;
+    if (force && (int64_t)gen > st.sp.warmup_gens) st.fallbacks += 1;
+    const int32_t si = (int32_t)(gen & 1u);
+    double *hs = st.hstats_dev + 8 * si;
     const int32_t L = st.lambda;
     // a screened generation builds bit sets only for the children it evaluates
     if ((rc = ga_launch_offspring(ga, s, !full)) != GAPA_OK) return rc;
     const bool predict = !random && (int64_t)gen > st.sp.warmup_gens;
     float *yhat = st.yhat.as<float>();
+    // the previous generation's judge has read its predictions, pool and fitness
+    GAPA_HIP(hipStreamWaitEvent(s, st.ev_judged, 0));
     if (!random) {
         // the snapshot holds the weights trained through generation gen - 2
         GAPA_HIP(hipStreamWaitEvent(s, st.ev_snap, 0));
@@ -1477,9 +1532,12 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         if ((rc = ga_rank_and_gather(ga, false, F, pool, npool, s)) != GAPA_OK) return rc;
     }
     double *ds = st.dstats.as<double>();
-    if (predict)
-        hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, neval, ds, st.hstats_dev + 2,
-                           st.hstats_dev + 5);
+    if (predict) {
+        GAPA_HIP(hipEventRecord(st.ev_evald, s));
+        GAPA_HIP(hipStreamWaitEvent(st.js, st.ev_evald, 0));
+        hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, st.js, yhat, pool, F, neval, ds, hs + 2, hs + 5);
+        GAPA_HIP(hipEventRecord(st.ev_judged, st.js));
+    }
     if (!random) {
         // generation gen - 1's training has copied its batches out of the
         // buffer (it goes on beside this generation); the loss reported is
@@ -1489,7 +1547,7 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         double *dloss = st.dloss.as<double>();
         hipLaunchKernelGGL(k_append, dim3(neval), dim3(256), 0, s, ga->children.as<int32_t>(), st.k, pool, F,
                            st.appended, st.sp.buffer, st.buf_genes.as<int32_t>(), st.buf_y.as<double>(),
-                           dloss + 1 + ((gen + 2u) & 3u), st.hstats_dev + 4);
+                           dloss + 1 + ((gen + 2u) & 3u), hs + 4);
         st.appended += neval;
         const int32_t count = (int32_t)std::min<int64_t>(st.appended, st.sp.buffer);
         GAPA_HIP(hipGetLastError());
@@ -1500,30 +1558,37 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         hipLaunchKernelGGL(k_label_stats, dim3(1), dim3(1024), 0, st.ts, st.buf_y.as<double>(), count,
                            st.tstats.as<double>());
         const int32_t B = st.sp.batch;
+        const int32_t nchunks = (st.n + kBitChunk - 1) / kBitChunk;
+        const int64_t pstride = (int64_t)B * (nchunks + 1);
         for (int32_t t = 0; t < st.sp.train_steps; ++t)
             hipLaunchKernelGGL(k_sample, dim3(B), dim3(256), 0, st.ts, st.seed, gen, (uint32_t)t, count,
                                st.buf_genes.as<int32_t>(), st.buf_y.as<double>(), st.tstats.as<double>(), st.k,
-                               st.bgenes.as<int32_t>() + (int64_t)t * B * st.k, st.target.as<float>() + (int64_t)t * B);
+                               st.bgenes.as<int32_t>() + (int64_t)t * B * st.k, st.target.as<float>() + (int64_t)t * B,
+                               nchunks, st.bpos.as<int32_t>() + t * pstride);
         GAPA_HIP(hipEventRecord(st.ev_sampled, st.ts));
         for (int32_t t = 0; t < st.sp.train_steps; ++t)
             if ((rc = train_step(ga, st.bgenes.as<int32_t>() + (int64_t)t * B * st.k,
-                                 st.target.as<float>() + (int64_t)t * B, B, false, dloss + 1 + (gen & 3u), true,
-                                 st.ts)) != GAPA_OK)
+                                 st.target.as<float>() + (int64_t)t * B, B, false, dloss + 1 + (gen & 3u),
+                                 st.bpos.as<int32_t>() + t * pstride, st.ts)) != GAPA_OK)
                 return rc;
     }
-    GAPA_HIP(hipGetLastError());
-    GAPA_HIP(hipEventRecord(st.ready, s));
-    st.stats_pending = true;
-    st.last_gen = gen;
-    st.last_evaluated = neval;
-    st.last_pooled = npool;
-    st.last_screened = !full;
-    st.last_predicted = predict;
     if (full) {
         // the pool of a full generation is every child
         hipLaunchKernelGGL(k_iota, dim3((L + 255) / 256), dim3(256), 0, s, st.pool.as<int32_t>(), L);
-        GAPA_HIP(hipGetLastError());
     }
+    GAPA_HIP(hipGetLastError());
+    // the generation's figures are final once both its main-stream work and its judge are done
+    GAPA_HIP(hipEventRecord(st.ev_end, s));
+    GAPA_HIP(hipStreamWaitEvent(st.js, st.ev_end, 0));
+    GAPA_HIP(hipEventRecord(st.ready[si], st.js));
+    st.last_gen = gen;
+    SurrogateState::Slot &sl = st.slot[si];
+    sl.gen = gen;
+    sl.evaluated = neval;
+    sl.pooled = npool;
+    sl.screened = !full;
+    sl.predicted = predict;
+    sl.judged = false;
     ga->generation += 1;
     return GAPA_OK;
 }
@@ -1550,7 +1615,7 @@ int surrogate_train_batch(gapa_ga *ga, const int32_t *genes, const float *target
         return GAPA_E_INVALID_ARG;
     }
     GAPA_HIP(hipStreamSynchronize(st.ts));
-    const int rc = train_step(ga, genes, target, B, keep_grads, st.dloss.as<double>(), false, s);
+    const int rc = train_step(ga, genes, target, B, keep_grads, st.dloss.as<double>(), nullptr, s);
     if (rc == GAPA_OK) st.explicit_loss = true;
     return rc;
 }
@@ -1588,22 +1653,26 @@ int surrogate_tensor(gapa_ga *ga, int32_t which, int32_t kind, float *host, int6
 int surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out)
 {
     SurrogateState &st = *ga->surr;
-    if (st.stats_pending) GAPA_HIP(hipEventSynchronize(st.ready));
+    const int32_t si = (int32_t)(st.last_gen & 1);
+    const SurrogateState::Slot &sl = st.slot[si];
+    const double *hs = st.hstats + 8 * si;
+    if (st.last_gen > 0) GAPA_HIP(hipEventSynchronize(st.ready[si]));
+    const bool predicted = st.last_gen > 0 && sl.predicted;
     out->generation = st.last_gen;
-    out->evaluated = st.last_evaluated;
-    out->pooled = st.last_pooled;
-    out->screened = st.last_screened ? 1 : 0;
-    out->spearman = st.last_predicted ? st.hstats[2] : 0.0;
-    out->rel_err = st.last_predicted ? st.hstats[3] : 0.0;
-    out->loss = st.hstats[4];
+    out->evaluated = st.last_gen > 0 ? sl.evaluated : 0;
+    out->pooled = st.last_gen > 0 ? sl.pooled : 0;
+    out->screened = st.last_gen > 0 && sl.screened ? 1 : 0;
+    out->spearman = predicted ? hs[2] : 0.0;
+    out->rel_err = predicted ? hs[3] : 0.0;
+    out->loss = hs[4];
     if (st.explicit_loss) {
         GAPA_HIP(hipDeviceSynchronize());
         GAPA_HIP(hipMemcpy(&out->loss, st.dloss.ptr, 8, hipMemcpyDeviceToHost));
     }
     out->fallbacks = st.fallbacks;
     out->train_steps = (int32_t)st.steps;
-    out->label_mean = st.last_predicted ? st.hstats[5] : 0.0;
-    out->label_spread = st.last_predicted ? st.hstats[6] : 0.0;
+    out->label_mean = predicted ? hs[5] : 0.0;
+    out->label_spread = predicted ? hs[6] : 0.0;
     return GAPA_OK;
 }
 
@@ -1633,7 +1702,7 @@ int surrogate_judge(const float *yhat, const int32_t *pool, const int64_t *F, in
 int surrogate_last_predictions(gapa_ga *ga, float *yhat, int32_t cap, int32_t *count)
 {
     SurrogateState &st = *ga->surr;
-    const int32_t c = st.last_gen > 0 && st.last_predicted ? st.lambda : 0;
+    const int32_t c = st.last_gen > 0 && st.slot[st.last_gen & 1].predicted ? st.lambda : 0;
     if (count) *count = c;
     if (yhat && c > 0) {
         GAPA_HIP(hipStreamSynchronize(ga->last_stream));
@@ -1645,7 +1714,7 @@ int surrogate_last_predictions(gapa_ga *ga, float *yhat, int32_t cap, int32_t *c
 int surrogate_last_pool(gapa_ga *ga, int32_t *pool, int32_t cap, int32_t *count)
 {
     SurrogateState &st = *ga->surr;
-    const int32_t c = st.last_gen > 0 ? st.last_evaluated : 0;
+    const int32_t c = st.last_gen > 0 ? st.slot[st.last_gen & 1].evaluated : 0;
     if (count) *count = c;
     if (pool && c > 0) {
         GAPA_HIP(hipStreamSynchronize(ga->last_stream));
