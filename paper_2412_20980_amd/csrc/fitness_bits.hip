@@ -1046,10 +1046,10 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
     const bool multi = it && it->count > 1;
     if (!multi && P <= 0) return GAPA_OK;
     // Chunks of 32 * Wd individuals, Wd a power of two <= 32: full chunks of
-    // 1024, then the rest in the narrowest chunk that holds it, or, when the
-    // rest is just above 512, as 512 and a chunk of at most 256 side by side
-    // (a pass's cost grows with its width: 512 + 32 individuals on two
-    // lanes take less time than one pass 1024 wide).
+    // 1024, then the rest in the narrowest chunk that holds it.  (A pass's
+    // cost is mostly per node, whatever its width: splitting a rest of 544 as
+    // 512 + 32 on two lanes cut its latency but nearly doubled its work, which
+    // a busy GPU pays.)
     std::vector<std::pair<int32_t, int32_t>> plan;  // (first individual, Wd)
     if (multi) {
         plan.emplace_back(0, it->bseg / 32);
@@ -1060,14 +1060,7 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         if (r > 0) {
             int32_t wd = 1;
             while (wd * 32 < r) wd <<= 1;
-            int32_t lo = 1;
-            while (r > 512 && lo * 32 < r - 512) lo <<= 1;
-            if (wd == 32 && r > 512 && lo <= 8) {
-                plan.emplace_back(c0, 16);
-                plan.emplace_back(c0 + 512, lo);
-            } else {
-                plan.emplace_back(c0, wd);
-            }
+            plan.emplace_back(c0, wd);
         }
     }
     const int32_t chunks = (int32_t)plan.size();

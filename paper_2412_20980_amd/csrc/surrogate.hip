@@ -292,6 +292,18 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpArgs a)
     const int lr = lane & 15, lg = lane >> 4;
     const int32_t row0 = blockIdx.x * kMlpRows;
     const int c0 = wv * 32;
+    // The wave's weight operands of both forward layers are loaded first:
+    // they do not depend on the block's data, and loads after a barrier
+    // could not be moved above it.
+    bf16x8 w1o[kD / 32][2], w2o[kH / 32][2];
+#pragma unroll
+    for (int ks = 0; ks < kD / 32; ++ks)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) w1o[ks][t] = ld8(a.W1b + (c0 + t * 16 + lr) * kD + ks * 32 + lg * 8);
+#pragma unroll
+    for (int ks = 0; ks < kH / 32; ++ks)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) w2o[ks][t] = ld8(a.W2b + (c0 + t * 16 + lr) * kH + ks * 32 + lg * 8);
 
     if (!kTrain && a.musd_dst && blockIdx.x == 0 && threadIdx.x < 2) a.musd_dst[threadIdx.x] = a.musd_src[threadIdx.x];
     if (threadIdx.x < kMlpRows * 8) {
@@ -317,7 +329,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpArgs a)
     for (int ks = 0; ks < kD / 32; ++ks) {
         const bf16x8 A = ld8(sX + lr * kSX + ks * 32 + lg * 8);
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[t] = mfma(A, ld8(a.W1b + (c0 + t * 16 + lr) * kD + ks * 32 + lg * 8), acc[t]);
+        for (int t = 0; t < 2; ++t) acc[t] = mfma(A, w1o[ks][t], acc[t]);
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -341,7 +353,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpArgs a)
     for (int ks = 0; ks < kH / 32; ++ks) {
         const bf16x8 A = ld8(sH1 + lr * kSH + ks * 32 + lg * 8);
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[t] = mfma(A, ld8(a.W2b + (c0 + t * 16 + lr) * kH + ks * 32 + lg * 8), acc[t]);
+        for (int t = 0; t < 2; ++t) acc[t] = mfma(A, w2o[ks][t], acc[t]);
     }
     float p[4] = {0.f, 0.f, 0.f, 0.f};
     float w3v[2];
@@ -387,6 +399,11 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpArgs a)
         sDy[r] = d;
     }
     if (!kTrain) return;
+    // the backward pass's W2^T operands (the forward ones are no longer needed)
+#pragma unroll
+    for (int ks = 0; ks < kH / 32; ++ks)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) w2o[ks][t] = ld8(a.W2bT + (c0 + t * 16 + lr) * kH + ks * 32 + lg * 8);
     __syncthreads();
 
     // dz2 = dyhat w3 [h2 > 0]
@@ -410,8 +427,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpArgs a)
     for (int ks = 0; ks < kH / 32; ++ks) {
         const bf16x8 A = ld8(sDZ2 + lr * kSH + ks * 32 + lg * 8);
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
-            acc[t] = mfma(A, ld8(a.W2bT + (c0 + t * 16 + lr) * kH + ks * 32 + lg * 8), acc[t]);
+        for (int t = 0; t < 2; ++t) acc[t] = mfma(A, w2o[ks][t], acc[t]);
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -591,18 +607,15 @@ __global__ __launch_bounds__(1024) void k_grad_adam_E(const uint32_t *__restrict
     for (int64_t tile = (int64_t)blockIdx.x * nw + wv; tile < tiles; tile += (int64_t)gridDim.x * nw) {
         const int64_t v0 = tile * 16;
         const int64_t row = v0 + lr;
-        // lane (lr, lg) holds words 8 lg .. 8 lg + 7 of node v0 + lr
-        uint32_t w8[8];
+        // every lane (lr, lg) holds all Wb <= 32 words of node v0 + lr's row
+        // (the four lanes of a node read the same 128 bytes), so a k-step
+        // needs no exchange between lanes
+        uint32_t w32[32];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int ks = 8 * lg + u;
-            w8[u] = (row < n && ks < Wb) ? bits[row * Wb + ks] : 0u;
-        }
+        for (int ks = 0; ks < 32; ++ks) w32[ks] = (row < n && ks < Wb) ? bits[row * Wb + ks] : 0u;
         uint32_t rowany = 0u;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) rowany |= w8[u];
-        rowany |= (uint32_t)__shfl_xor((int)rowany, 16, 64);
-        rowany |= (uint32_t)__shfl_xor((int)rowany, 32, 64);
+        for (int ks = 0; ks < 32; ++ks) rowany |= w32[ks];
         if (__ballot(rowany != 0u) == 0) {
             if (keep)
                 for (int q = lane; q < 16 * kD; q += 64)
@@ -614,8 +627,7 @@ __global__ __launch_bounds__(1024) void k_grad_adam_E(const uint32_t *__restrict
         for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < 32; ++ks) {
-            // word ks of this lane's row sits in lane lr + 16 (ks / 8), slot ks % 8
-            const uint32_t word = ks < Wb ? (uint32_t)__shfl((int)w8[ks & 7], lr + 16 * (ks >> 3), 64) : 0u;
+            const uint32_t word = w32[ks];
             if (__ballot(word != 0u) == 0) continue;
             const uint32_t byte = (word >> (8 * lg)) & 0xFFu;
             uint4 q;
@@ -907,7 +919,7 @@ __global__ __launch_bounds__(1024) void k_label_stats(const double *__restrict__
 // boundary c (node c kBitChunk, c = 0 .. nchunks), the position in the
 // sample's ascending gene row of the first gene at or above it:
 // pos[j][c] (binary searches over the row staged in LDS).
-constexpr int kBitChunk = 1024;
+constexpr int kBitChunk = 256;  // 32 KB of LDS per block at a batch of 1024: blocks of other kernels fit beside it
 constexpr int kSampleRowLds = 4096;      // longest row staged in LDS for the searches
 
 __global__ void k_sample(uint64_t seed, uint32_t gen, uint32_t step, int32_t count, const int32_t *__restrict__ buf_genes,
@@ -1083,13 +1095,6 @@ struct SurrogateState {
     // the predictions of generation g read a snapshot of the weights trained
     // through generation g - 2.
     hipStream_t ts = nullptr;
-    // The judge runs on a stream of its own beside the end of its generation
-    // and the start of the next, which waits for it before overwriting the
-    // predictions, pool and fitness it reads.
-    hipStream_t js = nullptr;
-    hipEvent_t ev_evald = nullptr;  // main stream: the generation's children are evaluated
-    hipEvent_t ev_judged = nullptr; // judge stream: the judge has read them
-    hipEvent_t ev_end = nullptr;    // main stream: the generation is complete
     hipEvent_t ev_pred = nullptr;   // main stream: the generation's predictions are made
     hipEvent_t ev_snap = nullptr;   // training stream: training done and snapshot taken
     hipEvent_t ev_data = nullptr;   // main stream: the generation's labels are in the buffer
@@ -1411,18 +1416,14 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     GAPA_HIP(hipEventCreateWithFlags(&st->ready[0], hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ready[1], hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_pred, hipEventDisableTiming));
-    GAPA_HIP(hipEventCreateWithFlags(&st->ev_evald, hipEventDisableTiming));
-    GAPA_HIP(hipEventCreateWithFlags(&st->ev_judged, hipEventDisableTiming));
-    GAPA_HIP(hipEventCreateWithFlags(&st->ev_end, hipEventDisableTiming));
-    GAPA_HIP(hipStreamCreateWithFlags(&st->js, hipStreamNonBlocking));
+
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_snap, hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_data, hipEventDisableTiming));
     GAPA_HIP(hipEventCreateWithFlags(&st->ev_sampled, hipEventDisableTiming));
     GAPA_HIP(hipStreamCreateWithFlags(&st->ts, hipStreamNonBlocking));
     GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_grad_adam_E), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)grad_E_lds(1024)));
-    GAPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch_bits), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 kBitChunk * 32 * 4));
+
     const unsigned blocks = (unsigned)((P + 255) / 256);
     hipLaunchKernelGGL(k_surr_init, dim3(blocks), dim3(256), 0, s, st->theta.as<float>(), (int64_t)st->n, st->seed,
                        0.05, std::sqrt(6.0 / kD), std::sqrt(6.0 / kH), std::sqrt(3.0 / kH));
@@ -1460,11 +1461,8 @@ void surrogate_release(SurrogateState *st)
                       &st->cmasks, &st->calive, &st->dstats, &st->bpos})
         b->release();
     if (st->hstats) (void)hipHostFree(st->hstats);
-    if (st->js) (void)hipStreamSynchronize(st->js);
-    for (hipEvent_t e : {st->ready[0], st->ready[1], st->ev_pred, st->ev_snap, st->ev_data, st->ev_sampled,
-                         st->ev_evald, st->ev_judged, st->ev_end})
+    for (hipEvent_t e : {st->ready[0], st->ready[1], st->ev_pred, st->ev_snap, st->ev_data, st->ev_sampled})
         if (e) (void)hipEventDestroy(e);
-    if (st->js) (void)hipStreamDestroy(st->js);
     if (st->ts) (void)hipStreamDestroy(st->ts);
     delete st;
 }
@@ -1487,8 +1485,6 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
     if ((rc = ga_launch_offspring(ga, s, !full)) != GAPA_OK) return rc;
     const bool predict = !random && (int64_t)gen > st.sp.warmup_gens;
     float *yhat = st.yhat.as<float>();
-    // the previous generation's judge has read its predictions, pool and fitness
-    GAPA_HIP(hipStreamWaitEvent(s, st.ev_judged, 0));
     if (!random) {
         // the snapshot holds the weights trained through generation gen - 2
         GAPA_HIP(hipStreamWaitEvent(s, st.ev_snap, 0));
@@ -1532,12 +1528,7 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         if ((rc = ga_rank_and_gather(ga, false, F, pool, npool, s)) != GAPA_OK) return rc;
     }
     double *ds = st.dstats.as<double>();
-    if (predict) {
-        GAPA_HIP(hipEventRecord(st.ev_evald, s));
-        GAPA_HIP(hipStreamWaitEvent(st.js, st.ev_evald, 0));
-        hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, st.js, yhat, pool, F, neval, ds, hs + 2, hs + 5);
-        GAPA_HIP(hipEventRecord(st.ev_judged, st.js));
-    }
+    if (predict) hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, neval, ds, hs + 2, hs + 5);
     if (!random) {
         // generation gen - 1's training has copied its batches out of the
         // buffer (it goes on beside this generation); the loss reported is
@@ -1577,10 +1568,7 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         hipLaunchKernelGGL(k_iota, dim3((L + 255) / 256), dim3(256), 0, s, st.pool.as<int32_t>(), L);
     }
     GAPA_HIP(hipGetLastError());
-    // the generation's figures are final once both its main-stream work and its judge are done
-    GAPA_HIP(hipEventRecord(st.ev_end, s));
-    GAPA_HIP(hipStreamWaitEvent(st.js, st.ev_end, 0));
-    GAPA_HIP(hipEventRecord(st.ready[si], st.js));
+    GAPA_HIP(hipEventRecord(st.ready[si], s));
     st.last_gen = gen;
     SurrogateState::Slot &sl = st.slot[si];
     sl.gen = gen;

@@ -65,8 +65,7 @@ def test_cl200k_full_population_hub_heavy(gp, cl200k):
 
 
 def test_many_chunks_and_padding(gp, ba10k):
-    # 544, 700 and 1568 leave a rest just above 512: it runs as 512 and a
-    # narrower chunk side by side
+    # rests of one to 1023 individuals after full chunks of 1024
     graph = gp.Graph.from_csr(ba10k)
     for P in (1, 31, 33, 544, 700, 1025, 1568, 2100):
         check(gp, ba10k, inputs.random_population(ba10k.n, 100, P, seed=P), graph=graph)
