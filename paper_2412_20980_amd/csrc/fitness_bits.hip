@@ -253,63 +253,50 @@ __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restr
 
 // A node's record for the sweeps: (node, first edge, end of its edges), by
 // position in the band order; the worklist holds the records of the nodes
-// still pending.  With the record in hand a node's first neighbour ids are
-// one load away.
+// still pending, so no sweep loads row pointers.
 //
 // Pull for one node by its lane group: OR the neighbours' reach rows (in
 // degree-descending order), four at a time, until every pending bit is
 // covered or max_scan neighbours have been read; the node keeps the bits of
 // individuals in which it survives.  Whatever stays pending is picked up by
 // a later sweep or, in the end, by the union-find pass, so the cap only
-// moves work.
+// moves work.  A node with nothing pending reads only its own two words.
 //
-// Reach rows are shared between the XCDs within one kernel: neighbours' rows
-// are read and a node's own row written with agent-scope atomics, which
-// bypass each XCD's own L2, so bits another XCD set earlier in the same sweep
-// are seen and spread at once (plain loads that hit a stale line in the local
-// L2 leave about 40 % more nodes pending at n = 200k and make the pass 20 %
-// slower).  A node's own row is written only by its own pull, once per sweep,
-// and its dead row not at all, so both are read with plain loads.
-//
-// A group walks its nodes one after another; the record and first four
-// neighbour ids of its next node are loaded while the current one pulls, so
-// each node costs two dependent round trips (its own rows, then its
-// neighbours' rows) instead of four.
+// Reach rows are shared between the XCDs within one kernel: they are read
+// and written with agent-scope atomics, which bypass each XCD's own L2, so
+// bits another XCD set earlier in the same sweep are seen and spread at once
+// (plain loads that hit a stale line in the local L2 leave about 40 % more
+// nodes pending at n = 200k and make the pass 20 % slower; plain loads for
+// the neighbours in earlier bands only, whose rows are final, were no
+// faster).  Loading the next node's record and first neighbour ids while
+// the current one pulls was tried too: 10 % slower, most of those loads
+// being wasted on nodes with nothing pending.
 struct PullOut {
     bool gained;   // the node gained bits
     bool pending;  // bits still pending after the pull
 };
 
-__device__ __forceinline__ void first_ids(const int4 r, int32_t max_scan, const int32_t *__restrict__ colD,
-                                          int32_t u[4])
-{
-    const int32_t e1 = r.z - r.y > max_scan ? r.y + max_scan : r.z;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) u[t] = r.x >= 0 && r.y + t < e1 ? colD[r.y + t] : -1;
-}
-
-__device__ __forceinline__ PullOut pull_node(const int4 r, const int32_t u[4], int Wd, int w, uint64_t gmask,
+__device__ __forceinline__ PullOut pull_node(const int4 r, int Wd, int w, uint64_t gmask,
                                              const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
                                              uint32_t *__restrict__ reach, int32_t max_scan)
 {
     const int64_t vo = (int64_t)r.x * Wd + w;
-    const uint32_t mine = reach[vo];
+    const uint32_t mine = ld_relaxed_u(reach + vo);
     const uint32_t pend = ~dead[vo] & ~mine;
     PullOut out{false, false};
     if ((__ballot(pend != 0) & gmask) == 0) return out;
     uint32_t acc = 0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-        if (u[t] >= 0) acc |= ld_relaxed_u(reach + (int64_t)u[t] * Wd + w);
-    const int32_t e1 = r.z - r.y > max_scan ? r.y + max_scan : r.z;
-    for (int32_t e = r.y + 4; e < e1 && (__ballot((acc & pend) != pend) & gmask) != 0; e += 4) {
-        int32_t x[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) x[t] = e + t < e1 ? colD[e + t] : -1;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            if (x[t] >= 0) acc |= ld_relaxed_u(reach + (int64_t)x[t] * Wd + w);
+    const int32_t e0 = r.y;
+    const int32_t e1 = r.z - e0 > max_scan ? e0 + max_scan : r.z;
+    int32_t e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        const int32_t u0 = colD[e], u1 = colD[e + 1], u2 = colD[e + 2], u3 = colD[e + 3];
+        acc |= ld_relaxed_u(reach + (int64_t)u0 * Wd + w) | ld_relaxed_u(reach + (int64_t)u1 * Wd + w) |
+               ld_relaxed_u(reach + (int64_t)u2 * Wd + w) | ld_relaxed_u(reach + (int64_t)u3 * Wd + w);
+        if ((__ballot((acc & pend) != pend) & gmask) == 0) break;
     }
+    if ((__ballot((acc & pend) != pend) & gmask) != 0)
+        for (; e < e1; ++e) acc |= ld_relaxed_u(reach + (int64_t)colD[e] * Wd + w);
     const uint32_t gain = acc & pend;
     if (gain) __hip_atomic_store(reach + vo, mine | gain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     out.pending = (__ballot((pend & ~gain) != 0) & gmask) != 0;
@@ -317,13 +304,13 @@ __device__ __forceinline__ PullOut pull_node(const int4 r, const int32_t u[4], i
     return out;
 }
 
-// A sweep over count records (recs[i], or recs[b0 + i]), a group of Wd lanes
-// per node.  Band sweep (pflag given): pflag[b0 + i] records whether node i
-// is still pending; a node's reach row is written only by its own pull, so
-// its pending bits are final once it has pulled (every non-isolated node has
-// one band position, so every flag the compaction reads is written here, and
-// consecutive groups write neighbouring bytes).  Returns whether any node
-// of the calling wave gained bits.
+// A sweep over count records (recs[b0 + i]), a group of Wd lanes per node.
+// Band sweep (pflag given): pflag[b0 + i] records whether node i is still
+// pending; a node's reach row is written only by its own pull, so its
+// pending bits are final once it has pulled (every non-isolated node has one
+// band position, so every flag the compaction reads is written here, and
+// consecutive groups write neighbouring bytes).  Returns whether any node of
+// the calling wave gained bits.
 __device__ __forceinline__ bool pull_sweep(const int4 *__restrict__ recs, int32_t b0, int32_t count, int32_t Wd,
                                            const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
                                            uint32_t *__restrict__ reach, int32_t max_scan, uint8_t *__restrict__ pflag)
@@ -333,25 +320,15 @@ __device__ __forceinline__ bool pull_sweep(const int4 *__restrict__ recs, int32_
     const uint64_t gmask = group_mask(Wd);
     const int64_t group = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / Wd;
     const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / Wd;
-    // every lane of a wave iterates the same number of times so that ballots
-    // see whole groups
     const int64_t iters = (count + ngroups - 1) / ngroups;
-    const int4 none = make_int4(-1, 0, 0, 0);
-    int4 r = group < count ? recs[b0 + group] : none;
-    int32_t u[4];
-    first_ids(r, max_scan, colD, u);
     bool any_gain = false;
     for (int64_t it = 0, idx = group; it < iters; ++it, idx += ngroups) {
-        // the next node's record, loaded before this node's rows
-        const int64_t nidx = idx + ngroups;
-        const int4 nr = nidx < count ? recs[b0 + nidx] : none;
-        if (r.x >= 0) {
-            const PullOut o = pull_node(r, u, Wd, w, gmask, colD, dead, reach, max_scan);
+        if (idx < count) {
+            const int4 r = recs[b0 + idx];
+            const PullOut o = pull_node(r, Wd, w, gmask, colD, dead, reach, max_scan);
             any_gain |= o.gained;
             if (pflag && w == 0) pflag[b0 + idx] = o.pending ? 1 : 0;
         }
-        r = nr;
-        first_ids(r, max_scan, colD, u);
     }
     return __ballot(any_gain) != 0;
 }
