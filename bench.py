@@ -56,7 +56,9 @@ def algorithmic_bytes_per_eval(n: int, nnz: int) -> int:
     return 4 * (n + 1) + 4 * nnz + 4 * math.ceil(n / 32) + 8 * n + 8
 
 
-FITNESS_SOURCES = ("fitness_bits.hip", "fitness.hip", "device_common.h")
+# the pass's kernels, and api.hip for the graph orderings (bands, neighbour
+# order) they run on
+FITNESS_SOURCES = ("fitness_bits.hip", "fitness.hip", "device_common.h", "api.hip")
 
 # Launch shapes of the fitness pass per workload (sweep_grid, band_scan,
 # sweeps, band_blocks): the autotuner's choice on each workload's warmed-up

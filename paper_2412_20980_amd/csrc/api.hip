@@ -235,7 +235,7 @@ int validate_graph(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci)
 //            level after their instance's last one.
 constexpr int kSources = 64;
 constexpr int kMaxBands = 24;
-constexpr int kMinBand = 4096;
+constexpr int kMinBand = 16384;  // at n = 200k the 8.9k nodes of BFS levels 3+ join level 2's band: 2 % faster
 
 void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, const std::vector<int32_t> &voff,
                      std::vector<int32_t> &order, std::vector<int32_t> &colD, std::vector<int32_t> &band_v,
