@@ -143,6 +143,29 @@ def test_judge_statistics_match_oracle(gp):
     assert e.value.code == gp.GAPA_E_INVALID_ARG
 
 
+def test_generation_training_moves_exactly_the_sampled_rows(gp):
+    """A generation's training builds its batches' membership bits straight
+    from the sampled rows (ascending): Adam is lazy on the embeddings, so the
+    rows it moves are exactly the nodes of the batches the oracle samples for
+    that generation, and every other row keeps its value bit for bit (also at
+    sizes that are not multiples of the kernels' 256-node ranges)."""
+    for n, k, batch in ((1500, 20, 64), (1031, 37, 32)):
+        g = inputs.barabasi_albert(n, 1, seed=n)
+        _, ga = make_ga(gp, g, k=k, batch=batch, buffer=1024)
+        before = ga.surrogate_tensor("E", n=g.n).copy()
+        ga.step(1)
+        after = ga.surrogate_tensor("E", n=g.n)
+        moved = np.any(after != before, axis=1)
+        sga = S.SurrogateGA(g, k, 32, 7, 128, batch=batch, steps=2, warmup=2, buffer=1024, bf16_ops=True)
+        sga.step()
+        count = min(sga.appended, sga.cap)
+        touched = np.zeros(g.n, bool)
+        for t in range(2):
+            touched[sga.buf_sets[S.sample_batch(7, 1, t, batch, count)].ravel()] = True
+        print(f"n={n}: {touched.sum()} rows touched, {moved.sum()} moved", flush=True)
+        assert np.array_equal(moved, touched)
+
+
 def test_adam_step_matches_formula(gp):
     import torch
     g = inputs.barabasi_albert(600, 3, seed=4)
