@@ -271,6 +271,11 @@ __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restr
 // faster).  Loading the next node's record and first neighbour ids while
 // the current one pulls was tried too: 10 % slower, most of those loads
 // being wasted on nodes with nothing pending.
+// Groups of at least kIdLanes lanes load a node's neighbour ids a chunk of Wd
+// at a time (one per lane) and read them back by shuffle; narrower groups
+// load them four at a time.
+constexpr int kIdLanes = 8;
+
 struct PullOut {
     bool gained;   // the node gained bits
     bool pending;  // bits still pending after the pull
@@ -288,15 +293,38 @@ __device__ __forceinline__ PullOut pull_node(const int4 r, int Wd, int w, uint64
     uint32_t acc = 0;
     const int32_t e0 = r.y;
     const int32_t e1 = r.z - e0 > max_scan ? e0 + max_scan : r.z;
-    int32_t e = e0;
-    for (; e + 4 <= e1; e += 4) {
-        const int32_t u0 = colD[e], u1 = colD[e + 1], u2 = colD[e + 2], u3 = colD[e + 3];
-        acc |= ld_relaxed_u(reach + (int64_t)u0 * Wd + w) | ld_relaxed_u(reach + (int64_t)u1 * Wd + w) |
-               ld_relaxed_u(reach + (int64_t)u2 * Wd + w) | ld_relaxed_u(reach + (int64_t)u3 * Wd + w);
-        if ((__ballot((acc & pend) != pend) & gmask) == 0) break;
+    if (Wd >= kIdLanes) {
+        // a chunk of Wd neighbour ids in one load, one id per lane, read back
+        // by shuffle within the group; four neighbours' bits at a time
+        const int gb = (threadIdx.x & 63) & ~(Wd - 1);
+        bool open = true;
+        for (int32_t c = e0; open && c < e1; c += Wd) {
+            const int32_t ids = c + w < e1 ? colD[c + w] : -1;
+            const int32_t m = e1 - c < Wd ? e1 - c : Wd;
+            for (int32_t t = 0; t < m; t += 4) {
+                const int32_t u0 = __shfl(ids, gb + t, 64), u1 = __shfl(ids, gb + t + 1, 64);
+                const int32_t u2 = __shfl(ids, gb + t + 2, 64), u3 = __shfl(ids, gb + t + 3, 64);
+                acc |= ld_relaxed_u(reach + (int64_t)u0 * Wd + w) |
+                       (u1 >= 0 ? ld_relaxed_u(reach + (int64_t)u1 * Wd + w) : 0u) |
+                       (u2 >= 0 ? ld_relaxed_u(reach + (int64_t)u2 * Wd + w) : 0u) |
+                       (u3 >= 0 ? ld_relaxed_u(reach + (int64_t)u3 * Wd + w) : 0u);
+                if ((__ballot((acc & pend) != pend) & gmask) == 0) {
+                    open = false;
+                    break;
+                }
+            }
+        }
+    } else {
+        int32_t e = e0;
+        for (; e + 4 <= e1; e += 4) {
+            const int32_t u0 = colD[e], u1 = colD[e + 1], u2 = colD[e + 2], u3 = colD[e + 3];
+            acc |= ld_relaxed_u(reach + (int64_t)u0 * Wd + w) | ld_relaxed_u(reach + (int64_t)u1 * Wd + w) |
+                   ld_relaxed_u(reach + (int64_t)u2 * Wd + w) | ld_relaxed_u(reach + (int64_t)u3 * Wd + w);
+            if ((__ballot((acc & pend) != pend) & gmask) == 0) break;
+        }
+        if ((__ballot((acc & pend) != pend) & gmask) != 0)
+            for (; e < e1; ++e) acc |= ld_relaxed_u(reach + (int64_t)colD[e] * Wd + w);
     }
-    if ((__ballot((acc & pend) != pend) & gmask) != 0)
-        for (; e < e1; ++e) acc |= ld_relaxed_u(reach + (int64_t)colD[e] * Wd + w);
     const uint32_t gain = acc & pend;
     if (gain) __hip_atomic_store(reach + vo, mine | gain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     out.pending = (__ballot((pend & ~gain) != 0) & gmask) != 0;
@@ -461,7 +489,29 @@ __device__ __forceinline__ void pending_split(const int4 r, int Wd, int w, uint6
     const int32_t e0 = valid ? r.y : 0, e1 = valid ? r.z : 0;
     const uint32_t pend = ~dv & ~rv;
     uint32_t nb = 0;
-    if ((__ballot(pend != 0) & gmask) != 0) {
+    const bool any = (__ballot(pend != 0) & gmask) != 0;
+    if (any && Wd >= kIdLanes) {
+        // ids a chunk of Wd at a time by lane, read back by shuffle;
+        // kSplitChunk neighbours' bits at a time
+        const int gb = (threadIdx.x & 63) & ~(Wd - 1);
+        bool open = true;
+        for (int32_t c = e0; open && c < e1; c += Wd) {
+            const int32_t ids = c + w < e1 ? colD[c + w] : -1;
+            const int32_t m = e1 - c < Wd ? e1 - c : Wd;
+            for (int32_t t = 0; t < m; t += kSplitChunk) {
+                int32_t u[kSplitChunk];
+#pragma unroll
+                for (int q = 0; q < kSplitChunk; ++q) u[q] = __shfl(ids, gb + t + q, 64);
+#pragma unroll
+                for (int q = 0; q < kSplitChunk; ++q)
+                    if (u[q] >= 0) nb |= ~dead[(int64_t)u[q] * Wd + w];
+                if ((__ballot((nb & pend) != pend) & gmask) == 0) {
+                    open = false;
+                    break;
+                }
+            }
+        }
+    } else if (any) {
         // kSplitChunk neighbours at a time (their ids, then their bits, each
         // set of loads in flight together); stopping once every pending bit
         // has a surviving neighbour (or at the end of the list) gives the same
