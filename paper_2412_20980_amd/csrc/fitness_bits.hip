@@ -271,9 +271,19 @@ __global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restr
 // faster).  Loading the next node's record and first neighbour ids while
 // the current one pulls was tried too: 10 % slower, most of those loads
 // being wasted on nodes with nothing pending.
-// Groups of at least kIdLanes lanes load a node's neighbour ids a chunk of Wd
-// at a time (one per lane) and read them back by shuffle; narrower groups
-// load them four at a time.
+//
+// In the band sweep the group's lanes load the neighbour ids, one id per
+// lane (a chunk of WD ids in one coalesced load; several chunks for groups
+// narrower than kPullIds lanes), and read them back by shuffle: one load
+// round trip per kPullIds or more neighbours instead of one per four.  The
+// band kernel is compiled for each group width.  Slower, on the same GPU:
+// the first chunk of ids loaded together with the node's own words, the
+// next record prefetched, eight neighbours' bits at a time.
+constexpr int kPullIds = 8;
+
+// Groups of at least kIdLanes lanes in the worklist sweep and the pending
+// split also load a chunk of Wd ids at a time (one per lane) and read them
+// back by shuffle; narrower groups load them four at a time.
 constexpr int kIdLanes = 8;
 
 struct PullOut {
@@ -281,9 +291,107 @@ struct PullOut {
     bool pending;  // bits still pending after the pull
 };
 
-__device__ __forceinline__ PullOut pull_node(const int4 r, int Wd, int w, uint64_t gmask,
-                                             const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
-                                             uint32_t *__restrict__ reach, int32_t max_scan)
+template <int WD>
+__device__ __forceinline__ PullOut pull_node(const int4 r, int w, uint64_t gmask, const int32_t *__restrict__ colD,
+                                             const uint32_t *__restrict__ dead, uint32_t *__restrict__ reach,
+                                             int32_t max_scan)
+{
+    constexpr int K = WD >= kPullIds ? 1 : kPullIds / WD;  // id loads per lane per round trip
+    constexpr int CH = WD * K;
+    const int64_t vo = (int64_t)r.x * WD + w;
+    const uint32_t mine = ld_relaxed_u(reach + vo);
+    const uint32_t pend = ~dead[vo] & ~mine;
+    PullOut out{false, false};
+    if ((__ballot(pend != 0) & gmask) == 0) return out;
+    uint32_t acc = 0;
+    const int32_t e0 = r.y;
+    const int32_t e1 = r.z - e0 > max_scan ? e0 + max_scan : r.z;
+    const int gb = (threadIdx.x & 63) & ~(WD - 1);
+    bool open = true;
+    for (int32_t c = e0; open && c < e1; c += CH) {
+        // ids c + q WD + w of chunk q in lane w: one coalesced load per chunk
+        int32_t ids[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) ids[q] = c + q * WD + w < e1 ? colD[c + q * WD + w] : -1;
+        // four neighbours' bits at a time, read back by shuffle in the group
+        if constexpr (K == 1) {
+            const int32_t m = e1 - c < WD ? e1 - c : WD;
+#pragma unroll 1
+            for (int32_t t = 0; t < m; t += 4) {
+                const int32_t u0 = __shfl(ids[0], gb + t, 64), u1 = __shfl(ids[0], gb + t + 1, 64);
+                const int32_t u2 = __shfl(ids[0], gb + t + 2, 64), u3 = __shfl(ids[0], gb + t + 3, 64);
+                acc |= ld_relaxed_u(reach + (int64_t)u0 * WD + w) |
+                       (u1 >= 0 ? ld_relaxed_u(reach + (int64_t)u1 * WD + w) : 0u) |
+                       (u2 >= 0 ? ld_relaxed_u(reach + (int64_t)u2 * WD + w) : 0u) |
+                       (u3 >= 0 ? ld_relaxed_u(reach + (int64_t)u3 * WD + w) : 0u);
+                if ((__ballot((acc & pend) != pend) & gmask) == 0) {
+                    open = false;
+                    break;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < CH; t += 4) {
+                if (!open || c + t >= e1) break;
+                int32_t u[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    u[j] = WD == 1 ? ids[t + j] : __shfl(ids[(t + j) / WD], gb + (t + j) % WD, 64);
+                uint32_t x = ld_relaxed_u(reach + (int64_t)u[0] * WD + w);
+#pragma unroll
+                for (int j = 1; j < 4; ++j) x |= u[j] >= 0 ? ld_relaxed_u(reach + (int64_t)u[j] * WD + w) : 0u;
+                acc |= x;
+                if ((__ballot((acc & pend) != pend) & gmask) == 0) open = false;
+            }
+        }
+    }
+    const uint32_t gain = acc & pend;
+    if (gain) __hip_atomic_store(reach + vo, mine | gain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    out.pending = (__ballot((pend & ~gain) != 0) & gmask) != 0;
+    out.gained = (__ballot(gain != 0) & gmask) != 0;
+    return out;
+}
+
+// A sweep over count records (recs[b0 + i]), a group of WD lanes per node.
+// Band sweep (pflag given): pflag[b0 + i] records whether node i is still
+// pending; a node's reach row is written only by its own pull, so its
+// pending bits are final once it has pulled (every non-isolated node has one
+// band position, so every flag the compaction reads is written here, and
+// consecutive groups write neighbouring bytes).  Returns whether any node of
+// the calling wave gained bits.
+template <int WD>
+__device__ __forceinline__ bool pull_sweep(const int4 *__restrict__ recs, int32_t b0, int32_t count,
+                                           const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
+                                           uint32_t *__restrict__ reach, int32_t max_scan, uint8_t *__restrict__ pflag)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = lane & (WD - 1);
+    const uint64_t gmask = group_mask(WD);
+    const int64_t group = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WD;
+    const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / WD;
+    const int64_t iters = (count + ngroups - 1) / ngroups;
+    bool any_gain = false;
+    for (int64_t it = 0, idx = group; it < iters; ++it, idx += ngroups) {
+        if (idx < count) {
+            const int4 r = recs[b0 + idx];
+            const PullOut o = pull_node<WD>(r, w, gmask, colD, dead, reach, max_scan);
+            any_gain |= o.gained;
+            if (pflag && w == 0) pflag[b0 + idx] = o.pending ? 1 : 0;
+        }
+    }
+    return __ballot(any_gain) != 0;
+}
+
+// The pull of the worklist sweeps, with the group width a run-time value.
+// Compiled per width like the band pull (ids in chunks of kPullIds or more
+// for every width), the worklist kernel measured slower on hub-heavy
+// populations at n = 200k: 63 against 31 us per pass at P = 64, 48 against
+// 38 us at P = 1024; equal on the benchmark's own population.  Its long scans
+// of hub neighbour lists are where the two differ; no cause was found in
+// the generated code.
+__device__ __forceinline__ PullOut pull_node_rt(const int4 r, int Wd, int w, uint64_t gmask,
+                                                const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
+                                                uint32_t *__restrict__ reach, int32_t max_scan)
 {
     const int64_t vo = (int64_t)r.x * Wd + w;
     const uint32_t mine = ld_relaxed_u(reach + vo);
@@ -332,16 +440,10 @@ __device__ __forceinline__ PullOut pull_node(const int4 r, int Wd, int w, uint64
     return out;
 }
 
-// A sweep over count records (recs[b0 + i]), a group of Wd lanes per node.
-// Band sweep (pflag given): pflag[b0 + i] records whether node i is still
-// pending; a node's reach row is written only by its own pull, so its
-// pending bits are final once it has pulled (every non-isolated node has one
-// band position, so every flag the compaction reads is written here, and
-// consecutive groups write neighbouring bytes).  Returns whether any node of
-// the calling wave gained bits.
-__device__ __forceinline__ bool pull_sweep(const int4 *__restrict__ recs, int32_t b0, int32_t count, int32_t Wd,
-                                           const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
-                                           uint32_t *__restrict__ reach, int32_t max_scan, uint8_t *__restrict__ pflag)
+// The sweep loop of pull_sweep around pull_node_rt (no pending flags).
+__device__ __forceinline__ bool pull_sweep_rt(const int4 *__restrict__ recs, int32_t count, int32_t Wd,
+                                              const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
+                                              uint32_t *__restrict__ reach, int32_t max_scan)
 {
     const int lane = threadIdx.x & 63;
     const int w = lane & (Wd - 1);
@@ -350,23 +452,18 @@ __device__ __forceinline__ bool pull_sweep(const int4 *__restrict__ recs, int32_
     const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / Wd;
     const int64_t iters = (count + ngroups - 1) / ngroups;
     bool any_gain = false;
-    for (int64_t it = 0, idx = group; it < iters; ++it, idx += ngroups) {
-        if (idx < count) {
-            const int4 r = recs[b0 + idx];
-            const PullOut o = pull_node(r, Wd, w, gmask, colD, dead, reach, max_scan);
-            any_gain |= o.gained;
-            if (pflag && w == 0) pflag[b0 + idx] = o.pending ? 1 : 0;
-        }
-    }
+    for (int64_t it = 0, idx = group; it < iters; ++it, idx += ngroups)
+        if (idx < count) any_gain |= pull_node_rt(recs[idx], Wd, w, gmask, colD, dead, reach, max_scan).gained;
     return __ballot(any_gain) != 0;
 }
 
 // One band of the ordered sweep: the nodes at band positions [b0, b1).
-__global__ void k_pull_band(const int4 *__restrict__ band_rec, int32_t b0, int32_t b1, int32_t Wd,
+template <int WD>
+__global__ void k_pull_band(const int4 *__restrict__ band_rec, int32_t b0, int32_t b1,
                             const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
                             uint32_t *__restrict__ reach, int32_t max_scan, uint8_t *__restrict__ pflag)
 {
-    (void)pull_sweep(band_rec, b0, b1 - b0, Wd, colD, dead, reach, max_scan, pflag);
+    (void)pull_sweep<WD>(band_rec, b0, b1 - b0, colD, dead, reach, max_scan, pflag);
 }
 
 // Block-level compaction: every block owns a contiguous range of the input,
@@ -460,7 +557,7 @@ __global__ void k_pull_worklist(const int4 *__restrict__ worklist, const int32_t
 {
     if (ld_relaxed(changed + s - 1) == 0) return;
     const int32_t count = ld_relaxed(wl_count);
-    const bool any_gain = pull_sweep(worklist, 0, count, Wd, colD, dead, reach, INT_MAX, nullptr);
+    const bool any_gain = pull_sweep_rt(worklist, count, Wd, colD, dead, reach, INT_MAX);
     // one flag for the whole grid: set it with a plain store, and only if no
     // other wave has (same-address atomics from every wave would serialise)
     if (any_gain && (threadIdx.x & 63) == 0 && ld_relaxed(changed + s) == 0)
@@ -765,6 +862,20 @@ __global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, in
 
 }  // namespace
 
+// Launch of KERNEL<WD>, kBlk threads a block, for the group width
+// WD = 2^log_wd of a pass (1 to 32 words a node row).
+#define GAPA_LAUNCH_WD(KERNEL, log_wd, grid, s, ...)                                       \
+    do {                                                                                   \
+        switch (log_wd) {                                                                  \
+        case 0: hipLaunchKernelGGL(KERNEL<1>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break;  \
+        case 1: hipLaunchKernelGGL(KERNEL<2>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break;  \
+        case 2: hipLaunchKernelGGL(KERNEL<4>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break;  \
+        case 3: hipLaunchKernelGGL(KERNEL<8>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break;  \
+        case 4: hipLaunchKernelGGL(KERNEL<16>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break; \
+        default: hipLaunchKernelGGL(KERNEL<32>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break; \
+        }                                                                                  \
+    } while (0)
+
 int launch_bits_transpose(const uint32_t *masks, int32_t P, int32_t W, int32_t n, uint32_t *rows, hipStream_t s)
 {
     int32_t Wd = P / 32, log_wd = 0;
@@ -872,8 +983,8 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
                 if (b1 <= b0) continue;
                 const int64_t threads = (int64_t)(b1 - b0) * Wd;
                 const int blocks = (int)std::min<int64_t>((threads + kBlk - 1) / kBlk, tu.band_blocks);
-                hipLaunchKernelGGL(k_pull_band, dim3(blocks), dim3(kBlk), 0, s, g->d_band_rec, b0, b1, Wd, g->d_colD,
-                                   dead, reach, tu.band_scan, ws.pflag.as<uint8_t>());
+                GAPA_LAUNCH_WD(k_pull_band, log_wd, dim3(blocks), s, g->d_band_rec, b0, b1, g->d_colD, dead, reach,
+                               tu.band_scan, ws.pflag.as<uint8_t>());
             }
         }
         if (noniso > 0) {
