@@ -829,7 +829,7 @@ int ga_allocate(gapa_ga *ga, int32_t count, const gapa_params *p, const int32_t 
     ga->use_graph = (p[0].flags & GAPA_GRAPH_REPLAY) != 0;
     ga->hinst.assign(count, GaInst{});
     int64_t pop_el = 0, child_el = 0, mask_w = 0;
-    int32_t fit_n = 0, rank_n = 0, noniso_w = 0, slots = 0;
+    int32_t fit_n = 0, noniso_w = 0, slots = 0;
     size_t lds = 0;
     for (int32_t b = 0; b < count; ++b) {
         GaInst &I = ga->hinst[b];
@@ -851,13 +851,11 @@ int ga_allocate(gapa_ga *ga, int32_t count, const gapa_params *p, const int32_t 
         I.mask_off = mask_w;
         I.fit_off = fit_n;
         I.slot_off = slot_stride > 0 ? b * slot_stride : slots;
-        I.rank_off = rank_n;
         I.noniso_off = noniso_w;
         pop_el += (int64_t)I.P * I.k;
         child_el += (int64_t)R * I.k;
         mask_w += (int64_t)R * I.W;
         fit_n += I.P;
-        rank_n += I.P + L;
         noniso_w += I.W;
         slots += R;
         ga->max_pop = std::max(ga->max_pop, I.P);
@@ -866,7 +864,6 @@ int ga_allocate(gapa_ga *ga, int32_t count, const gapa_params *p, const int32_t 
         lds = std::max(lds, ga_op_lds_bytes(n[b], p[b].k));
     }
     if (slot_stride > 0) slots = count * slot_stride;
-    ga->rank_total = rank_n;
     ga->op_lds_bytes = lds;
     if (pop_el >= (1ll << 31) || child_el >= (1ll << 31)) {
         set_error("population too large");
@@ -890,7 +887,6 @@ int ga_allocate(gapa_ga *ga, int32_t count, const gapa_params *p, const int32_t 
     if (rc == GAPA_OK) rc = ga->masks.reserve((size_t)mask_w * 4);
     if (rc == GAPA_OK) rc = ga->alive.reserve((size_t)slots * 4);
     if (rc == GAPA_OK) rc = ga->src.reserve((size_t)fit_n * 4);
-    if (rc == GAPA_OK) rc = ga->rank.reserve((size_t)rank_n * 4);
     if (rc == GAPA_OK) rc = ga->flag.reserve(16);
     if (rc == GAPA_OK) rc = ga->gen_ctr.reserve(16);
     if (rc == GAPA_OK) rc = ga->inst.reserve(sizeof(GaInst) * count);
@@ -1088,7 +1084,7 @@ void ga_release(gapa_ga *ga)
     if (ga->cap_stream) (void)hipStreamDestroy(ga->cap_stream);
     ga->cap_stream = nullptr;
     for (auto *b : {&ga->pop[0], &ga->pop[1], &ga->fit[0], &ga->fit[1], &ga->children, &ga->child_fit, &ga->child_mcn, &ga->masks,
-                    &ga->alive, &ga->src, &ga->rank, &ga->flag, &ga->gen_ctr, &ga->inst, &ga->noniso_buf,
+                    &ga->alive, &ga->src, &ga->flag, &ga->gen_ctr, &ga->inst, &ga->noniso_buf,
                     &ga->tab_voff, &ga->tab_live_init, &ga->tab_live_gen, &ga->tab_moff, &ga->tab_node_inst,
                     &ga->tab_tiles})
         b->release();

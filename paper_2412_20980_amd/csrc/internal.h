@@ -252,7 +252,6 @@ struct GaInst {
     int64_t mask_off;   // first word of its child masks (row stride W)
     int32_t fit_off;    // first entry in fit[*] and src
     int32_t slot_off;   // first entry in child_fit and alive
-    int32_t rank_off;   // first entry in rank
     int32_t noniso_off; // first word of its non-isolated node bit set
     uint64_t seed, t_pc, t_pm;
     int32_t P, L, k, n, W, KW, T, n_noniso;
@@ -317,8 +316,7 @@ struct gapa_ga {
     int32_t count = 1;            // instances
     std::vector<gapa::GaInst> hinst;
     gapa::DevBuf inst;            // GaInst [count]
-    int32_t max_pop = 0, max_lambda = 0, max_pop_lambda = 0, rank_total = 0;
-    bool rank_clear = false;  // rank counters zeroed (k_rank_place leaves them zero)
+    int32_t max_pop = 0, max_lambda = 0, max_pop_lambda = 0;
     gapa::DevBuf pop[2];          // int32 rows of every instance
     gapa::DevBuf fit[2];          // int64 [sum P]
     gapa::DevBuf children;        // int32 rows
@@ -330,7 +328,6 @@ struct gapa_ga {
     gapa::DevBuf masks;           // uint32 removed-node bit sets of the children
     gapa::DevBuf alive;           // int32 slots: surviving non-isolated nodes
     gapa::DevBuf src;             // int32 [sum P] elitism: source tag of each kept row
-    gapa::DevBuf rank;            // int32 [sum (P + lambda)] elitism: offspring below each key
     gapa::DevBuf flag;            // int32 [4] device error flags
     gapa::DevBuf gen_ctr;         // uint32 [1] generations completed (read by the operator kernel)
     uint32_t *noniso = nullptr;   // batch: per-instance non-isolated bit sets (else the graph's)
