@@ -65,7 +65,7 @@ FITNESS_SOURCES = ("fitness_bits.hip", "fitness.hip", "device_common.h", "api.hi
 # population, pinned so that timed runs and counter runs use the same ones.
 DEFAULT_TUNING = {
     "cl200k_k2000_p1024": "2048,16,2,2048",
-    "batched64_p128": "4096,32,3,8192",
+    "batched64_p128": "2048,8,3,16384",
 }
 
 

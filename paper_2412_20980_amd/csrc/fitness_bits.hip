@@ -283,8 +283,10 @@ constexpr int kPullIds = 8;
 
 // Groups of at least kIdLanes lanes in the worklist sweep and the pending
 // split also load a chunk of Wd ids at a time (one per lane) and read them
-// back by shuffle; narrower groups load them four at a time.
-constexpr int kIdLanes = 8;
+// back by shuffle; narrower groups load them four at a time (with 8-lane
+// groups too: the pass at P = 256, n = 200k took 0.193 ms with chunks of
+// eight against 0.176 ms).
+constexpr int kIdLanes = 16;
 
 struct PullOut {
     bool gained;   // the node gained bits
