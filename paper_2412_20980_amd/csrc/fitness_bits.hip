@@ -637,6 +637,9 @@ __device__ __forceinline__ void pending_split(const int4 r, int Wd, int w, uint6
 // with 64-entry ranges.
 __device__ __forceinline__ int32_t pair_range(int32_t Wd) { return kBlk / Wd; }
 
+// Ranges a block splits between two reservations of room in the pair list.
+constexpr int kPairBatch = 4;
+
 __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int4 *__restrict__ worklist,
                                                         const int32_t *__restrict__ wl_count, int32_t Wd, const Insts I,
                                                         const int32_t *__restrict__ colD,
@@ -661,28 +664,43 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int4 *__restrict__
     if (lds_singles)
         for (int32_t t = threadIdx.x; t < B; t += blockDim.x) s_single[t] = 0;
     __syncthreads();
-    for (int32_t r0 = blockIdx.x * range; r0 < count; r0 += gridDim.x * range) {
-        // one split per (node, word), kept for the write pass
-        const int32_t idx = r0 + (int32_t)(threadIdx.x / Wd);
-        const bool valid = idx < count;
-        const int4 rec = valid ? worklist[idx] : make_int4(0, 0, 0, 0);
-        const int32_t v = rec.x;
-        uint32_t single, mul;
-        pending_split(rec, Wd, w, gmask, colD, dead, reach, valid, single, mul);
-        const int32_t gbase = inst_of_node(I, v) * I.bseg + w * 32;
-        for (; single; single &= single - 1) {
-            if (lds_singles) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
-            else atomicAdd(other + gbase + __ffs(single) - 1, 1);
+    // the block's ranges r0, r0 + stride, ... are split kPairBatch at a time,
+    // their multi-neighbour bits kept in registers, and written after one
+    // reservation for all of them
+    const int32_t stride = gridDim.x * range;
+    for (int32_t r0 = blockIdx.x * range; r0 < count; r0 += kPairBatch * stride) {
+        uint32_t mulk[kPairBatch];
+        int32_t vk[kPairBatch];
+        int32_t mine = 0;
+#pragma unroll
+        for (int j = 0; j < kPairBatch; ++j) {
+            const int64_t idx = (int64_t)r0 + (int64_t)j * stride + (int32_t)(threadIdx.x / Wd);
+            const bool valid = idx < count;
+            const int4 rec = valid ? worklist[idx] : make_int4(0, 0, 0, 0);
+            uint32_t single, mul;
+            pending_split(rec, Wd, w, gmask, colD, dead, reach, valid, single, mul);
+            const int32_t gbase = inst_of_node(I, rec.x) * I.bseg + w * 32;
+            for (; single; single &= single - 1) {
+                if (lds_singles) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
+                else atomicAdd(other + gbase + __ffs(single) - 1, 1);
+            }
+            mulk[j] = mul;
+            vk[j] = rec.x;
+            mine += __popc(mul);
         }
-        const unsigned long long base = block_reserve(__popc(mul), pair_count, &s_tot, &s_base, &s_off);
-        if (mul) {
-            int64_t q = (int64_t)base + atomicAdd(&s_off, __popc(mul));
-            const int32_t b = inst_of_node(I, v);
-            const int32_t vl = v - i_voff(I, b);
-            for (; mul; mul &= mul - 1) {
-                const int32_t gi = b * I.bseg + w * 32 + __ffs(mul) - 1;
-                pairs[q++] = ((int64_t)gi << 32) | (uint32_t)v;
-                parent[uf_block(I, gi) + vl] = vl;
+        const unsigned long long base = block_reserve(mine, pair_count, &s_tot, &s_base, &s_off);
+        if (mine) {
+            int64_t q = (int64_t)base + atomicAdd(&s_off, mine);
+#pragma unroll
+            for (int j = 0; j < kPairBatch; ++j) {
+                const int32_t v = vk[j];
+                const int32_t b = inst_of_node(I, v);
+                const int32_t vl = v - i_voff(I, b);
+                for (uint32_t mul = mulk[j]; mul; mul &= mul - 1) {
+                    const int32_t gi = b * I.bseg + w * 32 + __ffs(mul) - 1;
+                    pairs[q++] = ((int64_t)gi << 32) | (uint32_t)v;
+                    parent[uf_block(I, gi) + vl] = vl;
+                }
             }
         }
         __syncthreads();
