@@ -287,18 +287,36 @@ __device__ void clear_lds(const OpLds &l, const Op &a)
 // surviving non-isolated nodes (n_noniso minus the genes that have an edge).
 __device__ void emit(const OpLds &l, const Op &a, int32_t idx)
 {
+    // removed non-isolated nodes, counted from the bit set while it is copied
+    // out (the set's words and the non-isolated set's are read in the same
+    // coalesced order), summed in LDS
+    __shared__ int32_t s_gone;
+    if (threadIdx.x == 0) s_gone = 0;
     __syncthreads();
     if (!a.rows_only) {
         uint32_t *m = a.masks + (int64_t)idx * a.W;
+        int32_t gone = 0;
         int32_t w = threadIdx.x;
         for (; w + 7 * (int32_t)blockDim.x < a.W; w += 8 * blockDim.x) {
-            uint32_t x[8];
+            uint32_t x[8], y[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = l.U[w + u * blockDim.x];
+            for (int u = 0; u < 8; ++u) {
+                x[u] = l.U[w + u * blockDim.x];
+                y[u] = a.noniso[w + u * blockDim.x];
+            }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) m[w + u * blockDim.x] = x[u];
+            for (int u = 0; u < 8; ++u) {
+                m[w + u * blockDim.x] = x[u];
+                gone += __popc(x[u] & y[u]);
+            }
         }
-        for (; w < a.W; w += blockDim.x) m[w] = l.U[w];
+        for (; w < a.W; w += blockDim.x) {
+            const uint32_t x = l.U[w];
+            m[w] = x;
+            gone += __popc(x & a.noniso[w]);
+        }
+        for (int off = 32; off > 0; off >>= 1) gone += __shfl_down(gone, off, 64);
+        if ((threadIdx.x & 63) == 0 && gone) atomicAdd(&s_gone, gone);
     }
     const int32_t per = (a.W + blockDim.x - 1) / blockDim.x;
     const int32_t w0 = min(a.W, (int32_t)threadIdx.x * per), w1 = min(a.W, w0 + per);
@@ -313,16 +331,9 @@ __device__ void emit(const OpLds &l, const Op &a, int32_t idx)
             if (off < a.k) l.row[off++] = w * 32 + __ffs(bits) - 1;
     __syncthreads();
     int32_t *dst = a.children + (int64_t)idx * a.k;
-    int32_t gone = 0;
-    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) {
-        const int32_t v = l.row[j];
-        dst[j] = v;
-        if (!a.rows_only) gone += (a.noniso[v >> 5] >> (v & 31)) & 1u;
-    }
-    int32_t gone_total = 0;
-    if (!a.rows_only) (void)block_exclusive_scan(gone, &gone_total);
+    for (int32_t j = threadIdx.x; j < a.k; j += blockDim.x) dst[j] = l.row[j];
     if (threadIdx.x == 0) {
-        if (!a.rows_only) a.alive[idx] = a.n_noniso - gone_total;
+        if (!a.rows_only) a.alive[idx] = a.n_noniso - s_gone;
         if (total != a.k) atomicOr(a.flag, 1);
     }
 }
