@@ -550,11 +550,14 @@ __global__ void k_mcn_objective(const int32_t *__restrict__ mcn, int64_t *__rest
 // A block takes kRankKeys keys.  Each of its waves holds a 64-entry slice of
 // the pool, one entry per lane, and compares it with one key at a time: a
 // ballot and a bit count give the slice's entries below the key.  The waves'
-// counts meet in LDS, and the block places its keys in the same launch:
-// 11.7 us per generation at P = lambda = 1024, against 14.2 for a
-// tile-by-tile count into atomic counters and a second launch placing the
-// keys.  Slower: counting the parents by ballot too (16.4 us), and the
-// comparison loop written without branches, eight keys a batch (29 us).
+// counts meet in LDS, and the block places its keys in the same launch.  At
+// P = lambda = 1024 elitism (ranks and the row gather) takes 13.9 us per
+// generation with 8 keys a block, against 15.1 with 16 and 20.0 with 64
+// (the keys' loop is a chain of LDS reads; more blocks share it), and 22 us
+// for a tile-by-tile count into atomic counters plus a second launch placing
+// the keys.
+// Slower: counting the parents by ballot too, and the comparison loop
+// written without branches, eight keys a batch.
 struct RankArgs {
     const GaInst *inst;
     const int64_t *f_par;   // current fitness (instance base fit_off)
@@ -582,7 +585,7 @@ __device__ __forceinline__ RankView rank_view(const RankArgs &a, int32_t b)
     return v;
 }
 
-constexpr int kRankKeys = 64;   // keys per block
+constexpr int kRankKeys = 8;    // keys per block
 constexpr int kRankWaves = 16;  // waves per block
 
 __global__ __launch_bounds__(64 * kRankWaves) void k_rank_place(RankArgs a)
