@@ -991,31 +991,49 @@ __global__ __launch_bounds__(256) void k_batch_bits(const int32_t *__restrict__ 
 // (average ranks), and the mean relative error of expm1(yhat sd + mu).
 // out[0] the correlation, out[1] the error; out_musd (optional) receives the
 // label mean and spread the predictions were made in.
-__global__ __launch_bounds__(1024) void k_judge(const float *__restrict__ yhat, const int32_t *__restrict__ pool,
-                                                const int64_t *__restrict__ F, int32_t m,
-                                                const double *__restrict__ mu_sd, double *__restrict__ out,
-                                                double *__restrict__ out_musd)
+constexpr int kJudgeKeys = 64;  // keys per k_judge_part block, 16 threads a key
+
+// Partial sums of the judge's statistics: block b ranks keys [64 b, 64 b + 64)
+// of the J evenly spaced evaluated children, each key by 16 threads that
+// split the others between them (their counts combined by shuffles), and
+// writes its keys' sums of ra rb, ra^2, rb^2 and the relative error to
+// part[4 b ..] in a fixed order.  (One block ranking every key by one
+// thread took 33 us per screened generation.)
+__global__ __launch_bounds__(1024) void k_judge_part(const float *__restrict__ yhat, const int32_t *__restrict__ pool,
+                                                     const int64_t *__restrict__ F, int32_t m,
+                                                     const double *__restrict__ mu_sd, double *__restrict__ part)
 {
     __shared__ float s_y[kJudgeMax];
     __shared__ int64_t s_f[kJudgeMax];
     __shared__ double s_w[4][16];
     const int32_t J = min(m, kJudgeMax);
-    const int32_t i = threadIdx.x;
-    if (i < J) {
+    for (int32_t i = threadIdx.x; i < J; i += blockDim.x) {
         const int32_t q = (int32_t)(((int64_t)i * m) / J);
         s_y[i] = yhat[pool ? pool[q] : q];
         s_f[i] = F[q];
     }
     __syncthreads();
-    double ra = 0.0, rb = 0.0, rel = 0.0;
+    const int32_t i = blockIdx.x * kJudgeKeys + (int32_t)(threadIdx.x >> 4), p = threadIdx.x & 15;
+    int32_t la = 0, ea = 0, lb = 0, eb = 0;
     if (i < J) {
-        int32_t la = 0, ea = 0, lb = 0, eb = 0;
-        for (int32_t j = 0; j < J; ++j) {
-            la += s_y[j] < s_y[i];
-            ea += s_y[j] == s_y[i];
-            lb += s_f[j] < s_f[i];
-            eb += s_f[j] == s_f[i];
+        const float yi = s_y[i];
+        const int64_t fi = s_f[i];
+        for (int32_t j = p; j < J; j += 16) {
+            la += s_y[j] < yi;
+            ea += s_y[j] == yi;
+            lb += s_f[j] < fi;
+            eb += s_f[j] == fi;
         }
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+        la += __shfl_xor(la, off, 64);
+        ea += __shfl_xor(ea, off, 64);
+        lb += __shfl_xor(lb, off, 64);
+        eb += __shfl_xor(eb, off, 64);
+    }
+    double ra = 0.0, rb = 0.0, rel = 0.0;
+    if (i < J && p == 0) {
         const double mid = (J + 1) / 2.0;
         ra = la + (ea + 1) / 2.0 - mid;
         rb = lb + (eb + 1) / 2.0 - mid;
@@ -1029,23 +1047,50 @@ __global__ __launch_bounds__(1024) void k_judge(const float *__restrict__ yhat, 
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) q[t] += __shfl_xor(q[t], off, 64);
-    if ((i & 63) == 0)
+    if ((threadIdx.x & 63) == 0)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) s_w[t][i >> 6] = q[t];
+        for (int t = 0; t < 4; ++t) s_w[t][threadIdx.x >> 6] = q[t];
     __syncthreads();
-    if (i == 0) {
+    if (threadIdx.x == 0) {
         double sum[4] = {0.0, 0.0, 0.0, 0.0};
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
 #pragma unroll
             for (int t = 0; t < 4; ++t) sum[t] += s_w[t][w];
-        const double den = sqrt(sum[1] * sum[2]);
-        out[0] = den > 0.0 ? sum[0] / den : 0.0;
-        out[1] = sum[3] / J;
-        if (out_musd) {
-            out_musd[0] = mu_sd[0];
-            out_musd[1] = mu_sd[1];
-        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) part[4 * blockIdx.x + t] = sum[t];
     }
+}
+
+// The judge's statistics from the nb blocks' partial sums, added in block
+// order: Spearman's rho (Pearson's over the average ranks) and the mean
+// relative error; with out_musd, the label mean and spread used.
+__global__ void k_judge_final(const double *__restrict__ part, int32_t nb, int32_t m, const double *__restrict__ mu_sd,
+                              double *__restrict__ out, double *__restrict__ out_musd)
+{
+    if (threadIdx.x != 0) return;
+    const int32_t J = min(m, kJudgeMax);
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t b = 0; b < nb; ++b)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) sum[t] += part[4 * b + t];
+    const double den = sqrt(sum[1] * sum[2]);
+    out[0] = den > 0.0 ? sum[0] / den : 0.0;
+    out[1] = sum[3] / J;
+    if (out_musd) {
+        out_musd[0] = mu_sd[0];
+        out_musd[1] = mu_sd[1];
+    }
+}
+
+int launch_judge(const float *yhat, const int32_t *pool, const int64_t *F, int32_t m, const double *mu_sd,
+                 double *part, double *out, double *out_musd, hipStream_t s)
+{
+    const int32_t J = std::min(m, kJudgeMax);
+    const int32_t nb = std::max(1, (J + kJudgeKeys - 1) / kJudgeKeys);
+    hipLaunchKernelGGL(k_judge_part, dim3(nb), dim3(1024), 0, s, yhat, pool, F, m, mu_sd, part);
+    hipLaunchKernelGGL(k_judge_final, dim3(1), dim3(64), 0, s, part, nb, m, mu_sd, out, out_musd);
+    GAPA_HIP(hipGetLastError());
+    return GAPA_OK;
 }
 
 }  // namespace
@@ -1082,6 +1127,7 @@ struct SurrogateState {
     DevBuf buf_genes, buf_y;                            // ring buffer
     DevBuf pool, crows, cmasks, calive;                 // screened children
     DevBuf dstats;                                      // double [2]: label mean and spread of the predictions
+    DevBuf jpart;                                       // double [16][4]: the judge's partial sums
     DevBuf dloss;                                       // double [5]: [0] the loss of the last explicit
                                                         // batch; [1 + (g & 3)] the loss of the last step of
                                                         // generation g's training
@@ -1407,6 +1453,7 @@ int surrogate_attach(gapa_ga *ga, const gapa_surrogate_params *sp, hipStream_t s
     res(st->cmasks, (size_t)(sp->screen + kJudgeExtra) * st->W * 4);
     res(st->calive, (size_t)(sp->screen + kJudgeExtra) * 4);
     res(st->dstats, 64);
+    res(st->jpart, (size_t)8 * 4 * (kJudgeMax / kJudgeKeys));
     res(st->dloss, 5 * 8);
     res(st->tstats, 16);
     if (rc != GAPA_OK) return rc;
@@ -1458,7 +1505,7 @@ void surrogate_release(SurrogateState *st)
                       &st->target, &st->lossv, &st->dy, &st->tflag, &st->dloss, &st->tstats,
                       &st->xT, &st->h1T, &st->h2T, &st->dz1T, &st->dz2T, &st->dxT, &st->bgenes, &st->bmasks,
                       &st->balive, &st->bflag, &st->brows, &st->buf_genes, &st->buf_y, &st->pool, &st->crows,
-                      &st->cmasks, &st->calive, &st->dstats, &st->bpos})
+                      &st->cmasks, &st->calive, &st->dstats, &st->jpart, &st->bpos})
         b->release();
     if (st->hstats) (void)hipHostFree(st->hstats);
     for (hipEvent_t e : {st->ready[0], st->ready[1], st->ev_pred, st->ev_snap, st->ev_data, st->ev_sampled})
@@ -1528,7 +1575,8 @@ int surrogate_generation(gapa_ga *ga, hipStream_t s)
         if ((rc = ga_rank_and_gather(ga, false, F, pool, npool, s)) != GAPA_OK) return rc;
     }
     double *ds = st.dstats.as<double>();
-    if (predict) hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, neval, ds, hs + 2, hs + 5);
+    if (predict && (rc = launch_judge(yhat, pool, F, neval, ds, st.jpart.as<double>(), hs + 2, hs + 5, s)) != GAPA_OK)
+        return rc;
     if (!random) {
         // generation gen - 1's training has copied its batches out of the
         // buffer (it goes on beside this generation); the loss reported is
@@ -1667,16 +1715,19 @@ int surrogate_stats(gapa_ga *ga, gapa_surrogate_report *out)
 int surrogate_judge(const float *yhat, const int32_t *pool, const int64_t *F, int32_t m, double mu, double sd,
                     double *out, hipStream_t s)
 {
-    DevBuf buf;  // [0, 2) mean and spread in, [2, 4) the statistics out
-    int rc = buf.reserve(32);
+    DevBuf buf;  // [0, 2) mean and spread in, [2, 4) the statistics out, [4, 4 + 4 * 16) partial sums
+    int rc = buf.reserve(8 * (4 + 4 * (kJudgeMax / kJudgeKeys)));
     if (rc != GAPA_OK) return rc;
     const double musd[2] = {mu, sd};
     double res[2] = {0.0, 0.0};
     hipError_t e = hipMemcpyAsync(buf.ptr, musd, 16, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_judge, dim3(1), dim3(1024), 0, s, yhat, pool, F, m, buf.as<double>(),
-                           buf.as<double>() + 2, nullptr);
-        e = hipGetLastError();
+        rc = launch_judge(yhat, pool, F, m, buf.as<double>(), buf.as<double>() + 4, buf.as<double>() + 2, nullptr, s);
+        if (rc != GAPA_OK) {
+            (void)hipStreamSynchronize(s);
+            buf.release();
+            return rc;
+        }
     }
     if (e == hipSuccess) e = hipMemcpyAsync(res, buf.as<double>() + 2, 16, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
