@@ -1,6 +1,6 @@
 // Bit-parallel batched fitness.
 //
-// A chunk of B individuals (B = 32 * Wd, Wd a power of two <= 32) is
+// A chunk of B individuals (B = 32 * Wd, Wd a power of two <= 64) is
 // evaluated together.  For every node v the chunk keeps two rows of Wd 32-bit
 // words, node-major so that one row is one contiguous 4*Wd-byte segment:
 //   dead[v]  bit i set: v is removed in individual i (the perturbation P^ of
@@ -34,6 +34,7 @@ namespace gapa {
 namespace {
 
 constexpr int kBlk = 256;
+constexpr int kMaxSlots = 2048;  // individuals of one pass: 64 words a node row
 
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p)
 {
@@ -117,8 +118,8 @@ constexpr int kTileWords = kTransposeWords;
 // tile [32 TW][Wd + 1] in the same buffer.
 __host__ __device__ constexpr int32_t transpose_lds_words(int32_t log_wd)
 {
-    return 1024 * kTileWords + ((32 << log_wd) > (32 * (kTileWords << (5 - log_wd))) ? (32 << log_wd)
-                                                                                        : 32 * (kTileWords << (5 - log_wd)));
+    return 1024 * kTileWords + ((32 << log_wd) > 32 * ((kTileWords * 32) >> log_wd) ? (32 << log_wd)
+                                                                                     : 32 * ((kTileWords * 32) >> log_wd));
 }
 
 // 32 x 32 bit-matrix transpose across the 32 lanes of a half-wave: lane r
@@ -666,12 +667,12 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int4 *__restrict__
 {
     __shared__ int32_t s_tot, s_off;
     __shared__ unsigned long long s_base;
-    __shared__ int32_t s_single[1024];
+    __shared__ int32_t s_single[kMaxSlots];
     const int w = threadIdx.x & (Wd - 1);
     const uint64_t gmask = group_mask(Wd);
     const int32_t range = pair_range(Wd);
     // singleton counts: per-block LDS counters written as a partial row when
-    // all slots fit (one instance, at most 1024 slots), else global atomics
+    // all slots fit (one instance, at most kMaxSlots slots), else global atomics
     const int32_t B = I.count * I.bseg;
     const bool lds_singles = I.count == 1;
     const int32_t count = *wl_count;
@@ -898,7 +899,7 @@ __global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, in
 }  // namespace
 
 // Launch of KERNEL<WD>, kBlk threads a block, for the group width
-// WD = 2^log_wd of a pass (1 to 32 words a node row).
+// WD = 2^log_wd of a pass (1 to 64 words a node row).
 #define GAPA_LAUNCH_WD(KERNEL, log_wd, grid, s, ...)                                       \
     do {                                                                                   \
         switch (log_wd) {                                                                  \
@@ -907,7 +908,8 @@ __global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, in
         case 2: hipLaunchKernelGGL(KERNEL<4>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break;  \
         case 3: hipLaunchKernelGGL(KERNEL<8>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break;  \
         case 4: hipLaunchKernelGGL(KERNEL<16>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break; \
-        default: hipLaunchKernelGGL(KERNEL<32>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break; \
+        case 5: hipLaunchKernelGGL(KERNEL<32>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break;  \
+        default: hipLaunchKernelGGL(KERNEL<64>, grid, dim3(kBlk), 0, s, __VA_ARGS__); break; \
         }                                                                                  \
     } while (0)
 
@@ -1224,8 +1226,8 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
 {
     const bool multi = it && it->count > 1;
     if (!multi && P <= 0) return GAPA_OK;
-    // Chunks of 32 * Wd individuals, Wd a power of two <= 32: full chunks of
-    // 1024, then the rest in the narrowest chunk that holds it.  (A pass's
+    // Chunks of 32 * Wd individuals, Wd a power of two <= 64: full chunks of
+    // 2048, then the rest in the narrowest chunk that holds it.  (A pass's
     // cost is mostly per node, whatever its width: splitting a rest of 544 as
     // 512 + 32 on two lanes cut its latency but nearly doubled its work, which
     // a busy GPU pays.)
@@ -1234,7 +1236,7 @@ int eval_masks_bits(gapa_graph *g, const uint32_t *masks, const int32_t *alive, 
         plan.emplace_back(0, it->bseg / 32);
     } else {
         int32_t c0 = 0;
-        for (; P - c0 >= 1024; c0 += 1024) plan.emplace_back(c0, 32);
+        for (; P - c0 >= kMaxSlots; c0 += kMaxSlots) plan.emplace_back(c0, kMaxSlots / 32);
         const int32_t r = P - c0;
         if (r > 0) {
             int32_t wd = 1;

@@ -64,10 +64,18 @@ def test_cl200k_full_population_hub_heavy(gp, cl200k):
     check(gp, cl200k, pop, graph=graph)
 
 
+def test_cl200k_one_pass_of_2048(gp, cl200k):
+    # the widest pass: 2048 individuals, 64 words a node row, one wave a node
+    graph = gp.Graph.from_csr(cl200k)
+    pop = np.concatenate([inputs.hub_biased_population(cl200k, 2000, 1024, seed=28, hub_frac=1.0),
+                          inputs.random_population(cl200k.n, 2000, 1024, seed=29)])
+    check(gp, cl200k, pop, graph=graph)
+
+
 def test_many_chunks_and_padding(gp, ba10k):
-    # rests of one to 1023 individuals after full chunks of 1024
+    # rests of one to 2047 individuals after full chunks of 2048
     graph = gp.Graph.from_csr(ba10k)
-    for P in (1, 31, 33, 544, 700, 1025, 1568, 2100):
+    for P in (1, 31, 33, 544, 700, 1025, 1568, 2048, 2100, 4099):
         check(gp, ba10k, inputs.random_population(ba10k.n, 100, P, seed=P), graph=graph)
 
 
