@@ -426,7 +426,7 @@ GAPA_API int gapa_batch_destroy(gapa_batch *b);
 
 /* Kernel timing: `enable` 1 brackets whole passes with HIP events on their
  * launch stream ("fitness_pass": the batched fitness of one chunk of up to
- * 1024 individuals; "ga_offspring", "ga_init": the operator kernel;
+ * 2048 individuals; "ga_offspring", "ga_init": the operator kernel;
  * "elitism"); 2 also brackets every kernel launch inside them (the extra
  * events add gaps, so pass totals are exact only at 1); 0 disables.
  * gapa_*_kernel_times fills up to `cap` entries with the scope name, count
