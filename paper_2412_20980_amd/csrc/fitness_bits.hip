@@ -759,9 +759,11 @@ __device__ __forceinline__ void uf_unite(int32_t *parent, int32_t a, int32_t b)
 // Union over the surviving edges of each pending pair (key: slot << 32 |
 // node): a surviving neighbour that is reached joins the root's set; a
 // pending one (each such edge once, from its smaller end) is united with it.
-// Neighbours are taken kHookChunk at a time: their ids, then their bits, each
-// set of loads in flight together, then the unions.
-constexpr int kHookChunk = 8;
+// A pair takes kHookLanes lanes, each walking every kHookLanes-th neighbour,
+// so a node's unions run side by side.  (One thread a pair, taking eight
+// neighbours' ids and bits at a time and uniting in turn, left most of the
+// GPU idle: the pairs of a pass fill about one wave per SIMD.)
+constexpr int kHookLanes = 8;
 
 __global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count,
                              const Insts I, int32_t Wd, const int32_t *__restrict__ row_ptr,
@@ -770,7 +772,9 @@ __global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const unsigned l
                              int32_t *__restrict__ parent)
 {
     const int64_t count = (int64_t)*pair_count;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t sub = threadIdx.x & (kHookLanes - 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x / kHookLanes;
+    for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kHookLanes; q < count; q += stride) {
         const int64_t key = pairs[q];
         const int32_t gi = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
         const int32_t b = gi / I.bseg, i = gi - b * I.bseg;
@@ -779,22 +783,11 @@ __global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const unsigned l
         const uint32_t bit = 1u << (i & 31);
         int32_t *pi = parent + uf_block(I, gi);
         const int32_t e1 = row_ptr[v + 1];
-        for (int32_t e = row_ptr[v]; e < e1; e += kHookChunk) {
-            int32_t u[kHookChunk];
-            uint32_t du[kHookChunk], ru[kHookChunk];
-#pragma unroll
-            for (int t = 0; t < kHookChunk; ++t) u[t] = e + t < e1 ? col[e + t] : -1;
-#pragma unroll
-            for (int t = 0; t < kHookChunk; ++t) {
-                du[t] = u[t] >= 0 ? dead[(int64_t)u[t] * Wd + w] : bit;
-                ru[t] = u[t] >= 0 ? reach[(int64_t)u[t] * Wd + w] : 0u;
-            }
-#pragma unroll
-            for (int t = 0; t < kHookChunk; ++t) {
-                if (du[t] & bit) continue;
-                if (ru[t] & bit) uf_unite(pi, v - off, root[gi] - off);
-                else if (v < u[t]) uf_unite(pi, v - off, u[t] - off);
-            }
+        for (int32_t e = row_ptr[v] + sub; e < e1; e += kHookLanes) {
+            const int32_t u = col[e];
+            if (dead[(int64_t)u * Wd + w] & bit) continue;
+            if (reach[(int64_t)u * Wd + w] & bit) uf_unite(pi, v - off, root[gi] - off);
+            else if (v < u) uf_unite(pi, v - off, u - off);
         }
     }
 }
