@@ -69,19 +69,42 @@ __global__ void k_mask_build_lds(const int32_t *__restrict__ genes, int32_t k, i
     const int32_t i = blockIdx.x;
     for (int32_t w = threadIdx.x; w < W; w += blockDim.x) U[w] = 0u;
     __syncthreads();
+    // eight genes a thread at a time, their loads in flight together
     const int32_t *row = genes + (int64_t)i * k;
-    for (int32_t j = threadIdx.x; j < k; j += blockDim.x) {
-        const int32_t v = row[j];
-        if (v < 0 || v >= n) {
-            atomicOr(flag, 1);
-            continue;
+    for (int32_t j0 = threadIdx.x; j0 < k; j0 += 8 * blockDim.x) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t j = j0 + u * (int32_t)blockDim.x;
+            v[u] = j < k ? row[j] : 0;
         }
-        atomicOr(U + (v >> 5), 1u << (v & 31));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (j0 + u * (int32_t)blockDim.x >= k) break;
+            if (v[u] < 0 || v[u] >= n) atomicOr(flag, 1);
+            else atomicOr(U + (v[u] >> 5), 1u << (v[u] & 31));
+        }
     }
     __syncthreads();
+    // the bit set out and the removed non-isolated nodes counted, eight words
+    // a thread at a time
     uint32_t *m = masks + (int64_t)i * W;
     int32_t gone = 0;
-    for (int32_t w = threadIdx.x; w < W; w += blockDim.x) {
+    int32_t w = threadIdx.x;
+    for (; w + 7 * (int32_t)blockDim.x < W; w += 8 * blockDim.x) {
+        uint32_t x[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            x[u] = U[w + u * blockDim.x];
+            y[u] = noniso[w + u * blockDim.x];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            m[w + u * blockDim.x] = x[u];
+            gone += __popc(x[u] & y[u]);
+        }
+    }
+    for (; w < W; w += blockDim.x) {
         m[w] = U[w];
         gone += __popc(U[w] & noniso[w]);
     }
