@@ -444,9 +444,14 @@ __device__ __forceinline__ PullOut pull_node_rt(const int4 r, int Wd, int w, uin
 }
 
 // The sweep loop of pull_sweep around pull_node_rt (no pending flags).
+// pflag[i] (worklist position i; pflag may be NULL): written after each
+// pull, 1 while the node has bits pending; read (read_flags) so that settled
+// nodes are skipped without loading their rows (a node's reach row changes
+// only by its own pull, so a settled node stays settled).
 __device__ __forceinline__ bool pull_sweep_rt(const int4 *__restrict__ recs, int32_t count, int32_t Wd,
                                               const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
-                                              uint32_t *__restrict__ reach, int32_t max_scan)
+                                              uint32_t *__restrict__ reach, int32_t max_scan,
+                                              uint8_t *__restrict__ pflag, bool read_flags)
 {
     const int lane = threadIdx.x & 63;
     const int w = lane & (Wd - 1);
@@ -455,8 +460,15 @@ __device__ __forceinline__ bool pull_sweep_rt(const int4 *__restrict__ recs, int
     const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / Wd;
     const int64_t iters = (count + ngroups - 1) / ngroups;
     bool any_gain = false;
-    for (int64_t it = 0, idx = group; it < iters; ++it, idx += ngroups)
-        if (idx < count) any_gain |= pull_node_rt(recs[idx], Wd, w, gmask, colD, dead, reach, max_scan).gained;
+    for (int64_t it = 0, idx = group; it < iters; ++it, idx += ngroups) {
+        if (idx < count) {
+            const int4 r = recs[idx];
+            if (pflag && read_flags && !pflag[idx]) continue;
+            const PullOut o = pull_node_rt(r, Wd, w, gmask, colD, dead, reach, max_scan);
+            any_gain |= o.gained;
+            if (pflag && w == 0) pflag[idx] = o.pending ? 1 : 0;
+        }
+    }
     return __ballot(any_gain) != 0;
 }
 
@@ -571,11 +583,14 @@ __global__ __launch_bounds__(kBlk) void k_collect_pending(const uint8_t *__restr
 // something (changed[s - 1] != 0; changed[0] is set by the caller).
 __global__ void k_pull_worklist(const int4 *__restrict__ worklist, const int32_t *__restrict__ wl_count,
                                 int32_t Wd, const int32_t *__restrict__ colD, const uint32_t *__restrict__ dead,
-                                uint32_t *__restrict__ reach, int32_t *__restrict__ changed, int32_t s)
+                                uint32_t *__restrict__ reach, int32_t *__restrict__ changed, int32_t s,
+                                uint8_t *__restrict__ pflag)
 {
     if (ld_relaxed(changed + s - 1) == 0) return;
     const int32_t count = ld_relaxed(wl_count);
-    const bool any_gain = pull_sweep_rt(worklist, count, Wd, colD, dead, reach, INT_MAX);
+    // with flags (pflag not NULL) the first sweep writes every worklist
+    // position's flag, later ones skip the nodes it (or they) left settled
+    const bool any_gain = pull_sweep_rt(worklist, count, Wd, colD, dead, reach, INT_MAX, pflag, s > 1);
     // one flag for the whole grid: set it with a plain store, and only if no
     // other wave has (same-address atomics from every wave would serialise)
     if (any_gain && (threadIdx.x & 63) == 0 && ld_relaxed(changed + s) == 0)
@@ -663,7 +678,8 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int4 *__restrict__
                                                         const uint32_t *__restrict__ reach, int64_t *__restrict__ pairs,
                                                         unsigned long long *__restrict__ pair_count,
                                                         int32_t *__restrict__ parent,
-                                                        int32_t *__restrict__ single_part, int32_t *__restrict__ other)
+                                                        int32_t *__restrict__ single_part, int32_t *__restrict__ other,
+                                                        const uint8_t *__restrict__ pflag)
 {
     __shared__ int32_t s_tot, s_off;
     __shared__ unsigned long long s_base;
@@ -691,7 +707,9 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int4 *__restrict__
 #pragma unroll
         for (int j = 0; j < kPairBatch; ++j) {
             const int64_t idx = (int64_t)r0 + (int64_t)j * stride + (int32_t)(threadIdx.x / Wd);
-            const bool valid = idx < count;
+            // pflag (the follow-up sweeps' flags by worklist position): a
+            // settled node has nothing to split
+            const bool valid = idx < count && (!pflag || pflag[idx]);
             const int4 rec = valid ? worklist[idx] : make_int4(0, 0, 0, 0);
             uint32_t single, mul;
             pending_split(rec, Wd, w, gmask, colD, dead, reach, valid, single, mul);
@@ -1029,16 +1047,23 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
                 hipLaunchKernelGGL(k_collect_pending<4>, grid_p, dim3(kBlk), 0, s, ws.pflag.as<uint8_t>(), noniso,
                                    g->d_band_rec, worklist, wl_count);
         }
+        // Settled-node flags (by worklist position, in the band flags' buffer,
+        // consumed by then) pay when later sweeps revisit many settled nodes:
+        // with three sweeps over the 64 batched graphs the pass went from 0.305
+        // to 0.287 ms; with two at n = 200k, whose worklist nodes mostly stay
+        // pending, from 0.162 to 0.164 ms.  So they are kept from three on.
+        const bool settled_flags = tu.sweeps >= 3;
         {
             TimedScope ts(timer, "k_pull_worklist", s);
             for (int32_t sw = 1; sw <= tu.sweeps; ++sw)
                 hipLaunchKernelGGL(k_pull_worklist, dim3(grid), dim3(kBlk), 0, s, worklist, wl_count, Wd, g->d_colD,
-                                   dead, reach, changed, sw);
+                                   dead, reach, changed, sw, settled_flags ? ws.pflag.as<uint8_t>() : nullptr);
         }
         {
             TimedScope ts(timer, "k_collect_pairs", s);
             hipLaunchKernelGGL(k_collect_pairs, dim3(grid), dim3(kBlk), 0, s, worklist, wl_count, Wd, I, g->d_colD,
-                               dead, reach, pairs, pair_count, parent, single_part, other);
+                               dead, reach, pairs, pair_count, parent, single_part, other,
+                               settled_flags ? ws.pflag.as<uint8_t>() : nullptr);
         }
         {
             TimedScope ts(timer, "k_pairs_hook", s);

@@ -98,7 +98,7 @@ struct FitnessWorkspace {
     DevBuf ucount;   // int32 [B][n]  set sizes of the leftover union-find, kept zero
     DevBuf pairs;    // int64 [B * n_noniso] pending (individual, node) keys
     DevBuf worklist; // int4 [n_noniso] records (node, first edge, edge end) of the nodes still pending after the ordered sweep
-    DevBuf pflag;    // uint8 [n_noniso] 1: the node at this band position is still pending after the ordered sweep
+    DevBuf pflag;    // uint8 [n_noniso] 1: the node at this band position is still pending after the ordered sweep (then: at this worklist position, after the last follow-up sweep)
     bool pflag_clear = false;  // pflag zeroed since it was (re)allocated
     DevBuf small;    // int32 roots, root-set sizes, counters, count partials
     int32_t *stats_ctr = nullptr;  // device counters of the last bit-parallel chunk
