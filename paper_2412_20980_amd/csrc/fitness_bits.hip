@@ -443,7 +443,7 @@ __device__ __forceinline__ PullOut pull_node_rt(const int4 r, int Wd, int w, uin
     return out;
 }
 
-// The sweep loop of pull_sweep around pull_node_rt (no pending flags).
+// The sweep loop of pull_sweep around pull_node_rt, for the worklist.
 // pflag[i] (worklist position i; pflag may be NULL): written after each
 // pull, 1 while the node has bits pending; read (read_flags) so that settled
 // nodes are skipped without loading their rows (a node's reach row changes
