@@ -20,7 +20,8 @@
 // connected and contains r_i, so an edge into R_i is an edge into r_i).
 // Every component other than the root's is then made only of pending nodes
 // and is counted directly; the root's component is what remains of the
-// surviving non-isolated nodes.  PC = sum |C|(|C|-1)/2 and MCN follow.
+// surviving non-isolated nodes: all of them but the pending nodes outside
+// the root's set.  PC = sum |C|(|C|-1)/2 and MCN follow.
 // Isolated nodes of G are singletons in every G - S and never enter.
 #include <algorithm>
 #include <climits>
@@ -597,11 +598,12 @@ __global__ void k_pull_worklist(const int4 *__restrict__ worklist, const int32_t
         __hip_atomic_store(changed + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Pending (individual, node) pairs.  A pending node with no surviving
-// neighbour is a component of its own: it is only counted (per block, into
-// one partial row of single_part, which k_pairs_count's extra blocks add to
-// other[i]; with several instances directly into other[i]).
-// The rest go to the pair list for the union-find (parent[i][v] = v).
+// Pending (individual, node) pairs.  Every pending node is counted for its
+// individual (per block, into one partial row of single_part, which
+// k_pairs_count's extra blocks add to other[i]; with several instances
+// directly into other[i]).  A pending node with no surviving neighbour is a
+// component of its own and stops there; the rest go to the pair list for the
+// union-find (parent[i][v] = v).
 // Padding individuals remove every node, so their bits are never pending.
 // A block takes one worklist entry per group at a time: it splits every
 // (node, word) entry, reserves room for the block's pairs with one global
@@ -687,7 +689,7 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int4 *__restrict__
     const int w = threadIdx.x & (Wd - 1);
     const uint64_t gmask = group_mask(Wd);
     const int32_t range = pair_range(Wd);
-    // singleton counts: per-block LDS counters written as a partial row when
+    // pending counts: per-block LDS counters written as a partial row when
     // all slots fit (one instance, at most kMaxSlots slots), else global atomics
     const int32_t B = I.count * I.bseg;
     const bool lds_singles = I.count == 1;
@@ -714,9 +716,11 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int4 *__restrict__
             uint32_t single, mul;
             pending_split(rec, Wd, w, gmask, colD, dead, reach, valid, single, mul);
             const int32_t gbase = inst_of_node(I, rec.x) * I.bseg + w * 32;
-            for (; single; single &= single - 1) {
-                if (lds_singles) atomicAdd(&s_single[w * 32 + __ffs(single) - 1], 1);
-                else atomicAdd(other + gbase + __ffs(single) - 1, 1);
+            // in LDS the pair nodes are counted where their pairs are written
+            // (one divergent loop fewer); the global counts take them here
+            for (uint32_t cnt = lds_singles ? single : single | mul; cnt; cnt &= cnt - 1) {
+                if (lds_singles) atomicAdd(&s_single[w * 32 + __ffs(cnt) - 1], 1);
+                else atomicAdd(other + gbase + __ffs(cnt) - 1, 1);
             }
             mulk[j] = mul;
             vk[j] = rec.x;
@@ -734,12 +738,13 @@ __global__ __launch_bounds__(kBlk) void k_collect_pairs(const int4 *__restrict__
                     const int32_t gi = b * I.bseg + w * 32 + __ffs(mul) - 1;
                     pairs[q++] = ((int64_t)gi << 32) | (uint32_t)v;
                     parent[uf_block(I, gi) + vl] = vl;
+                    if (lds_singles) atomicAdd(&s_single[gi], 1);
                 }
             }
         }
         __syncthreads();
     }
-    // singleton counts of this block: one partial row, summed by single_sum
+    // pending counts of this block: one partial row, summed by single_sum
     if (lds_singles)
         for (int32_t t = threadIdx.x; t < B; t += blockDim.x) single_part[(int64_t)blockIdx.x * B + t] = s_single[t];
 }
@@ -811,7 +816,7 @@ __global__ void k_pairs_hook(const int64_t *__restrict__ pairs, const unsigned l
 }
 
 // Pending nodes counted at the representative of their set.
-// Adds the singleton partial rows of the collect blocks that owned a range to
+// Adds the pending-count partial rows of the collect blocks that owned a range to
 // other[i]: block (x, y) sums rows [64 y, 64 y + 64) for individuals
 // [kBlk x, kBlk x + kBlk), loads unrolled, then one atomic per individual.
 constexpr int kSumRows = 64;
@@ -834,7 +839,7 @@ __device__ __forceinline__ void single_sum(int32_t bx, int32_t by, const int32_t
 
 // Blocks [0, grid): each pair's node counted at the representative of its
 // set.  Blocks from grid on (one instance only; sum_x blocks per row group)
-// add the singleton partial rows: independent work sharing the launch.
+// add the pending-count partial rows: independent work sharing the launch.
 __global__ void k_pairs_count(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count, const Insts I,
                               int32_t *__restrict__ parent, int32_t *__restrict__ ucount, int32_t grid,
                               const int32_t *__restrict__ single_part, const int32_t *__restrict__ wl_count,
@@ -863,19 +868,37 @@ __device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit
     if (mcn && s > 0) atomicMax(mcn, (int32_t)s);
 }
 
-// The root's component of slot gi: what remains of its surviving
-// non-isolated nodes once every other component is counted (or the root
-// alone when it is isolated).  Its union-find counter is cleared for reuse.
-// Components made only of pending nodes (set representative is a pending node
-// other than the root's representative): counted, and their sizes summed into
-// other[gi].  Their counters are cleared for reuse.
+// Blocks [0, grid): the components made only of pending nodes (set
+// representative is a pending node other than the root's representative),
+// counted; their counters are cleared for reuse.
+// Blocks from grid on, one slot a thread: the root's component, which holds
+// every surviving non-isolated node but the pending ones outside the root's
+// set: alive - other[gi] (all its pending nodes) + the root set's counter
+// (the root alone when it is isolated); that counter is cleared for reuse.
+// Neither part reads what the other writes: the root's counter is skipped by
+// the pair part, and other[] is final once k_pairs_count has ended.
 __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count, const Insts I,
-                               int32_t *__restrict__ parent, const int32_t *__restrict__ root,
-                               int32_t *__restrict__ ucount, int32_t *__restrict__ other,
+                               int32_t grid, int32_t *__restrict__ parent, const int32_t *__restrict__ root,
+                               int32_t *__restrict__ ucount, const int32_t *__restrict__ alive_noniso,
+                               const int32_t *__restrict__ other, const int32_t *__restrict__ row_ptr,
                                unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest)
 {
+    if ((int32_t)blockIdx.x >= grid) {
+        const int32_t gi = ((int32_t)blockIdx.x - grid) * blockDim.x + threadIdx.x;
+        if (gi >= I.count * I.bseg || root[gi] < 0) return;
+        const int32_t r = root[gi];
+        const int32_t off = i_voff(I, gi / I.bseg);
+        const int64_t blk = uf_block(I, gi);
+        const int32_t rep = uf_find(parent + blk, r - off);
+        const int64_t s = row_ptr[r + 1] > row_ptr[r]
+                              ? (int64_t)alive_noniso[gi] - other[gi] + ucount[blk + rep]
+                              : 1;
+        ucount[blk + rep] = 0;
+        add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
+        return;
+    }
     const int64_t count = (int64_t)*pair_count;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)grid * blockDim.x) {
         const int64_t key = pairs[q];
         const int32_t gi = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
         const int32_t off = i_voff(I, gi / I.bseg);
@@ -884,27 +907,8 @@ __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const unsigned
         if (parent[blk + vl] != vl || vl == uf_find(parent + blk, root[gi] - off)) continue;
         const int32_t s = ucount[blk + vl];
         ucount[blk + vl] = 0;
-        atomicAdd(other + gi, s);
         add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
     }
-}
-
-// The root's component of each slot: what remains of its surviving
-// non-isolated nodes once every other component is counted (or the root
-// alone when it is isolated).  Its union-find counter is cleared for reuse.
-__global__ void k_root_final(const int32_t *__restrict__ root, const Insts I, int32_t *__restrict__ parent,
-                             const int32_t *__restrict__ alive_noniso, const int32_t *__restrict__ other,
-                             const int32_t *__restrict__ row_ptr, int32_t *__restrict__ ucount,
-                             unsigned long long *__restrict__ fitness, int32_t *__restrict__ mcn, int32_t forest)
-{
-    const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= I.count * I.bseg || root[gi] < 0) return;
-    const int32_t r = root[gi];
-    const int32_t off = i_voff(I, gi / I.bseg);
-    const int64_t blk = uf_block(I, gi);
-    ucount[blk + uf_find(parent + blk, r - off)] = 0;
-    const int64_t s = row_ptr[r + 1] > row_ptr[r] ? (int64_t)alive_noniso[gi] - other[gi] : 1;
-    add_component(s, fitness + gi, mcn ? mcn + gi : nullptr, forest);
 }
 
 }  // namespace
@@ -1080,13 +1084,10 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
         }
         {
             TimedScope ts(timer, "k_pairs_reduce", s);
-            hipLaunchKernelGGL(k_pairs_reduce, dim3(grid), dim3(kBlk), 0, s, pairs, pair_count, I, parent, root,
-                               ucount, other, fit, mc, (int32_t)measure);
-        }
-        {
-            TimedScope ts(timer, "k_root_final", s);
-            hipLaunchKernelGGL(k_root_final, dim3((S + 63) / 64), dim3(64), 0, s, root, I, parent, al, other,
-                               g->d_row_ptr, ucount, fit, mc, (int32_t)measure);
+            // the root components ride in the same launch as extra blocks
+            const int32_t roots = (S + kBlk - 1) / kBlk;
+            hipLaunchKernelGGL(k_pairs_reduce, dim3(grid + roots), dim3(kBlk), 0, s, pairs, pair_count, I, grid,
+                               parent, root, ucount, al, other, g->d_row_ptr, fit, mc, (int32_t)measure);
         }
         GAPA_HIP(hipGetLastError());
     }

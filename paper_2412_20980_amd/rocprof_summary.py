@@ -30,8 +30,7 @@ import sys
 
 # kernels of one batched-fitness pass (bit-parallel path)
 FITNESS_KERNELS = ("k_dead_transpose", "k_seed", "k_pull_band", "k_collect_pending", "k_pull_worklist",
-                   "k_collect_pairs", "k_pairs_hook", "k_pairs_count", "k_pairs_reduce",
-                   "k_root_final", "k_fitness_tail")
+                   "k_collect_pairs", "k_pairs_hook", "k_pairs_count", "k_pairs_reduce")
 PASS_MARKER = "k_dead_transpose"  # launched first in every pass, once
 
 
