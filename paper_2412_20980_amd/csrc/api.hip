@@ -237,9 +237,13 @@ constexpr int kSources = 64;
 constexpr int kMaxBands = 24;
 constexpr int kMinBand = 16384;  // at n = 200k the 8.9k nodes of BFS levels 3+ join level 2's band: 2 % faster
 
+// Also returns each source's index among its instance's sources (the t-th
+// source is order[voff[b] + t]; -1 for every other node) and, when band 0
+// holds exactly the sources (no merge took them into band 1), its size in
+// src_band (else 0).
 void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, const std::vector<int32_t> &voff,
                      std::vector<int32_t> &order, std::vector<int32_t> &colD, std::vector<int32_t> &band_v,
-                     std::vector<int32_t> &band_off)
+                     std::vector<int32_t> &band_off, std::vector<int8_t> &src_idx, int32_t &src_band)
 {
     std::vector<int32_t> deg(n);
     for (int32_t v = 0; v < n; ++v) deg[v] = rp[v + 1] - rp[v];
@@ -251,6 +255,7 @@ void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, const std:
 
     std::vector<int32_t> level(n, -1);
     std::vector<int32_t> frontier, next;
+    std::vector<std::pair<int32_t, int8_t>> sources;
     int32_t nlev = 1;
     for (size_t b = 0; b + 1 < voff.size(); ++b) {
         const int32_t v0 = voff[b], v1 = voff[b + 1];
@@ -262,6 +267,7 @@ void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, const std:
             level[v] = 0;
             frontier.push_back(v);
         }
+        for (size_t t = 0; t < frontier.size(); ++t) sources.emplace_back(frontier[t], (int8_t)t);
         int32_t lv = 0;
         while (!frontier.empty()) {
             next.clear();
@@ -316,6 +322,9 @@ void graph_orderings(int32_t n, const int32_t *rp, const int32_t *ci, const std:
         }
         band_off.erase(band_off.begin() + best);
     }
+    src_idx.assign((size_t)std::max(n, 1), (int8_t)-1);
+    for (const auto &st : sources) src_idx[st.first] = st.second;
+    src_band = band_off.size() > 1 && band_off[1] == (int32_t)sources.size() ? (int32_t)sources.size() : 0;
 }
 
 #define API_TRY(expr)                  \
@@ -405,7 +414,8 @@ int graph_build(int dev, int32_t n, int64_t nnz, const int32_t *row_ptr, const i
     for (int32_t v = 0; v < n; ++v)
         for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) src[e] = v;
     std::vector<int32_t> order, colD, band_v;
-    graph_orderings(n, row_ptr, col_idx, voff, order, colD, band_v, g->band_off);
+    std::vector<int8_t> src_idx;
+    graph_orderings(n, row_ptr, col_idx, voff, order, colD, band_v, g->band_off, src_idx, g->src_band);
     g->n_noniso = (int32_t)band_v.size();
     std::vector<uint32_t> noniso_bits((size_t)g->words, 0u);
     for (int32_t v = 0; v < n; ++v)
@@ -437,6 +447,9 @@ int graph_build(int dev, int32_t n, int64_t nnz, const int32_t *row_ptr, const i
         return fail(hip_fail(e, "hipMemcpy"));
     if ((e = hipMalloc(&g->d_noniso, (size_t)g->words * 4)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
     if ((e = hipMemcpy(g->d_noniso, noniso_bits.data(), (size_t)g->words * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_fail(e, "hipMemcpy"));
+    if ((e = hipMalloc(&g->d_src_idx, src_idx.size())) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMemcpy(g->d_src_idx, src_idx.data(), src_idx.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(hip_fail(e, "hipMemcpy"));
     {
         std::vector<int4> rec(std::max<size_t>(band_v.size(), 1), make_int4(0, 0, 0, 0));
@@ -470,6 +483,7 @@ void graph_release(gapa_graph *g)
         for (int32_t *p : {g->d_src, g->d_colD, g->d_order})
             if (p) (void)hipFree(p);
         if (g->d_noniso) (void)hipFree(g->d_noniso);
+        if (g->d_src_idx) (void)hipFree(g->d_src_idx);
         if (g->d_band_rec) (void)hipFree(g->d_band_rec);
         release_workspace(g->ws);
     }

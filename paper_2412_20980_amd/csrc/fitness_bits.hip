@@ -211,44 +211,79 @@ __global__ __launch_bounds__(kBlk) void k_dead_transpose(const uint32_t *__restr
 // and counters and the pass's counters (ctr[2] is the "sweep 0 changed"
 // flag, set).  One wave per slot tests 64 candidates of the order at a time
 // (the highest-degree nodes are the ones a population removes most).
-__global__ void k_seed(const uint32_t *__restrict__ dead, const int32_t *__restrict__ order, const Insts I, int32_t Wd,
-                       int32_t *__restrict__ root, uint32_t *__restrict__ reach, int32_t *__restrict__ parent,
-                       int32_t *__restrict__ other, int32_t *__restrict__ ctr, unsigned long long *__restrict__ fitness,
-                       int32_t *__restrict__ mcn)
+// With src_band > 0, band 0 holds exactly the sources and is not swept:
+// instead the surviving sources next to each root take its bit here.  They
+// lead the root's neighbour list, which is by (degree desc, id), so its first
+// 64 entries hold them all.  A block's kSeedWaves slots share one word of the
+// rows, so their bits for each source are gathered in LDS and each source's
+// word gets one atomic OR.  Band 0's pending flags are set for the
+// compaction (a source with nothing pending only costs a worklist entry).
+constexpr int kSeedWaves = 16;
+
+__global__ __launch_bounds__(64 * kSeedWaves) void k_seed(
+    const uint32_t *__restrict__ dead, const int32_t *__restrict__ order, const Insts I, int32_t Wd,
+    int32_t *__restrict__ root, uint32_t *__restrict__ reach, int32_t *__restrict__ parent,
+    int32_t *__restrict__ other, int32_t *__restrict__ ctr, unsigned long long *__restrict__ fitness,
+    int32_t *__restrict__ mcn, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ colD,
+    const int8_t *__restrict__ src_idx, uint8_t *__restrict__ pflag, int32_t src_band)
 {
+    __shared__ uint32_t s_src[64];
     const int lane = threadIdx.x & 63;
-    const int32_t gi = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int32_t S = I.count * I.bseg;
+    const int32_t g0 = (int32_t)blockIdx.x * kSeedWaves;
+    const int32_t gi = g0 + (int32_t)(threadIdx.x >> 6);
     if (blockIdx.x == 0 && threadIdx.x < 64) ctr[threadIdx.x] = threadIdx.x == 2 ? 1 : 0;
-    if (gi >= I.count * I.bseg) return;  // uniform over the wave
-    const int32_t b = gi / I.bseg, i = gi - b * I.bseg;
-    if (i >= i_live(I, b)) {
-        if (lane == 0) {
+    if (blockIdx.x == 0)
+        for (int32_t t = threadIdx.x; t < src_band; t += blockDim.x) pflag[t] = 1;
+    if (threadIdx.x < 64) s_src[threadIdx.x] = 0u;
+    __syncthreads();
+    if (gi < S) {  // uniform over the wave, as is everything below up to the barrier
+        const int32_t b = gi / I.bseg, i = gi - b * I.bseg;
+        if (i < i_live(I, b)) {
+            const int32_t w = i >> 5;
+            const uint32_t bit = 1u << (i & 31);
+            const int32_t p0 = i_voff(I, b), p1 = i_voff(I, b + 1);
+            int32_t r = -1;
+            for (int32_t p = p0; p < p1; p += 64) {
+                const int32_t v = p + lane < p1 ? order[p + lane] : -1;
+                const bool alive = v >= 0 && !(dead[(int64_t)v * Wd + w] & bit);
+                const uint64_t hit = __ballot(alive);
+                if (hit) {
+                    r = __shfl(v, (int)__ffsll((unsigned long long)hit) - 1, 64);
+                    break;
+                }
+            }
+            if (src_band > 0 && r >= 0) {
+                const int32_t e = row_ptr[r] + lane;
+                if (e < row_ptr[r + 1]) {
+                    const int32_t u = colD[e];
+                    const int32_t t = src_idx[u];
+                    if (t >= 0 && !(dead[(int64_t)u * Wd + w] & bit)) atomicOr(&s_src[t], bit);
+                }
+            }
+            if (lane == 0) {
+                root[gi] = r;
+                other[gi] = 0;
+                fitness[gi] = 0ull;
+                if (mcn) mcn[gi] = 0;
+                if (r >= 0) {
+                    atomicOr(reach + (int64_t)r * Wd + w, bit);
+                    parent[uf_block(I, gi) + (r - p0)] = r - p0;
+                }
+            }
+        } else if (lane == 0) {
             root[gi] = -1;
             other[gi] = 0;
         }
-        return;
     }
-    const int32_t w = i >> 5;
-    const uint32_t bit = 1u << (i & 31);
-    const int32_t p0 = i_voff(I, b), p1 = i_voff(I, b + 1);
-    int32_t r = -1;
-    for (int32_t p = p0; p < p1; p += 64) {
-        const int32_t v = p + lane < p1 ? order[p + lane] : -1;
-        const bool alive = v >= 0 && !(dead[(int64_t)v * Wd + w] & bit);
-        const uint64_t hit = __ballot(alive);
-        if (hit) {
-            r = __shfl(v, (int)__ffsll((unsigned long long)hit) - 1, 64);
-            break;
-        }
-    }
-    if (lane == 0) {
-        root[gi] = r;
-        other[gi] = 0;
-        fitness[gi] = 0ull;
-        if (mcn) mcn[gi] = 0;
-        if (r >= 0) {
-            atomicOr(reach + (int64_t)r * Wd + w, bit);
-            parent[uf_block(I, gi) + (r - p0)] = r - p0;
+    if (src_band > 0) {  // uniform over the grid
+        __syncthreads();
+        // the block's slots lie in one instance and one word (kSeedWaves
+        // divides 32, and every instance's slots start at a multiple of 32)
+        if (threadIdx.x < 64 && g0 < S && s_src[threadIdx.x]) {
+            const int32_t b = g0 / I.bseg, w = (g0 - b * I.bseg) >> 5;
+            const int32_t u = order[i_voff(I, b) + (int32_t)threadIdx.x];
+            atomicOr(reach + (int64_t)u * Wd + w, s_src[threadIdx.x]);
         }
     }
 }
@@ -1024,13 +1059,15 @@ int run_pass(gapa_graph *g, FitnessWorkspace &ws, const PassShape &sh, const Ins
         }
         {
             TimedScope ts(timer, "k_seed", s);
-            // one wave per slot, four slots per block
-            hipLaunchKernelGGL(k_seed, dim3((S + 3) / 4), dim3(256), 0, s, dead, g->d_order, I, Wd, root, reach,
-                               parent, other, ctr, fit, mc);
+            // one wave per slot, kSeedWaves slots per block
+            hipLaunchKernelGGL(k_seed, dim3((S + kSeedWaves - 1) / kSeedWaves), dim3(64 * kSeedWaves), 0, s, dead,
+                               g->d_order, I, Wd, root, reach, parent, other, ctr, fit, mc, g->d_row_ptr, g->d_colD,
+                               g->d_src_idx, ws.pflag.as<uint8_t>(), g->src_band);
         }
         {
             TimedScope ts(timer, "k_pull_band", s);
-            for (int32_t b = 0; b < nb; ++b) {
+            // band 0, the sources, is taken by k_seed when it holds them alone
+            for (int32_t b = g->src_band > 0 ? 1 : 0; b < nb; ++b) {
                 const int32_t b0 = g->band_off[b], b1 = g->band_off[b + 1];
                 if (b1 <= b0) continue;
                 const int64_t threads = (int64_t)(b1 - b0) * Wd;

@@ -145,7 +145,9 @@ struct gapa_graph {
     int4 *d_band_rec = nullptr;   // [n_noniso] non-isolated nodes by (BFS level, id) as records
                                   // (node, row_ptr[node], row_ptr[node + 1], 0)
     uint32_t *d_noniso = nullptr; // [words] bit v set: v has at least one edge
+    int8_t *d_src_idx = nullptr;  // [n] index of a band source among its instance's (order[voff + t]), else -1
     std::vector<int32_t> band_off;  // host: band b is d_band_rec[band_off[b], band_off[b+1])
+    int32_t src_band = 0;       // size of band 0 when it holds exactly the sources, else 0
     int32_t n_noniso = 0;       // nodes with at least one edge
     int32_t algorithm = 0;      // 0: bit-parallel sweeps, 1: edge-parallel union-find
     gapa::Tuning tune;
