@@ -190,3 +190,25 @@ def test_population_sharded_over_streams(gp, cl200k):
     assert np.array_equal(got, whole)
     idx = np.arange(0, 1024, 97)
     assert np.array_equal(whole[idx], O.eval_population(cl200k, pop[idx]))
+
+
+def test_deep_layers_sources_band_merged(gp):
+    # 64 hubs over 26 layers of 16,384 nodes: the breadth-first levels from
+    # the hubs give more bands than the pass keeps, and the smallest pair of
+    # neighbouring bands is the hubs' band with the first layer's, so the
+    # sources share a band with other nodes and are swept like them rather
+    # than given their roots' bits when the roots are found
+    H, L, Wl = 64, 26, 16384
+    n = H + L * Wl
+    rng = np.random.default_rng(30)
+    j = np.arange(Wl)
+    us, vs = [j % H], [H + j]
+    for l in range(L - 1):
+        us += [H + l * Wl + j, H + l * Wl + j]
+        vs += [H + (l + 1) * Wl + j, H + (l + 1) * Wl + rng.integers(0, Wl, Wl)]
+    g = inputs.csr_from_edges(n, np.concatenate(us), np.concatenate(vs), name="layers26")
+    deg = g.degrees()
+    assert deg[:H].min() == Wl // H and deg[H:].max() < Wl // H  # the hubs are the sources
+    graph = gp.Graph.from_csr(g)
+    check(gp, g, inputs.random_population(n, 2000, 32, seed=31), graph=graph)
+    check(gp, g, inputs.hub_biased_population(g, 2000, 32, seed=32, hub_frac=0.5), graph=graph)
