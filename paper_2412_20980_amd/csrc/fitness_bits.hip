@@ -910,8 +910,10 @@ __device__ __forceinline__ void add_component(int64_t s, unsigned long long *fit
 // every surviving non-isolated node but the pending ones outside the root's
 // set: alive - other[gi] (all its pending nodes) + the root set's counter
 // (the root alone when it is isolated); that counter is cleared for reuse.
-// Neither part reads what the other writes: the root's counter is skipped by
-// the pair part, and other[] is final once k_pairs_count has ended.
+// Neither part reads a value the other changes: the root's counter is skipped
+// by the pair part, other[] is final once k_pairs_count has ended, and the
+// path compression both do in parent[] only points entries at ancestors with
+// the same representative.
 __global__ void k_pairs_reduce(const int64_t *__restrict__ pairs, const unsigned long long *__restrict__ pair_count, const Insts I,
                                int32_t grid, int32_t *__restrict__ parent, const int32_t *__restrict__ root,
                                int32_t *__restrict__ ucount, const int32_t *__restrict__ alive_noniso,
